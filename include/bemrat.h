@@ -1,0 +1,188 @@
+/*
+ * bemrat.h -- C ABI of libbemrat.so: the node sweep of the contour / Chebyshev rational
+ * approximation method for boundary-element acoustic eigenproblems T(kappa) x = 0
+ * (El-Guide, Miedlar, Saad, arXiv 1906.03938), on AMD Instinct MI355X (gfx950).
+ *
+ * The operator.  T(kappa) is the single-layer Helmholtz operator of a closed surface made
+ * of n flat triangles, discretised by piecewise-constant collocation at the centroids
+ * x_a (paper, Section 1: Green's function, eq. GreenFun; the matrix T(z) of
+ * eq. NEVPHelmholtz for a Dirichlet problem):
+ *     T_ab(kappa) = sum_{q<7} A_b w_q exp(i kappa r)/(4 pi r),  r = |x_a - y_bq|  (a != b)
+ *     T_aa(kappa) = integral over triangle a of exp(i kappa |x_a - y|)/(4 pi |x_a - y|)
+ * where (y_bq, w_q) is Radon's degree-5 seven-point rule mapped to triangle b and A_b its
+ * area; the self term is integrated exactly (polar coordinates around x_a).  kappa may be
+ * complex.  Entries are regenerated on the device for every use and never stored.
+ *
+ * Conventions shared by every entry point:
+ *   - complex numbers are interleaved (re, im) pairs of double, the layout of
+ *     std::complex<double>, C99 double _Complex and torch.complex128;
+ *   - pointers marked [host] are host memory read (or written) before the call returns;
+ *     every other array pointer is device memory owned by the caller;
+ *   - matrices are row-major; "ld" arguments are row strides in complex elements;
+ *   - calls are asynchronous on the given stream (0 = the null stream); host-side
+ *     argument checks happen before anything is launched, and an argument error launches
+ *     nothing;
+ *   - results are bitwise reproducible for identical inputs on the same device (fixed
+ *     reduction orders, no floating-point atomics);
+ *   - a mesh handle owns its device geometry and a workspace that grows on demand (the
+ *     first call of a given size may allocate device memory); one handle must not be
+ *     used from two host threads or on two streams concurrently;
+ *   - no C++ exception crosses this interface; on failure bem_last_error() describes the
+ *     most recent error of the calling thread.
+ */
+#ifndef BEMRAT_H
+#define BEMRAT_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bem_mesh *bem_mesh_t;
+
+typedef enum {
+    BEM_OK = 0,
+    BEM_EINVAL = 1,       /* bad argument: null pointer, size <= 0, ld < m, non-finite value */
+    BEM_EMESH = 2,        /* bad mesh: index out of range, degenerate (zero-area) triangle */
+    BEM_ENOMEM = 3,       /* device allocation failed */
+    BEM_EDEVICE = 4,      /* HIP runtime or kernel error */
+    BEM_EUNSUPPORTED = 5  /* option not built (e.g. a reduced-precision flag) */
+} bem_status;
+
+/* Sweep forms, passed in `flags`.
+ *   BEM_FORM_DIRECT: one regenerated operator per node, T(z_j) V for every node.
+ *   BEM_FORM_EXPAND: T(z) = sum_l t^l T_l with t = (z - c)/R about the centre c and
+ *     radius R of the nodes (Taylor expansion of exp(i z r) in z; for cheb_moments the
+ *     Jacobi-Anger expansion in Chebyshev polynomials of exp(i kappa r) on [a, b]);
+ *     the library generates L < N coefficient operators, truncated where the remainder
+ *     bound falls below 1e-17 relative, and combines them per node.
+ *   BEM_FORM_AUTO: EXPAND when it needs fewer operators than DIRECT, else DIRECT.
+ * Bits 4..7 select the arithmetic; only 0 (FP64 throughout) is built, any other value
+ * returns BEM_EUNSUPPORTED. */
+#define BEM_FORM_AUTO 0u
+#define BEM_FORM_DIRECT 1u
+#define BEM_FORM_EXPAND 2u
+#define BEM_FORM_MASK 3u
+#define BEM_PREC_MASK 0xF0u
+
+/* ---------------------------------------------------------------- mesh handle --- */
+
+/* Creates a mesh handle: uploads the surface, builds centroids, areas and quadrature
+ * points on the device (sweep step "geometry staging").  xyz [host]: nv x 3 vertex
+ * coordinates; tri [host]: n x 3 vertex indices (0-based).  Synchronises `stream` once
+ * (to check triangle areas).  Errors: BEM_EINVAL (null pointers, nv < 3, n < 1,
+ * non-finite coordinates), BEM_EMESH (index outside [0, nv), zero-area triangle),
+ * BEM_ENOMEM, BEM_EDEVICE.  On error *out is set to NULL. */
+bem_status bem_mesh_create(const double *xyz, int64_t nv, const int32_t *tri, int64_t n,
+                           hipStream_t stream, bem_mesh_t *out);
+
+/* Releases the handle and all its device memory (synchronises the device first).
+ * NULL is accepted. */
+void bem_mesh_destroy(bem_mesh_t mesh);
+
+/* Number of triangles (= degrees of freedom) of the mesh, or -1 for NULL. */
+int64_t bem_mesh_size(bem_mesh_t mesh);
+
+/* Geometry as built on the device, copied to host arrays (any may be NULL):
+ * area [host] n, centroid [host] n x 3, quad_xyz [host] n x 7 x 3,
+ * quad_w [host] n x 7 physical weights A_b w_q.  Synchronises `stream`. */
+bem_status bem_mesh_geometry(bem_mesh_t mesh, double *area, double *centroid,
+                             double *quad_xyz, double *quad_w, hipStream_t stream);
+
+/* ------------------------------------------------------------ nodes, weights --- */
+
+/* Trapezoidal rule for the Cauchy integral (paper, eq. Tz and eq. TzApp) on the circle
+ * |z - c| = radius with N nodes z_j = c + radius e^{i theta_j}, theta_j = 2 pi (j + 1/2)/N,
+ * and weights w_j = -(z_j - c)/N so that T(z) ~ sum_j w_j T(z_j)/(z - z_j).  If P > 0
+ * also writes the moment weights W[j][p] = w_j (z_j - shift)^{-(p+1)}, p < P, which turn
+ * the node sweep into the blocks sum_j B_j (z_j - shift)^{-(p+1)}, B_j = w_j T(z_j), of one
+ * inverse-power step (Algorithm 1).  z, w [host]: N complex; W [host]: N x P complex
+ * (may be NULL when P == 0).  Errors: BEM_EINVAL (N < 1, radius <= 0, P < 0, null
+ * outputs, a node equal to the shift). */
+bem_status bem_contour_nodes(double c_re, double c_im, double radius, int64_t N,
+                             double shift_re, double shift_im, int64_t P,
+                             double *z, double *w, double *W);
+
+/* First-kind Chebyshev points on [a, b] (paper, eq. Chebyshev) kappa_k = alpha + beta
+ * cos(pi (k + 1/2)/N), alpha = (a+b)/2, beta = (b-a)/2, and the DCT-II matrix
+ * coef[l][k] = (eps_l/N) cos(pi l (k + 1/2)/N), eps_0 = 1, eps_l = 2, of the degree N-1
+ * interpolant sum_l C_l T_l((kappa - alpha)/beta).  kappa [host]: N doubles;
+ * coef [host]: N x N doubles (may be NULL).  Errors: BEM_EINVAL (N < 1, a >= b). */
+bem_status bem_cheb_nodes(double a, double b, int64_t N, double *kappa, double *coef);
+
+/* ----------------------------------------------------------------- the sweep --- */
+
+/* Self terms S[k][a] = T_aa(kappa_k) (the exact singular integral over triangle a, see
+ * above), for nk wavenumbers.  kappa [host]: nk complex; S: device, nk x n complex,
+ * contiguous.  Errors: BEM_EINVAL (null, nk < 1, non-finite kappa), BEM_EDEVICE. */
+bem_status bem_self_terms(bem_mesh_t mesh, const double *kappa, int64_t nk, double *S,
+                          hipStream_t stream);
+
+/* Y[k] = T(kappa_k) V for k < nk: the operator regenerated at each wavenumber and
+ * applied to the probe block (paper, the products with B_i of Example 3).
+ * kappa [host]: nk complex.  V: device, n x m complex, row stride ldv >= m.
+ * Y: device, nk blocks of n x m complex; block k starts at Y + 2*k*n*ldy doubles, row
+ * stride ldy >= m.  flags: BEM_FORM_DIRECT (AUTO means DIRECT here).
+ * Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE. */
+bem_status bem_assemble_apply(bem_mesh_t mesh, const double *kappa, int64_t nk,
+                              const double *V, int64_t m, int64_t ldv, double *Y, int64_t ldy,
+                              uint32_t flags, hipStream_t stream);
+
+/* Contour moments M[p] = sum_j W[j][p] T(z_j) V, p < P (paper, eq. TzApp with
+ * B_j = w_j T(z_j), folded with the per-node weights of eq. linsyssim; with
+ * W[j][0] = w_j/(z_j - c) the sum is -S V, S = T~(c) the Schur complement).
+ * z [host]: N complex nodes; W [host]: N x P complex.  V: device n x m (ldv >= m).
+ * M: device, P blocks of n x m; block p starts at M + 2*p*n*ldm doubles, row stride
+ * ldm >= m.  Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE. */
+bem_status contour_moments(bem_mesh_t mesh, const double *z, int64_t N, const double *W,
+                           int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
+                           int64_t ldm, uint32_t flags, hipStream_t stream);
+
+/* Chebyshev coefficient blocks C[l] = sum_k coef[l][k] T(kappa_k) V, l < L <= N, on the
+ * first-kind points of [a, b] (paper, eq. Chebyshev; nodes and coef as in
+ * bem_cheb_nodes).  a < b real.  V: device n x m (ldv >= m).  C: device, L blocks of
+ * n x m, block l at C + 2*l*n*ldc doubles, row stride ldc >= m.
+ * Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE. */
+bem_status cheb_moments(bem_mesh_t mesh, double a, double b, int64_t N, int64_t L,
+                        const double *V, int64_t m, int64_t ldv, double *C, int64_t ldc,
+                        uint32_t flags, hipStream_t stream);
+
+/* Rayleigh-Ritz projections Pout[j] = U^H T(z_j) U, j < N, each m x m row-major
+ * contiguous (paper, Section 3: B^_j = w_j U^H T(z_j) U), optionally fused with the
+ * moments M[p] = sum_j W[j][p] T(z_j) U, p < Pw, of the same sweep (W [host] N x Pw, M
+ * device with row stride ldm >= m; pass W = NULL, Pw = 0, M = NULL to skip them).
+ * z [host]: N complex.  U: device n x m (ldu >= m).  Pout: device, N x m x m complex.
+ * Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE. */
+bem_status rr_project(bem_mesh_t mesh, const double *z, int64_t N, const double *U,
+                      int64_t m, int64_t ldu, double *Pout, const double *W, int64_t Pw,
+                      double *M, int64_t ldm, uint32_t flags, hipStream_t stream);
+
+/* ---------------------------------------------------------------- diagnostics --- */
+
+/* Form the last sweep call on this handle used: BEM_FORM_DIRECT or BEM_FORM_EXPAND, and
+ * the number of generated operators (nodes for DIRECT, expansion terms for EXPAND).
+ * Either output may be NULL.  Returns BEM_EINVAL for a NULL handle. */
+bem_status bem_last_form(bem_mesh_t mesh, uint32_t *form, int64_t *operators);
+
+/* Enables (on != 0) or disables timing of the generate-and-contract kernel: when on,
+ * every sweep call records HIP events around that kernel on the call's stream. */
+bem_status bem_set_timing(bem_mesh_t mesh, int on);
+
+/* Device time in milliseconds of the generate-and-contract kernel of the most recent
+ * timed sweep call (synchronises on its end event).  BEM_EINVAL if none was timed. */
+bem_status bem_last_kernel_ms(bem_mesh_t mesh, float *ms);
+
+/* Synchronises `stream` and reports any asynchronous device error as BEM_EDEVICE. */
+bem_status bem_stream_status(hipStream_t stream);
+
+/* Message describing the most recent error of the calling thread ("" if none). */
+const char *bem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEMRAT_H */

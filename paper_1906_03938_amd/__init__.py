@@ -1,0 +1,18 @@
+"""MI355X-native node sweep of the contour / Chebyshev rational approximation method for
+boundary-element acoustic eigenproblems T(kappa) x = 0 (arXiv 1906.03938).
+
+The numerical work runs in libbemrat.so (HIP kernels for gfx950, C ABI in
+include/bemrat.h); this package is its ctypes binding plus the host driver that
+orchestrates sweeps into eigenvalues.
+"""
+from ._lib import (  # noqa: F401
+    FORM_AUTO,
+    FORM_DIRECT,
+    FORM_EXPAND,
+    BemError,
+    Mesh,
+    cheb_nodes,
+    contour_nodes,
+    lib,
+    stream_status,
+)

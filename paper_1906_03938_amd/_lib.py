@@ -1,0 +1,251 @@
+"""ctypes binding of libbemrat.so (C ABI in include/bemrat.h).
+
+Argument marshalling only: tensors are passed as device pointers with their row
+strides, the stream is torch's current stream, and every numerical step runs in the
+library's HIP kernels.  There is no fallback: if the library is missing or no HIP device
+is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbemrat.so")
+
+BEM_OK, BEM_EINVAL, BEM_EMESH, BEM_ENOMEM, BEM_EDEVICE, BEM_EUNSUPPORTED = range(6)
+FORM_AUTO, FORM_DIRECT, FORM_EXPAND = 0, 1, 2
+STATUS_NAMES = {0: "BEM_OK", 1: "BEM_EINVAL", 2: "BEM_EMESH", 3: "BEM_ENOMEM", 4: "BEM_EDEVICE",
+                5: "BEM_EUNSUPPORTED"}
+
+# every symbol declared in include/bemrat.h
+EXPORTS = [
+    "bem_mesh_create", "bem_mesh_destroy", "bem_mesh_size", "bem_mesh_geometry",
+    "bem_contour_nodes", "bem_cheb_nodes", "bem_self_terms", "bem_assemble_apply",
+    "contour_moments", "cheb_moments", "rr_project", "bem_last_form", "bem_set_timing",
+    "bem_last_kernel_ms", "bem_stream_status", "bem_last_error",
+]
+
+
+class BemError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_lib = None
+
+
+def lib():
+    """Loads libbemrat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1906_03938_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.bem_mesh_create.argtypes = [_dp, _i64, ctypes.POINTER(ctypes.c_int32), _i64, _vp, ctypes.POINTER(_vp)]
+    L.bem_mesh_destroy.argtypes = [_vp]
+    L.bem_mesh_destroy.restype = None
+    L.bem_mesh_size.argtypes = [_vp]
+    L.bem_mesh_size.restype = _i64
+    L.bem_mesh_geometry.argtypes = [_vp, _dp, _dp, _dp, _dp, _vp]
+    L.bem_contour_nodes.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _i64, ctypes.c_double,
+                                    ctypes.c_double, _i64, _dp, _dp, _dp]
+    L.bem_cheb_nodes.argtypes = [ctypes.c_double, ctypes.c_double, _i64, _dp, _dp]
+    L.bem_self_terms.argtypes = [_vp, _dp, _i64, _vp, _vp]
+    L.bem_assemble_apply.argtypes = [_vp, _dp, _i64, _vp, _i64, _i64, _vp, _i64, _u32, _vp]
+    L.contour_moments.argtypes = [_vp, _dp, _i64, _dp, _i64, _vp, _i64, _i64, _vp, _i64, _u32, _vp]
+    L.cheb_moments.argtypes = [_vp, ctypes.c_double, ctypes.c_double, _i64, _i64, _vp, _i64, _i64, _vp, _i64,
+                               _u32, _vp]
+    L.rr_project.argtypes = [_vp, _dp, _i64, _vp, _i64, _i64, _vp, _dp, _i64, _vp, _i64, _u32, _vp]
+    L.bem_last_form.argtypes = [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_i64)]
+    L.bem_set_timing.argtypes = [_vp, ctypes.c_int]
+    L.bem_last_kernel_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
+    L.bem_stream_status.argtypes = [_vp]
+    L.bem_last_error.argtypes = []
+    L.bem_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("bem_mesh_destroy", "bem_mesh_size", "bem_last_error"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != BEM_OK:
+        raise BemError(status, lib().bem_last_error().decode())
+
+
+def _host_complex(values) -> np.ndarray:
+    return np.ascontiguousarray(np.atleast_1d(np.asarray(values, dtype=np.complex128)))
+
+
+def _hp(a: np.ndarray):
+    return a.view(np.float64).ctypes.data_as(_dp) if a.dtype == np.complex128 else a.ctypes.data_as(_dp)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _block(t, name):
+    """(pointer, m, ld) of a complex128 CUDA matrix whose rows may be strided."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D with unit column stride")
+    return ctypes.c_void_p(t.data_ptr()), t.shape[1], t.stride(0)
+
+
+# ------------------------------------------------------------------- host routines
+
+
+def contour_nodes(c, radius, N, shift=None, P=0):
+    """Trapezoidal nodes/weights on |z - c| = radius and moment weights (host, in C)."""
+    c = complex(c)
+    shift = c if shift is None else complex(shift)
+    z = np.zeros(N, dtype=np.complex128)
+    w = np.zeros(N, dtype=np.complex128)
+    W = np.zeros((N, max(P, 1)), dtype=np.complex128)
+    _check(lib().bem_contour_nodes(c.real, c.imag, float(radius), N, shift.real, shift.imag, P, _hp(z), _hp(w),
+                                   _hp(W)))
+    return z, w, (W[:, :P] if P else None)
+
+
+def cheb_nodes(a, b, N):
+    kappa = np.zeros(N)
+    coef = np.zeros((N, N))
+    _check(lib().bem_cheb_nodes(float(a), float(b), N, kappa.ctypes.data_as(_dp), coef.ctypes.data_as(_dp)))
+    return kappa, coef
+
+
+# ------------------------------------------------------------------------- the mesh
+
+
+class Mesh:
+    """A triangle mesh resident on the current HIP device."""
+
+    def __init__(self, xyz, tri):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        if xyz.ndim != 2 or xyz.shape[1] != 3 or tri.ndim != 2 or tri.shape[1] != 3:
+            raise ValueError("xyz must be (nv, 3) and tri (n, 3)")
+        h = ctypes.c_void_p()
+        _check(lib().bem_mesh_create(xyz.ctypes.data_as(_dp), xyz.shape[0],
+                                     tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), tri.shape[0], _stream(),
+                                     ctypes.byref(h)))
+        self._h = h
+        self.n = tri.shape[0]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bem_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- helpers
+    def _out(self, blocks, m):
+        torch = _torch()
+        return torch.empty((blocks, self.n, m), dtype=torch.complex128, device="cuda")
+
+    def geometry(self):
+        n = self.n
+        area = np.zeros(n)
+        cen = np.zeros((n, 3))
+        qp = np.zeros((n, 7, 3))
+        qw = np.zeros((n, 7))
+        _check(lib().bem_mesh_geometry(self._h, area.ctypes.data_as(_dp), cen.ctypes.data_as(_dp),
+                                       qp.ctypes.data_as(_dp), qw.ctypes.data_as(_dp), _stream()))
+        return area, cen, qp, qw
+
+    def self_terms(self, kappas):
+        torch = _torch()
+        k = _host_complex(kappas)
+        S = torch.empty((k.size, self.n), dtype=torch.complex128, device="cuda")
+        _check(lib().bem_self_terms(self._h, _hp(k), k.size, ctypes.c_void_p(S.data_ptr()), _stream()))
+        return S
+
+    def assemble_apply(self, kappas, V, out=None, form=FORM_DIRECT):
+        k = _host_complex(kappas)
+        pv, m, ldv = _block(V, "V")
+        Y = self._out(k.size, m) if out is None else out
+        _check(lib().bem_assemble_apply(self._h, _hp(k), k.size, pv, m, ldv, ctypes.c_void_p(Y.data_ptr()),
+                                        Y.stride(1), form, _stream()))
+        return Y
+
+    def contour_moments(self, z, W, V, out=None, form=FORM_AUTO):
+        z = _host_complex(z)
+        W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(z.size, -1))
+        pv, m, ldv = _block(V, "V")
+        M = self._out(W.shape[1], m) if out is None else out
+        _check(lib().contour_moments(self._h, _hp(z), z.size, _hp(W), W.shape[1], pv, m, ldv,
+                                     ctypes.c_void_p(M.data_ptr()), M.stride(1), form, _stream()))
+        return M
+
+    def cheb_moments(self, a, b, N, L, V, out=None, form=FORM_AUTO):
+        pv, m, ldv = _block(V, "V")
+        C = self._out(L, m) if out is None else out
+        _check(lib().cheb_moments(self._h, float(a), float(b), N, L, pv, m, ldv, ctypes.c_void_p(C.data_ptr()),
+                                  C.stride(1), form, _stream()))
+        return C
+
+    def rr_project(self, z, U, W=None, out=None, moments_out=None, form=FORM_AUTO):
+        torch = _torch()
+        z = _host_complex(z)
+        pu, m, ldu = _block(U, "U")
+        Pout = torch.empty((z.size, m, m), dtype=torch.complex128, device="cuda") if out is None else out
+        M = None
+        if W is not None:
+            W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(z.size, -1))
+            M = self._out(W.shape[1], m) if moments_out is None else moments_out
+            _check(lib().rr_project(self._h, _hp(z), z.size, pu, m, ldu, ctypes.c_void_p(Pout.data_ptr()), _hp(W),
+                                    W.shape[1], ctypes.c_void_p(M.data_ptr()), M.stride(1), form, _stream()))
+        else:
+            _check(lib().rr_project(self._h, _hp(z), z.size, pu, m, ldu, ctypes.c_void_p(Pout.data_ptr()), None, 0,
+                                    None, m, form, _stream()))
+        return (Pout, M) if W is not None else Pout
+
+    def last_form(self):
+        f = _u32()
+        ops = _i64()
+        _check(lib().bem_last_form(self._h, ctypes.byref(f), ctypes.byref(ops)))
+        return int(f.value), int(ops.value)
+
+    def set_timing(self, on=True):
+        _check(lib().bem_set_timing(self._h, 1 if on else 0))
+
+    def last_kernel_ms(self):
+        ms = ctypes.c_float()
+        _check(lib().bem_last_kernel_ms(self._h, ctypes.byref(ms)))
+        return float(ms.value)
+
+
+def stream_status():
+    _check(lib().bem_stream_status(_stream()))

@@ -1,0 +1,823 @@
+// C ABI of libbemrat.so (declared in include/bemrat.h): argument checks, handle and
+// workspace management, choice of sweep form, host-side node/weight construction, and
+// the launch sequence of each call.  All numerical work on the operator runs in the HIP
+// kernels of mesh.hip, sweep.hip and combine.hip.
+#include "bemrat.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using bemrat::DeviceMesh;
+using cplx = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_error;
+
+bem_status fail(bem_status s, const std::string &msg) {
+    g_error = msg;
+    return s;
+}
+
+bem_status hip_fail(hipError_t e, const char *what) {
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? BEM_ENOMEM : BEM_EDEVICE;
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Device buffer that only grows.
+struct Buffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need) {
+        if (need <= bytes) return hipSuccess;
+        if (ptr) {
+            hipError_t e = hipFree(ptr);
+            ptr = nullptr;
+            bytes = 0;
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipMalloc(&ptr, need);
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            return e;
+        }
+        bytes = need;
+        return hipSuccess;
+    }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Pinned host staging for per-call parameters; reused once its last upload completed.
+struct Staging {
+    void *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    hipError_t ensure(size_t need) {
+        if (pending) {
+            hipError_t e = hipEventSynchronize(done);
+            if (e != hipSuccess) return e;
+            pending = false;
+        }
+        if (need <= bytes) return hipSuccess;
+        if (host) (void)hipHostFree(host);
+        host = nullptr;
+        bytes = 0;
+        hipError_t e = hipHostMalloc(&host, need, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            host = nullptr;
+            return e;
+        }
+        bytes = need;
+        return hipSuccess;
+    }
+};
+
+}  // namespace
+
+struct bem_mesh {
+    int device = 0;
+    DeviceMesh dm;
+    double diameter = 0.0;  // upper bound on every distance in the operator
+    Buffer geom, gl, self, aux, Z, params, partial;
+    Staging staging;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timing = false, timed = false;
+    uint32_t last_form = 0;
+    int64_t last_ops = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool finite_c(const double *p, int64_t count) {
+    for (int64_t i = 0; i < 2 * count; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// True when `p` is device (or managed) memory usable by kernels of the current device.
+bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+bem_status check_block(const void *p, int64_t m, int64_t ld, const char *name) {
+    if (!p) return fail(BEM_EINVAL, std::string(name) + " is NULL");
+    if (m <= 0) return fail(BEM_EINVAL, "m must be positive");
+    if (ld < m) return fail(BEM_EINVAL, std::string("leading dimension of ") + name + " is smaller than m");
+    if (!is_device_ptr(p)) return fail(BEM_EINVAL, std::string(name) + " is not device memory");
+    return BEM_OK;
+}
+
+bem_status check_flags(uint32_t flags) {
+    if (flags & BEM_PREC_MASK) return fail(BEM_EUNSUPPORTED, "only FP64 arithmetic is built");
+    if (flags & ~(BEM_FORM_MASK | BEM_PREC_MASK)) return fail(BEM_EINVAL, "unknown flag bits");
+    if ((flags & BEM_FORM_MASK) == 3u) return fail(BEM_EINVAL, "invalid form");
+    return BEM_OK;
+}
+
+bem_status check_kappas(const bem_mesh *h, const double *k, int64_t nk, const char *name) {
+    if (!k) return fail(BEM_EINVAL, std::string(name) + " is NULL");
+    if (nk < 1) return fail(BEM_EINVAL, std::string("number of ") + name + " must be positive");
+    if (!finite_c(k, nk)) return fail(BEM_EINVAL, std::string(name) + " has a non-finite value");
+    for (int64_t i = 0; i < nk; ++i)
+    {
+        if (std::fabs(k[2 * i + 1]) * h->diameter > 700.0)
+            return fail(BEM_EINVAL, std::string(name) + ": |Im kappa| x mesh diameter exceeds 700 (exp overflow)");
+        if (std::fabs(k[2 * i]) * h->diameter > 1e6)
+            return fail(BEM_EINVAL, std::string(name) + ": |Re kappa| x mesh diameter exceeds 1e6");
+    }
+    return BEM_OK;
+}
+
+// Radon's degree-5 seven-point rule: barycentric coordinates (7 x 3) then weights (7),
+// weights summing to one.
+void radon_rule(double *rule) {
+    const double s = std::sqrt(15.0);
+    const double p1 = (6.0 - s) / 21.0, q1 = (9.0 + 2.0 * s) / 21.0;  // orbit near vertices
+    const double p2 = (6.0 + s) / 21.0, q2 = (9.0 - 2.0 * s) / 21.0;  // orbit near edges
+    const double wv = (155.0 - s) / 1200.0, we = (155.0 + s) / 1200.0;
+    const double pts[7][3] = {{1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0}, {q1, p1, p1}, {p1, q1, p1},
+                              {p1, p1, q1}, {q2, p2, p2}, {p2, q2, p2}, {p2, p2, q2}};
+    const double w[7] = {0.225, wv, wv, wv, we, we, we};
+    for (int q = 0; q < 7; ++q) {
+        for (int c = 0; c < 3; ++c) rule[3 * q + c] = pts[q][c];
+        rule[21 + q] = w[q];
+    }
+}
+
+// Gauss-Legendre rule of order n on [-1, 1]: Newton iteration on P_n from the
+// asymptotic initial guesses, P_n and P_n' by the Bonnet recurrence.
+void gauss_legendre(int n, double *x, double *w) {
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(pi * (4.0 * i + 3.0) / (4.0 * n + 2.0));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = t;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (t * p1 - p0) / (t * t - 1.0);
+        x[i] = t;
+        w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+// Parameter block assembled on the host, uploaded once per call.
+struct Params {
+    std::vector<double> d;
+    size_t add(const double *p, size_t count) {
+        const size_t off = d.size();
+        d.insert(d.end(), p, p + count);
+        // keep 16-byte alignment for double2 reads
+        if (d.size() & 1) d.push_back(0.0);
+        return off;
+    }
+};
+
+bem_status upload(bem_mesh *h, const Params &p, hipStream_t s) {
+    const size_t bytes = p.d.size() * sizeof(double);
+    HIP_TRY(h->staging.ensure(bytes), "staging buffer");
+    HIP_TRY(h->params.ensure(bytes), "parameter buffer");
+    std::memcpy(h->staging.host, p.d.data(), bytes);
+    HIP_TRY(hipMemcpyAsync(h->params.ptr, h->staging.host, bytes, hipMemcpyHostToDevice, s), "parameter upload");
+    HIP_TRY(hipEventRecord(h->staging.done, s), "event record");
+    h->staging.pending = true;
+    return BEM_OK;
+}
+
+// The generated operators of one sweep and how each node combines them.
+struct Plan {
+    bemrat::Gen gen = bemrat::Gen::Direct;
+    int L = 0;
+    cplx c = 0.0;
+    double R = 0.0;
+    std::vector<cplx> kappa;  // Direct: L wavenumbers
+    std::vector<cplx> Cf;     // N x L: T(z_j) = sum_l Cf[j][l] T_l
+};
+
+// Smallest L with x^L/L! / (1 - x/(L+1)) <= 1e-17 e^{-x}: truncation of the Taylor series
+// of exp(i R r t) below 1e-17 relative to its smallest value on |t| <= 1.
+int taylor_length(double x) {
+    const double target = 1e-17 * std::exp(-x);
+    double term = 1.0;
+    for (int L = 1; L < bemrat::kMaxTaylor; ++L) {
+        term *= x / L;
+        if (L > x && term / (1.0 - x / (L + 1)) <= target) return L;
+    }
+    return bemrat::kMaxTaylor;
+}
+
+Plan make_plan(const bem_mesh *h, const double *z, int64_t N, uint32_t flags) {
+    Plan plan;
+    std::vector<cplx> zs(N);
+    for (int64_t j = 0; j < N; ++j) zs[j] = cplx(z[2 * j], z[2 * j + 1]);
+    double rmin = 1e300, rmax = -1e300, imin = 1e300, imax = -1e300;
+    for (auto &v : zs) {
+        rmin = std::min(rmin, v.real());
+        rmax = std::max(rmax, v.real());
+        imin = std::min(imin, v.imag());
+        imax = std::max(imax, v.imag());
+    }
+    const cplx c(0.5 * (rmin + rmax), 0.5 * (imin + imax));
+    double R = 0.0;
+    for (auto &v : zs) R = std::max(R, std::abs(v - c));
+    const uint32_t form = flags & BEM_FORM_MASK;
+    int L = R > 0.0 ? taylor_length(R * h->diameter) : bemrat::kMaxTaylor;
+    const bool expand_ok = R > 0.0 && L < bemrat::kMaxTaylor;
+    const bool expand = form == BEM_FORM_EXPAND ? expand_ok : (form == BEM_FORM_AUTO && expand_ok && L < N);
+    if (!expand) {
+        plan.gen = bemrat::Gen::Direct;
+        plan.L = (int)N;
+        plan.kappa = zs;
+        plan.Cf.assign((size_t)N * N, 0.0);
+        for (int64_t j = 0; j < N; ++j) plan.Cf[j * N + j] = 1.0;
+        return plan;
+    }
+    plan.gen = bemrat::Gen::Taylor;
+    plan.L = L;
+    plan.c = c;
+    plan.R = R;
+    plan.Cf.resize((size_t)N * L);
+    for (int64_t j = 0; j < N; ++j) {
+        const cplx t = (zs[j] - c) / R;
+        cplx p = 1.0;
+        for (int l = 0; l < L; ++l) {
+            plan.Cf[j * L + l] = p;
+            p *= t;
+        }
+    }
+    return plan;
+}
+
+// Self terms for the plan's operators into h->self (L x n_pad).
+bem_status build_self(bem_mesh *h, const Plan &plan, Params &prm, size_t &off_self_kappa,
+                      size_t &off_dft, int &K, hipStream_t s) {
+    const int64_t n_pad = h->dm.n_pad;
+    HIP_TRY(h->self.ensure(sizeof(double2) * (size_t)plan.L * n_pad), "self-term table");
+    if (plan.gen == bemrat::Gen::Direct) {
+        std::vector<double> k(2 * plan.L);
+        for (int l = 0; l < plan.L; ++l) {
+            k[2 * l] = plan.kappa[l].real();
+            k[2 * l + 1] = plan.kappa[l].imag();
+        }
+        off_self_kappa = prm.add(k.data(), k.size());
+        K = 0;
+        return BEM_OK;
+    }
+    // Expansion: sample T_aa on K points of the circle |kappa - c| = R and take the
+    // Taylor coefficients by the trapezoidal (DFT) rule: S_l = (1/K) sum_k T_aa(c + R e^{i phi_k}) e^{-i l phi_k}.
+    K = plan.L < 64 ? 64 : 128;
+    const double pi = 3.14159265358979323846;
+    std::vector<double> k(2 * K), F(2 * (size_t)K * plan.L);
+    for (int q = 0; q < K; ++q) {
+        const double phi = 2.0 * pi * q / K;
+        const cplx kap = plan.c + plan.R * std::polar(1.0, phi);
+        k[2 * q] = kap.real();
+        k[2 * q + 1] = kap.imag();
+        for (int l = 0; l < plan.L; ++l) {
+            const cplx f = std::polar(1.0 / K, -phi * l);
+            F[2 * ((size_t)q * plan.L + l)] = f.real();
+            F[2 * ((size_t)q * plan.L + l) + 1] = f.imag();
+        }
+    }
+    off_self_kappa = prm.add(k.data(), k.size());
+    off_dft = prm.add(F.data(), F.size());
+    HIP_TRY(h->aux.ensure(sizeof(double2) * (size_t)K * n_pad), "self-term samples");
+    return BEM_OK;
+}
+
+// Runs self terms + sweep for `plan` on probe block V; Z receives L blocks (zstride, ldz).
+bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, int64_t ldv,
+                     double2 *Z, int64_t ldz, int64_t zstride, Params &prm, size_t off_self_kappa,
+                     size_t off_dft, int K, size_t off_tables, hipStream_t s) {
+    const DeviceMesh &dm = h->dm;
+    const double *pbase = h->params.as<double>();
+    if (plan.gen == bemrat::Gen::Direct) {
+        HIP_TRY(bemrat::launch_self_terms(dm, reinterpret_cast<const double2 *>(pbase + off_self_kappa),
+                                          plan.L, h->self.as<double2>(), dm.n_pad, s),
+                "self-term kernel");
+    } else {
+        HIP_TRY(bemrat::launch_self_terms(dm, reinterpret_cast<const double2 *>(pbase + off_self_kappa), K,
+                                          h->aux.as<double2>(), dm.n_pad, s),
+                "self-term kernel");
+        HIP_TRY(bemrat::launch_coef_dft(h->aux.as<double2>(), dm.n_pad, K,
+                                        reinterpret_cast<const double2 *>(pbase + off_dft), plan.L,
+                                        h->self.as<double2>(), s),
+                "self-term expansion kernel");
+    }
+    bemrat::SweepArgs a{};
+    a.colloc = dm.colloc;
+    a.quad = dm.quad;
+    a.self = h->self.as<double2>();
+    a.V = reinterpret_cast<const double2 *>(V);
+    a.ldv = ldv;
+    a.Z = Z;
+    a.ldz = ldz;
+    a.zstride = zstride;
+    a.n = dm.n;
+    a.n_pad = dm.n_pad;
+    a.m = m;
+    a.L = plan.L;
+    a.kappa = reinterpret_cast<const double2 *>(pbase + off_self_kappa);
+    a.c_re = plan.c.real();
+    a.c_im = plan.c.imag();
+    a.R = plan.R;
+    a.decay = 0;
+    if (plan.gen == bemrat::Gen::Taylor) a.decay = plan.c.imag() != 0.0;
+    for (const cplx &k : plan.kappa) a.decay |= k.imag() != 0.0;
+    a.inv_fact = pbase + off_tables;
+    a.inv_int = pbase + off_tables + bemrat::kMaxTaylor;
+    if (h->timing) HIP_TRY(hipEventRecord(h->ev0, s), "event record");
+    HIP_TRY(bemrat::launch_sweep(plan.gen, a, s), "sweep kernel");
+    if (h->timing) {
+        HIP_TRY(hipEventRecord(h->ev1, s), "event record");
+        h->timed = true;
+    }
+    h->last_form = plan.gen == bemrat::Gen::Direct ? BEM_FORM_DIRECT : BEM_FORM_EXPAND;
+    h->last_ops = plan.L;
+    return BEM_OK;
+}
+
+size_t add_tables(Params &prm) {
+    std::vector<double> t(2 * bemrat::kMaxTaylor);
+    double f = 1.0;
+    for (int l = 0; l < bemrat::kMaxTaylor; ++l) {
+        if (l > 0) f /= l;
+        t[l] = f;                                            // 1/l!
+        t[bemrat::kMaxTaylor + l] = l > 0 ? 1.0 / l : 0.0;  // 1/l
+    }
+    return prm.add(t.data(), t.size());
+}
+
+size_t add_complex(Params &prm, const std::vector<cplx> &v) {
+    return prm.add(reinterpret_cast<const double *>(v.data()), 2 * v.size());
+}
+
+bem_status sync_status(hipStream_t s) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "device error");
+    return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bem_last_error(void) { return g_error.c_str(); }
+
+bem_status bem_stream_status(hipStream_t stream) { return sync_status(stream); }
+
+bem_status bem_mesh_create(const double *xyz, int64_t nv, const int32_t *tri, int64_t n, hipStream_t stream,
+                           bem_mesh_t *out) {
+    if (!out) return fail(BEM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!xyz || !tri) return fail(BEM_EINVAL, "xyz or tri is NULL");
+    if (nv < 3 || n < 1) return fail(BEM_EINVAL, "need nv >= 3 and n >= 1");
+    if (n > (int64_t)1 << 31) return fail(BEM_EINVAL, "too many triangles");
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(xyz[i])) return fail(BEM_EINVAL, "non-finite vertex coordinate");
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (tri[i] < 0 || tri[i] >= nv) return fail(BEM_EMESH, "triangle vertex index out of range");
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < nv; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], xyz[3 * i + c]);
+            hi[c] = std::max(hi[c], xyz[3 * i + c]);
+        }
+    auto *h = new (std::nothrow) bem_mesh;
+    if (!h) return fail(BEM_ENOMEM, "host allocation failed");
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(BEM_EDEVICE, "no HIP device");
+    }
+    // twice the radius of a ball around the box centre holding every vertex: an upper
+    // bound on the distance between any two points of the surface
+    double rad2 = 0.0;
+    for (int64_t i = 0; i < nv; ++i) {
+        double d2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double d = xyz[3 * i + c] - 0.5 * (lo[c] + hi[c]);
+            d2 += d * d;
+        }
+        rad2 = std::max(rad2, d2);
+    }
+    h->diameter = 2.0 * std::sqrt(rad2) * (1.0 + 1e-12);
+    const int64_t n_pad = (n + bemrat::kPad - 1) / bemrat::kPad * bemrat::kPad;
+    h->dm.n = n;
+    h->dm.n_pad = n_pad;
+    // geometry: colloc (n_pad double4) | quad (7 n_pad double4) | vtx (9 n_pad) | area (n_pad)
+    const size_t geom_bytes = sizeof(double4) * 8 * (size_t)n_pad + sizeof(double) * 10 * (size_t)n_pad;
+    bem_status st = BEM_OK;
+    hipError_t e = h->geom.ensure(geom_bytes);
+    double *staging = nullptr;
+    std::vector<double> area_host(n);
+    if (e == hipSuccess) e = h->gl.ensure(sizeof(double) * (2 * bemrat::kSelfGL + 28));
+    if (e == hipSuccess) e = hipEventCreate(&h->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev1);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->staging.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&staging, sizeof(double) * 3 * nv + sizeof(int32_t) * 3 * n);
+    if (e != hipSuccess) {
+        st = hip_fail(e, "mesh allocation");
+    } else {
+        char *g = h->geom.as<char>();
+        h->dm.colloc = reinterpret_cast<double4 *>(g);
+        h->dm.quad = reinterpret_cast<double4 *>(g + sizeof(double4) * n_pad);
+        h->dm.vtx = reinterpret_cast<double *>(g + sizeof(double4) * 8 * n_pad);
+        h->dm.area = h->dm.vtx + 9 * n_pad;
+        h->dm.gl = h->gl.as<double>();
+        std::vector<double> glh(2 * bemrat::kSelfGL + 28);
+        gauss_legendre(bemrat::kSelfGL, glh.data(), glh.data() + bemrat::kSelfGL);
+        radon_rule(glh.data() + 2 * bemrat::kSelfGL);
+        double *d_xyz = staging;
+        int32_t *d_tri = reinterpret_cast<int32_t *>(staging + 3 * nv);
+        e = hipMemcpy(d_xyz, xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_tri, tri, sizeof(int32_t) * 3 * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(h->dm.gl, glh.data(), sizeof(double) * glh.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = bemrat::launch_prepare_mesh(d_xyz, d_tri, n, n_pad, h->dm, h->dm.gl + 2 * bemrat::kSelfGL, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) e = hipMemcpy(area_host.data(), h->dm.area, sizeof(double) * n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = hip_fail(e, "mesh preparation");
+        (void)hipFree(staging);
+    }
+    if (st == BEM_OK) {
+        for (int64_t b = 0; b < n; ++b)
+            if (!(area_host[b] > 0.0) || !std::isfinite(area_host[b])) {
+                char msg[96];
+                std::snprintf(msg, sizeof msg, "degenerate triangle %lld (zero area)", (long long)b);
+                st = fail(BEM_EMESH, msg);
+                break;
+            }
+    }
+    if (st != BEM_OK) {
+        bem_mesh_destroy(h);
+        return st;
+    }
+    *out = h;
+    return BEM_OK;
+}
+
+void bem_mesh_destroy(bem_mesh_t h) {
+    if (!h) return;
+    DeviceGuard guard(h->device);
+    (void)hipDeviceSynchronize();
+    h->geom.release();
+    h->gl.release();
+    h->self.release();
+    h->aux.release();
+    h->Z.release();
+    h->params.release();
+    h->partial.release();
+    if (h->staging.host) (void)hipHostFree(h->staging.host);
+    if (h->staging.done) (void)hipEventDestroy(h->staging.done);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    delete h;
+}
+
+int64_t bem_mesh_size(bem_mesh_t h) { return h ? h->dm.n : -1; }
+
+bem_status bem_mesh_geometry(bem_mesh_t h, double *area, double *centroid, double *quad_xyz, double *quad_w,
+                             hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = sync_status(stream);
+    if (st != BEM_OK) return st;
+    const int64_t n = h->dm.n;
+    if (area) HIP_TRY(hipMemcpy(area, h->dm.area, sizeof(double) * n, hipMemcpyDeviceToHost), "copy");
+    if (centroid || quad_xyz || quad_w) {
+        std::vector<double4> c(n), q(7 * n);
+        HIP_TRY(hipMemcpy(c.data(), h->dm.colloc, sizeof(double4) * n, hipMemcpyDeviceToHost), "copy");
+        HIP_TRY(hipMemcpy(q.data(), h->dm.quad, sizeof(double4) * 7 * n, hipMemcpyDeviceToHost), "copy");
+        const double fourpi = 4.0 * 3.14159265358979323846;
+        for (int64_t b = 0; b < n; ++b) {
+            if (centroid) {
+                centroid[3 * b] = c[b].x;
+                centroid[3 * b + 1] = c[b].y;
+                centroid[3 * b + 2] = c[b].z;
+            }
+            for (int k = 0; k < 7; ++k) {
+                const double4 p = q[7 * b + k];
+                if (quad_xyz) {
+                    quad_xyz[21 * b + 3 * k] = p.x;
+                    quad_xyz[21 * b + 3 * k + 1] = p.y;
+                    quad_xyz[21 * b + 3 * k + 2] = p.z;
+                }
+                if (quad_w) quad_w[7 * b + k] = p.w * fourpi;
+            }
+        }
+    }
+    return BEM_OK;
+}
+
+bem_status bem_contour_nodes(double c_re, double c_im, double radius, int64_t N, double shift_re,
+                             double shift_im, int64_t P, double *z, double *w, double *W) {
+    if (N < 1) return fail(BEM_EINVAL, "N must be positive");
+    if (!(radius > 0.0) || !std::isfinite(radius)) return fail(BEM_EINVAL, "radius must be positive");
+    if (!std::isfinite(c_re) || !std::isfinite(c_im) || !std::isfinite(shift_re) || !std::isfinite(shift_im))
+        return fail(BEM_EINVAL, "non-finite centre or shift");
+    if (P < 0) return fail(BEM_EINVAL, "P must be >= 0");
+    if (!z || !w || (P > 0 && !W)) return fail(BEM_EINVAL, "output is NULL");
+    const double pi = 3.14159265358979323846;
+    const cplx c(c_re, c_im), sh(shift_re, shift_im);
+    for (int64_t j = 0; j < N; ++j) {
+        const cplx e = std::polar(1.0, 2.0 * pi * (j + 0.5) / N);
+        const cplx zj = c + radius * e;
+        const cplx wj = -radius * e / (double)N;
+        z[2 * j] = zj.real();
+        z[2 * j + 1] = zj.imag();
+        w[2 * j] = wj.real();
+        w[2 * j + 1] = wj.imag();
+        if (P > 0) {
+            const cplx d = zj - sh;
+            if (d == cplx(0.0, 0.0)) return fail(BEM_EINVAL, "a node coincides with the shift");
+            const cplx inv = 1.0 / d;
+            cplx acc = wj;
+            for (int64_t p = 0; p < P; ++p) {
+                acc *= inv;
+                W[2 * (j * P + p)] = acc.real();
+                W[2 * (j * P + p) + 1] = acc.imag();
+            }
+        }
+    }
+    return BEM_OK;
+}
+
+bem_status bem_cheb_nodes(double a, double b, int64_t N, double *kappa, double *coef) {
+    if (N < 1) return fail(BEM_EINVAL, "N must be positive");
+    if (!std::isfinite(a) || !std::isfinite(b) || !(a < b)) return fail(BEM_EINVAL, "need finite a < b");
+    if (!kappa) return fail(BEM_EINVAL, "kappa is NULL");
+    const double pi = 3.14159265358979323846;
+    const double alpha = 0.5 * (a + b), beta = 0.5 * (b - a);
+    for (int64_t k = 0; k < N; ++k) kappa[k] = alpha + beta * std::cos(pi * (k + 0.5) / N);
+    if (coef)
+        for (int64_t l = 0; l < N; ++l)
+            for (int64_t k = 0; k < N; ++k)
+                coef[l * N + k] = (l == 0 ? 1.0 : 2.0) / N * std::cos(pi * l * (k + 0.5) / N);
+    return BEM_OK;
+}
+
+bem_status bem_self_terms(bem_mesh_t h, const double *kappa, int64_t nk, double *S, hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_kappas(h, kappa, nk, "kappa");
+    if (st != BEM_OK) return st;
+    if (!S || !is_device_ptr(S)) return fail(BEM_EINVAL, "S is not device memory");
+    if (nk > 65535) return fail(BEM_EINVAL, "at most 65535 wavenumbers per call");
+    Params prm;
+    const size_t off = prm.add(kappa, 2 * nk);
+    st = upload(h, prm, stream);
+    if (st != BEM_OK) return st;
+    // the kernel writes n_pad entries per wavenumber; stage through the workspace
+    HIP_TRY(h->aux.ensure(sizeof(double2) * (size_t)nk * h->dm.n_pad), "self-term buffer");
+    HIP_TRY(bemrat::launch_self_terms(h->dm, reinterpret_cast<const double2 *>(h->params.as<double>() + off), nk,
+                                      h->aux.as<double2>(), h->dm.n_pad, stream),
+            "self-term kernel");
+    HIP_TRY(hipMemcpy2DAsync(S, sizeof(double2) * h->dm.n, h->aux.ptr, sizeof(double2) * h->dm.n_pad,
+                             sizeof(double2) * h->dm.n, nk, hipMemcpyDeviceToDevice, stream),
+            "copy");
+    return BEM_OK;
+}
+
+bem_status bem_assemble_apply(bem_mesh_t h, const double *kappa, int64_t nk, const double *V, int64_t m,
+                              int64_t ldv, double *Y, int64_t ldy, uint32_t flags, hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_flags(flags);
+    if (st != BEM_OK) return st;
+    if ((flags & BEM_FORM_MASK) == BEM_FORM_EXPAND)
+        return fail(BEM_EUNSUPPORTED, "bem_assemble_apply evaluates each wavenumber directly");
+    if ((st = check_kappas(h, kappa, nk, "kappa")) != BEM_OK) return st;
+    if (nk > 65535) return fail(BEM_EINVAL, "at most 65535 wavenumbers per call");
+    if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
+    if ((st = check_block(Y, m, ldy, "Y")) != BEM_OK) return st;
+    Plan plan = make_plan(h, kappa, nk, BEM_FORM_DIRECT);
+    Params prm;
+    const size_t off_tables = add_tables(prm);
+    size_t off_k = 0, off_dft = 0;
+    int K = 0;
+    if ((st = build_self(h, plan, prm, off_k, off_dft, K, stream)) != BEM_OK) return st;
+    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
+    return run_sweep(h, plan, V, m, ldv, reinterpret_cast<double2 *>(Y), ldy, h->dm.n * ldy, prm, off_k, off_dft,
+                     K, off_tables, stream);
+}
+
+
+bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const double *W, int64_t P, const double *V,
+                           int64_t m, int64_t ldv, double *M, int64_t ldm, uint32_t flags, hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_flags(flags);
+    if (st != BEM_OK) return st;
+    if ((st = check_kappas(h, z, N, "z")) != BEM_OK) return st;
+    if (!W || P < 1) return fail(BEM_EINVAL, "need W and P >= 1");
+    if (!finite_c(W, N * P)) return fail(BEM_EINVAL, "W has a non-finite value");
+    if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
+    if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
+    Plan plan = make_plan(h, z, N, flags);
+    Params prm;
+    const size_t off_tables = add_tables(prm);
+    size_t off_k = 0, off_dft = 0;
+    int K = 0;
+    if ((st = build_self(h, plan, prm, off_k, off_dft, K, stream)) != BEM_OK) return st;
+    // combine coefficients: coef[l][p] = sum_j Cf[j][l] W[j][p]
+    std::vector<cplx> coef((size_t)plan.L * P, 0.0);
+    for (int64_t j = 0; j < N; ++j)
+        for (int l = 0; l < plan.L; ++l) {
+            const cplx cf = plan.Cf[j * plan.L + l];
+            if (cf == cplx(0.0, 0.0)) continue;
+            for (int64_t p = 0; p < P; ++p) coef[l * P + p] += cf * cplx(W[2 * (j * P + p)], W[2 * (j * P + p) + 1]);
+        }
+    const size_t off_coef = add_complex(prm, coef);
+    const size_t zstride = (size_t)h->dm.n * m;
+    HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * plan.L), "sweep workspace");
+    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
+    double2 *Z = h->Z.as<double2>();
+    if ((st = run_sweep(h, plan, V, m, ldv, Z, m, zstride, prm, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
+        return st;
+    HIP_TRY(bemrat::launch_combine(Z, zstride, m, plan.L,
+                                   reinterpret_cast<const double2 *>(h->params.as<double>() + off_coef), (int)P,
+                                   h->dm.n, m, reinterpret_cast<double2 *>(M), ldm, stream),
+            "combine kernel");
+    return BEM_OK;
+}
+
+bem_status cheb_moments(bem_mesh_t h, double a, double b, int64_t N, int64_t L, const double *V, int64_t m,
+                        int64_t ldv, double *C, int64_t ldc, uint32_t flags, hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_flags(flags);
+    if (st != BEM_OK) return st;
+    if (N < 1 || L < 1 || L > N) return fail(BEM_EINVAL, "need 1 <= L <= N");
+    if (!std::isfinite(a) || !std::isfinite(b) || !(a < b)) return fail(BEM_EINVAL, "need finite a < b");
+    if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
+    if ((st = check_block(C, m, ldc, "C")) != BEM_OK) return st;
+    std::vector<double> kap(N), cf((size_t)N * N);
+    bem_cheb_nodes(a, b, N, kap.data(), cf.data());
+    std::vector<double> z(2 * N);
+    for (int64_t k = 0; k < N; ++k) {
+        z[2 * k] = kap[k];
+        z[2 * k + 1] = 0.0;
+    }
+    Plan plan = make_plan(h, z.data(), N, BEM_FORM_DIRECT);
+    Params prm;
+    const size_t off_tables = add_tables(prm);
+    size_t off_k = 0, off_dft = 0;
+    int K = 0;
+    if ((st = build_self(h, plan, prm, off_k, off_dft, K, stream)) != BEM_OK) return st;
+    // combine coefficients: coef[k][l] = cf[l][k]
+    std::vector<cplx> coef((size_t)N * L);
+    for (int64_t k = 0; k < N; ++k)
+        for (int64_t l = 0; l < L; ++l) coef[k * L + l] = cf[l * N + k];
+    const size_t off_coef = add_complex(prm, coef);
+    const size_t zstride = (size_t)h->dm.n * m;
+    HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * plan.L), "sweep workspace");
+    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
+    double2 *Z = h->Z.as<double2>();
+    if ((st = run_sweep(h, plan, V, m, ldv, Z, m, zstride, prm, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
+        return st;
+    HIP_TRY(bemrat::launch_combine(Z, zstride, m, plan.L,
+                                   reinterpret_cast<const double2 *>(h->params.as<double>() + off_coef), (int)L,
+                                   h->dm.n, m, reinterpret_cast<double2 *>(C), ldc, stream),
+            "combine kernel");
+    return BEM_OK;
+}
+
+bem_status rr_project(bem_mesh_t h, const double *z, int64_t N, const double *U, int64_t m, int64_t ldu,
+                      double *Pout, const double *W, int64_t Pw, double *M, int64_t ldm, uint32_t flags,
+                      hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_flags(flags);
+    if (st != BEM_OK) return st;
+    if ((st = check_kappas(h, z, N, "z")) != BEM_OK) return st;
+    if ((st = check_block(U, m, ldu, "U")) != BEM_OK) return st;
+    if (!Pout || !is_device_ptr(Pout)) return fail(BEM_EINVAL, "Pout is not device memory");
+    if (Pw < 0) return fail(BEM_EINVAL, "Pw must be >= 0");
+    if (Pw > 0) {
+        if (!W) return fail(BEM_EINVAL, "W is NULL");
+        if (!finite_c(W, N * Pw)) return fail(BEM_EINVAL, "W has a non-finite value");
+        if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
+    }
+    Plan plan = make_plan(h, z, N, flags);
+    Params prm;
+    const size_t off_tables = add_tables(prm);
+    size_t off_k = 0, off_dft = 0;
+    int K = 0;
+    if ((st = build_self(h, plan, prm, off_k, off_dft, K, stream)) != BEM_OK) return st;
+    const size_t off_cf = add_complex(prm, plan.Cf);  // N x L
+    size_t off_coef = 0;
+    if (Pw > 0) {
+        std::vector<cplx> coef((size_t)plan.L * Pw, 0.0);
+        for (int64_t j = 0; j < N; ++j)
+            for (int l = 0; l < plan.L; ++l) {
+                const cplx cf = plan.Cf[j * plan.L + l];
+                if (cf == cplx(0.0, 0.0)) continue;
+                for (int64_t p = 0; p < Pw; ++p)
+                    coef[l * Pw + p] += cf * cplx(W[2 * (j * Pw + p)], W[2 * (j * Pw + p) + 1]);
+            }
+        off_coef = add_complex(prm, coef);
+    }
+    const int64_t n = h->dm.n;
+    const size_t zstride = (size_t)n * m;
+    const int64_t rows_per_chunk = 4096;
+    const int nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
+    HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * plan.L), "sweep workspace");
+    HIP_TRY(h->partial.ensure(sizeof(double2) * (size_t)plan.L * nchunks * m * m), "projection workspace");
+    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
+    double2 *Z = h->Z.as<double2>();
+    if ((st = run_sweep(h, plan, U, m, ldu, Z, m, zstride, prm, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
+        return st;
+    const double *pbase = h->params.as<double>();
+    HIP_TRY(bemrat::launch_project_partial(reinterpret_cast<const double2 *>(U), ldu, Z, zstride, m, plan.L, n, m,
+                                           rows_per_chunk, nchunks, h->partial.as<double2>(), stream),
+            "projection kernel");
+    HIP_TRY(bemrat::launch_project_finish(h->partial.as<double2>(), nchunks, plan.L, m,
+                                          reinterpret_cast<const double2 *>(pbase + off_cf), (int)N,
+                                          reinterpret_cast<double2 *>(Pout), stream),
+            "projection reduction kernel");
+    if (Pw > 0)
+        HIP_TRY(bemrat::launch_combine(Z, zstride, m, plan.L, reinterpret_cast<const double2 *>(pbase + off_coef),
+                                       (int)Pw, n, m, reinterpret_cast<double2 *>(M), ldm, stream),
+                "combine kernel");
+    return BEM_OK;
+}
+
+bem_status bem_last_form(bem_mesh_t h, uint32_t *form, int64_t *operators) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    if (form) *form = h->last_form;
+    if (operators) *operators = h->last_ops;
+    return BEM_OK;
+}
+
+bem_status bem_set_timing(bem_mesh_t h, int on) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    h->timing = on != 0;
+    return BEM_OK;
+}
+
+bem_status bem_last_kernel_ms(bem_mesh_t h, float *ms) {
+    if (!h || !ms) return fail(BEM_EINVAL, "mesh or ms is NULL");
+    if (!h->timed) return fail(BEM_EINVAL, "no timed sweep yet");
+    DeviceGuard guard(h->device);
+    HIP_TRY(hipEventSynchronize(h->ev1), "event synchronize");
+    HIP_TRY(hipEventElapsedTime(ms, h->ev0, h->ev1), "event elapsed time");
+    return BEM_OK;
+}
+
+}  // extern "C"

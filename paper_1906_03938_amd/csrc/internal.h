@@ -1,0 +1,69 @@
+// Internal declarations shared by the HIP translation units of libbemrat.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bemrat {
+
+constexpr int kQuad = 7;        // points of the triangle rule
+constexpr int kRowTile = 64;    // target rows per sweep block: 4 waves x 16 MFMA rows
+constexpr int kChunk = 32;      // source triangles staged in LDS per step of the K loop
+constexpr int kPad = 64;        // n is padded to a multiple of this on the device
+constexpr int kMaxGroup = 4;    // coefficient operators generated together per block
+constexpr int kSelfGL = 32;     // Gauss-Legendre points per edge for the self term
+constexpr int kMaxTaylor = 96;  // largest expansion length supported
+
+// Device geometry of one mesh (all arrays padded to n_pad entries).
+struct DeviceMesh {
+    int64_t n = 0, n_pad = 0;
+    double4 *colloc = nullptr;  // n_pad: collocation point (centroid), w unused
+    double4 *quad = nullptr;    // n_pad * 7: (x, y, z, A_b w_q / (4 pi)); pads have weight 0
+    double *vtx = nullptr;      // n_pad * 9: vertex coordinates (self terms)
+    double *area = nullptr;     // n_pad
+    double *gl = nullptr;       // 2 * kSelfGL: Gauss-Legendre nodes then weights on [-1, 1]
+};
+
+// Generator of the coefficient operators of one sweep.
+enum class Gen : int { Direct = 0, Taylor = 1, Cheb = 2 };
+
+struct SweepArgs {
+    const double4 *colloc;
+    const double4 *quad;
+    const double2 *self;  // L x n_pad: diagonal entry of each generated operator
+    const double2 *V;
+    int64_t ldv;
+    double2 *Z;           // operator l writes n x m block at Z + l * zstride, row stride ldz
+    int64_t ldz, zstride;
+    int64_t n, n_pad, m;
+    int L;                // number of generated operators
+    int decay;            // some wavenumber (Direct) or the centre (Taylor) has Im != 0
+    // Direct: wavenumbers of the L nodes
+    const double2 *kappa;
+    // Taylor: exp(i (c + R t) r) = exp(i c r) sum_l (i R r t)^l / l!
+    // Cheb:   exp(i (alpha + beta xi) r) = exp(i alpha r) sum_l eps_l i^l J_l(beta r) T_l(xi)
+    double c_re, c_im, R;
+    const double *inv_fact;  // 1/l!, l < kMaxTaylor
+    const double *inv_int;   // 1/l, l < kMaxTaylor (entry 0 unused)
+};
+
+// Launchers (asynchronous on `stream`; return hipSuccess or the launch error).
+hipError_t launch_prepare_mesh(const double *xyz, const int32_t *tri, int64_t n, int64_t n_pad,
+                               DeviceMesh mesh, const double *rule, hipStream_t stream);
+hipError_t launch_self_terms(const DeviceMesh &mesh, const double2 *kappa, int64_t nk,
+                             double2 *S, int64_t lds, hipStream_t stream);
+hipError_t launch_sweep(Gen gen, const SweepArgs &args, hipStream_t stream);
+hipError_t launch_combine(const double2 *Z, int64_t zstride, int64_t ldz, int L,
+                          const double2 *coef, int P, int64_t n, int64_t m, double2 *out,
+                          int64_t ldo, hipStream_t stream);
+hipError_t launch_coef_dft(const double2 *samples, int64_t n_pad, int K, const double2 *F,
+                           int L, double2 *out, hipStream_t stream);
+hipError_t launch_project_partial(const double2 *U, int64_t ldu, const double2 *Z,
+                                  int64_t zstride, int64_t ldz, int L, int64_t n, int64_t m,
+                                  int64_t rows_per_chunk, int nchunks, double2 *partial,
+                                  hipStream_t stream);
+hipError_t launch_project_finish(const double2 *partial, int nchunks, int L, int64_t m,
+                                 const double2 *coef, int N, double2 *out,
+                                 hipStream_t stream);
+
+}  // namespace bemrat
