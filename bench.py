@@ -1,0 +1,180 @@
+"""Benchmark: the node sweep of the contour rational approximation on one MI355X.
+
+Workload "sphere-81920" (the headline configuration): unit icosphere at subdivision level
+6 (n = 81920 flat triangles, P0 collocation at centroids, single-layer kernel
+exp(i kappa r)/(4 pi r), 7-point rule plus exact self terms), circular contour
+|z - 5| = 2 with N = 64 trapezoidal nodes, probe block of m = 64 seeded complex Gaussian
+columns (seed 2).  One step = the nodes and moment weights (host) plus one rr_project
+call with fused moments: the per-node projections U^H T(z_j) U for all 64 nodes and the
+first P = 2 contour moments sum_j w_j (z_j - c)^-p T(z_j) U, with the self terms, the
+sweep, the combination and the projection all on the device.
+
+Metric: kernel-entry x RHS per second, N n^2 m / t_step (operator entries at every node
+times probe columns, whatever form evaluates them).
+
+Prints one JSON line (see the repository's design notes for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_MFMA_TFLOPS = 78.6  # MI355X published dense FP64 matrix peak
+WORKLOAD = dict(name="sphere-81920", level=6, c=5.0, radius=2.0, N=64, m=64, P=2, seed=2)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "devmath.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1906_03938_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_hash: str):
+    """HBM bytes per launch measured by rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE), if the
+    committed summary was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "sweep_sphere81920_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(xyz, tri, z, V, rows_per_thread=6):
+    """The oracle (plain FP64 C, OpenMP over target rows) on a bounded sample: the full
+    N-node sweep of T(z_j) V for a few target rows, scaled to entry x RHS per second."""
+    import numpy as np
+
+    from oracle import _clib
+
+    threads = _clib.num_threads()
+    n = tri.shape[0]
+    rows = np.linspace(0, n - 1, max(1, rows_per_thread * threads)).astype(np.int64)
+    t0 = time.perf_counter()
+    for zj in z:
+        _clib.apply_rows(xyz, tri, zj, V, rows)
+    dt = time.perf_counter() - t0
+    units = rows.size * n * len(z) * V.shape[1]
+    return {
+        "value": units / dt,
+        "unit": "kernel-entry*RHS/s",
+        "cores": int(min(threads, rows.size)),
+        "kind": "oracle",
+        "sample": f"{rows.size} of {n} target rows x all {n} source triangles x {len(z)} nodes x "
+                  f"{V.shape[1]} probes ({dt:.1f} s), scaled by entry*RHS count",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", choices=["auto", "direct", "expand"], default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep's multi-GPU "
+              "row split is a design note, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1906_03938_amd as bem
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = WORKLOAD
+    xyz, tri = synth.icosphere(w["level"])
+    n = tri.shape[0]
+    Vh = synth.probe_block(n, w["m"], seed=w["seed"])
+    U = torch.from_numpy(Vh).to("cuda")
+    form = {"auto": bem.FORM_AUTO, "direct": bem.FORM_DIRECT, "expand": bem.FORM_EXPAND}[args.form]
+    mesh = bem.Mesh(xyz, tri)
+    mesh.set_timing(True)
+    Pout = torch.empty((w["N"], w["m"], w["m"]), dtype=torch.complex128, device="cuda")
+    Mout = torch.empty((w["P"], n, w["m"]), dtype=torch.complex128, device="cuda")
+
+    def step():
+        z, _, W = bem.contour_nodes(w["c"], w["radius"], w["N"], P=w["P"])
+        mesh.rr_project(z, U, W=W, out=Pout, moments_out=Mout, form=form)
+        return z
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        z = step()
+        kernel_ms.append(mesh.last_kernel_ms())  # waits for this step's sweep kernel only
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    used_form, L = mesh.last_form()
+    bem.stream_status()
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    units = w["N"] * n * n * w["m"]
+    value = units / (elapsed / args.steps)
+    kms = float(np.mean(kernel_ms))
+    flops = 8.0 * L * n * n * w["m"]  # 8 real flops per complex MAC of the generated operators
+    achieved = flops / (kms * 1e-3) / 1e12
+    khash = kernel_source_hash()
+    out = {
+        "metric": "kernel-entry*RHS/s of sum_j T(z_j)V sweep (rr_project + fused moments)",
+        "value": value,
+        "unit": "kernel-entry*RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w["name"],
+            "mesh": f"unit icosphere level {w['level']}, n={n} triangles",
+            "contour": f"circle c={w['c']} r={w['radius']}, N={w['N']} trapezoidal nodes",
+            "m": w["m"], "moments": w["P"], "seed": w["seed"],
+            "form": "expand" if used_form == bem.FORM_EXPAND else "direct",
+            "operators_generated": L,
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+            "traffic": load_traffic(khash),
+            "kernel": "sweep_kernel",
+            "kernel_ms": kms,
+            "kernel_hash": khash,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(xyz, tri, z, Vh)
+    mesh.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

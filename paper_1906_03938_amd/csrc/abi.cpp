@@ -248,19 +248,24 @@ struct Plan {
     std::vector<cplx> Cf;     // N x L: T(z_j) = sum_l Cf[j][l] T_l
 };
 
-// Smallest L with x^L/L! / (1 - x/(L+1)) <= 1e-17 e^{-x}: truncation of the Taylor series
-// of exp(i R r t) below 1e-17 relative to its smallest value on |t| <= 1.
-int taylor_length(double x) {
-    const double target = 1e-17 * std::exp(-x);
+// Expansion length: smallest L with x^L/L! / (1 - x/(L+1)) <= 1e-14 e^{-x} -- the
+// truncated Taylor series of exp(i R r t) is then accurate to 1e-14 relative to its
+// smallest value on |t| <= 1 -- rounded up to a whole number of sweep blocks (the extra
+// terms cost nothing and only add accuracy).
+int taylor_length(double x, int block) {
+    const double target = 1e-14 * std::exp(-x);
     double term = 1.0;
     for (int L = 1; L < bemrat::kMaxTaylor; ++L) {
         term *= x / L;
-        if (L > x && term / (1.0 - x / (L + 1)) <= target) return L;
+        if (L > x && term / (1.0 - x / (L + 1)) <= target) {
+            const int r = (L + block - 1) / block * block;
+            return std::min(r, bemrat::kMaxTaylor - 1);
+        }
     }
     return bemrat::kMaxTaylor;
 }
 
-Plan make_plan(const bem_mesh *h, const double *z, int64_t N, uint32_t flags) {
+Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_t flags) {
     Plan plan;
     std::vector<cplx> zs(N);
     for (int64_t j = 0; j < N; ++j) zs[j] = cplx(z[2 * j], z[2 * j + 1]);
@@ -275,7 +280,7 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, uint32_t flags) {
     double R = 0.0;
     for (auto &v : zs) R = std::max(R, std::abs(v - c));
     const uint32_t form = flags & BEM_FORM_MASK;
-    int L = R > 0.0 ? taylor_length(R * h->diameter) : bemrat::kMaxTaylor;
+    int L = R > 0.0 ? taylor_length(R * h->diameter, bemrat::sweep_ops_per_block(m)) : bemrat::kMaxTaylor;
     const bool expand_ok = R > 0.0 && L < bemrat::kMaxTaylor;
     const bool expand = form == BEM_FORM_EXPAND ? expand_ok : (form == BEM_FORM_AUTO && expand_ok && L < N);
     if (!expand) {
@@ -646,7 +651,7 @@ bem_status bem_assemble_apply(bem_mesh_t h, const double *kappa, int64_t nk, con
     if (nk > 65535) return fail(BEM_EINVAL, "at most 65535 wavenumbers per call");
     if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
     if ((st = check_block(Y, m, ldy, "Y")) != BEM_OK) return st;
-    Plan plan = make_plan(h, kappa, nk, BEM_FORM_DIRECT);
+    Plan plan = make_plan(h, kappa, nk, m, BEM_FORM_DIRECT);
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
@@ -669,7 +674,7 @@ bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const doubl
     if (!finite_c(W, N * P)) return fail(BEM_EINVAL, "W has a non-finite value");
     if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
     if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
-    Plan plan = make_plan(h, z, N, flags);
+    Plan plan = make_plan(h, z, N, m, flags);
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
@@ -714,7 +719,7 @@ bem_status cheb_moments(bem_mesh_t h, double a, double b, int64_t N, int64_t L, 
         z[2 * k] = kap[k];
         z[2 * k + 1] = 0.0;
     }
-    Plan plan = make_plan(h, z.data(), N, BEM_FORM_DIRECT);
+    Plan plan = make_plan(h, z.data(), N, m, BEM_FORM_DIRECT);
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
@@ -754,7 +759,7 @@ bem_status rr_project(bem_mesh_t h, const double *z, int64_t N, const double *U,
         if (!finite_c(W, N * Pw)) return fail(BEM_EINVAL, "W has a non-finite value");
         if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
     }
-    Plan plan = make_plan(h, z, N, flags);
+    Plan plan = make_plan(h, z, N, m, flags);
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;

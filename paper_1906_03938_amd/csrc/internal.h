@@ -7,10 +7,7 @@
 namespace bemrat {
 
 constexpr int kQuad = 7;        // points of the triangle rule
-constexpr int kRowTile = 64;    // target rows per sweep block: 4 waves x 16 MFMA rows
-constexpr int kChunk = 32;      // source triangles staged in LDS per step of the K loop
 constexpr int kPad = 64;        // n is padded to a multiple of this on the device
-constexpr int kMaxGroup = 4;    // coefficient operators generated together per block
 constexpr int kSelfGL = 32;     // Gauss-Legendre points per edge for the self term
 constexpr int kMaxTaylor = 96;  // largest expansion length supported
 
@@ -53,6 +50,8 @@ hipError_t launch_prepare_mesh(const double *xyz, const int32_t *tri, int64_t n,
 hipError_t launch_self_terms(const DeviceMesh &mesh, const double2 *kappa, int64_t nk,
                              double2 *S, int64_t lds, hipStream_t stream);
 hipError_t launch_sweep(Gen gen, const SweepArgs &args, hipStream_t stream);
+// Coefficient operators one sweep block generates together (they share its base terms).
+int sweep_ops_per_block(int64_t m);
 hipError_t launch_combine(const double2 *Z, int64_t zstride, int64_t ldz, int L,
                           const double2 *coef, int P, int64_t n, int64_t m, double2 *out,
                           int64_t ldo, hipStream_t stream);

@@ -1,21 +1,28 @@
 // Generate-and-contract sweep: Z_l = T_l V for a group of coefficient operators T_l.
 //
-// Block = 4 waves (256 threads) owning 64 target rows (16 per wave, the M dimension of
-// v_mfma_f64_16x16x4f64) and 16*CB probe columns, for G consecutive operators l.
-// The K loop runs over all source triangles b in chunks of kChunk = 32: a chunk's probe
-// rows V[b, cols] and the 7 quadrature points of its triangles are staged in LDS and
-// shared by the four waves.  Each k-step covers 4 source triangles; lane
-// (i = lane & 15, k = lane >> 4) of a wave generates the entry T_l[row0 + i, b0 + k] of
-// the G operators in registers -- exactly the A-operand element it feeds to the MFMA --
-// so generated tiles never touch LDS or HBM.  Two blocks run on every CU (one wave of
-// each per SIMD): while one wave generates entries on the vector ALU, the other one's
-// MFMAs keep the matrix core busy, and a block waiting at a chunk barrier leaves the
-// SIMDs to the other block.
+// On gfx950 the FP64 MFMA and the FP64 vector ALU share one pipe (they do not overlap),
+// so the kernel minimises the total FP64 work per (entry, operator):
 //
-// Complex product with four real MFMAs: Re += Gr Vr - Gi Vi, Im += Gr Vi + Gi Vr.
+// * Block = 4 waves (256 threads), all owning the same 16 target rows (the M dimension
+//   of v_mfma_f64_16x16x4f64) and 16*CB probe columns; wave w handles the G operators
+//   l0 = 4 G blockIdx.z + G w, ..., so a block covers 4 G operators.
+// * The K loop runs over the source triangles in stages of kStage = 16.  For a stage the
+//   probe rows V[b, cols] (with Vr + Vi for the three-multiplication product) and the 7
+//   quadrature points of each triangle are staged in LDS (prefetched into registers
+//   during the previous stage).
+// * Base phase: thread t computes, for target row t & 15 and source triangle t >> 4 of
+//   the stage, the operator-independent part of all 7 quadrature terms (the distance,
+//   the weight over 4 pi r, and for the expansion the factor exp(i c r)) once, into LDS.
+//   The expensive transcendental work is thus shared by all 4 G operators of the block.
+// * Contract phase: per k-step (4 source triangles) lane (i = lane & 15, k = lane >> 4)
+//   reads the 7 base terms of entry (row i, triangle 4 ks + k), forms the entries of its
+//   wave's G operators -- exactly the A-operand elements it feeds to the MFMA, so
+//   generated tiles never reach HBM -- and accumulates with Gauss's three-multiplication
+//   complex product: P1 += Gr Vr, P2 += Gi Vi, P3 += (Gr + Gi)(Vr + Vi); at the end
+//   Re Z = P1 - P2, Im Z = P3 - P1 - P2.
 //
-// Operator generators (entry of T_l at a != b, summed over the 7 points; the weight
-// A_b w_q / (4 pi) is folded into the staged points):
+// Operator families (entry of T_l at a != b, summed over the 7 points, with the weight
+// A_b w_q / (4 pi) folded into the staged points):
 //   Direct: T_l = T(kappa_l):              w/r exp(i kappa_l r)
 //   Taylor: T(c + R t) = sum_l t^l T_l:    w/r exp(i c r) (i R r)^l / l!
 // The diagonal entry of T_l comes from a precomputed table (exact self terms or their
@@ -29,26 +36,81 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+constexpr int kStage = 16;                  // source triangles per stage
+constexpr int kStageSteps = kStage / 4;     // k-steps per stage
+constexpr int kBase = kQuad * kStage * 16;  // base terms per stage (q, triangle, row)
+
 __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int G, Gen GEN, bool DECAY>
-struct Generator;
+// Base terms of one quadrature point, stored as one double4 per (q, triangle, row):
+//   Direct: (r, w/r, -, -)
+//   Taylor: (x = R r, y = w/r exp(i c r) (i x)^L0 / L0!) for the block's first operator L0.
+template <Gen GEN, bool DECAY>
+struct Base;
 
-// T(kappa_l): w/r exp(-Im(kappa) r) (cos(Re(kappa) r) + i sin(Re(kappa) r))
+template <bool DECAY>
+struct Base<Gen::Direct, DECAY> {
+    __device__ void init(const SweepArgs &, int, int) {}
+    __device__ __forceinline__ double4 make(double r, double wr, const SweepArgs &) const {
+        return make_double4(r, wr, 0.0, 0.0);
+    }
+};
+
+template <bool DECAY>
+struct Base<Gen::Taylor, DECAY> {
+    int L0, z, B;  // L0 = z B: block z of B operators
+    double inv_fact;
+    __device__ void init(const SweepArgs &p, int L0_, int B_) {
+        L0 = L0_;
+        B = B_;
+        z = L0 / B;
+        inv_fact = p.inv_fact[min(L0, kMaxTaylor - 1)];
+    }
+    __device__ __forceinline__ double4 make(double r, double wr, const SweepArgs &p) const {
+        const double e = DECAY ? exp_cw(-p.c_im * r) * wr : wr;
+        double s, c;
+        sincos_cw(p.c_re * r, s, c);
+        const double x = p.R * r;
+        // x^L0 / L0! = (x^B)^z / L0!: x^B by squaring (B = 8 or 12), then the at most 4
+        // bits of the block-uniform z by selects (no branches)
+        const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
+        double base = B == 8 ? x8 : x8 * x4;
+        double pw = inv_fact;
+#pragma unroll
+        for (int bit = 0; bit < 4; ++bit) {
+            pw = ((z >> bit) & 1) ? pw * base : pw;
+            base *= base;
+        }
+        double yr = e * c * pw, yi = e * s * pw;
+        // times i^L0 (L0 is a multiple of 4 when B = 8 or 12: i^L0 = 1) -- kept general
+        const double t = yr;
+        yr = (L0 & 1) ? -yi : yr;
+        yi = (L0 & 1) ? t : yi;
+        yr = (L0 & 2) ? -yr : yr;
+        yi = (L0 & 2) ? -yi : yi;
+        return make_double4(x, yr, yi, 0.0);
+    }
+};
+
+// Entries of a wave's G operators from the base terms.
+template <int G, Gen GEN, bool DECAY>
+struct Ops;
+
 template <int G, bool DECAY>
-struct Generator<G, Gen::Direct, DECAY> {
+struct Ops<G, Gen::Direct, DECAY> {
     double kr[G], ki[G];
-    __device__ void init(const SweepArgs &p, int g0) {
+    __device__ void init(const SweepArgs &p, int L0, int wave) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int l = min(g0 + g, p.L - 1);
+            const int l = min(L0 + G * wave + g, p.L - 1);
             kr[g] = p.kappa[l].x;
             ki[g] = p.kappa[l].y;
         }
     }
-    __device__ __forceinline__ void point(double r, double wr, double (&gr)[G], double (&gi)[G]) const {
+    __device__ __forceinline__ void term(const double4 &b, double (&gr)[G], double (&gi)[G]) const {
+        const double r = b.x, wr = b.y;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const double e = DECAY ? exp_cw(-ki[g] * r) * wr : wr;
@@ -60,51 +122,43 @@ struct Generator<G, Gen::Direct, DECAY> {
     }
 };
 
-// Taylor terms l0 .. l0+G-1 of exp(i (c + R t) r) in t: w/r exp(i c r) (i R r)^l / l!
+// Wave w's operators are l = L0 + G w + g: term = y (i x)^(G w) L0!/(L0 + G w)! then
+// times i x / (l + 1) per further operator.
 template <int G, bool DECAY>
-struct Generator<G, Gen::Taylor, DECAY> {
-    double cr, ci, R, inv_fact0;
-    int l0;
+struct Ops<G, Gen::Taylor, DECAY> {
+    static constexpr int kBits = G <= 2 ? 3 : 4;  // bits of the wave offset G w <= 3 G
+    int e;                                        // G w (uniform)
+    double cw;                                    // i^(G w) L0! / (L0 + G w)! (real: G w even or sign folded below)
+    bool rot;                                     // G w odd: one more factor i
     double inv_int[G];
-    __device__ void init(const SweepArgs &p, int g0) {
-        cr = p.c_re;
-        ci = p.c_im;
-        R = p.R;
-        l0 = g0;
-        inv_fact0 = p.inv_fact[g0];
+    __device__ void init(const SweepArgs &p, int L0, int wave) {
+        e = G * wave;
+        double f = 1.0;
+        for (int j = 1; j <= e; ++j) f *= p.inv_int[min(L0 + j, kMaxTaylor - 1)];
+        // i^e = (-1)^(e/2) for even e, i (-1)^((e-1)/2) for odd e
+        cw = ((e >> 1) & 1) ? -f : f;
+        rot = e & 1;
 #pragma unroll
-        for (int g = 0; g < G; ++g) inv_int[g] = p.inv_int[min(g0 + g + 1, kMaxTaylor - 1)];
+        for (int g = 0; g < G; ++g) inv_int[g] = p.inv_int[min(L0 + e + g + 1, kMaxTaylor - 1)];
     }
-    __device__ __forceinline__ void point(double r, double wr, double (&gr)[G], double (&gi)[G]) const {
-        const double e = DECAY ? exp_cw(-ci * r) * wr : wr;
-        double s, c;
-        sincos_cw(cr * r, s, c);
-        const double x = R * r;
-        // x^l0 / l0! by binary powering; l0 is uniform across the block, so the bit tests
-        // are scalar branches
-        double pw = inv_fact0, base = x;
-        for (int e2 = l0; e2; e2 >>= 1) {
-            if (e2 & 1) pw *= base;
+    __device__ __forceinline__ void term(const double4 &b, double (&gr)[G], double (&gi)[G]) const {
+        const double x = b.x;
+        // x^e with selects (e uniform, at most kBits bits)
+        double pw = cw, base = x;
+#pragma unroll
+        for (int bit = 0; bit < kBits; ++bit) {
+            pw = ((e >> bit) & 1) ? pw * base : pw;
             base *= base;
         }
-        const double m = e * pw;
-        double tr = m * c, ti = m * s;
-        // times i^l0 (uniform)
-        if (l0 & 1) {
-            const double t = tr;
-            tr = -ti;
-            ti = t;
-        }
-        if (l0 & 2) {
-            tr = -tr;
-            ti = -ti;
-        }
+        double tr = b.y * pw, ti = b.z * pw;
+        const double t0 = tr;
+        tr = rot ? -ti : tr;
+        ti = rot ? t0 : ti;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             gr[g] += tr;
             gi[g] += ti;
-            // next term: times i x / (l0 + g + 1)
-            const double f = x * inv_int[g];
+            const double f = x * inv_int[g];  // next term: times i x / (l + 1)
             const double t = tr;
             tr = -ti * f;
             ti = t * f;
@@ -112,99 +166,123 @@ struct Generator<G, Gen::Taylor, DECAY> {
     }
 };
 
-// Entries of the G operators at (a, b) from the 7 staged points of triangle b.
-template <int G, class GenT>
-__device__ __forceinline__ void generate(const GenT &gen, const double4 *__restrict__ q7, const double4 &xa,
-                                         bool diag, const double2 (&self)[G], double (&gr)[G], double (&gi)[G]) {
-#pragma unroll
-    for (int g = 0; g < G; ++g) gr[g] = gi[g] = 0.0;
-#pragma unroll
-    for (int q = 0; q < kQuad; ++q) {
-        const double4 y = q7[q];
-        const double dx = xa.x - y.x, dy = xa.y - y.y, dz = xa.z - y.z;
-        double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        r2 = diag ? 1.0 : r2;  // the diagonal is replaced below; keep it finite
-        const double rinv = rsqrt(r2);
-        gen.point(r2 * rinv, y.w * rinv, gr, gi);
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        gr[g] = diag ? self[g].x : gr[g];
-        gi[g] = diag ? self[g].y : gi[g];
-    }
-}
-
 template <int G, int CB, Gen GEN, bool DECAY>
-__global__ __launch_bounds__(256, 2) void sweep_kernel(SweepArgs p) {
+__global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
     constexpr int NC = 16 * CB;
-    constexpr int VPT = kChunk * NC / 256;  // staged probe elements per thread
-    constexpr int QN = kChunk * kQuad;      // staged points per chunk (224 <= 256)
-    constexpr int KSTEPS = kChunk / 4;
-    __shared__ double2 sV[kChunk * NC];
+    constexpr int VPT = kStage * NC / 256;  // staged probe elements per thread (1, 2, 4)
+    constexpr int QN = kStage * kQuad;      // staged points per stage (112)
+    __shared__ double4 sV[kStage * NC];  // (Vr, Vi, Vr + Vi, -)
     __shared__ double4 sQ[QN];
+    __shared__ double4 sB[kBase];        // [(q * kStage + triangle) * 16 + row]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * kRowTile + wave * 16;
-    const int64_t a = row0 + (lane & 15);
-    const int kq = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * 16;
     const int64_t col0 = (int64_t)blockIdx.y * NC;
-    const int g0 = blockIdx.z * G;
+    const int L0 = blockIdx.z * 4 * G;
+    const int l0 = L0 + wave * G;
 
-    Generator<G, GEN, DECAY> gen;
-    gen.init(p, g0);
-    const double4 xa = p.colloc[a];
+    Base<GEN, DECAY> basef;
+    basef.init(p, L0, 4 * G);
+    Ops<G, GEN, DECAY> ops;
+    ops.init(p, L0, wave);
+    // base phase coordinates: row t & 15, stage triangle t >> 4
+    const int brow = tid & 15, btri = tid >> 4;
+    const double4 xa = p.colloc[row0 + brow];
+    // contract phase coordinates
+    const int ci = lane & 15, ck = lane >> 4;
+    const int64_t arow = row0 + ci;
     double2 self[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) self[g] = p.self[(int64_t)min(g0 + g, p.L - 1) * p.n_pad + a];
+    for (int g = 0; g < G; ++g) self[g] = p.self[(int64_t)min(l0 + g, p.L - 1) * p.n_pad + arow];
 
-    v4d acc_r[G][CB], acc_i[G][CB];
+    v4d P1[G][CB], P2[G][CB], P3[G][CB];
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-            acc_r[g][cb] = v4d{0.0, 0.0, 0.0, 0.0};
-            acc_i[g][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+            P1[g][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+            P2[g][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+            P3[g][cb] = v4d{0.0, 0.0, 0.0, 0.0};
         }
 
-    const int64_t nchunks = p.n_pad / kChunk;
-    for (int64_t ch = 0; ch < nchunks; ++ch) {
-        const int64_t b0 = ch * kChunk;
-        __syncthreads();  // every wave has consumed the previous chunk
+    // stage staging through registers
+    double2 rv[VPT];
+    double4 rq = make_double4(0.0, 0.0, 0.0, 0.0);
+    auto fetch = [&](int64_t st) {
+        const int64_t b0 = st * kStage;
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             const int idx = tid + 256 * i;
             const int r = idx / NC, c = idx % NC;
             const int64_t b = b0 + r, col = col0 + c;
-            sV[idx] = (b < p.n && col < p.m) ? p.V[b * p.ldv + col] : make_double2(0.0, 0.0);
+            rv[i] = (b < p.n && col < p.m) ? p.V[b * p.ldv + col] : make_double2(0.0, 0.0);
         }
-        if (tid < QN) sQ[tid] = p.quad[b0 * kQuad + tid];
+        if (tid < QN) rq = p.quad[b0 * kQuad + tid];
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) sV[tid + 256 * i] = make_double4(rv[i].x, rv[i].y, rv[i].x + rv[i].y, 0.0);
+        if (tid < QN) sQ[tid] = rq;
+    };
+
+    const int64_t nstages = p.n_pad / kStage;
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int64_t st = 0; st < nstages; ++st) {
+        const int64_t b0 = st * kStage;
+        // base phase
+        {
+            const bool diag = b0 + btri == row0 + brow;
+#pragma unroll
+            for (int q = 0; q < kQuad; ++q) {
+                const double4 y = sQ[btri * kQuad + q];
+                const double dx = xa.x - y.x, dy = xa.y - y.y, dz = xa.z - y.z;
+                double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                r2 = diag ? 1.0 : r2;  // the diagonal is replaced by the self term
+                const double rinv = rsqrt(r2);
+                sB[(q * kStage + btri) * 16 + brow] = basef.make(r2 * rinv, diag ? 0.0 : y.w * rinv, p);
+            }
+        }
         __syncthreads();
-#pragma unroll 2
-        for (int ks = 0; ks < KSTEPS; ++ks) {
-            const int bl = 4 * ks + kq;
+        if (st + 1 < nstages) fetch(st + 1);
+        // contract phase
+#pragma unroll 1
+        for (int ks = 0; ks < kStageSteps; ++ks) {
+            const int tri = 4 * ks + ck;
             double gr[G], gi[G];
-            generate<G>(gen, &sQ[bl * kQuad], xa, b0 + bl == a, self, gr, gi);
-            double2 v[CB];
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) v[cb] = sV[bl * NC + cb * 16 + (lane & 15)];
-            // first the products that start each accumulator's update, then the ones that
-            // finish it, so dependent MFMAs are 2 G CB apart
+            for (int g = 0; g < G; ++g) gr[g] = gi[g] = 0.0;
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
+            for (int q = 0; q < kQuad; ++q) {
+                ops.term(sB[(q * kStage + tri) * 16 + ci], gr, gi);
+            }
+            const bool diag = b0 + tri == arow;
+            double gs[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                gr[g] = diag ? self[g].x : gr[g];
+                gi[g] = diag ? self[g].y : gi[g];
+                gs[g] = gr[g] + gi[g];
+            }
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const double4 v = sV[tri * NC + cb * 16 + ci];
+                const double vr_ = v.x, vi_ = v.y, vs_ = v.z;
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    acc_r[g][cb] = mfma(gr[g], v[cb].x, acc_r[g][cb]);
-                    acc_i[g][cb] = mfma(gi[g], v[cb].x, acc_i[g][cb]);
+                    P1[g][cb] = mfma(gr[g], vr_, P1[g][cb]);
+                    P2[g][cb] = mfma(gi[g], vi_, P2[g][cb]);
+                    P3[g][cb] = mfma(gs[g], vs_, P3[g][cb]);
                 }
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    acc_r[g][cb] = mfma(-gi[g], v[cb].y, acc_r[g][cb]);
-                    acc_i[g][cb] = mfma(gr[g], v[cb].y, acc_i[g][cb]);
-                }
+            }
+        }
+        __syncthreads();  // stage fully consumed
+        if (st + 1 < nstages) {
+            stash();
+            __syncthreads();
         }
     }
 
@@ -212,15 +290,16 @@ __global__ __launch_bounds__(256, 2) void sweep_kernel(SweepArgs p) {
     // column lane & 15.
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        if (g0 + g >= p.L) break;
-        double2 *Z = p.Z + (int64_t)(g0 + g) * p.zstride;
+        if (l0 + g >= p.L) break;
+        double2 *Z = p.Z + (int64_t)(l0 + g) * p.zstride;
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-            const int64_t col = col0 + cb * 16 + (lane & 15);
+            const int64_t col = col0 + cb * 16 + ci;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int64_t row = row0 + kq + 4 * i;
-                if (row < p.n && col < p.m) Z[row * p.ldz + col] = make_double2(acc_r[g][cb][i], acc_i[g][cb][i]);
+                const int64_t row = row0 + ck + 4 * i;
+                const double p1 = P1[g][cb][i], p2 = P2[g][cb][i], p3 = P3[g][cb][i];
+                if (row < p.n && col < p.m) Z[row * p.ldz + col] = make_double2(p1 - p2, p3 - p1 - p2);
             }
         }
     }
@@ -229,21 +308,23 @@ __global__ __launch_bounds__(256, 2) void sweep_kernel(SweepArgs p) {
 template <int G, int CB, Gen GEN, bool DECAY>
 hipError_t launch_t(const SweepArgs &p, hipStream_t stream) {
     constexpr int NC = 16 * CB;
-    dim3 grid((unsigned)(p.n_pad / kRowTile), (unsigned)((p.m + NC - 1) / NC), (unsigned)((p.L + G - 1) / G));
+    dim3 grid((unsigned)(p.n_pad / 16), (unsigned)((p.m + NC - 1) / NC), (unsigned)((p.L + 4 * G - 1) / (4 * G)));
     hipLaunchKernelGGL((sweep_kernel<G, CB, GEN, DECAY>), grid, dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 
-// Two operators per block: the 8 G CB accumulator doubles plus the generator must fit
-// the 256 registers a wave gets when two waves share a SIMD.
+// Operators per wave: 3 while the three accumulator sets (12 G CB doubles per lane) leave
+// room for the generator, 2 at 64 columns.
 template <Gen GEN, bool DECAY>
 hipError_t launch_gen(const SweepArgs &p, hipStream_t stream) {
-    if (p.m <= 16) return launch_t<2, 1, GEN, DECAY>(p, stream);
-    if (p.m <= 32) return launch_t<2, 2, GEN, DECAY>(p, stream);
+    if (p.m <= 16) return launch_t<3, 1, GEN, DECAY>(p, stream);
+    if (p.m <= 32) return launch_t<3, 2, GEN, DECAY>(p, stream);
     return launch_t<2, 4, GEN, DECAY>(p, stream);
 }
 
 }  // namespace
+
+int sweep_ops_per_block(int64_t m) { return m <= 32 ? 12 : 8; }
 
 hipError_t launch_sweep(Gen gen, const SweepArgs &args, hipStream_t stream) {
     const bool decay = args.decay != 0;
