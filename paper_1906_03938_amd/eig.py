@@ -1,0 +1,173 @@
+"""Eigenvalues inside a contour from device sweeps (the host steps of the method).
+
+Algorithm 3 of the paper with the restarts of Section 3.2: q steps of inverse iteration
+on the linearisation of the Cauchy approximation (Algorithm 1) build a basis U; the
+Rayleigh-Ritz blocks B^_j = w_j U^H T(z_j) U give the reduced pencil eq. sc1_cauchy_red,
+solved by the QZ algorithm; Ritz pairs inside the contour are accepted when every relative
+residual ||T(lambda) x|| / ||x|| is at most `tol`, otherwise the next outer iteration
+restarts from them.
+
+Every application of the BEM operator is a library sweep (contour_moments, rr_project,
+bem_assemble_apply).  The host only does small dense algebra with LAPACK through SciPy: one
+LU of the n x n Schur complement, QR of n x nu blocks and QZ of the (N+1) nu pencil.
+
+Inverse iteration without storing the N v-blocks.  With shift s = c, d_i = z_i - s,
+B_i = w_i T(z_i) and the moment blocks M_p = sum_i B_i d_i^-p, one step of Algorithm 1 --
+S u' = sum_i B_i v_i / d_i with the Schur complement S = M_1, then v_i' = (v_i - u')/d_i
+(block elimination of (A - s M) w' = M w, whose bottom right-hand block is zero) -- keeps
+every v-block of the form
+    v_i = sum_p a_p d_i^-p + b / (lam - z_i)
+(the last term only on restarts, which start from v_i = x/(lam - z_i)).  Substituting,
+    u'   = S^-1 [ sum_p M_{p+1} a_p + (M_1 + R_lam) b / (lam - c) ],
+    a'_1 = -u' + b/(lam - c),   a'_{p+1} = a_p,   b' = b/(lam - c),
+with R_lam = sum_i B_i/(lam - z_i).  So a_p at step j is the a_1 created at step j-p+1,
+and each new a_1 is swept once with every moment order it will still be needed for.
+Columns are not normalised between steps (a per-column scale does not change the span the
+Rayleigh-Ritz step uses); only the final block is orthonormalised.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import _lib
+
+
+class ContourSolver:
+    """Cauchy-approximation eigensolver for T(kappa) x = 0 inside |kappa - c| < radius,
+    with N trapezoidal nodes, q inverse-iteration steps per outer iteration."""
+
+    def __init__(self, mesh, c, radius, N, q=10, tol=1e-12, max_outer=30):
+        import torch
+
+        self.torch = torch
+        self.mesh = mesh
+        self.n = mesh.n
+        self.c = complex(c)
+        self.radius = float(radius)
+        self.N = int(N)
+        self.q = int(q)
+        self.tol = float(tol)
+        self.max_outer = int(max_outer)
+        self.z, self.w, self.W = _lib.contour_nodes(self.c, self.radius, self.N, shift=self.c, P=self.q + 1)
+        self._S_lu = None
+        self.history = []
+
+    def _dev(self, a):
+        return self.torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to("cuda")
+
+    # -- sweeps -------------------------------------------------------------------
+    def moments(self, X, orders):
+        """M_p X for moment orders p >= 1: one contour_moments sweep of X."""
+        W = np.ascontiguousarray(self.W[:, [p - 1 for p in orders]])
+        return self.mesh.contour_moments(self.z, W, self._dev(X)).cpu().numpy()
+
+    def r_lam(self, x, lam):
+        """R_lam x = sum_i w_i T(z_i) x / (lam - z_i), one column."""
+        W = (self.w / (lam - self.z))[:, None]
+        return self.mesh.contour_moments(self.z, W, self._dev(x.reshape(-1, 1))).cpu().numpy()[0, :, 0]
+
+    def schur_lu(self):
+        """LU of S = M_1 = sum_i B_i/(z_i - c), assembled by one sweep of the identity."""
+        if self._S_lu is None:
+            S = self.moments(np.eye(self.n, dtype=np.complex128), [1])[0]
+            self._S_lu = sla.lu_factor(S)
+        return self._S_lu
+
+    # -- Algorithm 1, q steps -------------------------------------------------------
+    def inverse_iteration(self, u0, lam=None):
+        """u after q steps from v_i = u0/(c - z_i) (lam None) or v_i = u0/(lam_k - z_i)."""
+        lu = self.schur_lu()
+        q = self.q
+        restart = lam is not None
+        swept = []  # swept[k][o] = M_{o+2} a_1^(k)
+        if restart:
+            rho = 1.0 / (np.asarray(lam, dtype=np.complex128) - self.c)  # per column
+            x = np.asarray(u0, dtype=np.complex128)
+            Mx = self.moments(x, list(range(1, q + 2)))                  # M_1 x .. M_{q+1} x
+            Rx = np.stack([self.r_lam(x[:, k], lam[k]) for k in range(x.shape[1])], axis=1)
+            base = Mx[0] + Rx                                            # (M_1 + R_lam) x
+            swept.append(None)                                           # no a_1^(0) on restarts
+        else:
+            swept.append(self.moments(-u0, list(range(2, q + 2))))       # a_1^(0) = -u0
+        u = u0
+        for j in range(q):
+            acc = np.zeros_like(u0, dtype=np.complex128)
+            for k in range(j + 1):
+                if swept[k] is not None:
+                    acc += swept[k][j - k]                               # M_{j-k+2} a_1^(k)
+            if restart:
+                acc += base * rho[None, :] ** (j + 1)
+            u = sla.lu_solve(lu, acc)
+            if j + 1 < q:
+                a1 = -u
+                orders = list(range(2, q - j + 1))                       # still needed by steps j+1 .. q-1
+                Ma = self.moments(a1, orders)
+                if restart:                                              # a_1 += x rho^(j+1)
+                    Ma = Ma + Mx[1:1 + len(orders)] * rho[None, None, :] ** (j + 1)
+                swept.append(Ma)
+        return u
+
+    # -- Rayleigh-Ritz ---------------------------------------------------------------
+    def reduced_pencil(self, Bhat):
+        """eq. sc1_cauchy_red over all N nodes: unknowns [v^_0 .. v^_{N-1}, y]."""
+        N, m = len(Bhat), Bhat[0].shape[0]
+        A = np.zeros(((N + 1) * m, (N + 1) * m), dtype=np.complex128)
+        M = np.zeros_like(A)
+        eye = np.eye(m)
+        for j in range(N):
+            sl = slice(j * m, (j + 1) * m)
+            A[sl, sl] = self.z[j] * eye
+            A[sl, N * m:] = eye
+            A[N * m:, sl] = -Bhat[j]
+            M[sl, sl] = eye
+        return A, M
+
+    def rayleigh_ritz(self, U):
+        P = self.mesh.rr_project(self.z, self._dev(U)).cpu().numpy()
+        Bhat = [self.w[j] * P[j] for j in range(self.N)]
+        A, M = self.reduced_pencil(Bhat)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            lam, V = sla.eig(A, M)
+        m = U.shape[1]
+        Y = V[-m:, :]
+        return lam, Y
+
+    def residuals(self, lam, X):
+        out = np.empty(lam.size)
+        for k in range(lam.size):
+            y = self.mesh.assemble_apply([lam[k]], self._dev(X[:, k:k + 1])).cpu().numpy()[0, :, 0]
+            out[k] = np.linalg.norm(y) / np.linalg.norm(X[:, k])
+        return out
+
+    # -- Algorithm 3 with restarts -------------------------------------------------------
+    def solve(self, U0):
+        u0 = np.asarray(U0, dtype=np.complex128)
+        nu = u0.shape[1]
+        lam_restart = None
+        for outer in range(self.max_outer):
+            u = self.inverse_iteration(u0, lam_restart)
+            U, _ = np.linalg.qr(u)
+            lam, Y = self.rayleigh_ritz(U)
+            finite = np.isfinite(lam)
+            inside = finite & (np.abs(lam - self.c) < self.radius)
+            Yin = Y[:, inside]
+            X = U @ (Yin / np.linalg.norm(Yin, axis=0, keepdims=True))
+            lam_in = lam[inside]
+            res = self.residuals(lam_in, X)
+            self.history.append((lam_in.copy(), res.copy()))
+            if lam_in.size and res.max() <= self.tol:
+                order = np.argsort(lam_in.real)
+                return lam_in[order], X[:, order], res[order], outer + 1
+            idx = np.flatnonzero(finite)[np.argsort(np.abs(lam[finite] - self.c))][:nu]
+            Yr = Y[:, idx]
+            u0 = U @ (Yr / np.linalg.norm(Yr, axis=0, keepdims=True))
+            lam_restart = lam[idx]
+        order = np.argsort(lam_in.real)
+        return lam_in[order], X[:, order], res[order], self.max_outer
+
+
+def eigs_in_contour(mesh, c, radius, N, U0, q=10, tol=1e-12, max_outer=30):
+    """(eigenvalues, eigenvectors, relative residuals, outer iterations) of T(kappa) x = 0
+    inside |kappa - c| < radius; U0 is the n x nu starting block."""
+    return ContourSolver(mesh, c, radius, N, q=q, tol=tol, max_outer=max_outer).solve(U0)
