@@ -78,6 +78,30 @@ def cpu_baseline(xyz, tri, z, V, rows_per_thread=6):
     }
 
 
+def eigen_check():
+    """Eigenvalues of the sphere-1280 workload (icosphere level 3, |z - 4| < 1.5, N = 32,
+    16 probes, seed 1) by the host driver on device sweeps, against the oracle's values
+    stored in tests/golden/sphere1280_eigs.txt (written by an oracle-only script)."""
+    import numpy as np
+
+    import paper_1906_03938_amd as bem
+    import synth
+    from paper_1906_03938_amd.eig import eigs_in_contour
+
+    ref = np.loadtxt(os.path.join(ROOT, "tests", "golden", "sphere1280_eigs.txt"))
+    lam_ref = np.sort_complex(ref[:, 0] + 1j * ref[:, 1])
+    xyz, tri = synth.icosphere(3)
+    t0 = time.perf_counter()
+    with bem.Mesh(xyz, tri) as mesh:
+        lam, _, res, outer = eigs_in_contour(mesh, 4.0, 1.5, 32, synth.probe_block(1280, 16, seed=1))
+    dt = time.perf_counter() - t0
+    ok = lam.size == lam_ref.size
+    err = float(np.max(np.abs(np.sort_complex(lam) - lam_ref) / np.abs(lam_ref))) if ok else None
+    return {"workload": "sphere-1280", "eigenvalues": [[float(l.real), float(l.imag)] for l in np.sort_complex(lam)],
+            "max_rel_err_vs_oracle": err, "max_rel_residual": float(res.max()), "outer_iterations": int(outer),
+            "seconds": dt}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +109,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", choices=["auto", "direct", "expand"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-eigen-check", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -128,6 +153,7 @@ def main():
         z, _, W = bem.contour_nodes(w["c"], w["radius"], w["N"], P=w["P"])
         mesh.rr_project(z, U, W=W, out=Pout, moments_out=Mout, form=form)
         return z
+
 
     for _ in range(args.warmup):
         step()
@@ -182,9 +208,11 @@ def main():
             "kernel_hash": khash,
         },
     }
+    mesh.close()
+    if not args.no_eigen_check:
+        out["eigen_check"] = eigen_check()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xyz, tri, z, Vh)
-    mesh.close()
     print(json.dumps(out), flush=True)
 
 

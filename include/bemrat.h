@@ -55,10 +55,11 @@ typedef enum {
 /* Sweep forms, passed in `flags`.
  *   BEM_FORM_DIRECT: one regenerated operator per node, T(z_j) V for every node.
  *   BEM_FORM_EXPAND: T(z) = sum_l t^l T_l with t = (z - c)/R about the centre c and
- *     radius R of the nodes (Taylor expansion of exp(i z r) in z; for cheb_moments the
- *     Jacobi-Anger expansion in Chebyshev polynomials of exp(i kappa r) on [a, b]);
- *     the library generates L < N coefficient operators, truncated where the remainder
- *     bound falls below 1e-17 relative, and combines them per node.
+ *     radius R of the node set (Taylor expansion of exp(i z r) in z; for cheb_moments the
+ *     nodes are the real Chebyshev points, c = (a+b)/2, R ~ (b-a)/2); the library
+ *     generates L coefficient operators, truncated where the remainder bound falls below
+ *     1e-14 relative to the smallest kernel value at the nodes, and recombines them per
+ *     node or weight set.
  *   BEM_FORM_AUTO: EXPAND when it needs fewer operators than DIRECT, else DIRECT.
  * Bits 4..7 select the arithmetic; only 0 (FP64 throughout) is built, any other value
  * returns BEM_EUNSUPPORTED. */
@@ -143,7 +144,7 @@ bem_status contour_moments(bem_mesh_t mesh, const double *z, int64_t N, const do
 
 /* Chebyshev coefficient blocks C[l] = sum_k coef[l][k] T(kappa_k) V, l < L <= N, on the
  * first-kind points of [a, b] (paper, eq. Chebyshev; nodes and coef as in
- * bem_cheb_nodes).  a < b real.  V: device n x m (ldv >= m).  C: device, L blocks of
+ * bem_cheb_nodes).  a < b real.  flags: BEM_FORM_* as for contour_moments.  V: device n x m (ldv >= m).  C: device, L blocks of
  * n x m, block l at C + 2*l*n*ldc doubles, row stride ldc >= m.
  * Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE. */
 bem_status cheb_moments(bem_mesh_t mesh, double a, double b, int64_t N, int64_t L,

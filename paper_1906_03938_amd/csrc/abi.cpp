@@ -100,7 +100,7 @@ struct bem_mesh {
     int device = 0;
     DeviceMesh dm;
     double diameter = 0.0;  // upper bound on every distance in the operator
-    Buffer geom, gl, self, aux, Z, params, partial;
+    Buffer geom, gl, self, aux, Z, params, partial, probe;
     Staging staging;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false, timed = false;
@@ -248,12 +248,13 @@ struct Plan {
     std::vector<cplx> Cf;     // N x L: T(z_j) = sum_l Cf[j][l] T_l
 };
 
-// Expansion length: smallest L with x^L/L! / (1 - x/(L+1)) <= 1e-14 e^{-x} -- the
-// truncated Taylor series of exp(i R r t) is then accurate to 1e-14 relative to its
-// smallest value on |t| <= 1 -- rounded up to a whole number of sweep blocks (the extra
-// terms cost nothing and only add accuracy).
-int taylor_length(double x, int block) {
-    const double target = 1e-14 * std::exp(-x);
+// Expansion length: smallest L with x^L/L! / (1 - x/(L+1)) <= 1e-14 e^{-x h}, where
+// h = max_j max(Im t_j, 0) over the scaled nodes t_j = (z_j - c)/R: the truncated Taylor
+// series of exp(i R r t) is then accurate to 1e-14 relative to its smallest value at the
+// nodes (|exp(i R r t)| = e^{-R r Im t}; h = 1 on a circle, 0 for real nodes).  L is rounded
+// up to a whole number of sweep blocks (the extra terms cost nothing and add accuracy).
+int taylor_length(double x, double h, int block) {
+    const double target = 1e-14 * std::exp(-x * h);
     double term = 1.0;
     for (int L = 1; L < bemrat::kMaxTaylor; ++L) {
         term *= x / L;
@@ -280,7 +281,10 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
     double R = 0.0;
     for (auto &v : zs) R = std::max(R, std::abs(v - c));
     const uint32_t form = flags & BEM_FORM_MASK;
-    int L = R > 0.0 ? taylor_length(R * h->diameter, bemrat::sweep_ops_per_block(m)) : bemrat::kMaxTaylor;
+    double hmax = 0.0;
+    if (R > 0.0)
+        for (auto &v : zs) hmax = std::max(hmax, (v - c).imag() / R);
+    int L = R > 0.0 ? taylor_length(R * h->diameter, hmax, bemrat::sweep_ops_per_block(m)) : bemrat::kMaxTaylor;
     const bool expand_ok = R > 0.0 && L < bemrat::kMaxTaylor;
     const bool expand = form == BEM_FORM_EXPAND ? expand_ok : (form == BEM_FORM_AUTO && expand_ok && L < N);
     if (!expand) {
@@ -363,7 +367,18 @@ bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, 
                                         h->self.as<double2>(), s),
                 "self-term expansion kernel");
     }
+    // zero-padded (Vr, Vi) / Vr + Vi copy of the probe block read by the sweep
+    const int64_t m_pad = bemrat::sweep_m_pad(m);
+    const size_t np = (size_t)dm.n_pad * m_pad;
+    HIP_TRY(h->probe.ensure(np * (sizeof(double2) + sizeof(double))), "probe copy");
+    double2 *Vp2 = h->probe.as<double2>();
+    double *Vps = reinterpret_cast<double *>(Vp2 + np);
+    HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V), ldv, dm.n, m, dm.n_pad, m_pad, Vp2, Vps, s),
+            "probe copy kernel");
     bemrat::SweepArgs a{};
+    a.Vp2 = Vp2;
+    a.Vps = Vps;
+    a.m_pad = m_pad;
     a.colloc = dm.colloc;
     a.quad = dm.quad;
     a.self = h->self.as<double2>();
@@ -528,6 +543,7 @@ void bem_mesh_destroy(bem_mesh_t h) {
     h->Z.release();
     h->params.release();
     h->partial.release();
+    h->probe.release();
     if (h->staging.host) (void)hipHostFree(h->staging.host);
     if (h->staging.done) (void)hipEventDestroy(h->staging.done);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -719,16 +735,20 @@ bem_status cheb_moments(bem_mesh_t h, double a, double b, int64_t N, int64_t L, 
         z[2 * k] = kap[k];
         z[2 * k + 1] = 0.0;
     }
-    Plan plan = make_plan(h, z.data(), N, m, BEM_FORM_DIRECT);
+    Plan plan = make_plan(h, z.data(), N, m, flags);
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
     int K = 0;
     if ((st = build_self(h, plan, prm, off_k, off_dft, K, stream)) != BEM_OK) return st;
-    // combine coefficients: coef[k][l] = cf[l][k]
-    std::vector<cplx> coef((size_t)N * L);
+    // combine coefficients: C_l = sum_k cf[l][k] T(kappa_k) V = sum_j (sum_k cf[l][k] Cf[k][j]) Z_j
+    std::vector<cplx> coef((size_t)plan.L * L, 0.0);
     for (int64_t k = 0; k < N; ++k)
-        for (int64_t l = 0; l < L; ++l) coef[k * L + l] = cf[l * N + k];
+        for (int j = 0; j < plan.L; ++j) {
+            const cplx t = plan.Cf[k * plan.L + j];
+            if (t == cplx(0.0, 0.0)) continue;
+            for (int64_t l = 0; l < L; ++l) coef[j * L + l] += cf[l * N + k] * t;
+        }
     const size_t off_coef = add_complex(prm, coef);
     const size_t zstride = (size_t)h->dm.n * m;
     HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * plan.L), "sweep workspace");

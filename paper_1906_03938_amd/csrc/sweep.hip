@@ -7,9 +7,9 @@
 //   of v_mfma_f64_16x16x4f64) and 16*CB probe columns; wave w handles the G operators
 //   l0 = 4 G blockIdx.z + G w, ..., so a block covers 4 G operators.
 // * The K loop runs over the source triangles in stages of kStage = 16.  For a stage the
-//   probe rows V[b, cols] (with Vr + Vi for the three-multiplication product) and the 7
-//   quadrature points of each triangle are staged in LDS (prefetched into registers
-//   during the previous stage).
+//   probe rows (Vr, Vi) and Vr + Vi -- read from a zero-padded copy made once per call, so
+//   no bounds checks or additions are repeated per block -- and the 7 quadrature points of
+//   each triangle are staged in LDS (prefetched into registers during the previous stage).
 // * Base phase: thread t computes, for target row t & 15 and source triangle t >> 4 of
 //   the stage, the operator-independent part of all 7 quadrature terms (the distance,
 //   the weight over 4 pi r, and for the expansion the factor exp(i c r)) once, into LDS.
@@ -171,9 +171,12 @@ __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
     constexpr int NC = 16 * CB;
     constexpr int VPT = kStage * NC / 256;  // staged probe elements per thread (1, 2, 4)
     constexpr int QN = kStage * kQuad;      // staged points per stage (112)
-    __shared__ double4 sV[kStage * NC];  // (Vr, Vi, Vr + Vi, -)
+    // double2 + double arrays keep every LDS read and write free of bank conflicts
+    __shared__ double2 sV2[kStage * NC];  // (Vr, Vi)
+    __shared__ double sVs[kStage * NC];   // Vr + Vi
     __shared__ double4 sQ[QN];
-    __shared__ double4 sB[kBase];        // [(q * kStage + triangle) * 16 + row]
+    __shared__ double2 sB2[kBase];        // base terms [(q * kStage + triangle) * 16 + row]
+    __shared__ double sB1[kBase];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -207,23 +210,34 @@ __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
             P3[g][cb] = v4d{0.0, 0.0, 0.0, 0.0};
         }
 
-    // stage staging through registers
+    // stage staging through registers, from the zero-padded probe copy (n_pad x m_pad)
     double2 rv[VPT];
+    double rs[VPT];
     double4 rq = make_double4(0.0, 0.0, 0.0, 0.0);
+    const double2 *vsrc2[VPT];
+    const double *vsrcs[VPT];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+        const int idx = tid + 256 * i;
+        const int64_t off = (int64_t)(idx / NC) * p.m_pad + col0 + idx % NC;
+        vsrc2[i] = p.Vp2 + off;
+        vsrcs[i] = p.Vps + off;
+    }
+    const int64_t vstride = (int64_t)kStage * p.m_pad;
     auto fetch = [&](int64_t st) {
-        const int64_t b0 = st * kStage;
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
-            const int idx = tid + 256 * i;
-            const int r = idx / NC, c = idx % NC;
-            const int64_t b = b0 + r, col = col0 + c;
-            rv[i] = (b < p.n && col < p.m) ? p.V[b * p.ldv + col] : make_double2(0.0, 0.0);
+            rv[i] = vsrc2[i][st * vstride];
+            rs[i] = vsrcs[i][st * vstride];
         }
-        if (tid < QN) rq = p.quad[b0 * kQuad + tid];
+        if (tid < QN) rq = p.quad[st * kStage * kQuad + tid];
     };
     auto stash = [&]() {
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) sV[tid + 256 * i] = make_double4(rv[i].x, rv[i].y, rv[i].x + rv[i].y, 0.0);
+        for (int i = 0; i < VPT; ++i) {
+            sV2[tid + 256 * i] = rv[i];
+            sVs[tid + 256 * i] = rs[i];
+        }
         if (tid < QN) sQ[tid] = rq;
     };
 
@@ -243,7 +257,9 @@ __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
                 double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                 r2 = diag ? 1.0 : r2;  // the diagonal is replaced by the self term
                 const double rinv = rsqrt(r2);
-                sB[(q * kStage + btri) * 16 + brow] = basef.make(r2 * rinv, diag ? 0.0 : y.w * rinv, p);
+                const double4 bt = basef.make(r2 * rinv, diag ? 0.0 : y.w * rinv, p);
+                sB2[(q * kStage + btri) * 16 + brow] = make_double2(bt.x, bt.y);
+                sB1[(q * kStage + btri) * 16 + brow] = bt.z;
             }
         }
         __syncthreads();
@@ -257,7 +273,9 @@ __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
             for (int g = 0; g < G; ++g) gr[g] = gi[g] = 0.0;
 #pragma unroll
             for (int q = 0; q < kQuad; ++q) {
-                ops.term(sB[(q * kStage + tri) * 16 + ci], gr, gi);
+                const int bi = (q * kStage + tri) * 16 + ci;
+                const double2 b2 = sB2[bi];
+                ops.term(make_double4(b2.x, b2.y, sB1[bi], 0.0), gr, gi);
             }
             const bool diag = b0 + tri == arow;
             double gs[G];
@@ -269,8 +287,8 @@ __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
             }
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-                const double4 v = sV[tri * NC + cb * 16 + ci];
-                const double vr_ = v.x, vi_ = v.y, vs_ = v.z;
+                const double2 v = sV2[tri * NC + cb * 16 + ci];
+                const double vr_ = v.x, vi_ = v.y, vs_ = sVs[tri * NC + cb * 16 + ci];
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     P1[g][cb] = mfma(gr[g], vr_, P1[g][cb]);
@@ -322,9 +340,35 @@ hipError_t launch_gen(const SweepArgs &p, hipStream_t stream) {
     return launch_t<2, 4, GEN, DECAY>(p, stream);
 }
 
+// Zero-padded copy of the probe block: Vp2[b][c] = (Vr, Vi), Vps[b][c] = Vr + Vi for
+// b < n_pad, c < m_pad (zeros outside n x m).
+__global__ void prep_probe_kernel(const double2 *__restrict__ V, int64_t ldv, int64_t n, int64_t m,
+                                  int64_t n_pad, int64_t m_pad, double2 *__restrict__ Vp2,
+                                  double *__restrict__ Vps) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_pad * m_pad) return;
+    const int64_t b = idx / m_pad, c = idx % m_pad;
+    const double2 v = (b < n && c < m) ? V[b * ldv + c] : make_double2(0.0, 0.0);
+    Vp2[idx] = v;
+    Vps[idx] = v.x + v.y;
+}
+
 }  // namespace
 
 int sweep_ops_per_block(int64_t m) { return m <= 32 ? 12 : 8; }
+
+int64_t sweep_m_pad(int64_t m) {
+    const int nc = m <= 16 ? 16 : (m <= 32 ? 32 : 64);
+    return (m + nc - 1) / nc * nc;
+}
+
+hipError_t launch_prep_probe(const double2 *V, int64_t ldv, int64_t n, int64_t m, int64_t n_pad, int64_t m_pad,
+                             double2 *Vp2, double *Vps, hipStream_t stream) {
+    const int bs = 256;
+    const unsigned grid = (unsigned)((n_pad * m_pad + bs - 1) / bs);
+    hipLaunchKernelGGL(prep_probe_kernel, dim3(grid), dim3(bs), 0, stream, V, ldv, n, m, n_pad, m_pad, Vp2, Vps);
+    return hipGetLastError();
+}
 
 hipError_t launch_sweep(Gen gen, const SweepArgs &args, hipStream_t stream) {
     const bool decay = args.decay != 0;
