@@ -209,7 +209,8 @@ def solve_cauchy_reduced(Bhat, s, c, radius):
 
 def solve_cheb_reduced(Bhat, a, b, imag_tol=1e-8):
     """Eigenvalues kappa = alpha + beta xi of the reduced Chebyshev pencil with kappa in
-    [a, b] and |Im kappa| <= imag_tol (b - a); y is the first block of w."""
+    [a, b] and |Im kappa| <= imag_tol (b - a); y is the first block of w.  Returns
+    (kappa inside, y inside, every kappa, every y)."""
     A, M = cheb_pencil(Bhat)
     with np.errstate(invalid="ignore", divide="ignore"):
         xi, W = sla.eig(A, M)
@@ -221,7 +222,7 @@ def solve_cheb_reduced(Bhat, a, b, imag_tol=1e-8):
           & (np.abs(kap.imag) <= imag_tol * (b - a)))
     Y = W[:m, ok]
     Y = Y / np.linalg.norm(Y, axis=0, keepdims=True)
-    return kap[ok], Y
+    return kap[ok], Y, kap, W[:m, :]
 
 
 def relative_residual(op: Operator, lam, x):
@@ -294,6 +295,89 @@ def subspace_iteration(op: Operator, c, radius, N, U0, q=10, tol=1e-12, max_oute
         lr = lam_all[idx]
         u = Xr
         v = [Xr / (lr[None, :] - s[i]) for i in range(N)]
+    order = np.argsort(lam_in.real)
+    return lam_in[order], X[:, order], res[order], max_outer, history
+
+
+def cheb_inverse_power_step(Bs, shift, v, G_lu=None):
+    """One step of Algorithm 2 (inverse power step for the Chebyshev linearisation
+    eq. sc1_chebyshev) with shift s in the xi variable: solve (A - s M) w' = M w for
+    w = [v_0 (= u); v_1; ...; v_{d-1}], d = len(Bs) - 1, by block elimination.
+
+    The first d-1 block rows are the three-term recurrence of the T_l, so
+    v'_l = T_l(s) v'_0 + p_l with p_0 = 0, p_1 = v_0, p_{l+1} = 2 s p_l - p_{l-1} + 2 v_l.
+    Extending the recurrence to p_d, the last block row becomes
+    T~(s) v'_0 = -sum_{l=0}^{d} B_l p_l with T~(s) = sum_l B_l T_l(s) (at s = 0 this is the
+    matrix G of eq. Gmtx up to sign, and the right-hand side that eq. bodd / eq. beven
+    write out for the two parities of d).  Returns v'."""
+    d = len(Bs) - 1
+    s = complex(shift)
+    t = [1.0 + 0j, s]
+    for _ in range(2, d + 1):
+        t.append(2 * s * t[-1] - t[-2])
+    if G_lu is None:
+        G_lu = sla.lu_factor(sum(Bs[l] * t[l] for l in range(d + 1)))
+    p = [np.zeros_like(v[0]), v[0]]
+    for l in range(1, d):
+        p.append(2 * s * p[l] - p[l - 1] + 2 * v[l])
+    rhs = -sum(Bs[l] @ p[l] for l in range(1, d + 1))
+    u_new = sla.lu_solve(G_lu, rhs)
+    return [t[l] * u_new + p[l] for l in range(d)]
+
+
+def cheb_subspace_iteration(op: Operator, a, b, N, U0, q=10, tol=1e-12, max_outer=30,
+                            shift=0.0, imag_tol=1e-3, verbose=False):
+    """Algorithm 3 for the Chebyshev interpolant of degree d = N-1 on [a, b] (Section 3):
+    q steps of Algorithm 2 per outer iteration with shift xi = `shift` (0 is the centre of
+    the interval, kappa = alpha + beta xi), QR of the u parts, B_hat_l = U^H B_l U, the
+    reduced pencil eq. sc1_chebyshev_red, and restarts from the Ritz pairs nearest the
+    centre until every accepted pair has relative residual <= tol.
+
+    The iteration starts from v_l = T_l(s) u (the block structure of an eigenvector of the
+    linearisation at xi = s) and restarts from v_l = T_l(xi_k) x_k.  Ritz values are
+    accepted in [a, b] with |Im kappa| <= imag_tol (b - a)."""
+    kappa, coef = cheb_nodes(a, b, N)
+    alpha, beta = 0.5 * (a + b), 0.5 * (b - a)
+    Ts = [op.dense(k) for k in kappa]
+    Bs = [sum(coef[l, k] * Ts[k] for k in range(N)) for l in range(N)]
+    del Ts
+    d = N - 1
+    s = complex(shift)
+    G_lu = sla.lu_factor(cheb_eval(Bs, s))
+    u = np.array(U0, dtype=np.complex128)
+    nu = u.shape[1]
+
+    def structured(x, xi):
+        xi = np.broadcast_to(np.asarray(xi, dtype=np.complex128), (x.shape[1],))
+        blocks, tp, tc = [x], np.ones_like(xi), xi
+        for l in range(1, d):
+            blocks.append(x * tc[None, :])
+            tp, tc = tc, 2 * xi * tc - tp
+        return blocks
+
+    v = structured(u, s)
+    history = []
+    for outer in range(max_outer):
+        for _ in range(q):
+            v = cheb_inverse_power_step(Bs, s, v, G_lu)
+            scale = 1.0 / np.linalg.norm(v[0], axis=0)
+            v = [vl * scale for vl in v]
+        Q, _ = np.linalg.qr(v[0])
+        Bhat = [Q.conj().T @ B @ Q for B in Bs]
+        lam_in, Y_in, lam_all, Y_all = solve_cheb_reduced(Bhat, a, b, imag_tol)
+        X = Q @ Y_in
+        res = np.array([relative_residual(op, lam_in[k], X[:, k]) for k in range(lam_in.size)])
+        history.append((lam_in.copy(), res.copy()))
+        if verbose:
+            print(f"outer {outer}: {lam_in.size} eigenvalues, max residual "
+                  f"{res.max() if res.size else float('nan'):.2e}", flush=True)
+        if lam_in.size and res.max() <= tol:
+            order = np.argsort(lam_in.real)
+            return lam_in[order], X[:, order], res[order], outer + 1, history
+        fin = np.isfinite(lam_all)
+        idx = np.flatnonzero(fin)[np.argsort(np.abs(lam_all[fin] - (alpha + beta * s)))][:nu]
+        Xr = Q @ (Y_all[:, idx] / np.linalg.norm(Y_all[:, idx], axis=0, keepdims=True))
+        v = structured(Xr, (lam_all[idx] - alpha) / beta)
     order = np.argsort(lam_in.real)
     return lam_in[order], X[:, order], res[order], max_outer, history
 

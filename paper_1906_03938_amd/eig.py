@@ -1,4 +1,6 @@
-"""Eigenvalues inside a contour from device sweeps (the host steps of the method).
+"""Eigenvalues inside a contour or in a real interval from device sweeps (the host steps of
+the method).  ContourSolver below is the Cauchy form; IntervalSolver, further down, the
+Chebyshev form.
 
 Algorithm 3 of the paper with the restarts of Section 3.2: q steps of inverse iteration
 on the linearisation of the Cauchy approximation (Algorithm 1) build a basis U; the
@@ -7,7 +9,7 @@ solved by the QZ algorithm; Ritz pairs inside the contour are accepted when ever
 residual ||T(lambda) x|| / ||x|| is at most `tol`, otherwise the next outer iteration
 restarts from them.
 
-Every application of the BEM operator is a library sweep (contour_moments, rr_project,
+Every application of the BEM operator is a library sweep (contour_moments, cheb_moments, rr_project,
 bem_assemble_apply).  The host only does small dense algebra with LAPACK through SciPy: one
 LU of the n x n Schur complement, QR of n x nu blocks and QZ of the (N+1) nu pencil.
 
@@ -171,3 +173,191 @@ def eigs_in_contour(mesh, c, radius, N, U0, q=10, tol=1e-12, max_outer=30):
     """(eigenvalues, eigenvectors, relative residuals, outer iterations) of T(kappa) x = 0
     inside |kappa - c| < radius; U0 is the n x nu starting block."""
     return ContourSolver(mesh, c, radius, N, q=q, tol=tol, max_outer=max_outer).solve(U0)
+
+
+class IntervalSolver:
+    """Chebyshev-interpolation eigensolver for T(kappa) x = 0 with kappa in [a, b]: the
+    degree d = N-1 interpolant at first-kind nodes (eq. Chebyshev), q steps of Algorithm 2
+    per outer iteration with the shift xi = `shift` (0 is the centre of the interval,
+    kappa = alpha + beta xi), Rayleigh-Ritz with eq. sc1_chebyshev_red and restarts.
+
+    Algorithm 2 without storing the d v-blocks.  Block elimination of (A - s M) w' = M w for
+    the linearisation eq. sc1_chebyshev gives v'_l = T_l(s) v'_0 + p_l with p_0 = 0,
+    p_1 = v_0, p_{l+1} = 2 s p_l - p_{l-1} + 2 v_l, and G v'_0 = -sum_{l=0}^{d} B_l p_l with
+    G = sum_l B_l T_l(s).  Every block is a combination of earlier iterates h_k with scalar
+    coefficients, v_l = sum_k g_k[l] h_k, and each coefficient vector evolves on its own:
+    g' = (p_0 .. p_{d-1}) of the recurrence driven by g.  So an iterate of age a (swept a
+    steps after it was made) enters the right-hand side as sum_j T(kappa_j) W_a[j] h_k with
+    W_a[j] = -sum_l coef[l, j] p^(a)_l, a table fixed once s is chosen: each new iterate is
+    swept once (contour_moments on the Chebyshev nodes) with all the ages it will reach.
+    A restart block x_k = Ritz vector with its own xi_k has per-column coefficients
+    g[l] = T_l(xi_k); it is swept once by cheb_moments (all B_l x) and combined on the host."""
+
+    def __init__(self, mesh, a, b, N, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2):
+        import torch
+
+        if N < 3:
+            raise ValueError("the Chebyshev pencil needs N >= 3 nodes")
+        self.torch = torch
+        self.mesh = mesh
+        self.n = mesh.n
+        self.a, self.b, self.N = float(a), float(b), int(N)
+        self.alpha, self.beta = 0.5 * (self.a + self.b), 0.5 * (self.b - self.a)
+        self.q = int(q)
+        self.tol = float(tol)
+        self.max_outer = int(max_outer)
+        self.s = complex(shift)
+        self.imag_tol = float(imag_tol)
+        self.d = self.N - 1
+        kappa, self.coef = _lib.cheb_nodes(self.a, self.b, self.N)
+        self.z = kappa.astype(np.complex128)
+        self.t_s = self._tvals(self.s)                              # T_0(s) .. T_d(s)
+        self.W_age = np.empty((self.N, self.q), dtype=np.complex128)
+        g = self.t_s[:self.d].copy()
+        for age in range(self.q):
+            p = self._drive(g[:, None])[:, 0]
+            self.W_age[:, age] = -(self.coef.T @ p)
+            g = p[:self.d]
+        self._G_lu = None
+        self.history = []
+
+    def _tvals(self, xi):
+        """T_0(xi) .. T_d(xi) (xi scalar or per-column vector: rows l, columns k)."""
+        xi = np.asarray(xi, dtype=np.complex128)
+        out = np.empty((self.d + 1,) + xi.shape, dtype=np.complex128)
+        out[0] = 1.0
+        if self.d >= 1:
+            out[1] = xi
+        for l in range(2, self.d + 1):
+            out[l] = 2 * xi * out[l - 1] - out[l - 2]
+        return out
+
+    def _drive(self, g):
+        """p_0 .. p_d of the recurrence driven by block coefficients g (d x k)."""
+        p = np.zeros((self.d + 1, g.shape[1]), dtype=np.complex128)
+        p[1] = g[0]
+        for l in range(1, self.d):
+            p[l + 1] = 2 * self.s * p[l] - p[l - 1] + 2 * g[l]
+        return p
+
+    def _dev(self, a):
+        return self.torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to("cuda")
+
+    def sweep(self, X, ages):
+        W = np.ascontiguousarray(self.W_age[:, list(ages)])
+        return self.mesh.contour_moments(self.z, W, self._dev(X)).cpu().numpy()
+
+    def g_lu(self):
+        """LU of G = sum_l B_l T_l(s) = sum_j T(kappa_j) sum_l coef[l, j] T_l(s), assembled by
+        one sweep of the identity."""
+        if self._G_lu is None:
+            wg = (self.coef.T @ self.t_s)[:, None]
+            G = self.mesh.contour_moments(self.z, wg, self._dev(np.eye(self.n))).cpu().numpy()[0]
+            self._G_lu = sla.lu_factor(G)
+        return self._G_lu
+
+    def inverse_iteration(self, u0, xi=None):
+        """u after q steps of Algorithm 2 from v_l = T_l(s) u0 (xi None) or from the restart
+        blocks v_l = T_l(xi_k) u0[:, k]."""
+        lu = self.g_lu()
+        q = self.q
+        u0 = np.asarray(u0, dtype=np.complex128)
+        swept = []                                   # swept[k][a]: age-a sweep of iterate k
+        restart = None
+        if xi is None:
+            swept.append(self.sweep(u0, range(q)))
+        else:
+            Cx = self.mesh.cheb_moments(self.a, self.b, self.N, self.N, self._dev(u0)).cpu().numpy()
+            g = self._tvals(np.asarray(xi, dtype=np.complex128))[:self.d]   # d x m
+            restart = []
+            for _ in range(q):
+                p = self._drive(g)
+                restart.append(-np.einsum("lk,lak->ak", p, Cx))
+                g = p[:self.d]
+            swept.append(None)
+        u = u0
+        for j in range(q):
+            rhs = np.zeros_like(u0)
+            for k in range(j + 1):
+                if swept[k] is not None:
+                    rhs += swept[k][j - k]
+            if restart is not None:
+                rhs += restart[j]
+            u = sla.lu_solve(lu, rhs)
+            if j + 1 < q:
+                swept.append(self.sweep(u, range(q - 1 - j)))
+        return u
+
+    def reduced_pencil(self, Bhat):
+        """eq. sc1_chebyshev_red: unknowns [y, v_1 .. v_{d-1}]; rows xi y = v_1,
+        2 xi v_l = v_{l-1} + v_{l+1}, and 2 xi B_d v_{d-1} = B_d v_{d-2} - sum_{l<d} B_l v_l."""
+        d, m = self.d, Bhat.shape[1]
+        A = np.zeros((d * m, d * m), dtype=np.complex128)
+        M = np.zeros_like(A)
+        eye = np.eye(m)
+        A[:m, m:2 * m] = eye
+        M[:m, :m] = eye
+        for l in range(1, d - 1):
+            r = slice(l * m, (l + 1) * m)
+            A[r, (l - 1) * m:l * m] = eye
+            A[r, (l + 1) * m:(l + 2) * m] = eye
+            M[r, r] = 2 * eye
+        last = slice((d - 1) * m, d * m)
+        for l in range(d):
+            A[last, l * m:(l + 1) * m] = -Bhat[l]
+        A[last, (d - 2) * m:(d - 1) * m] += Bhat[d]
+        M[last, last] = 2 * Bhat[d]
+        return A, M
+
+    def rayleigh_ritz(self, U):
+        """kappa and y of the reduced pencil with B_hat_l = sum_j coef[l, j] U^H T(kappa_j) U."""
+        P = self.mesh.rr_project(self.z, self._dev(U)).cpu().numpy()
+        Bhat = np.einsum("lj,jab->lab", self.coef, P)
+        A, M = self.reduced_pencil(Bhat)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            xi, V = sla.eig(A, M)
+            kap = self.alpha + self.beta * xi
+        return kap, V[:U.shape[1], :]
+
+    def residuals(self, lam, X):
+        out = np.empty(lam.size)
+        for k in range(lam.size):
+            y = self.mesh.assemble_apply([lam[k]], self._dev(X[:, k:k + 1])).cpu().numpy()[0, :, 0]
+            out[k] = np.linalg.norm(y) / np.linalg.norm(X[:, k])
+        return out
+
+    def solve(self, U0):
+        u0 = np.asarray(U0, dtype=np.complex128)
+        nu = u0.shape[1]
+        xi = None
+        centre = self.alpha + self.beta * self.s
+        for outer in range(self.max_outer):
+            u = self.inverse_iteration(u0, xi)
+            U, _ = np.linalg.qr(u)
+            lam, Y = self.rayleigh_ritz(U)
+            finite = np.isfinite(lam)
+            with np.errstate(invalid="ignore"):
+                inside = (finite & (lam.real >= self.a) & (lam.real <= self.b)
+                          & (np.abs(lam.imag) <= self.imag_tol * (self.b - self.a)))
+            Yin = Y[:, inside]
+            X = U @ (Yin / np.linalg.norm(Yin, axis=0, keepdims=True))
+            lam_in = lam[inside]
+            res = self.residuals(lam_in, X)
+            self.history.append((lam_in.copy(), res.copy()))
+            if lam_in.size and res.max() <= self.tol:
+                order = np.argsort(lam_in.real)
+                return lam_in[order], X[:, order], res[order], outer + 1
+            idx = np.flatnonzero(finite)[np.argsort(np.abs(lam[finite] - centre))][:nu]
+            Yr = Y[:, idx]
+            u0 = U @ (Yr / np.linalg.norm(Yr, axis=0, keepdims=True))
+            xi = (lam[idx] - self.alpha) / self.beta
+        order = np.argsort(lam_in.real)
+        return lam_in[order], X[:, order], res[order], self.max_outer
+
+
+def eigs_in_interval(mesh, a, b, N, U0, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2):
+    """(eigenvalues, eigenvectors, relative residuals, outer iterations) of T(kappa) x = 0
+    with kappa in [a, b] (|Im kappa| <= imag_tol (b - a)), from the Chebyshev interpolant
+    with N first-kind nodes; U0 is the n x nu starting block."""
+    return IntervalSolver(mesh, a, b, N, q=q, tol=tol, max_outer=max_outer, shift=shift,
+                          imag_tol=imag_tol).solve(U0)

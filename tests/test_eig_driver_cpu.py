@@ -7,7 +7,7 @@ import torch
 
 import synth
 from oracle import method as M
-from paper_1906_03938_amd.eig import ContourSolver
+from paper_1906_03938_amd.eig import ContourSolver, IntervalSolver
 
 
 class DenseMesh:
@@ -22,6 +22,11 @@ class DenseMesh:
         out = sum(np.asarray(W)[j][:, None, None] * self.op.dense(z[j]) @ V for j in range(len(z)))
         return torch.from_numpy(np.ascontiguousarray(out.reshape(np.asarray(W).shape[1], self.n, -1)))
 
+    def cheb_moments(self, a, b, N, L, V):
+        kappa, coef = M.cheb_nodes(a, b, N)
+        Y = np.stack([self.op.dense(k) @ V.numpy() for k in kappa])
+        return torch.from_numpy(np.einsum("lk,kam->lam", coef[:L], Y))
+
     def rr_project(self, z, U):
         U = U.numpy()
         return torch.from_numpy(np.stack([U.conj().T @ self.op.dense(zj) @ U for zj in z]))
@@ -32,6 +37,11 @@ class DenseMesh:
 
 
 class CpuSolver(ContourSolver):
+    def _dev(self, a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
+
+
+class CpuIntervalSolver(IntervalSolver):
     def _dev(self, a):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
 
@@ -86,5 +96,54 @@ def test_driver_eigenvalues_match_oracle(setup):
     V = synth.probe_block(op.n, 8, seed=1)
     lam, X, res, outer = CpuSolver(mesh, 4.0, 1.5, 32, q=10, tol=1e-12).solve(V)
     lo, _, reso, _, _ = M.subspace_iteration(op, 4.0, 1.5, 32, V, q=10, tol=1e-12)
+    assert res.max() <= 1e-12 and lam.size == lo.size == 4
+    assert np.abs(np.sort_complex(lam) - np.sort_complex(lo)).max() <= 1e-10 * np.abs(lo).max()
+
+
+def _oracle_cheb_iterate(op, a, b, N, v, s, q):
+    kappa, coef = M.cheb_nodes(a, b, N)
+    Ts = [op.dense(k) for k in kappa]
+    Bs = [sum(coef[l, k] * Ts[k] for k in range(N)) for l in range(N)]
+    for _ in range(q):
+        v = M.cheb_inverse_power_step(Bs, s, v)
+        sc = 1.0 / np.linalg.norm(v[0], axis=0)
+        v = [vl * sc for vl in v]
+    return v[0]
+
+
+def _tblocks(x, xi, d):
+    xi = np.broadcast_to(np.asarray(xi, dtype=np.complex128), (x.shape[1],))
+    out, tp, tc = [x], np.ones_like(xi), xi
+    for _ in range(1, d):
+        out.append(x * tc[None, :])
+        tp, tc = tc, 2 * xi * tc - tp
+    return out
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.2])
+def test_swept_history_equals_algorithm2(setup, shift):
+    op, mesh = setup
+    a, b, N, q = 2.5, 5.0, 16, 6
+    u0 = synth.probe_block(op.n, 5, seed=3)
+    u = CpuIntervalSolver(mesh, a, b, N, q=q, shift=shift).inverse_iteration(u0)
+    uo = _oracle_cheb_iterate(op, a, b, N, _tblocks(u0, shift, N - 1), shift, q)
+    assert np.abs(_unit_cols(u) - uo).max() < 1e-12
+
+
+def test_interval_restart_equals_algorithm2(setup):
+    op, mesh = setup
+    a, b, N, q = 2.5, 5.0, 16, 5
+    x = synth.probe_block(op.n, 3, seed=4)
+    xi = np.array([-0.3 + 0.01j, 0.6, 0.1 - 0.05j])
+    u = CpuIntervalSolver(mesh, a, b, N, q=q).inverse_iteration(x, xi)
+    uo = _oracle_cheb_iterate(op, a, b, N, _tblocks(x, xi, N - 1), 0.0, q)
+    assert np.abs(_unit_cols(u) - uo).max() < 1e-12
+
+
+def test_interval_driver_matches_oracle(setup):
+    op, mesh = setup
+    V = synth.probe_block(op.n, 8, seed=1)
+    lam, X, res, outer = CpuIntervalSolver(mesh, 2.5, 5.0, 16, q=10, tol=1e-12).solve(V)
+    lo, _, reso, _, _ = M.cheb_subspace_iteration(op, 2.5, 5.0, 16, V, q=10, tol=1e-12, imag_tol=1e-2)
     assert res.max() <= 1e-12 and lam.size == lo.size == 4
     assert np.abs(np.sort_complex(lam) - np.sort_complex(lo)).max() <= 1e-10 * np.abs(lo).max()

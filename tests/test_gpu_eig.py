@@ -1,8 +1,9 @@
 """GPU eigen-extraction at the sphere-1280 workload: the host driver on device sweeps
-reproduces the oracle's eigenvalues (stored by tests/golden/make_sphere1280_eigs.py) to
-1e-10 relative, with every residual below 1e-12, and the eigenvalues sit near the
-interior Dirichlet eigenvalues of the unit sphere (paper, Table 2) at the mesh's
-discretisation error."""
+reproduces the oracle's eigenvalues (stored by tests/golden/make_sphere1280_eigs.py and
+make_sphere1280_interval_eigs.py) to 1e-10 relative, with every residual below 1e-12, and
+the eigenvalues sit near the interior Dirichlet eigenvalues of the unit sphere (paper,
+Table 2) at the mesh's discretisation error.  Both the Cauchy route (circle) and the
+Chebyshev route (interval) are checked."""
 import os
 
 import numpy as np
@@ -36,3 +37,23 @@ def test_sphere1280_eigenvalues_match_oracle():
     assert err.max() <= 1e-10, err
     tab = np.loadtxt(os.path.join(GOLDEN, "sphere_dirichlet_eigs.txt"))
     assert abs(lam[0] - tab[0, 0]) < 0.02 and np.all(np.abs(lam[1:] - tab[1, 0]) < 0.02)
+
+
+def test_sphere1280_interval_eigenvalues_match_oracle():
+    import torch
+
+    import paper_1906_03938_amd as bem
+    from paper_1906_03938_amd.eig import eigs_in_interval
+
+    assert torch.cuda.is_available()
+    ref = np.loadtxt(os.path.join(GOLDEN, "sphere1280_interval_eigs.txt"))
+    lam_ref = ref[:, 0] + 1j * ref[:, 1]
+    xyz, tri = synth.icosphere(3)
+    with bem.Mesh(xyz, tri) as mesh:
+        V = synth.probe_block(1280, 16, seed=1)
+        lam, X, res, outer = eigs_in_interval(mesh, 2.5, 5.0, 32, V, q=10, tol=1e-12)
+    print("eigenvalues", lam, "residuals", res, "outer", outer, flush=True)
+    assert res.max() <= 1e-12
+    assert lam.size == lam_ref.size == 4
+    err = np.abs(np.sort_complex(lam) - np.sort_complex(lam_ref)) / np.abs(lam_ref)
+    assert err.max() <= 1e-10, err

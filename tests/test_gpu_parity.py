@@ -124,6 +124,30 @@ def test_rr_project_matches_oracle(sphere3, torch, bem, form):
 
 
 @pytest.mark.parametrize("form", ["direct", "expand"])
+def test_real_nodes_match_oracle(sphere3, torch, bem, form):
+    """The calls the interval driver makes: projections and weighted sums on the real
+    Chebyshev nodes of [2.5, 5] (the expansion then has no decay factor)."""
+    from oracle import method as M
+
+    mesh, op, _, _ = sphere3
+    U, _ = np.linalg.qr(synth.probe_block(op.n, 16, seed=5))
+    U = np.ascontiguousarray(U)
+    kappa, coef = M.cheb_nodes(2.5, 5.0, 32)
+    W = np.ascontiguousarray(coef[:3].T.astype(np.complex128))
+    f = bem.FORM_DIRECT if form == "direct" else bem.FORM_EXPAND
+    P, Mg = mesh.rr_project(kappa, _dev(torch, U), W=W, form=f)
+    assert mesh.last_form()[0] == f
+    P = P.cpu().numpy()
+    Po = M.rr_project(op, kappa, U)
+    for j in range(32):
+        assert _rel(P[j], Po[j]) <= TOL, (form, j, _rel(P[j], Po[j]))
+    Mo = M.contour_moments(op, kappa, W, U)
+    Mg = Mg.cpu().numpy()
+    for p in range(3):
+        assert _rel(Mg[p], Mo[p]) <= TOL, (form, p, _rel(Mg[p], Mo[p]))
+
+
+@pytest.mark.parametrize("form", ["direct", "expand"])
 def test_cheb_moments_match_oracle(sphere3, torch, bem, form):
     from oracle import method as M
 

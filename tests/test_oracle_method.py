@@ -187,7 +187,7 @@ def test_cheb_pencil_recovers_polynomial_eigenvalues():
     E3 = 0.01 * rng.standard_normal((n, n))
     T = lambda k: A - k * np.eye(n) + E2 * (k - 5) ** 2 + E3 * (k - 5) ** 3  # noqa: E731
     Bs = [sum(coef[l, k] * T(kappa[k]) for k in range(N)) for l in range(N)]
-    found, Y = M.solve_cheb_reduced(Bs, a, b)
+    found, Y, _, _ = M.solve_cheb_reduced(Bs, a, b)
     assert found.size >= 1
     for k, y in zip(found, Y.T):
         smin = np.linalg.svd(T(k), compute_uv=False)[-1]
@@ -208,6 +208,33 @@ def test_inverse_power_step_equals_dense_shift_invert():
     v2, u2 = M.inverse_power_step(Bs, s, shift, v, u)
     got = np.vstack(v2 + [u2])
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("d", [5, 6])
+@pytest.mark.parametrize("shift", [0.0, 0.3 + 0.1j])
+def test_cheb_inverse_power_step_equals_dense_shift_invert(d, shift):
+    """One step of Algorithm 2 by block elimination equals (A - s M)^{-1} M w for the
+    Chebyshev linearisation, for both parities of the degree d."""
+    rng = np.random.Generator(np.random.PCG64(9 + d))
+    n = 4
+    Bs = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for _ in range(d + 1)]
+    A, Mm = M.cheb_pencil(Bs)
+    v = [rng.standard_normal((n, 2)) + 1j * rng.standard_normal((n, 2)) for _ in range(d)]
+    ref = np.linalg.solve(A - shift * Mm, Mm @ np.vstack(v))
+    got = np.vstack(M.cheb_inverse_power_step(Bs, shift, v))
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_interval_iteration_matches_contour_iteration(sphere1):
+    """n = 80: the Chebyshev route (Algorithm 2 in Algorithm 3, pencil eq. sc1_chebyshev_red)
+    on [2.5, 5] finds the same four eigenvalues as the Cauchy route on |z - 4| < 1.5, each
+    with residual <= 1e-12; the two share only the operator."""
+    op = sphere1
+    V = synth.probe_block(op.n, 8, seed=1)
+    lc, _, rc, _, _ = M.subspace_iteration(op, 4.0, 1.5, 32, V, q=10, tol=1e-12)
+    li, _, ri, _, _ = M.cheb_subspace_iteration(op, 2.5, 5.0, 24, V, q=10, tol=1e-12, imag_tol=1e-2)
+    assert ri.max() <= 1e-12 and li.size == lc.size == 4
+    assert np.abs(np.sort_complex(li) - np.sort_complex(lc)).max() <= 1e-10 * np.abs(lc).max()
 
 
 def test_end_to_end_small_sphere_vs_brute_force(sphere1):
