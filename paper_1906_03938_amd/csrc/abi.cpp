@@ -367,17 +367,15 @@ bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, 
                                         h->self.as<double2>(), s),
                 "self-term expansion kernel");
     }
-    // zero-padded (Vr, Vi) / Vr + Vi copy of the probe block read by the sweep
+    // zero-padded copy of the probe block read by the sweep
     const int64_t m_pad = bemrat::sweep_m_pad(m);
     const size_t np = (size_t)dm.n_pad * m_pad;
-    HIP_TRY(h->probe.ensure(np * (sizeof(double2) + sizeof(double))), "probe copy");
+    HIP_TRY(h->probe.ensure(np * sizeof(double2)), "probe copy");
     double2 *Vp2 = h->probe.as<double2>();
-    double *Vps = reinterpret_cast<double *>(Vp2 + np);
-    HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V), ldv, dm.n, m, dm.n_pad, m_pad, Vp2, Vps, s),
+    HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V), ldv, dm.n, m, dm.n_pad, m_pad, Vp2, s),
             "probe copy kernel");
     bemrat::SweepArgs a{};
     a.Vp2 = Vp2;
-    a.Vps = Vps;
     a.m_pad = m_pad;
     a.colloc = dm.colloc;
     a.quad = dm.quad;

@@ -30,8 +30,7 @@ struct SweepArgs {
     const double2 *self;  // L x n_pad: diagonal entry of each generated operator
     const double2 *V;     // caller's probe block (row stride ldv)
     int64_t ldv;
-    const double2 *Vp2;   // zero-padded copy n_pad x m_pad: (Vr, Vi)
-    const double *Vps;    // and Vr + Vi
+    const double2 *Vp2;   // zero-padded copy n_pad x m_pad
     int64_t m_pad;
     double2 *Z;           // operator l writes n x m block at Z + l * zstride, row stride ldz
     int64_t ldz, zstride;
@@ -58,7 +57,7 @@ int sweep_ops_per_block(int64_t m);
 // Column padding of the probe copy the sweep reads (a multiple of its column tile).
 int64_t sweep_m_pad(int64_t m);
 hipError_t launch_prep_probe(const double2 *V, int64_t ldv, int64_t n, int64_t m, int64_t n_pad, int64_t m_pad,
-                             double2 *Vp2, double *Vps, hipStream_t stream);
+                             double2 *Vp2, hipStream_t stream);
 hipError_t launch_combine(const double2 *Z, int64_t zstride, int64_t ldz, int L,
                           const double2 *coef, int P, int64_t n, int64_t m, double2 *out,
                           int64_t ldo, hipStream_t stream);

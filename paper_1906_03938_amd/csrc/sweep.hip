@@ -1,32 +1,32 @@
 // Generate-and-contract sweep: Z_l = T_l V for a group of coefficient operators T_l.
 //
 // On gfx950 the FP64 MFMA and the FP64 vector ALU share one pipe (they do not overlap),
-// so the kernel minimises the total FP64 work per (entry, operator):
+// and the LDS is the next scarcest resource, so the kernel generates every operator
+// entry exactly once and moves as few bytes through the LDS as it can:
 //
 // * Block = 4 waves (256 threads), all owning the same 16 target rows (the M dimension
-//   of v_mfma_f64_16x16x4f64) and 16*CB probe columns; wave w handles the G operators
-//   l0 = 4 G blockIdx.z + G w, ..., so a block covers 4 G operators.
+//   of v_mfma_f64_16x16x4f64) and 16*CB probe columns; wave w contracts the G operators
+//   L0 + G w, ..., L0 + G w + G - 1 of the block's NOPS = 4 G operators
+//   (L0 = NOPS blockIdx.z).
 // * The K loop runs over the source triangles in stages of kStage = 16.  For a stage the
-//   probe rows (Vr, Vi) and Vr + Vi -- read from a zero-padded copy made once per call, so
-//   no bounds checks or additions are repeated per block -- and the 7 quadrature points of
-//   each triangle are staged in LDS (prefetched into registers during the previous stage).
-// * Base phase: thread t computes, for target row t & 15 and source triangle t >> 4 of
-//   the stage, the operator-independent part of all 7 quadrature terms (the distance,
-//   the weight over 4 pi r, and for the expansion the factor exp(i c r)) once, into LDS.
-//   The expensive transcendental work is thus shared by all 4 G operators of the block.
+//   probe rows (Vr, Vi) -- read from a zero-padded copy made once per call, so no bounds
+//   checks are repeated per block -- and the 7 quadrature points of each triangle are
+//   staged in LDS (prefetched into registers during the previous stage).
+// * Generation phase: thread t computes, for target row t & 15 and source triangle t >> 4
+//   of the stage, the entries of all NOPS operators (the 7 quadrature terms and their
+//   transcendental parts once, then the operator sequence by recurrence) and stores them
+//   in LDS in the layout of the MFMA A operand.  The diagonal entry is the precomputed
+//   self term of each operator.
 // * Contract phase: per k-step (4 source triangles) lane (i = lane & 15, k = lane >> 4)
-//   reads the 7 base terms of entry (row i, triangle 4 ks + k), forms the entries of its
-//   wave's G operators -- exactly the A-operand elements it feeds to the MFMA, so
-//   generated tiles never reach HBM -- and accumulates with Gauss's three-multiplication
-//   complex product: P1 += Gr Vr, P2 += Gi Vi, P3 += (Gr + Gi)(Vr + Vi); at the end
-//   Re Z = P1 - P2, Im Z = P3 - P1 - P2.
+//   reads its entry of each of its wave's G operators (16 bytes each) and the probe rows,
+//   and accumulates with Gauss's three-multiplication complex product:
+//   P1 += Gr Vr, P2 += Gi Vi, P3 += (Gr + Gi)(Vr + Vi); at the end Re Z = P1 - P2,
+//   Im Z = P3 - P1 - P2.  Generated tiles never reach HBM.
 //
 // Operator families (entry of T_l at a != b, summed over the 7 points, with the weight
 // A_b w_q / (4 pi) folded into the staged points):
 //   Direct: T_l = T(kappa_l):              w/r exp(i kappa_l r)
 //   Taylor: T(c + R t) = sum_l t^l T_l:    w/r exp(i c r) (i R r)^l / l!
-// The diagonal entry of T_l comes from a precomputed table (exact self terms or their
-// expansion coefficients).
 #include "devmath.h"
 #include "internal.h"
 
@@ -36,169 +36,132 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kStage = 16;                  // source triangles per stage
-constexpr int kStageSteps = kStage / 4;     // k-steps per stage
-constexpr int kBase = kQuad * kStage * 16;  // base terms per stage (q, triangle, row)
+constexpr int kStage = 16;               // source triangles per stage
+constexpr int kStageSteps = kStage / 4;  // k-steps per stage
 
 __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Base terms of one quadrature point, stored as one double4 per (q, triangle, row):
-//   Direct: (r, w/r, -, -)
-//   Taylor: (x = R r, y = w/r exp(i c r) (i x)^L0 / L0!) for the block's first operator L0.
-template <Gen GEN, bool DECAY>
-struct Base;
+// Entries of the NOPS operators L0 .. L0 + NOPS - 1 at one (row, triangle) off the
+// diagonal, from the distances r_q and weights w_q / r_q of the 7 quadrature points.
+template <int NOPS, Gen GEN, bool DECAY>
+struct Generator;
 
-template <bool DECAY>
-struct Base<Gen::Direct, DECAY> {
-    __device__ void init(const SweepArgs &, int, int) {}
-    __device__ __forceinline__ double4 make(double r, double wr, const SweepArgs &) const {
-        return make_double4(r, wr, 0.0, 0.0);
+template <int NOPS, bool DECAY>
+struct Generator<NOPS, Gen::Direct, DECAY> {
+    double kr[NOPS], ki[NOPS];
+    __device__ void init(const SweepArgs &p, int L0) {
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) {
+            const int l = min(L0 + j, p.L - 1);
+            kr[j] = p.kappa[l].x;
+            ki[j] = p.kappa[l].y;
+        }
+    }
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &, double2 (&out)[NOPS]) const {
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) {
+            double gr = 0.0, gi = 0.0;
+#pragma unroll
+            for (int q = 0; q < kQuad; ++q) {
+                const double e = DECAY ? exp_cw(-ki[j] * r[q]) * wr[q] : wr[q];
+                double sn, cs;
+                sincos_cw(kr[j] * r[q], sn, cs);
+                gr = fma(e, cs, gr);
+                gi = fma(e, sn, gi);
+            }
+            out[j] = make_double2(gr, gi);
+        }
     }
 };
 
-template <bool DECAY>
-struct Base<Gen::Taylor, DECAY> {
-    int L0, z, B;  // L0 = z B: block z of B operators
-    double inv_fact;
-    __device__ void init(const SweepArgs &p, int L0_, int B_) {
-        L0 = L0_;
-        B = B_;
+// Term of operator L0 + j at one point: w/r exp(i c r) (i x)^(L0 + j) / (L0 + j)!, x = R r.
+// L0 is a multiple of 4, so (i x)^L0 = x^L0; the rest is y0 i^j x^j c_j with
+// y0 = w/r exp(i c r) x^L0 / L0! and the block-uniform c_j = L0! / (L0 + j)!.  The power
+// x^j is a running product, so no per-operator factor can be hoisted out and kept live.
+template <int NOPS, bool DECAY>
+struct Generator<NOPS, Gen::Taylor, DECAY> {
+    static constexpr int B = NOPS;  // L0 = z B
+    int z;
+    double inv_fact;                // 1 / L0!
+    double cj[NOPS];                // L0! / (L0 + j)!
+    __device__ void init(const SweepArgs &p, int L0) {
         z = L0 / B;
         inv_fact = p.inv_fact[min(L0, kMaxTaylor - 1)];
-    }
-    __device__ __forceinline__ double4 make(double r, double wr, const SweepArgs &p) const {
-        const double e = DECAY ? exp_cw(-p.c_im * r) * wr : wr;
-        double s, c;
-        sincos_cw(p.c_re * r, s, c);
-        const double x = p.R * r;
-        // x^L0 / L0! = (x^B)^z / L0!: x^B by squaring (B = 8 or 12), then the at most 4
-        // bits of the block-uniform z by selects (no branches)
-        const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
-        double base = B == 8 ? x8 : x8 * x4;
-        double pw = inv_fact;
+        double c = 1.0;
 #pragma unroll
-        for (int bit = 0; bit < 4; ++bit) {
-            pw = ((z >> bit) & 1) ? pw * base : pw;
-            base *= base;
-        }
-        double yr = e * c * pw, yi = e * s * pw;
-        // times i^L0 (L0 is a multiple of 4 when B = 8 or 12: i^L0 = 1) -- kept general
-        const double t = yr;
-        yr = (L0 & 1) ? -yi : yr;
-        yi = (L0 & 1) ? t : yi;
-        yr = (L0 & 2) ? -yr : yr;
-        yi = (L0 & 2) ? -yi : yi;
-        return make_double4(x, yr, yi, 0.0);
-    }
-};
-
-// Entries of a wave's G operators from the base terms.
-template <int G, Gen GEN, bool DECAY>
-struct Ops;
-
-template <int G, bool DECAY>
-struct Ops<G, Gen::Direct, DECAY> {
-    double kr[G], ki[G];
-    __device__ void init(const SweepArgs &p, int L0, int wave) {
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int l = min(L0 + G * wave + g, p.L - 1);
-            kr[g] = p.kappa[l].x;
-            ki[g] = p.kappa[l].y;
+        for (int j = 0; j < NOPS; ++j) {
+            cj[j] = c;
+            c *= p.inv_int[min(L0 + j + 1, kMaxTaylor - 1)];
         }
     }
-    __device__ __forceinline__ void term(const double4 &b, double (&gr)[G], double (&gi)[G]) const {
-        const double r = b.x, wr = b.y;
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &p, double2 (&out)[NOPS]) const {
+        double gr[NOPS], gi[NOPS];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const double e = DECAY ? exp_cw(-ki[g] * r) * wr : wr;
-            double s, c;
-            sincos_cw(kr[g] * r, s, c);
-            gr[g] = fma(e, c, gr[g]);
-            gi[g] = fma(e, s, gi[g]);
+        for (int j = 0; j < NOPS; ++j) gr[j] = gi[j] = 0.0;
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+            const double x = p.R * r[q];
+            // x^L0 / L0! = (x^B)^z / L0!: x^B by squaring (B = 8 or 12), then the at most
+            // 4 bits of the block-uniform z by selects (no branches)
+            const double x2 = x * x, x4 = x2 * x2;
+            double base = B == 8 ? x4 * x4 : x4 * x4 * x4, pw = inv_fact;
+#pragma unroll
+            for (int bit = 0; bit < 4; ++bit) {
+                pw = ((z >> bit) & 1) ? pw * base : pw;
+                base *= base;
+            }
+            const double e = (DECAY ? exp_cw(-p.c_im * r[q]) * wr[q] : wr[q]) * pw;
+            double sn, cs;
+            sincos_cw(p.c_re * r[q], sn, cs);
+            const double yr = e * cs, yi = e * sn;
+            double xp = 1.0;
+#pragma unroll
+            for (int j = 0; j < NOPS; ++j) {
+                const double sc = j == 0 ? 1.0 : xp * cj[j];
+                // times i^j (compile-time rotation)
+                switch (j & 3) {
+                    case 0: gr[j] = fma(yr, sc, gr[j]); gi[j] = fma(yi, sc, gi[j]); break;
+                    case 1: gr[j] = fma(-yi, sc, gr[j]); gi[j] = fma(yr, sc, gi[j]); break;
+                    case 2: gr[j] = fma(-yr, sc, gr[j]); gi[j] = fma(-yi, sc, gi[j]); break;
+                    default: gr[j] = fma(yi, sc, gr[j]); gi[j] = fma(-yr, sc, gi[j]); break;
+                }
+                xp *= x;
+            }
         }
-    }
-};
-
-// Wave w's operators are l = L0 + G w + g: term = y (i x)^(G w) L0!/(L0 + G w)! then
-// times i x / (l + 1) per further operator.
-template <int G, bool DECAY>
-struct Ops<G, Gen::Taylor, DECAY> {
-    static constexpr int kBits = G <= 2 ? 3 : 4;  // bits of the wave offset G w <= 3 G
-    int e;                                        // G w (uniform)
-    double cw;                                    // i^(G w) L0! / (L0 + G w)! (real: G w even or sign folded below)
-    bool rot;                                     // G w odd: one more factor i
-    double inv_int[G];
-    __device__ void init(const SweepArgs &p, int L0, int wave) {
-        e = G * wave;
-        double f = 1.0;
-        for (int j = 1; j <= e; ++j) f *= p.inv_int[min(L0 + j, kMaxTaylor - 1)];
-        // i^e = (-1)^(e/2) for even e, i (-1)^((e-1)/2) for odd e
-        cw = ((e >> 1) & 1) ? -f : f;
-        rot = e & 1;
 #pragma unroll
-        for (int g = 0; g < G; ++g) inv_int[g] = p.inv_int[min(L0 + e + g + 1, kMaxTaylor - 1)];
-    }
-    __device__ __forceinline__ void term(const double4 &b, double (&gr)[G], double (&gi)[G]) const {
-        const double x = b.x;
-        // x^e with selects (e uniform, at most kBits bits)
-        double pw = cw, base = x;
-#pragma unroll
-        for (int bit = 0; bit < kBits; ++bit) {
-            pw = ((e >> bit) & 1) ? pw * base : pw;
-            base *= base;
-        }
-        double tr = b.y * pw, ti = b.z * pw;
-        const double t0 = tr;
-        tr = rot ? -ti : tr;
-        ti = rot ? t0 : ti;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            gr[g] += tr;
-            gi[g] += ti;
-            const double f = x * inv_int[g];  // next term: times i x / (l + 1)
-            const double t = tr;
-            tr = -ti * f;
-            ti = t * f;
-        }
+        for (int j = 0; j < NOPS; ++j) out[j] = make_double2(gr[j], gi[j]);
     }
 };
 
 template <int G, int CB, Gen GEN, bool DECAY>
 __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
     constexpr int NC = 16 * CB;
+    constexpr int NOPS = 4 * G;
     constexpr int VPT = kStage * NC / 256;  // staged probe elements per thread (1, 2, 4)
     constexpr int QN = kStage * kQuad;      // staged points per stage (112)
-    // double2 + double arrays keep every LDS read and write free of bank conflicts
-    __shared__ double2 sV2[kStage * NC];  // (Vr, Vi)
-    __shared__ double sVs[kStage * NC];   // Vr + Vi
-    __shared__ double4 sQ[QN];
-    __shared__ double2 sB2[kBase];        // base terms [(q * kStage + triangle) * 16 + row]
-    __shared__ double sB1[kBase];
+    __shared__ double2 sV[kStage * NC];         // (Vr, Vi) [triangle][column]
+    __shared__ double4 sQ[QN];                  // quadrature points [triangle][q]
+    __shared__ double2 sA[NOPS * kStage * 16];  // entries [(operator * kStage + triangle) * 16 + row]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * 16;
     const int64_t col0 = (int64_t)blockIdx.y * NC;
-    const int L0 = blockIdx.z * 4 * G;
-    const int l0 = L0 + wave * G;
+    const int L0 = blockIdx.z * NOPS;
 
-    Base<GEN, DECAY> basef;
-    basef.init(p, L0, 4 * G);
-    Ops<G, GEN, DECAY> ops;
-    ops.init(p, L0, wave);
-    // base phase coordinates: row t & 15, stage triangle t >> 4
+    Generator<NOPS, GEN, DECAY> gen;
+    gen.init(p, L0);
+    // generation phase coordinates: row t & 15, stage triangle t >> 4
     const int brow = tid & 15, btri = tid >> 4;
-    const double4 xa = p.colloc[row0 + brow];
+    const int64_t grow = row0 + brow;
+    const double4 xa = p.colloc[grow];
     // contract phase coordinates
     const int ci = lane & 15, ck = lane >> 4;
-    const int64_t arow = row0 + ci;
-    double2 self[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) self[g] = p.self[(int64_t)min(l0 + g, p.L - 1) * p.n_pad + arow];
 
     v4d P1[G][CB], P2[G][CB], P3[G][CB];
 #pragma unroll
@@ -212,32 +175,22 @@ __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
 
     // stage staging through registers, from the zero-padded probe copy (n_pad x m_pad)
     double2 rv[VPT];
-    double rs[VPT];
     double4 rq = make_double4(0.0, 0.0, 0.0, 0.0);
-    const double2 *vsrc2[VPT];
-    const double *vsrcs[VPT];
+    const double2 *vsrc[VPT];
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
         const int idx = tid + 256 * i;
-        const int64_t off = (int64_t)(idx / NC) * p.m_pad + col0 + idx % NC;
-        vsrc2[i] = p.Vp2 + off;
-        vsrcs[i] = p.Vps + off;
+        vsrc[i] = p.Vp2 + (int64_t)(idx / NC) * p.m_pad + col0 + idx % NC;
     }
     const int64_t vstride = (int64_t)kStage * p.m_pad;
     auto fetch = [&](int64_t st) {
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-            rv[i] = vsrc2[i][st * vstride];
-            rs[i] = vsrcs[i][st * vstride];
-        }
+        for (int i = 0; i < VPT; ++i) rv[i] = vsrc[i][st * vstride];
         if (tid < QN) rq = p.quad[st * kStage * kQuad + tid];
     };
     auto stash = [&]() {
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-            sV2[tid + 256 * i] = rv[i];
-            sVs[tid + 256 * i] = rs[i];
-        }
+        for (int i = 0; i < VPT; ++i) sV[tid + 256 * i] = rv[i];
         if (tid < QN) sQ[tid] = rq;
     };
 
@@ -247,20 +200,28 @@ __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
     __syncthreads();
     for (int64_t st = 0; st < nstages; ++st) {
         const int64_t b0 = st * kStage;
-        // base phase
+        // generation phase
         {
-            const bool diag = b0 + btri == row0 + brow;
+            const bool diag = b0 + btri == grow;
+            double r[kQuad], wr[kQuad];
 #pragma unroll
             for (int q = 0; q < kQuad; ++q) {
                 const double4 y = sQ[btri * kQuad + q];
                 const double dx = xa.x - y.x, dy = xa.y - y.y, dz = xa.z - y.z;
                 double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                r2 = diag ? 1.0 : r2;  // the diagonal is replaced by the self term
+                r2 = diag ? 1.0 : r2;  // the diagonal is replaced by the self term below
                 const double rinv = rsqrt(r2);
-                const double4 bt = basef.make(r2 * rinv, diag ? 0.0 : y.w * rinv, p);
-                sB2[(q * kStage + btri) * 16 + brow] = make_double2(bt.x, bt.y);
-                sB1[(q * kStage + btri) * 16 + brow] = bt.z;
+                r[q] = r2 * rinv;
+                wr[q] = y.w * rinv;
             }
+            double2 a[NOPS];
+            gen.entries(r, wr, p, a);
+            if (diag) {
+#pragma unroll
+                for (int j = 0; j < NOPS; ++j) a[j] = p.self[(int64_t)min(L0 + j, p.L - 1) * p.n_pad + grow];
+            }
+#pragma unroll
+            for (int j = 0; j < NOPS; ++j) sA[(j * kStage + btri) * 16 + brow] = a[j];
         }
         __syncthreads();
         if (st + 1 < nstages) fetch(st + 1);
@@ -268,32 +229,23 @@ __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
 #pragma unroll 1
         for (int ks = 0; ks < kStageSteps; ++ks) {
             const int tri = 4 * ks + ck;
-            double gr[G], gi[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) gr[g] = gi[g] = 0.0;
-#pragma unroll
-            for (int q = 0; q < kQuad; ++q) {
-                const int bi = (q * kStage + tri) * 16 + ci;
-                const double2 b2 = sB2[bi];
-                ops.term(make_double4(b2.x, b2.y, sB1[bi], 0.0), gr, gi);
-            }
-            const bool diag = b0 + tri == arow;
-            double gs[G];
+            double gr[G], gi[G], gs[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                gr[g] = diag ? self[g].x : gr[g];
-                gi[g] = diag ? self[g].y : gi[g];
-                gs[g] = gr[g] + gi[g];
+                const double2 a = sA[((wave * G + g) * kStage + tri) * 16 + ci];
+                gr[g] = a.x;
+                gi[g] = a.y;
+                gs[g] = a.x + a.y;
             }
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-                const double2 v = sV2[tri * NC + cb * 16 + ci];
-                const double vr_ = v.x, vi_ = v.y, vs_ = sVs[tri * NC + cb * 16 + ci];
+                const double2 v = sV[tri * NC + cb * 16 + ci];
+                const double vs = v.x + v.y;
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    P1[g][cb] = mfma(gr[g], vr_, P1[g][cb]);
-                    P2[g][cb] = mfma(gi[g], vi_, P2[g][cb]);
-                    P3[g][cb] = mfma(gs[g], vs_, P3[g][cb]);
+                    P1[g][cb] = mfma(gr[g], v.x, P1[g][cb]);
+                    P2[g][cb] = mfma(gi[g], v.y, P2[g][cb]);
+                    P3[g][cb] = mfma(gs[g], vs, P3[g][cb]);
                 }
             }
         }
@@ -306,6 +258,7 @@ __global__ __launch_bounds__(256, 1) void sweep_kernel(SweepArgs p) {
 
     // D layout of the 16x16x4 f64 MFMA: register i of a lane holds row (lane >> 4) + 4 i,
     // column lane & 15.
+    const int l0 = L0 + wave * G;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         if (l0 + g >= p.L) break;
@@ -340,17 +293,14 @@ hipError_t launch_gen(const SweepArgs &p, hipStream_t stream) {
     return launch_t<2, 4, GEN, DECAY>(p, stream);
 }
 
-// Zero-padded copy of the probe block: Vp2[b][c] = (Vr, Vi), Vps[b][c] = Vr + Vi for
-// b < n_pad, c < m_pad (zeros outside n x m).
+// Zero-padded copy of the probe block: Vp2[b][c] = V[b][c] for b < n_pad, c < m_pad
+// (zeros outside n x m).
 __global__ void prep_probe_kernel(const double2 *__restrict__ V, int64_t ldv, int64_t n, int64_t m,
-                                  int64_t n_pad, int64_t m_pad, double2 *__restrict__ Vp2,
-                                  double *__restrict__ Vps) {
+                                  int64_t n_pad, int64_t m_pad, double2 *__restrict__ Vp2) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_pad * m_pad) return;
     const int64_t b = idx / m_pad, c = idx % m_pad;
-    const double2 v = (b < n && c < m) ? V[b * ldv + c] : make_double2(0.0, 0.0);
-    Vp2[idx] = v;
-    Vps[idx] = v.x + v.y;
+    Vp2[idx] = (b < n && c < m) ? V[b * ldv + c] : make_double2(0.0, 0.0);
 }
 
 }  // namespace
@@ -363,10 +313,10 @@ int64_t sweep_m_pad(int64_t m) {
 }
 
 hipError_t launch_prep_probe(const double2 *V, int64_t ldv, int64_t n, int64_t m, int64_t n_pad, int64_t m_pad,
-                             double2 *Vp2, double *Vps, hipStream_t stream) {
+                             double2 *Vp2, hipStream_t stream) {
     const int bs = 256;
     const unsigned grid = (unsigned)((n_pad * m_pad + bs - 1) / bs);
-    hipLaunchKernelGGL(prep_probe_kernel, dim3(grid), dim3(bs), 0, stream, V, ldv, n, m, n_pad, m_pad, Vp2, Vps);
+    hipLaunchKernelGGL(prep_probe_kernel, dim3(grid), dim3(bs), 0, stream, V, ldv, n, m, n_pad, m_pad, Vp2);
     return hipGetLastError();
 }
 
