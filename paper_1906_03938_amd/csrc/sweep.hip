@@ -45,6 +45,15 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// 1/sqrt(a) for finite a > 0 (squared distances between distinct points, or 1 on the
+// diagonal): hardware estimate and one Newton step y (3 - a y^2) / 2, written as
+// y + y/2 (1 - a y^2) with fused multiply-adds.
+__device__ __forceinline__ double rsqrt_pos(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    const double e = fma(-a * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 // Entries of the NOPS operators L0 .. L0 + NOPS - 1 at one (row, triangle) off the
 // diagonal, from the distances r_q and weights w_q / r_q of the 7 quadrature points.
 template <int NOPS, Gen GEN, bool DECAY>
@@ -81,8 +90,9 @@ struct Generator<NOPS, Gen::Direct, DECAY> {
 
 // Term of operator L0 + j at one point: w/r exp(i c r) (i x)^(L0 + j) / (L0 + j)!, x = R r.
 // L0 is a multiple of 4, so (i x)^L0 = x^L0; the rest is y0 i^j x^j c_j with
-// y0 = w/r exp(i c r) x^L0 / L0! and the block-uniform c_j = L0! / (L0 + j)!.  The power
-// x^j is a running product, so no per-operator factor can be hoisted out and kept live.
+// y0 = w/r exp(i c r) x^L0 / L0! and the block-uniform c_j = L0! / (L0 + j)!, which with
+// i^j is applied once to the sum over the points.  The power x^j is a running product, so
+// no per-operator factor can be hoisted out of the point loop and kept live.
 template <int NOPS, bool DECAY>
 struct Generator<NOPS, Gen::Taylor, DECAY> {
     static constexpr int B = NOPS;  // L0 = z B
@@ -104,34 +114,50 @@ struct Generator<NOPS, Gen::Taylor, DECAY> {
         double gr[NOPS], gi[NOPS];
 #pragma unroll
         for (int j = 0; j < NOPS; ++j) gr[j] = gi[j] = 0.0;
+        // x^L0 / L0! = (x^B)^z / L0! for all points together: z is uniform over the block,
+        // so the loop over its bits does not diverge and costs two products per point and bit
+        double xq[kQuad], base[kQuad], pwq[kQuad];
 #pragma unroll
         for (int q = 0; q < kQuad; ++q) {
-            const double x = p.R * r[q];
-            // x^L0 / L0! = (x^B)^z / L0!: x^B by squaring (B = 8 or 12), then the at most
-            // 4 bits of the block-uniform z by selects (no branches)
-            const double x2 = x * x, x4 = x2 * x2;
-            double base = B == 8 ? x4 * x4 : x4 * x4 * x4, pw = inv_fact;
+            xq[q] = p.R * r[q];
+            const double x2 = xq[q] * xq[q], x4 = x2 * x2;
+            base[q] = B == 8 ? x4 * x4 : x4 * x4 * x4;
+            pwq[q] = inv_fact;
+        }
+        for (int zz = z; zz != 0; zz >>= 1) {
+            if (zz & 1) {
 #pragma unroll
-            for (int bit = 0; bit < 4; ++bit) {
-                pw = ((z >> bit) & 1) ? pw * base : pw;
-                base *= base;
+                for (int q = 0; q < kQuad; ++q) pwq[q] *= base[q];
             }
+#pragma unroll
+            for (int q = 0; q < kQuad; ++q) base[q] *= base[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+            const double x = xq[q], pw = pwq[q];
             const double e = (DECAY ? exp_cw(-p.c_im * r[q]) * wr[q] : wr[q]) * pw;
             double sn, cs;
             sincos_cw(p.c_re * r[q], sn, cs);
             const double yr = e * cs, yi = e * sn;
-            double xp = 1.0;
+            // sum_q y x^j (c_j and i^j are applied once per operator below)
+            double xp = x;
+            gr[0] += yr;
+            gi[0] += yi;
 #pragma unroll
-            for (int j = 0; j < NOPS; ++j) {
-                const double sc = j == 0 ? 1.0 : xp * cj[j];
-                // times i^j (compile-time rotation)
-                switch (j & 3) {
-                    case 0: gr[j] = fma(yr, sc, gr[j]); gi[j] = fma(yi, sc, gi[j]); break;
-                    case 1: gr[j] = fma(-yi, sc, gr[j]); gi[j] = fma(yr, sc, gi[j]); break;
-                    case 2: gr[j] = fma(-yr, sc, gr[j]); gi[j] = fma(-yi, sc, gi[j]); break;
-                    default: gr[j] = fma(yi, sc, gr[j]); gi[j] = fma(-yr, sc, gi[j]); break;
-                }
+            for (int j = 1; j < NOPS; ++j) {
+                gr[j] = fma(yr, xp, gr[j]);
+                gi[j] = fma(yi, xp, gi[j]);
                 xp *= x;
+            }
+        }
+#pragma unroll
+        for (int j = 1; j < NOPS; ++j) {
+            const double a = gr[j] * cj[j], b = gi[j] * cj[j];
+            switch (j & 3) {  // times i^j (compile-time rotation)
+                case 0: gr[j] = a; gi[j] = b; break;
+                case 1: gr[j] = -b; gi[j] = a; break;
+                case 2: gr[j] = -a; gi[j] = -b; break;
+                default: gr[j] = b; gi[j] = -a; break;
             }
         }
 #pragma unroll
@@ -199,7 +225,7 @@ __global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
                     const double dx = xa.x - y.x, dy = xa.y - y.y, dz = xa.z - y.z;
                     double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                     r2 = diag ? 1.0 : r2;  // the diagonal is replaced by the self term below
-                    const double rinv = rsqrt(r2);
+                    const double rinv = rsqrt_pos(r2);
                     r[q] = r2 * rinv;
                     wr[q] = y.w * rinv;
                 }
