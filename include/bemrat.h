@@ -60,12 +60,20 @@ typedef enum {
  *     generates L coefficient operators, truncated where the remainder bound falls below
  *     1e-14 relative to the smallest kernel value at the nodes, and recombines them per
  *     node or weight set.
- *   BEM_FORM_AUTO: EXPAND when it needs fewer operators than DIRECT, else DIRECT.
+ *   BEM_FORM_CHEB: for node sets on the real axis only: T(alpha + beta xi) =
+ *     sum_l eps_l i^l T_l(xi) B_l with alpha, beta the centre and half-width of the nodes
+ *     and B_l the operators of the Chebyshev (Jacobi-Anger) expansion of exp(i kappa r),
+ *     entries w/r exp(i alpha r) J_l(beta r); truncated where the tail bound falls below
+ *     1e-14 (|T_l| <= 1 on the interval, so recombination does not amplify errors).
+ *     Complex nodes return BEM_EUNSUPPORTED.
+ *   BEM_FORM_AUTO: the form with the fewest generated operators among those that apply
+ *     (CHEB before EXPAND before DIRECT on ties).
  * Bits 4..7 select the arithmetic; only 0 (FP64 throughout) is built, any other value
  * returns BEM_EUNSUPPORTED. */
 #define BEM_FORM_AUTO 0u
 #define BEM_FORM_DIRECT 1u
 #define BEM_FORM_EXPAND 2u
+#define BEM_FORM_CHEB 3u
 #define BEM_FORM_MASK 3u
 #define BEM_PREC_MASK 0xF0u
 
@@ -163,8 +171,9 @@ bem_status rr_project(bem_mesh_t mesh, const double *z, int64_t N, const double 
 
 /* ---------------------------------------------------------------- diagnostics --- */
 
-/* Form the last sweep call on this handle used: BEM_FORM_DIRECT or BEM_FORM_EXPAND, and
- * the number of generated operators (nodes for DIRECT, expansion terms for EXPAND).
+/* Form the last sweep call on this handle used: BEM_FORM_DIRECT, BEM_FORM_EXPAND or
+ * BEM_FORM_CHEB, and the number of generated operators (nodes for DIRECT, expansion terms
+ * for EXPAND and CHEB).
  * Either output may be NULL.  Returns BEM_EINVAL for a NULL handle. */
 bem_status bem_last_form(bem_mesh_t mesh, uint32_t *form, int64_t *operators);
 

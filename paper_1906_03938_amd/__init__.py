@@ -7,6 +7,7 @@ orchestrates sweeps into eigenvalues.
 """
 from ._lib import (  # noqa: F401
     FORM_AUTO,
+    FORM_CHEB,
     FORM_DIRECT,
     FORM_EXPAND,
     BemError,

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbemrat.so")
 
 BEM_OK, BEM_EINVAL, BEM_EMESH, BEM_ENOMEM, BEM_EDEVICE, BEM_EUNSUPPORTED = range(6)
-FORM_AUTO, FORM_DIRECT, FORM_EXPAND = 0, 1, 2
+FORM_AUTO, FORM_DIRECT, FORM_EXPAND, FORM_CHEB = 0, 1, 2, 3
 STATUS_NAMES = {0: "BEM_OK", 1: "BEM_EINVAL", 2: "BEM_EMESH", 3: "BEM_ENOMEM", 4: "BEM_EDEVICE",
                 5: "BEM_EUNSUPPORTED"}
 

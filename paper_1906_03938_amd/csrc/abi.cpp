@@ -150,7 +150,6 @@ bem_status check_block(const void *p, int64_t m, int64_t ld, const char *name) {
 bem_status check_flags(uint32_t flags) {
     if (flags & BEM_PREC_MASK) return fail(BEM_EUNSUPPORTED, "only FP64 arithmetic is built");
     if (flags & ~(BEM_FORM_MASK | BEM_PREC_MASK)) return fail(BEM_EINVAL, "unknown flag bits");
-    if ((flags & BEM_FORM_MASK) == 3u) return fail(BEM_EINVAL, "invalid form");
     return BEM_OK;
 }
 
@@ -242,8 +241,10 @@ bem_status upload(bem_mesh *h, const Params &p, hipStream_t s) {
 struct Plan {
     bemrat::Gen gen = bemrat::Gen::Direct;
     int L = 0;
-    cplx c = 0.0;
-    double R = 0.0;
+    cplx c = 0.0;             // Taylor: centre; Cheb: alpha (real)
+    double R = 0.0;           // Taylor: radius; Cheb: beta
+    int miller_M = 0;         // Cheb: start index of the Bessel recurrence
+    bool unsupported = false; // the requested form does not apply to these nodes
     std::vector<cplx> kappa;  // Direct: L wavenumbers
     std::vector<cplx> Cf;     // N x L: T(z_j) = sum_l Cf[j][l] T_l
 };
@@ -259,6 +260,22 @@ int taylor_length(double x, double h, int block) {
     for (int L = 1; L < bemrat::kMaxTaylor; ++L) {
         term *= x / L;
         if (L > x && term / (1.0 - x / (L + 1)) <= target) {
+            const int r = (L + block - 1) / block * block;
+            return std::min(r, bemrat::kMaxTaylor - 1);
+        }
+    }
+    return bemrat::kMaxTaylor;
+}
+
+// Chebyshev (Jacobi-Anger) length for real nodes: smallest L > x/2 with
+// 2 (x/2)^L / L! / (1 - (x/2)^2 / (L + 1)) <= 1e-14, x = beta diam (a bound on
+// sum_{l >= L} |eps_l J_l(x)|, and |T_l| <= 1 on the interval), rounded up to whole blocks.
+int cheb_length(double x, int block) {
+    double term = 2.0;
+    for (int L = 1; L < bemrat::kMaxTaylor; ++L) {
+        term *= 0.5 * x / L;
+        const double q = 0.25 * x * x / (L + 1);
+        if (L > 0.5 * x && q < 1.0 && term / (1.0 - q) <= 1e-14) {
             const int r = (L + block - 1) / block * block;
             return std::min(r, bemrat::kMaxTaylor - 1);
         }
@@ -284,8 +301,44 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
     double hmax = 0.0;
     if (R > 0.0)
         for (auto &v : zs) hmax = std::max(hmax, (v - c).imag() / R);
-    int L = R > 0.0 ? taylor_length(R * h->diameter, hmax, bemrat::sweep_ops_per_block(m)) : bemrat::kMaxTaylor;
+    const int block = bemrat::sweep_ops_per_block(m);
+    int L = R > 0.0 ? taylor_length(R * h->diameter, hmax, block) : bemrat::kMaxTaylor;
     const bool expand_ok = R > 0.0 && L < bemrat::kMaxTaylor;
+    // Chebyshev form: every node real (then c is real and R is the half-width)
+    const bool real_nodes = imin == 0.0 && imax == 0.0;
+    const int Lc = real_nodes && R > 0.0 ? cheb_length(R * h->diameter, block) : bemrat::kMaxTaylor;
+    const bool cheb_ok = real_nodes && R > 0.0 && Lc + 10 < bemrat::kMaxTaylor;
+    if (form == BEM_FORM_CHEB && !cheb_ok) {
+        plan.unsupported = true;
+        return plan;
+    }
+    bool cheb = form == BEM_FORM_CHEB;
+    if (form == BEM_FORM_AUTO && cheb_ok && Lc < N && (!expand_ok || Lc < L)) cheb = true;
+    if (cheb) {
+        plan.gen = bemrat::Gen::Cheb;
+        plan.L = Lc;
+        plan.c = c;
+        plan.R = R;
+        plan.miller_M = (Lc + 10 + 3) / 4 * 4;
+        plan.Cf.resize((size_t)N * Lc);
+        const cplx ipow[4] = {cplx(1, 0), cplx(0, 1), cplx(-1, 0), cplx(0, -1)};
+        for (int64_t j = 0; j < N; ++j) {
+            const double xi = std::max(-1.0, std::min(1.0, (zs[j].real() - c.real()) / R));
+            double tp = 1.0, tc = xi;  // T_0, T_1
+            for (int l = 0; l < Lc; ++l) {
+                const double tl = l == 0 ? 1.0 : (l == 1 ? xi : 0.0);
+                double T = tl;
+                if (l >= 2) {
+                    const double tn = 2.0 * xi * tc - tp;
+                    tp = tc;
+                    tc = tn;
+                    T = tn;
+                }
+                plan.Cf[j * Lc + l] = (l == 0 ? 1.0 : 2.0) * ipow[l & 3] * T;
+            }
+        }
+        return plan;
+    }
     const bool expand = form == BEM_FORM_EXPAND ? expand_ok : (form == BEM_FORM_AUTO && expand_ok && L < N);
     if (!expand) {
         plan.gen = bemrat::Gen::Direct;
@@ -324,6 +377,29 @@ bem_status build_self(bem_mesh *h, const Plan &plan, Params &prm, size_t &off_se
         }
         off_self_kappa = prm.add(k.data(), k.size());
         K = 0;
+        return BEM_OK;
+    }
+    if (plan.gen == bemrat::Gen::Cheb) {
+        // Chebyshev coefficients of T_aa(alpha + beta xi) from K first-kind points (DCT-II),
+        // divided by eps_l i^l (which the recombination applies):
+        // S_l = (1 / (K i^l)) sum_k cos(pi l (k + 1/2) / K) T_aa(kappa_k)
+        K = plan.L < 48 ? 64 : 128;
+        const double pi = 3.14159265358979323846;
+        const cplx ipow_inv[4] = {cplx(1, 0), cplx(0, -1), cplx(-1, 0), cplx(0, 1)};
+        std::vector<double> k(2 * K), F(2 * (size_t)K * plan.L);
+        for (int q = 0; q < K; ++q) {
+            const double th = pi * (q + 0.5) / K;
+            k[2 * q] = plan.c.real() + plan.R * std::cos(th);
+            k[2 * q + 1] = 0.0;
+            for (int l = 0; l < plan.L; ++l) {
+                const cplx f = ipow_inv[l & 3] * (std::cos(th * l) / K);
+                F[2 * ((size_t)q * plan.L + l)] = f.real();
+                F[2 * ((size_t)q * plan.L + l) + 1] = f.imag();
+            }
+        }
+        off_self_kappa = prm.add(k.data(), k.size());
+        off_dft = prm.add(F.data(), F.size());
+        HIP_TRY(h->aux.ensure(sizeof(double2) * (size_t)K * n_pad), "self-term samples");
         return BEM_OK;
     }
     // Expansion: sample T_aa on K points of the circle |kappa - c| = R and take the
@@ -398,13 +474,16 @@ bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, 
     for (const cplx &k : plan.kappa) a.decay |= k.imag() != 0.0;
     a.inv_fact = pbase + off_tables;
     a.inv_int = pbase + off_tables + bemrat::kMaxTaylor;
+    a.miller_M = plan.miller_M;
     if (h->timing) HIP_TRY(hipEventRecord(h->ev0, s), "event record");
     HIP_TRY(bemrat::launch_sweep(plan.gen, a, s), "sweep kernel");
     if (h->timing) {
         HIP_TRY(hipEventRecord(h->ev1, s), "event record");
         h->timed = true;
     }
-    h->last_form = plan.gen == bemrat::Gen::Direct ? BEM_FORM_DIRECT : BEM_FORM_EXPAND;
+    h->last_form = plan.gen == bemrat::Gen::Direct ? BEM_FORM_DIRECT
+                   : plan.gen == bemrat::Gen::Taylor ? BEM_FORM_EXPAND
+                                                     : BEM_FORM_CHEB;
     h->last_ops = plan.L;
     return BEM_OK;
 }
@@ -659,7 +738,7 @@ bem_status bem_assemble_apply(bem_mesh_t h, const double *kappa, int64_t nk, con
     DeviceGuard guard(h->device);
     bem_status st = check_flags(flags);
     if (st != BEM_OK) return st;
-    if ((flags & BEM_FORM_MASK) == BEM_FORM_EXPAND)
+    if ((flags & BEM_FORM_MASK) == BEM_FORM_EXPAND || (flags & BEM_FORM_MASK) == BEM_FORM_CHEB)
         return fail(BEM_EUNSUPPORTED, "bem_assemble_apply evaluates each wavenumber directly");
     if ((st = check_kappas(h, kappa, nk, "kappa")) != BEM_OK) return st;
     if (nk > 65535) return fail(BEM_EINVAL, "at most 65535 wavenumbers per call");
@@ -689,6 +768,7 @@ bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const doubl
     if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
     if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
     Plan plan = make_plan(h, z, N, m, flags);
+    if (plan.unsupported) return fail(BEM_EUNSUPPORTED, "the Chebyshev form needs real nodes in a bounded interval");
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
@@ -734,6 +814,7 @@ bem_status cheb_moments(bem_mesh_t h, double a, double b, int64_t N, int64_t L, 
         z[2 * k + 1] = 0.0;
     }
     Plan plan = make_plan(h, z.data(), N, m, flags);
+    if (plan.unsupported) return fail(BEM_EUNSUPPORTED, "the Chebyshev form needs real nodes in a bounded interval");
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
@@ -778,6 +859,7 @@ bem_status rr_project(bem_mesh_t h, const double *z, int64_t N, const double *U,
         if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
     }
     Plan plan = make_plan(h, z, N, m, flags);
+    if (plan.unsupported) return fail(BEM_EUNSUPPORTED, "the Chebyshev form needs real nodes in a bounded interval");
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;

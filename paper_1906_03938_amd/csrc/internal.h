@@ -40,10 +40,12 @@ struct SweepArgs {
     // Direct: wavenumbers of the L nodes
     const double2 *kappa;
     // Taylor: exp(i (c + R t) r) = exp(i c r) sum_l (i R r t)^l / l!
-    // Cheb:   exp(i (alpha + beta xi) r) = exp(i alpha r) sum_l eps_l i^l J_l(beta r) T_l(xi)
+    // Cheb:   exp(i (alpha + beta xi) r) = exp(i alpha r) sum_l eps_l i^l J_l(beta r) T_l(xi),
+    //         alpha in c_re, beta in R
     double c_re, c_im, R;
     const double *inv_fact;  // 1/l!, l < kMaxTaylor
     const double *inv_int;   // 1/l, l < kMaxTaylor (entry 0 unused)
+    int miller_M;            // Cheb: start index of the Bessel recurrence (multiple of 4)
 };
 
 // Launchers (asynchronous on `stream`; return hipSuccess or the launch error).

@@ -165,6 +165,102 @@ struct Generator<NOPS, Gen::Taylor, DECAY> {
     }
 };
 
+// Chebyshev (Jacobi-Anger) form for real nodes kappa = alpha + beta xi, xi in [-1, 1]:
+// exp(i kappa r) = exp(i alpha r) sum_l eps_l i^l J_l(beta r) T_l(xi), so with the factors
+// eps_l i^l left to the host's recombination, operator l has entries
+// sum_q w_q / r_q exp(i alpha r_q) J_l(beta r_q).  The J_l come from Miller's backward
+// recurrence J_{l-1} = (2 l / x) J_l - J_{l+1}, started at J_{M+1} = 0, J_M = 2^-1000 (M a
+// multiple of 4 above the block, chosen by the host) and normalised by
+// J_0 + 2 sum_k J_{2k} = 1.  The recurrence runs four steps per trip; after each trip the
+// values are scaled down by 2^-500 if they exceed 2^500 (they grow like M! (2/x)^M for
+// small x), and a factor f carries that scaling to the block's values stored earlier.
+template <int NOPS, bool DECAY>
+struct Generator<NOPS, Gen::Cheb, DECAY> {
+    int L0, M;
+    __device__ void init(const SweepArgs &p, int L0_) {
+        L0 = L0_;
+        M = p.miller_M;
+    }
+    // four steps from index l (a multiple of 4) down to l - 4; S gains 2 J at the even
+    // indices l - 2 and l - 4
+    __device__ __forceinline__ static void steps4(int l, double tx, double &jp, double &jc, double &S) {
+        double t = l * tx;
+        double jn = fma(t, jc, -jp);  // J_{l-1}
+        jp = jc;
+        jc = jn;
+        t -= tx;
+        jn = fma(t, jc, -jp);         // J_{l-2}
+        jp = jc;
+        jc = jn;
+        S = fma(2.0, jc, S);
+        t -= tx;
+        jn = fma(t, jc, -jp);         // J_{l-3}
+        jp = jc;
+        jc = jn;
+        t -= tx;
+        jn = fma(t, jc, -jp);         // J_{l-4}
+        jp = jc;
+        jc = jn;
+        S = fma(2.0, jc, S);
+    }
+    __device__ __forceinline__ static double rescale(double &jp, double &jc, double &S) {
+        const double sc = fabs(jc) > 0x1p500 ? 0x1p-500 : 1.0;
+        jp *= sc;
+        jc *= sc;
+        S *= sc;
+        return sc;
+    }
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &p, double2 (&out)[NOPS]) const {
+        double gr[NOPS], gi[NOPS];
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) gr[j] = gi[j] = 0.0;
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+            const double x = p.R * r[q];
+            // 2 / x by the reciprocal estimate and two Newton steps (x > 0)
+            double tx = __builtin_amdgcn_rcp(x);
+            tx = fma(fma(-x, tx, 1.0), tx, tx);
+            tx = 2.0 * fma(fma(-x, tx, 1.0), tx, tx);
+            double sn, cs;
+            sincos_cw(p.c_re * r[q], sn, cs);
+            const double yr = wr[q] * cs, yi = wr[q] * sn;
+            double jp = 0.0, jc = 0x1p-1000, S = 2.0 * jc;  // J_{M+1}, J_M (M even, > 0)
+            for (int l = M; l > L0 + NOPS; l -= 4) {
+                steps4(l, tx, jp, jc, S);
+                rescale(jp, jc, S);
+            }
+            // the block's indices L0 + NOPS - 1 .. L0 (jc is J_{L0+NOPS} here)
+            double jb[NOPS];
+            double t = (L0 + NOPS) * tx;
+#pragma unroll
+            for (int j = NOPS - 1; j >= 0; --j) {
+                const double jn = fma(t, jc, -jp);
+                jp = jc;
+                jc = jn;
+                t -= tx;
+                jb[j] = jc;
+                if ((j & 1) == 0) S = fma(2.0, jc, S);  // L0 is even
+            }
+            double f = 1.0;
+            for (int l = L0; l > 0; l -= 4) {
+                steps4(l, tx, jp, jc, S);
+                f *= rescale(jp, jc, S);
+            }
+            S -= jc;  // J_0 was counted twice
+            const double nrm = f / S;
+#pragma unroll
+            for (int j = 0; j < NOPS; ++j) {
+                const double v = jb[j] * nrm;
+                gr[j] = fma(yr, v, gr[j]);
+                gi[j] = fma(yi, v, gi[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) out[j] = make_double2(gr[j], gi[j]);
+    }
+};
+
 // Producer / consumer form: waves 0-3 generate the entries of stage s + 1 while waves
 // 4-7 contract stage s, through double-buffered LDS; every SIMD then runs one wave of
 // each kind, so the vector work of one fills the gaps of the other's MFMA stream on the
@@ -363,6 +459,8 @@ hipError_t launch_sweep(Gen gen, const SweepArgs &args, hipStream_t stream) {
             return decay ? launch_gen<Gen::Direct, true>(args, stream) : launch_gen<Gen::Direct, false>(args, stream);
         case Gen::Taylor:
             return decay ? launch_gen<Gen::Taylor, true>(args, stream) : launch_gen<Gen::Taylor, false>(args, stream);
+        case Gen::Cheb:
+            return decay ? hipErrorInvalidValue : launch_gen<Gen::Cheb, false>(args, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -123,7 +123,7 @@ def test_rr_project_matches_oracle(sphere3, torch, bem, form):
         assert _rel(Mg[p], Mo[p]) <= TOL
 
 
-@pytest.mark.parametrize("form", ["direct", "expand"])
+@pytest.mark.parametrize("form", ["direct", "expand", "cheb"])
 def test_real_nodes_match_oracle(sphere3, torch, bem, form):
     """The calls the interval driver makes: projections and weighted sums on the real
     Chebyshev nodes of [2.5, 5] (the expansion then has no decay factor)."""
@@ -134,7 +134,7 @@ def test_real_nodes_match_oracle(sphere3, torch, bem, form):
     U = np.ascontiguousarray(U)
     kappa, coef = M.cheb_nodes(2.5, 5.0, 32)
     W = np.ascontiguousarray(coef[:3].T.astype(np.complex128))
-    f = bem.FORM_DIRECT if form == "direct" else bem.FORM_EXPAND
+    f = {"direct": bem.FORM_DIRECT, "expand": bem.FORM_EXPAND, "cheb": bem.FORM_CHEB}[form]
     P, Mg = mesh.rr_project(kappa, _dev(torch, U), W=W, form=f)
     assert mesh.last_form()[0] == f
     P = P.cpu().numpy()
@@ -147,14 +147,14 @@ def test_real_nodes_match_oracle(sphere3, torch, bem, form):
         assert _rel(Mg[p], Mo[p]) <= TOL, (form, p, _rel(Mg[p], Mo[p]))
 
 
-@pytest.mark.parametrize("form", ["direct", "expand"])
+@pytest.mark.parametrize("form", ["direct", "expand", "cheb"])
 def test_cheb_moments_match_oracle(sphere3, torch, bem, form):
     from oracle import method as M
 
     mesh, op, _, _ = sphere3
     V = synth.probe_block(op.n, 16, seed=3)
     a, b, N, L = 2.5, 5.5, 24, 20
-    f = bem.FORM_DIRECT if form == "direct" else bem.FORM_EXPAND
+    f = {"direct": bem.FORM_DIRECT, "expand": bem.FORM_EXPAND, "cheb": bem.FORM_CHEB}[form]
     C = mesh.cheb_moments(a, b, N, L, _dev(torch, V), form=f).cpu().numpy()
     assert mesh.last_form()[0] == f
     Co = M.cheb_moments(op, a, b, N, L, V)
@@ -206,6 +206,14 @@ def test_error_paths(torch, bem):
         with pytest.raises(bem.BemError) as e:
             mesh.cheb_moments(2.0, 8.0, 8, 9, V)
         assert e.value.status == _lib.BEM_EINVAL
+        # the Chebyshev form needs real nodes; assemble_apply takes no expansion form
+        z, _, W = bem.contour_nodes(4.0, 1.0, 8, P=1)
+        with pytest.raises(bem.BemError) as e:
+            mesh.contour_moments(z, W, V, form=bem.FORM_CHEB)
+        assert e.value.status == _lib.BEM_EUNSUPPORTED
+        with pytest.raises(bem.BemError) as e:
+            mesh.assemble_apply([4.0], V, form=bem.FORM_CHEB)
+        assert e.value.status == _lib.BEM_EUNSUPPORTED
         # a host pointer passed as the probe block is rejected, nothing is launched
         import ctypes
 
