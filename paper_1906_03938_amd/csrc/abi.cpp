@@ -270,16 +270,20 @@ int taylor_length(double x, double h, int block) {
 // Chebyshev (Jacobi-Anger) length for real nodes: smallest L > x/2 with
 // 2 (x/2)^L / L! / (1 - (x/2)^2 / (L + 1)) <= 1e-14, x = beta diam (a bound on
 // sum_{l >= L} |eps_l J_l(x)|, and |T_l| <= 1 on the interval), rounded up to whole blocks.
-int cheb_length(double x, int block) {
+// Also returns the unrounded length in *need (the Bessel recurrence starts 10 above it,
+// which is accurate to a few units of 1e-16 for these x).
+int cheb_length(double x, int block, int *need) {
     double term = 2.0;
     for (int L = 1; L < bemrat::kMaxTaylor; ++L) {
         term *= 0.5 * x / L;
         const double q = 0.25 * x * x / (L + 1);
         if (L > 0.5 * x && q < 1.0 && term / (1.0 - q) <= 1e-14) {
+            *need = L;
             const int r = (L + block - 1) / block * block;
             return std::min(r, bemrat::kMaxTaylor - 1);
         }
     }
+    *need = bemrat::kMaxTaylor;
     return bemrat::kMaxTaylor;
 }
 
@@ -306,20 +310,23 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
     const bool expand_ok = R > 0.0 && L < bemrat::kMaxTaylor;
     // Chebyshev form: every node real (then c is real and R is the half-width)
     const bool real_nodes = imin == 0.0 && imax == 0.0;
-    const int Lc = real_nodes && R > 0.0 ? cheb_length(R * h->diameter, block) : bemrat::kMaxTaylor;
+    int need = 0;
+    const int Lc = real_nodes && R > 0.0 ? cheb_length(R * h->diameter, block, &need) : bemrat::kMaxTaylor;
     const bool cheb_ok = real_nodes && R > 0.0 && Lc + 10 < bemrat::kMaxTaylor;
     if (form == BEM_FORM_CHEB && !cheb_ok) {
         plan.unsupported = true;
         return plan;
     }
-    bool cheb = form == BEM_FORM_CHEB;
-    if (form == BEM_FORM_AUTO && cheb_ok && Lc < N && (!expand_ok || Lc < L)) cheb = true;
-    if (cheb) {
+    // FP64: the Chebyshev form only on request (each block reruns the whole Bessel
+    // recurrence, so it generates fewer operators than EXPAND but costs more at these sizes)
+    if (form == BEM_FORM_CHEB) {
         plan.gen = bemrat::Gen::Cheb;
         plan.L = Lc;
         plan.c = c;
         plan.R = R;
-        plan.miller_M = (Lc + 10 + 3) / 4 * 4;
+        // a multiple of 8 (the recurrence runs 8 steps per trip) at least need + 10 and at
+        // least the block's top index
+        plan.miller_M = std::max((need + 10 + 7) / 8 * 8, Lc);
         plan.Cf.resize((size_t)N * Lc);
         const cplx ipow[4] = {cplx(1, 0), cplx(0, 1), cplx(-1, 0), cplx(0, -1)};
         for (int64_t j = 0; j < N; ++j) {

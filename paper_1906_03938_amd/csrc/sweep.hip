@@ -170,10 +170,11 @@ struct Generator<NOPS, Gen::Taylor, DECAY> {
 // eps_l i^l left to the host's recombination, operator l has entries
 // sum_q w_q / r_q exp(i alpha r_q) J_l(beta r_q).  The J_l come from Miller's backward
 // recurrence J_{l-1} = (2 l / x) J_l - J_{l+1}, started at J_{M+1} = 0, J_M = 2^-1000 (M a
-// multiple of 4 above the block, chosen by the host) and normalised by
-// J_0 + 2 sum_k J_{2k} = 1.  The recurrence runs four steps per trip; after each trip the
-// values are scaled down by 2^-500 if they exceed 2^500 (they grow like M! (2/x)^M for
-// small x), and a factor f carries that scaling to the block's values stored earlier.
+// multiple of 8, at least the block's top index, chosen by the host) and normalised by
+// J_0 + 2 sum_k J_{2k} = 1.  The recurrence runs eight steps per trip; after each trip the
+// values are scaled down by 2^-400 if they exceed 2^400 (they grow like M! (2/x)^M for
+// small x; eight steps grow them by less than 2^250 for x >= 1e-7 and M <= 96), and a
+// factor f carries that scaling to the block's values stored earlier.
 template <int NOPS, bool DECAY>
 struct Generator<NOPS, Gen::Cheb, DECAY> {
     int L0, M;
@@ -181,30 +182,20 @@ struct Generator<NOPS, Gen::Cheb, DECAY> {
         L0 = L0_;
         M = p.miller_M;
     }
-    // four steps from index l (a multiple of 4) down to l - 4; S gains 2 J at the even
-    // indices l - 2 and l - 4
-    __device__ __forceinline__ static void steps4(int l, double tx, double &jp, double &jc, double &S) {
+    // eight steps from index l (a multiple of 8) down to l - 8; S gains 2 J at each even index
+    __device__ __forceinline__ static void steps8(int l, double tx, double &jp, double &jc, double &S) {
         double t = l * tx;
-        double jn = fma(t, jc, -jp);  // J_{l-1}
-        jp = jc;
-        jc = jn;
-        t -= tx;
-        jn = fma(t, jc, -jp);         // J_{l-2}
-        jp = jc;
-        jc = jn;
-        S = fma(2.0, jc, S);
-        t -= tx;
-        jn = fma(t, jc, -jp);         // J_{l-3}
-        jp = jc;
-        jc = jn;
-        t -= tx;
-        jn = fma(t, jc, -jp);         // J_{l-4}
-        jp = jc;
-        jc = jn;
-        S = fma(2.0, jc, S);
+#pragma unroll
+        for (int i = 1; i <= 8; ++i) {
+            const double jn = fma(t, jc, -jp);  // J_{l-i}
+            jp = jc;
+            jc = jn;
+            t -= tx;
+            if ((i & 1) == 0) S = fma(2.0, jc, S);
+        }
     }
     __device__ __forceinline__ static double rescale(double &jp, double &jc, double &S) {
-        const double sc = fabs(jc) > 0x1p500 ? 0x1p-500 : 1.0;
+        const double sc = fabs(jc) > 0x1p400 ? 0x1p-400 : 1.0;
         jp *= sc;
         jc *= sc;
         S *= sc;
@@ -226,8 +217,8 @@ struct Generator<NOPS, Gen::Cheb, DECAY> {
             sincos_cw(p.c_re * r[q], sn, cs);
             const double yr = wr[q] * cs, yi = wr[q] * sn;
             double jp = 0.0, jc = 0x1p-1000, S = 2.0 * jc;  // J_{M+1}, J_M (M even, > 0)
-            for (int l = M; l > L0 + NOPS; l -= 4) {
-                steps4(l, tx, jp, jc, S);
+            for (int l = M; l > L0 + NOPS; l -= 8) {
+                steps8(l, tx, jp, jc, S);
                 rescale(jp, jc, S);
             }
             // the block's indices L0 + NOPS - 1 .. L0 (jc is J_{L0+NOPS} here)
@@ -243,8 +234,8 @@ struct Generator<NOPS, Gen::Cheb, DECAY> {
                 if ((j & 1) == 0) S = fma(2.0, jc, S);  // L0 is even
             }
             double f = 1.0;
-            for (int l = L0; l > 0; l -= 4) {
-                steps4(l, tx, jp, jc, S);
+            for (int l = L0; l > 0; l -= 8) {
+                steps8(l, tx, jp, jc, S);
                 f *= rescale(jp, jc, S);
             }
             S -= jc;  // J_0 was counted twice
