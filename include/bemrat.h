@@ -68,14 +68,27 @@ typedef enum {
  *     Complex nodes return BEM_EUNSUPPORTED.
  *   BEM_FORM_AUTO: the form with the fewest generated operators among those that apply
  *     (CHEB before EXPAND before DIRECT on ties).
- * Bits 4..7 select the arithmetic; only 0 (FP64 throughout) is built, any other value
- * returns BEM_EUNSUPPORTED. */
+ * Bits 4..7 select the arithmetic:
+ *   BEM_PREC_F64 (0): FP64 throughout.
+ *   BEM_PREC_F32, BEM_PREC_BF16, BEM_PREC_F16: operator entries generated in FP64, scaled
+ *     and rounded to FP32 / BF16 / FP16 together with the probe block, contracted on the
+ *     matrix cores with FP32 accumulation; the self terms (diagonal) are added in FP64
+ *     afterwards; expansion lengths follow the looser tolerance of the type.  With these,
+ *     BEM_FORM_AUTO takes CHEB for real node sets and DIRECT otherwise (EXPAND amplifies
+ *     rounding errors by up to e^{2 R diam} on complex nodes and is used only on request).
+ *     Results are accurate to about the unit roundoff of the type (see the tests for
+ *     the tolerances), not to FP64.
+ *   Other values return BEM_EUNSUPPORTED. */
 #define BEM_FORM_AUTO 0u
 #define BEM_FORM_DIRECT 1u
 #define BEM_FORM_EXPAND 2u
 #define BEM_FORM_CHEB 3u
 #define BEM_FORM_MASK 3u
 #define BEM_PREC_MASK 0xF0u
+#define BEM_PREC_F64 0x00u
+#define BEM_PREC_F32 0x10u
+#define BEM_PREC_BF16 0x20u
+#define BEM_PREC_F16 0x30u
 
 /* ---------------------------------------------------------------- mesh handle --- */
 

@@ -10,6 +10,10 @@ from ._lib import (  # noqa: F401
     FORM_CHEB,
     FORM_DIRECT,
     FORM_EXPAND,
+    PREC_BF16,
+    PREC_F16,
+    PREC_F32,
+    PREC_F64,
     BemError,
     Mesh,
     cheb_nodes,

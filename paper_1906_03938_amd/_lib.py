@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbemrat.so")
 
 BEM_OK, BEM_EINVAL, BEM_EMESH, BEM_ENOMEM, BEM_EDEVICE, BEM_EUNSUPPORTED = range(6)
 FORM_AUTO, FORM_DIRECT, FORM_EXPAND, FORM_CHEB = 0, 1, 2, 3
+PREC_F64, PREC_F32, PREC_BF16, PREC_F16 = 0x00, 0x10, 0x20, 0x30
 STATUS_NAMES = {0: "BEM_OK", 1: "BEM_EINVAL", 2: "BEM_EMESH", 3: "BEM_ENOMEM", 4: "BEM_EDEVICE",
                 5: "BEM_EUNSUPPORTED"}
 

@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbemrat.so")
-SOURCES = ["abi.cpp", "mesh.hip", "sweep.hip", "combine.hip"]
-HEADERS = ["internal.h"]
+SOURCES = ["abi.cpp", "mesh.hip", "sweep.hip", "sweep_lp.hip", "combine.hip"]
+HEADERS = ["internal.h", "generators.h", "devmath.h"]
 
 
 def command(out: str = LIB, arch: str = "gfx950", extra=()):

@@ -100,6 +100,7 @@ struct bem_mesh {
     int device = 0;
     DeviceMesh dm;
     double diameter = 0.0;  // upper bound on every distance in the operator
+    double mean_area = 0.0; // mean triangle area (sets the scale of reduced-precision entries)
     Buffer geom, gl, self, aux, Z, params, partial, probe;
     Staging staging;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -148,8 +149,8 @@ bem_status check_block(const void *p, int64_t m, int64_t ld, const char *name) {
 }
 
 bem_status check_flags(uint32_t flags) {
-    if (flags & BEM_PREC_MASK) return fail(BEM_EUNSUPPORTED, "only FP64 arithmetic is built");
     if (flags & ~(BEM_FORM_MASK | BEM_PREC_MASK)) return fail(BEM_EINVAL, "unknown flag bits");
+    if ((flags & BEM_PREC_MASK) > BEM_PREC_F16) return fail(BEM_EUNSUPPORTED, "unknown arithmetic");
     return BEM_OK;
 }
 
@@ -237,6 +238,19 @@ bem_status upload(bem_mesh *h, const Params &p, hipStream_t s) {
     return BEM_OK;
 }
 
+bemrat::Prec prec_of(uint32_t flags) { return static_cast<bemrat::Prec>((flags & BEM_PREC_MASK) >> 4); }
+
+// Truncation tolerance of the expansion forms: 1e-14 in FP64; below the unit roundoff of
+// the contraction type otherwise (FP32 6e-8, FP16 4.9e-4, BF16 3.9e-3).
+double trunc_tol(bemrat::Prec p) {
+    switch (p) {
+        case bemrat::Prec::F32: return 1e-9;
+        case bemrat::Prec::F16: return 1e-6;
+        case bemrat::Prec::BF16: return 1e-5;
+        default: return 1e-14;
+    }
+}
+
 // The generated operators of one sweep and how each node combines them.
 struct Plan {
     bemrat::Gen gen = bemrat::Gen::Direct;
@@ -245,6 +259,7 @@ struct Plan {
     double R = 0.0;           // Taylor: radius; Cheb: beta
     int miller_M = 0;         // Cheb: start index of the Bessel recurrence
     bool unsupported = false; // the requested form does not apply to these nodes
+    bemrat::Prec prec = bemrat::Prec::F64;
     std::vector<cplx> kappa;  // Direct: L wavenumbers
     std::vector<cplx> Cf;     // N x L: T(z_j) = sum_l Cf[j][l] T_l
 };
@@ -254,8 +269,8 @@ struct Plan {
 // series of exp(i R r t) is then accurate to 1e-14 relative to its smallest value at the
 // nodes (|exp(i R r t)| = e^{-R r Im t}; h = 1 on a circle, 0 for real nodes).  L is rounded
 // up to a whole number of sweep blocks (the extra terms cost nothing and add accuracy).
-int taylor_length(double x, double h, int block) {
-    const double target = 1e-14 * std::exp(-x * h);
+int taylor_length(double x, double h, int block, double tol) {
+    const double target = tol * std::exp(-x * h);
     double term = 1.0;
     for (int L = 1; L < bemrat::kMaxTaylor; ++L) {
         term *= x / L;
@@ -272,12 +287,12 @@ int taylor_length(double x, double h, int block) {
 // sum_{l >= L} |eps_l J_l(x)|, and |T_l| <= 1 on the interval), rounded up to whole blocks.
 // Also returns the unrounded length in *need (the Bessel recurrence starts 10 above it,
 // which is accurate to a few units of 1e-16 for these x).
-int cheb_length(double x, int block, int *need) {
+int cheb_length(double x, int block, int *need, double tol) {
     double term = 2.0;
     for (int L = 1; L < bemrat::kMaxTaylor; ++L) {
         term *= 0.5 * x / L;
         const double q = 0.25 * x * x / (L + 1);
-        if (L > 0.5 * x && q < 1.0 && term / (1.0 - q) <= 1e-14) {
+        if (L > 0.5 * x && q < 1.0 && term / (1.0 - q) <= tol) {
             *need = L;
             const int r = (L + block - 1) / block * block;
             return std::min(r, bemrat::kMaxTaylor - 1);
@@ -306,20 +321,26 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
     if (R > 0.0)
         for (auto &v : zs) hmax = std::max(hmax, (v - c).imag() / R);
     const int block = bemrat::sweep_ops_per_block(m);
-    int L = R > 0.0 ? taylor_length(R * h->diameter, hmax, block) : bemrat::kMaxTaylor;
+    const bemrat::Prec prec = prec_of(flags);
+    plan.prec = prec;
+    const double tol = trunc_tol(prec);
+    int L = R > 0.0 ? taylor_length(R * h->diameter, hmax, block, tol) : bemrat::kMaxTaylor;
     const bool expand_ok = R > 0.0 && L < bemrat::kMaxTaylor;
     // Chebyshev form: every node real (then c is real and R is the half-width)
     const bool real_nodes = imin == 0.0 && imax == 0.0;
     int need = 0;
-    const int Lc = real_nodes && R > 0.0 ? cheb_length(R * h->diameter, block, &need) : bemrat::kMaxTaylor;
+    const int Lc = real_nodes && R > 0.0 ? cheb_length(R * h->diameter, block, &need, tol) : bemrat::kMaxTaylor;
     const bool cheb_ok = real_nodes && R > 0.0 && Lc + 10 < bemrat::kMaxTaylor;
     if (form == BEM_FORM_CHEB && !cheb_ok) {
         plan.unsupported = true;
         return plan;
     }
     // FP64: the Chebyshev form only on request (each block reruns the whole Bessel
-    // recurrence, so it generates fewer operators than EXPAND but costs more at these sizes)
-    if (form == BEM_FORM_CHEB) {
+    // recurrence, so it generates fewer operators than EXPAND but costs more at these sizes).
+    // Reduced precision: AUTO takes it for real nodes (the recombination does not amplify
+    // rounding errors) and DIRECT for complex ones; EXPAND only on request.
+    const bool lp = prec != bemrat::Prec::F64;
+    if (form == BEM_FORM_CHEB || (lp && form == BEM_FORM_AUTO && cheb_ok && Lc < N)) {
         plan.gen = bemrat::Gen::Cheb;
         plan.L = Lc;
         plan.c = c;
@@ -346,7 +367,7 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
         }
         return plan;
     }
-    const bool expand = form == BEM_FORM_EXPAND ? expand_ok : (form == BEM_FORM_AUTO && expand_ok && L < N);
+    const bool expand = form == BEM_FORM_EXPAND ? expand_ok : (!lp && form == BEM_FORM_AUTO && expand_ok && L < N);
     if (!expand) {
         plan.gen = bemrat::Gen::Direct;
         plan.L = (int)N;
@@ -483,7 +504,15 @@ bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, 
     a.inv_int = pbase + off_tables + bemrat::kMaxTaylor;
     a.miller_M = plan.miller_M;
     if (h->timing) HIP_TRY(hipEventRecord(h->ev0, s), "event record");
-    HIP_TRY(bemrat::launch_sweep(plan.gen, a, s), "sweep kernel");
+    if (plan.prec == bemrat::Prec::F64) {
+        HIP_TRY(bemrat::launch_sweep(plan.gen, a, s), "sweep kernel");
+    } else {
+        // entries ~ A_b w_q / (4 pi r): scaled to ~ w_q / r, well inside the FP16 range
+        a.a_scale = 4.0 * 3.14159265358979323846 / h->mean_area;
+        HIP_TRY(bemrat::launch_sweep_lp(plan.prec, plan.gen, a, s), "reduced-precision sweep kernel");
+        HIP_TRY(bemrat::launch_add_diag(h->self.as<double2>(), dm.n_pad, a.V, ldv, Z, ldz, zstride, dm.n, m, plan.L, s),
+                "diagonal kernel");
+    }
     if (h->timing) {
         HIP_TRY(hipEventRecord(h->ev1, s), "event record");
         h->timed = true;
@@ -561,6 +590,16 @@ bem_status bem_mesh_create(const double *xyz, int64_t nv, const int32_t *tri, in
         rad2 = std::max(rad2, d2);
     }
     h->diameter = 2.0 * std::sqrt(rad2) * (1.0 + 1e-12);
+    double area_sum = 0.0;
+    for (int64_t t = 0; t < n; ++t) {
+        const double *P0 = xyz + 3 * (int64_t)tri[3 * t], *P1 = xyz + 3 * (int64_t)tri[3 * t + 1],
+                     *P2 = xyz + 3 * (int64_t)tri[3 * t + 2];
+        const double u[3] = {P1[0] - P0[0], P1[1] - P0[1], P1[2] - P0[2]};
+        const double v[3] = {P2[0] - P0[0], P2[1] - P0[1], P2[2] - P0[2]};
+        const double c[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+        area_sum += 0.5 * std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    }
+    h->mean_area = area_sum / (double)n;
     const int64_t n_pad = (n + bemrat::kPad - 1) / bemrat::kPad * bemrat::kPad;
     h->dm.n = n;
     h->dm.n_pad = n_pad;
@@ -751,7 +790,7 @@ bem_status bem_assemble_apply(bem_mesh_t h, const double *kappa, int64_t nk, con
     if (nk > 65535) return fail(BEM_EINVAL, "at most 65535 wavenumbers per call");
     if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
     if ((st = check_block(Y, m, ldy, "Y")) != BEM_OK) return st;
-    Plan plan = make_plan(h, kappa, nk, m, BEM_FORM_DIRECT);
+    Plan plan = make_plan(h, kappa, nk, m, BEM_FORM_DIRECT | (flags & BEM_PREC_MASK));
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;

@@ -1,0 +1,223 @@
+// Operator-entry generators shared by the FP64 sweep and the reduced-precision sweep:
+// for one (target row, source triangle) and the 7 quadrature points, the entries of a block
+// of NOPS consecutive coefficient operators (Direct, Taylor or Chebyshev family), in FP64.
+#pragma once
+
+#include "devmath.h"
+#include "internal.h"
+
+namespace bemrat {
+namespace {
+
+constexpr int kStage = 16;               // source triangles per stage
+constexpr int kStageSteps = kStage / 4;  // k-steps per stage
+
+// 1/sqrt(a) for finite a > 0 (squared distances between distinct points, or 1 on the
+// diagonal): hardware estimate and one Newton step y (3 - a y^2) / 2, written as
+// y + y/2 (1 - a y^2) with fused multiply-adds.
+__device__ __forceinline__ double rsqrt_pos(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    const double e = fma(-a * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// Entries of the NOPS operators L0 .. L0 + NOPS - 1 at one (row, triangle) off the
+// diagonal, from the distances r_q and weights w_q / r_q of the 7 quadrature points.
+template <int NOPS, Gen GEN, bool DECAY>
+struct Generator;
+
+template <int NOPS, bool DECAY>
+struct Generator<NOPS, Gen::Direct, DECAY> {
+    double kr[NOPS], ki[NOPS];
+    __device__ void init(const SweepArgs &p, int L0) {
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) {
+            const int l = min(L0 + j, p.L - 1);
+            kr[j] = p.kappa[l].x;
+            ki[j] = p.kappa[l].y;
+        }
+    }
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &, double2 (&out)[NOPS]) const {
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) {
+            double gr = 0.0, gi = 0.0;
+#pragma unroll
+            for (int q = 0; q < kQuad; ++q) {
+                const double e = DECAY ? exp_cw(-ki[j] * r[q]) * wr[q] : wr[q];
+                double sn, cs;
+                sincos_cw(kr[j] * r[q], sn, cs);
+                gr = fma(e, cs, gr);
+                gi = fma(e, sn, gi);
+            }
+            out[j] = make_double2(gr, gi);
+        }
+    }
+};
+
+// Term of operator L0 + j at one point: w/r exp(i c r) (i x)^(L0 + j) / (L0 + j)!, x = R r.
+// L0 is a multiple of 4, so (i x)^L0 = x^L0; the rest is y0 i^j x^j c_j with
+// y0 = w/r exp(i c r) x^L0 / L0! and the block-uniform c_j = L0! / (L0 + j)!, which with
+// i^j is applied once to the sum over the points.  The power x^j is a running product, so
+// no per-operator factor can be hoisted out of the point loop and kept live.
+template <int NOPS, bool DECAY>
+struct Generator<NOPS, Gen::Taylor, DECAY> {
+    static constexpr int B = NOPS;  // L0 = z B
+    int z;
+    double inv_fact;                // 1 / L0!
+    double cj[NOPS];                // L0! / (L0 + j)!
+    __device__ void init(const SweepArgs &p, int L0) {
+        z = L0 / B;
+        inv_fact = p.inv_fact[min(L0, kMaxTaylor - 1)];
+        double c = 1.0;
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) {
+            cj[j] = c;
+            c *= p.inv_int[min(L0 + j + 1, kMaxTaylor - 1)];
+        }
+    }
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &p, double2 (&out)[NOPS]) const {
+        double gr[NOPS], gi[NOPS];
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) gr[j] = gi[j] = 0.0;
+        // x^L0 / L0! = (x^B)^z / L0! for all points together: z is uniform over the block,
+        // so the loop over its bits does not diverge and costs two products per point and bit
+        double xq[kQuad], base[kQuad], pwq[kQuad];
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+            xq[q] = p.R * r[q];
+            const double x2 = xq[q] * xq[q], x4 = x2 * x2;
+            base[q] = B == 8 ? x4 * x4 : x4 * x4 * x4;
+            pwq[q] = inv_fact;
+        }
+        for (int zz = z; zz != 0; zz >>= 1) {
+            if (zz & 1) {
+#pragma unroll
+                for (int q = 0; q < kQuad; ++q) pwq[q] *= base[q];
+            }
+#pragma unroll
+            for (int q = 0; q < kQuad; ++q) base[q] *= base[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+            const double x = xq[q], pw = pwq[q];
+            const double e = (DECAY ? exp_cw(-p.c_im * r[q]) * wr[q] : wr[q]) * pw;
+            double sn, cs;
+            sincos_cw(p.c_re * r[q], sn, cs);
+            const double yr = e * cs, yi = e * sn;
+            // sum_q y x^j (c_j and i^j are applied once per operator below)
+            double xp = x;
+            gr[0] += yr;
+            gi[0] += yi;
+#pragma unroll
+            for (int j = 1; j < NOPS; ++j) {
+                gr[j] = fma(yr, xp, gr[j]);
+                gi[j] = fma(yi, xp, gi[j]);
+                xp *= x;
+            }
+        }
+#pragma unroll
+        for (int j = 1; j < NOPS; ++j) {
+            const double a = gr[j] * cj[j], b = gi[j] * cj[j];
+            switch (j & 3) {  // times i^j (compile-time rotation)
+                case 0: gr[j] = a; gi[j] = b; break;
+                case 1: gr[j] = -b; gi[j] = a; break;
+                case 2: gr[j] = -a; gi[j] = -b; break;
+                default: gr[j] = b; gi[j] = -a; break;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) out[j] = make_double2(gr[j], gi[j]);
+    }
+};
+
+// Chebyshev (Jacobi-Anger) form for real nodes kappa = alpha + beta xi, xi in [-1, 1]:
+// exp(i kappa r) = exp(i alpha r) sum_l eps_l i^l J_l(beta r) T_l(xi), so with the factors
+// eps_l i^l left to the host's recombination, operator l has entries
+// sum_q w_q / r_q exp(i alpha r_q) J_l(beta r_q).  The J_l come from Miller's backward
+// recurrence J_{l-1} = (2 l / x) J_l - J_{l+1}, started at J_{M+1} = 0, J_M = 2^-1000 (M a
+// multiple of 8, at least the block's top index, chosen by the host) and normalised by
+// J_0 + 2 sum_k J_{2k} = 1.  The recurrence runs eight steps per trip; after each trip the
+// values are scaled down by 2^-400 if they exceed 2^400 (they grow like M! (2/x)^M for
+// small x; eight steps grow them by less than 2^250 for x >= 1e-7 and M <= 96), and a
+// factor f carries that scaling to the block's values stored earlier.
+template <int NOPS, bool DECAY>
+struct Generator<NOPS, Gen::Cheb, DECAY> {
+    int L0, M;
+    __device__ void init(const SweepArgs &p, int L0_) {
+        L0 = L0_;
+        M = p.miller_M;
+    }
+    // eight steps from index l (a multiple of 8) down to l - 8; S gains 2 J at each even index
+    __device__ __forceinline__ static void steps8(int l, double tx, double &jp, double &jc, double &S) {
+        double t = l * tx;
+#pragma unroll
+        for (int i = 1; i <= 8; ++i) {
+            const double jn = fma(t, jc, -jp);  // J_{l-i}
+            jp = jc;
+            jc = jn;
+            t -= tx;
+            if ((i & 1) == 0) S = fma(2.0, jc, S);
+        }
+    }
+    __device__ __forceinline__ static double rescale(double &jp, double &jc, double &S) {
+        const double sc = fabs(jc) > 0x1p400 ? 0x1p-400 : 1.0;
+        jp *= sc;
+        jc *= sc;
+        S *= sc;
+        return sc;
+    }
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &p, double2 (&out)[NOPS]) const {
+        double gr[NOPS], gi[NOPS];
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) gr[j] = gi[j] = 0.0;
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+            const double x = p.R * r[q];
+            // 2 / x by the reciprocal estimate and two Newton steps (x > 0)
+            double tx = __builtin_amdgcn_rcp(x);
+            tx = fma(fma(-x, tx, 1.0), tx, tx);
+            tx = 2.0 * fma(fma(-x, tx, 1.0), tx, tx);
+            double sn, cs;
+            sincos_cw(p.c_re * r[q], sn, cs);
+            const double yr = wr[q] * cs, yi = wr[q] * sn;
+            double jp = 0.0, jc = 0x1p-1000, S = 2.0 * jc;  // J_{M+1}, J_M (M even, > 0)
+            for (int l = M; l > L0 + NOPS; l -= 8) {
+                steps8(l, tx, jp, jc, S);
+                rescale(jp, jc, S);
+            }
+            // the block's indices L0 + NOPS - 1 .. L0 (jc is J_{L0+NOPS} here)
+            double jb[NOPS];
+            double t = (L0 + NOPS) * tx;
+#pragma unroll
+            for (int j = NOPS - 1; j >= 0; --j) {
+                const double jn = fma(t, jc, -jp);
+                jp = jc;
+                jc = jn;
+                t -= tx;
+                jb[j] = jc;
+                if ((j & 1) == 0) S = fma(2.0, jc, S);  // L0 is even
+            }
+            double f = 1.0;
+            for (int l = L0; l > 0; l -= 8) {
+                steps8(l, tx, jp, jc, S);
+                f *= rescale(jp, jc, S);
+            }
+            S -= jc;  // J_0 was counted twice
+            const double nrm = f / S;
+#pragma unroll
+            for (int j = 0; j < NOPS; ++j) {
+                const double v = jb[j] * nrm;
+                gr[j] = fma(yr, v, gr[j]);
+                gi[j] = fma(yi, v, gi[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) out[j] = make_double2(gr[j], gi[j]);
+    }
+};
+
+}  // namespace
+}  // namespace bemrat

@@ -24,6 +24,10 @@ struct DeviceMesh {
 // Generator of the coefficient operators of one sweep.
 enum class Gen : int { Direct = 0, Taylor = 1, Cheb = 2 };
 
+// Arithmetic of the contraction (bits 4..7 of the flags): FP64 throughout, or FP64
+// generation with an FP32 / BF16 / FP16 matrix-core contraction and FP32 accumulation.
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
+
 struct SweepArgs {
     const double4 *colloc;
     const double4 *quad;
@@ -45,7 +49,8 @@ struct SweepArgs {
     double c_re, c_im, R;
     const double *inv_fact;  // 1/l!, l < kMaxTaylor
     const double *inv_int;   // 1/l, l < kMaxTaylor (entry 0 unused)
-    int miller_M;            // Cheb: start index of the Bessel recurrence (multiple of 4)
+    int miller_M;            // Cheb: start index of the Bessel recurrence (multiple of 8)
+    double a_scale;          // reduced precision: entries are scaled by this before rounding
 };
 
 // Launchers (asynchronous on `stream`; return hipSuccess or the launch error).
@@ -54,6 +59,11 @@ hipError_t launch_prepare_mesh(const double *xyz, const int32_t *tri, int64_t n,
 hipError_t launch_self_terms(const DeviceMesh &mesh, const double2 *kappa, int64_t nk,
                              double2 *S, int64_t lds, hipStream_t stream);
 hipError_t launch_sweep(Gen gen, const SweepArgs &args, hipStream_t stream);
+// Reduced-precision sweep (diagonal entries zero) and the FP64 diagonal pass that completes it.
+hipError_t launch_sweep_lp(Prec prec, Gen gen, const SweepArgs &args, hipStream_t stream);
+hipError_t launch_add_diag(const double2 *S, int64_t n_pad, const double2 *V, int64_t ldv, double2 *Z, int64_t ldz,
+                           int64_t zstride, int64_t n, int64_t m, int L, hipStream_t stream);
+int sweep_lp_ops_per_block(Gen gen);
 // Coefficient operators one sweep block generates together (they share its base terms).
 int sweep_ops_per_block(int64_t m);
 // Column padding of the probe copy the sweep reads (a multiple of its column tile).

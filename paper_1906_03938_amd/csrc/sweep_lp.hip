@@ -1,0 +1,322 @@
+// Reduced-precision sweep: Z_l = T_l V with the contraction on FP32, BF16 or FP16 matrix
+// cores and FP32 accumulation.
+//
+// Same block and pipeline as the FP64 sweep (8 waves; producer waves 0-3 generate the
+// entries of stage s + 1 while consumer waves 4-7 contract stage s through double-buffered
+// LDS), with these differences:
+// * The producer generates in FP64 (the shared generators; on gfx950 FP32 and FP64 vector
+//   instructions issue at the same rate when packed FP32 is not used), then scales the
+//   entries by a_scale (which keeps them inside the FP16 range) and rounds the real part,
+//   the imaginary part and their sum (Gauss's three-multiplication product) to the
+//   contraction type.  The probe rows are rounded the same way when staged.
+// * Diagonal entries are stored as zero: the exact FP64 self terms are added afterwards by
+//   add_diag_kernel (Z_l[a] += T_l[a,a] V[a]), so they never pass through low precision.
+// * FP32: v_mfma_f32_16x16x4f32 per k-step of 4 triangles, entries stored [triangle][row].
+//   BF16 / FP16: one v_mfma_f32_16x16x16{bf16,f16} per stage of 16 triangles; each lane
+//   holds 4 consecutive triangles, so entries are stored [row][triangle] and probe rows
+//   [column][triangle].
+// * D layout of the FP32-accumulating 16x16 MFMAs (checked on the device): register i of a
+//   lane holds row 4 (lane >> 4) + i, column lane & 15.
+#include "generators.h"
+
+namespace bemrat {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ short bf16_bits(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+template <Prec P>
+struct Lp;
+
+template <>
+struct Lp<Prec::F32> {
+    typedef float T;
+    static constexpr bool k16 = false;
+    __device__ static T cvt(float v) { return v; }
+};
+
+template <>
+struct Lp<Prec::BF16> {
+    typedef short T;
+    typedef v4s V4;
+    static constexpr bool k16 = true;
+    __device__ static T cvt(float v) { return bf16_bits(v); }
+    __device__ static v4f mma(V4 a, V4 b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+};
+
+template <>
+struct Lp<Prec::F16> {
+    typedef _Float16 T;
+    typedef v4h V4;
+    static constexpr bool k16 = true;
+    __device__ static T cvt(float v) { return (_Float16)v; }
+    __device__ static v4f mma(V4 a, V4 b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
+};
+
+// LDS index of component c (0: real, 1: imaginary, 2: their sum) of the entry of operator j
+// at (row, stage triangle), and of a staged probe value at (stage triangle, column).
+template <bool K16>
+__device__ __forceinline__ int a_index(int j, int c, int row, int tri) {
+    return K16 ? ((j * 3 + c) * 16 + row) * kStage + tri : ((j * 3 + c) * kStage + tri) * 16 + row;
+}
+template <bool K16, int NC>
+__device__ __forceinline__ int v_index(int c, int tri, int col) {
+    return K16 ? (c * NC + col) * kStage + tri : (c * kStage + tri) * NC + col;
+}
+
+template <Prec P, int G, int CB, Gen GEN, bool DECAY>
+__global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
+    typedef Lp<P> LP;
+    typedef typename LP::T T;
+    constexpr bool K16 = LP::k16;
+    constexpr int NC = 16 * CB;
+    constexpr int NOPS = 4 * G;
+    constexpr int VPT = kStage * NC / 256;
+    __shared__ __attribute__((aligned(16))) T sA[2][NOPS * 3 * kStage * 16];
+    __shared__ __attribute__((aligned(16))) T sV[2][3 * kStage * NC];
+    __shared__ double4 sQ[2][kStage * kQuad];
+
+    const int tid = threadIdx.x;
+    const int64_t row0 = (int64_t)blockIdx.x * 16;
+    const int64_t col0 = (int64_t)blockIdx.y * NC;
+    const int L0 = blockIdx.z * NOPS;
+    const int64_t nstages = p.n_pad / kStage;
+
+    if (tid < 256) {
+        // ---- producer: thread t generates row t & 15, stage triangle t >> 4
+        constexpr int QN = kStage * kQuad;
+        const int brow = tid & 15, btri = tid >> 4;
+        const int64_t grow = row0 + brow;
+        const double4 xa = p.colloc[grow];
+        const double scale = p.a_scale;
+        Generator<NOPS, GEN, DECAY> gen;
+        gen.init(p, L0);
+        int64_t voff[VPT];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int idx = tid + 256 * i;
+            voff[i] = (int64_t)(idx / NC) * p.m_pad + col0 + idx % NC;
+        }
+        const int64_t vstride = (int64_t)kStage * p.m_pad;
+        double2 rv[VPT];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) rv[i] = p.Vp2[voff[i]];
+        double4 rq = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (tid < QN) {
+            sQ[0][tid] = p.quad[tid];
+            if (nstages > 1) rq = p.quad[QN + tid];
+        }
+        __syncthreads();
+        for (int64_t it = 0; it <= nstages; ++it) {
+            if (it < nstages) {
+                const int buf = (int)(it & 1);
+#pragma unroll
+                for (int i = 0; i < VPT; ++i) {
+                    const int idx = tid + 256 * i;
+                    const int tri = idx / NC, col = idx % NC;
+                    const float vr = (float)rv[i].x, vi = (float)rv[i].y;
+                    sV[buf][v_index<K16, NC>(0, tri, col)] = LP::cvt(vr);
+                    sV[buf][v_index<K16, NC>(1, tri, col)] = LP::cvt(vi);
+                    sV[buf][v_index<K16, NC>(2, tri, col)] = LP::cvt(vr + vi);
+                }
+                if (tid < QN && it + 1 < nstages) sQ[buf ^ 1][tid] = rq;
+                const bool diag = it * kStage + btri == grow;
+                double r[kQuad], wr[kQuad];
+#pragma unroll
+                for (int q = 0; q < kQuad; ++q) {
+                    const double4 y = sQ[buf][btri * kQuad + q];
+                    const double dx = xa.x - y.x, dy = xa.y - y.y, dz = xa.z - y.z;
+                    double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    r2 = diag ? 1.0 : r2;  // the diagonal is added in FP64 afterwards
+                    const double rinv = rsqrt_pos(r2);
+                    r[q] = r2 * rinv;
+                    wr[q] = y.w * rinv;
+                }
+                if (it + 1 < nstages) {
+#pragma unroll
+                    for (int i = 0; i < VPT; ++i) rv[i] = p.Vp2[voff[i] + (it + 1) * vstride];
+                }
+                if (tid < QN && it + 2 < nstages) rq = p.quad[(it + 2) * QN + tid];
+                double2 a[NOPS];
+                gen.entries(r, wr, p, a);
+                const double s = diag ? 0.0 : scale;
+#pragma unroll
+                for (int j = 0; j < NOPS; ++j) {
+                    const float ar = (float)(a[j].x * s), ai = (float)(a[j].y * s);
+                    sA[buf][a_index<K16>(j, 0, brow, btri)] = LP::cvt(ar);
+                    sA[buf][a_index<K16>(j, 1, brow, btri)] = LP::cvt(ai);
+                    sA[buf][a_index<K16>(j, 2, brow, btri)] = LP::cvt(ar + ai);
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        // ---- consumer: wave w contracts operators L0 + G w ... of stage it - 1
+        const int w = (tid >> 6) - 4;
+        const int lane = tid & 63;
+        const int ci = lane & 15, ck = lane >> 4;
+        v4f P1[G][CB], P2[G][CB], P3[G][CB];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                P1[g][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+                P2[g][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+                P3[g][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+        __syncthreads();  // pairs with the producers' prologue barrier
+        for (int64_t it = 0; it <= nstages; ++it) {
+            if (it >= 1) {
+                const int buf = (int)((it - 1) & 1);
+                if constexpr (K16) {
+                    typedef typename LP::V4 V4;
+                    // lane (ci, ck) holds triangles 4 ck .. 4 ck + 3 of the stage
+                    V4 ga[G][3];
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            ga[g][c] = *reinterpret_cast<const V4 *>(&sA[buf][a_index<true>(w * G + g, c, ci, 4 * ck)]);
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        V4 vb[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            vb[c] = *reinterpret_cast<const V4 *>(&sV[buf][v_index<true, NC>(c, 4 * ck, cb * 16 + ci)]);
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            P1[g][cb] = LP::mma(ga[g][0], vb[0], P1[g][cb]);
+                            P2[g][cb] = LP::mma(ga[g][1], vb[1], P2[g][cb]);
+                            P3[g][cb] = LP::mma(ga[g][2], vb[2], P3[g][cb]);
+                        }
+                    }
+                } else {
+#pragma unroll 2
+                    for (int ks = 0; ks < kStageSteps; ++ks) {
+                        const int tri = 4 * ks + ck;
+                        float ga[G][3];
+#pragma unroll
+                        for (int g = 0; g < G; ++g)
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) ga[g][c] = sA[buf][a_index<false>(w * G + g, c, ci, tri)];
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) {
+                            float vb[3];
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) vb[c] = sV[buf][v_index<false, NC>(c, tri, cb * 16 + ci)];
+#pragma unroll
+                            for (int g = 0; g < G; ++g) {
+                                P1[g][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[g][0], vb[0], P1[g][cb], 0, 0, 0);
+                                P2[g][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[g][1], vb[1], P2[g][cb], 0, 0, 0);
+                                P3[g][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[g][2], vb[2], P3[g][cb], 0, 0, 0);
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const double inv = 1.0 / p.a_scale;
+        const int l0 = L0 + w * G;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (l0 + g >= p.L) break;
+            double2 *Z = p.Z + (int64_t)(l0 + g) * p.zstride;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int64_t col = col0 + cb * 16 + ci;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t row = row0 + 4 * ck + i;
+                    const double p1 = P1[g][cb][i], p2 = P2[g][cb][i], p3 = P3[g][cb][i];
+                    if (row < p.n && col < p.m)
+                        Z[row * p.ldz + col] = make_double2((p1 - p2) * inv, (p3 - p1 - p2) * inv);
+                }
+            }
+        }
+    }
+}
+
+// Z_l[a][c] += S_l[a] V[a][c]: the FP64 diagonal (self-term) contribution.
+__global__ void add_diag_kernel(const double2 *__restrict__ S, int64_t n_pad, const double2 *__restrict__ V,
+                                int64_t ldv, double2 *__restrict__ Z, int64_t ldz, int64_t zstride, int64_t n,
+                                int64_t m) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (idx >= n * m) return;
+    const int64_t a = idx / m, c = idx % m;
+    const double2 s = S[(int64_t)l * n_pad + a], v = V[a * ldv + c];
+    double2 &z = Z[(int64_t)l * zstride + a * ldz + c];
+    z.x += s.x * v.x - s.y * v.y;
+    z.y += s.x * v.y + s.y * v.x;
+}
+
+template <Prec P, int G, int CB, Gen GEN, bool DECAY>
+hipError_t launch_lp_t(const SweepArgs &p, hipStream_t stream) {
+    constexpr int NC = 16 * CB;
+    constexpr int NOPS = 4 * G;
+    dim3 grid((unsigned)(p.n_pad / 16), (unsigned)((p.m + NC - 1) / NC), (unsigned)((p.L + NOPS - 1) / NOPS));
+    hipLaunchKernelGGL((sweep_lp_kernel<P, G, CB, GEN, DECAY>), grid, dim3(512), 0, stream, p);
+    return hipGetLastError();
+}
+
+// Operators per consumer wave: 4 (16 per block) for the direct form, whose generation has no
+// per-point state shared across operators, 2 (8 per block) for the expansion forms, whose
+// producers would otherwise run out of registers.  The matrix work is cheap at these
+// precisions, so the block amortises its generation over as many operators and columns as
+// the registers allow.
+template <Prec P, Gen GEN, bool DECAY>
+hipError_t launch_lp_gen(const SweepArgs &p, hipStream_t stream) {
+    constexpr int G = GEN == Gen::Direct ? 4 : 2;
+    if (p.m <= 16) return launch_lp_t<P, G, 1, GEN, DECAY>(p, stream);
+    if (p.m <= 32) return launch_lp_t<P, G, 2, GEN, DECAY>(p, stream);
+    return launch_lp_t<P, G, 4, GEN, DECAY>(p, stream);
+}
+
+template <Prec P>
+hipError_t launch_lp_prec(Gen gen, const SweepArgs &args, hipStream_t stream) {
+    const bool decay = args.decay != 0;
+    switch (gen) {
+        case Gen::Direct:
+            return decay ? launch_lp_gen<P, Gen::Direct, true>(args, stream)
+                         : launch_lp_gen<P, Gen::Direct, false>(args, stream);
+        case Gen::Taylor:
+            return decay ? launch_lp_gen<P, Gen::Taylor, true>(args, stream)
+                         : launch_lp_gen<P, Gen::Taylor, false>(args, stream);
+        case Gen::Cheb:
+            return decay ? hipErrorInvalidValue : launch_lp_gen<P, Gen::Cheb, false>(args, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int sweep_lp_ops_per_block(Gen gen) { return gen == Gen::Direct ? 16 : 8; }
+
+hipError_t launch_sweep_lp(Prec prec, Gen gen, const SweepArgs &args, hipStream_t stream) {
+    switch (prec) {
+        case Prec::F32: return launch_lp_prec<Prec::F32>(gen, args, stream);
+        case Prec::BF16: return launch_lp_prec<Prec::BF16>(gen, args, stream);
+        case Prec::F16: return launch_lp_prec<Prec::F16>(gen, args, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_add_diag(const double2 *S, int64_t n_pad, const double2 *V, int64_t ldv, double2 *Z, int64_t ldz,
+                           int64_t zstride, int64_t n, int64_t m, int L, hipStream_t stream) {
+    const int bs = 256;
+    dim3 grid((unsigned)((n * m + bs - 1) / bs), (unsigned)L);
+    hipLaunchKernelGGL(add_diag_kernel, grid, dim3(bs), 0, stream, S, n_pad, V, ldv, Z, ldz, zstride, n, m);
+    return hipGetLastError();
+}
+
+}  // namespace bemrat

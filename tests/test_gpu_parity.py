@@ -195,7 +195,7 @@ def test_error_paths(torch, bem):
     with bem.Mesh(xyz, tri) as mesh:
         V = torch.zeros((80, 4), dtype=torch.complex128, device="cuda")
         with pytest.raises(bem.BemError) as e:
-            mesh.assemble_apply([4.0], V, form=0x10)
+            mesh.assemble_apply([4.0], V, form=0x40)
         assert e.value.status == _lib.BEM_EUNSUPPORTED
         with pytest.raises(bem.BemError) as e:
             mesh.assemble_apply([float("nan")], V)
