@@ -39,7 +39,7 @@ class ContourSolver:
     """Cauchy-approximation eigensolver for T(kappa) x = 0 inside |kappa - c| < radius,
     with N trapezoidal nodes, q inverse-iteration steps per outer iteration."""
 
-    def __init__(self, mesh, c, radius, N, q=10, tol=1e-12, max_outer=30):
+    def __init__(self, mesh, c, radius, N, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0):
         import torch
 
         self.torch = torch
@@ -52,6 +52,8 @@ class ContourSolver:
         self.tol = float(tol)
         self.max_outer = int(max_outer)
         self.z, self.w, self.W = _lib.contour_nodes(self.c, self.radius, self.N, shift=self.c, P=self.q + 1)
+        self.sweep_flags = int(sweep_prec)  # arithmetic of the subspace sweeps (moments, S)
+        self.rr_flags = int(rr_prec)        # arithmetic of the Rayleigh-Ritz projections
         self._S_lu = None
         self.history = []
 
@@ -62,12 +64,12 @@ class ContourSolver:
     def moments(self, X, orders):
         """M_p X for moment orders p >= 1: one contour_moments sweep of X."""
         W = np.ascontiguousarray(self.W[:, [p - 1 for p in orders]])
-        return self.mesh.contour_moments(self.z, W, self._dev(X)).cpu().numpy()
+        return self.mesh.contour_moments(self.z, W, self._dev(X), form=self.sweep_flags).cpu().numpy()
 
     def r_lam(self, x, lam):
         """R_lam x = sum_i w_i T(z_i) x / (lam - z_i), one column."""
         W = (self.w / (lam - self.z))[:, None]
-        return self.mesh.contour_moments(self.z, W, self._dev(x.reshape(-1, 1))).cpu().numpy()[0, :, 0]
+        return self.mesh.contour_moments(self.z, W, self._dev(x.reshape(-1, 1)), form=self.sweep_flags).cpu().numpy()[0, :, 0]
 
     def schur_lu(self):
         """LU of S = M_1 = sum_i B_i/(z_i - c), assembled by one sweep of the identity."""
@@ -126,7 +128,7 @@ class ContourSolver:
         return A, M
 
     def rayleigh_ritz(self, U):
-        P = self.mesh.rr_project(self.z, self._dev(U)).cpu().numpy()
+        P = self.mesh.rr_project(self.z, self._dev(U), form=self.rr_flags).cpu().numpy()
         Bhat = [self.w[j] * P[j] for j in range(self.N)]
         A, M = self.reduced_pencil(Bhat)
         with np.errstate(invalid="ignore", divide="ignore"):
@@ -169,10 +171,13 @@ class ContourSolver:
         return lam_in[order], X[:, order], res[order], self.max_outer
 
 
-def eigs_in_contour(mesh, c, radius, N, U0, q=10, tol=1e-12, max_outer=30):
+def eigs_in_contour(mesh, c, radius, N, U0, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0):
     """(eigenvalues, eigenvectors, relative residuals, outer iterations) of T(kappa) x = 0
-    inside |kappa - c| < radius; U0 is the n x nu starting block."""
-    return ContourSolver(mesh, c, radius, N, q=q, tol=tol, max_outer=max_outer).solve(U0)
+    inside |kappa - c| < radius; U0 is the n x nu starting block.  sweep_prec / rr_prec are
+    the library's precision flags (PREC_*) for the subspace sweeps and for the Rayleigh-Ritz
+    projections; residuals are always evaluated in FP64."""
+    return ContourSolver(mesh, c, radius, N, q=q, tol=tol, max_outer=max_outer, sweep_prec=sweep_prec,
+                         rr_prec=rr_prec).solve(U0)
 
 
 class IntervalSolver:
@@ -193,7 +198,8 @@ class IntervalSolver:
     A restart block x_k = Ritz vector with its own xi_k has per-column coefficients
     g[l] = T_l(xi_k); it is swept once by cheb_moments (all B_l x) and combined on the host."""
 
-    def __init__(self, mesh, a, b, N, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2):
+    def __init__(self, mesh, a, b, N, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2, sweep_prec=0,
+                 rr_prec=0):
         import torch
 
         if N < 3:
@@ -209,6 +215,8 @@ class IntervalSolver:
         self.s = complex(shift)
         self.imag_tol = float(imag_tol)
         self.d = self.N - 1
+        self.sweep_flags = int(sweep_prec)
+        self.rr_flags = int(rr_prec)
         kappa, self.coef = _lib.cheb_nodes(self.a, self.b, self.N)
         self.z = kappa.astype(np.complex128)
         self.t_s = self._tvals(self.s)                              # T_0(s) .. T_d(s)
@@ -245,14 +253,14 @@ class IntervalSolver:
 
     def sweep(self, X, ages):
         W = np.ascontiguousarray(self.W_age[:, list(ages)])
-        return self.mesh.contour_moments(self.z, W, self._dev(X)).cpu().numpy()
+        return self.mesh.contour_moments(self.z, W, self._dev(X), form=self.sweep_flags).cpu().numpy()
 
     def g_lu(self):
         """LU of G = sum_l B_l T_l(s) = sum_j T(kappa_j) sum_l coef[l, j] T_l(s), assembled by
         one sweep of the identity."""
         if self._G_lu is None:
             wg = (self.coef.T @ self.t_s)[:, None]
-            G = self.mesh.contour_moments(self.z, wg, self._dev(np.eye(self.n))).cpu().numpy()[0]
+            G = self.mesh.contour_moments(self.z, wg, self._dev(np.eye(self.n)), form=self.sweep_flags).cpu().numpy()[0]
             self._G_lu = sla.lu_factor(G)
         return self._G_lu
 
@@ -267,7 +275,7 @@ class IntervalSolver:
         if xi is None:
             swept.append(self.sweep(u0, range(q)))
         else:
-            Cx = self.mesh.cheb_moments(self.a, self.b, self.N, self.N, self._dev(u0)).cpu().numpy()
+            Cx = self.mesh.cheb_moments(self.a, self.b, self.N, self.N, self._dev(u0), form=self.sweep_flags).cpu().numpy()
             g = self._tvals(np.asarray(xi, dtype=np.complex128))[:self.d]   # d x m
             restart = []
             for _ in range(q):
@@ -311,7 +319,7 @@ class IntervalSolver:
 
     def rayleigh_ritz(self, U):
         """kappa and y of the reduced pencil with B_hat_l = sum_j coef[l, j] U^H T(kappa_j) U."""
-        P = self.mesh.rr_project(self.z, self._dev(U)).cpu().numpy()
+        P = self.mesh.rr_project(self.z, self._dev(U), form=self.rr_flags).cpu().numpy()
         Bhat = np.einsum("lj,jab->lab", self.coef, P)
         A, M = self.reduced_pencil(Bhat)
         with np.errstate(invalid="ignore", divide="ignore"):
@@ -355,9 +363,11 @@ class IntervalSolver:
         return lam_in[order], X[:, order], res[order], self.max_outer
 
 
-def eigs_in_interval(mesh, a, b, N, U0, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2):
+def eigs_in_interval(mesh, a, b, N, U0, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2, sweep_prec=0,
+                     rr_prec=0):
     """(eigenvalues, eigenvectors, relative residuals, outer iterations) of T(kappa) x = 0
     with kappa in [a, b] (|Im kappa| <= imag_tol (b - a)), from the Chebyshev interpolant
-    with N first-kind nodes; U0 is the n x nu starting block."""
+    with N first-kind nodes; U0 is the n x nu starting block.  sweep_prec / rr_prec as for
+    eigs_in_contour."""
     return IntervalSolver(mesh, a, b, N, q=q, tol=tol, max_outer=max_outer, shift=shift,
-                          imag_tol=imag_tol).solve(U0)
+                          imag_tol=imag_tol, sweep_prec=sweep_prec, rr_prec=rr_prec).solve(U0)

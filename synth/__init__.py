@@ -9,13 +9,15 @@ compared on.
 The paper's own meshes (a unit cube with 864 triangles, a unit sphere with 384
 triangles, an industrial pump casing) are not available; the stand-ins are seeded
 synthetic meshes of the same kind (closed, flat triangles, Dirichlet single layer):
-icospheres at subdivision level L (20*4**L triangles) and perturbed variants.
+icospheres at subdivision level L (20*4**L triangles) and perturbed variants, and box
+surfaces meshed by uniform face grids.
 """
 from __future__ import annotations
 
 import numpy as np
 
 __all__ = [
+    "box_surface",
     "icosahedron",
     "icosphere",
     "perturbed_icosphere",
@@ -98,6 +100,45 @@ def ellipsoid(level: int, semi_axes):
     """Icosphere scaled to an ellipsoid with the given semi-axes (ax, ay, az)."""
     xyz, tri = icosphere(level)
     return xyz * np.asarray(semi_axes, dtype=np.float64)[None, :], tri
+
+
+def box_surface(dims=(1.0, 0.8, 0.6), counts=(126, 101, 76)):
+    """Surface of the box [0, a] x [0, b] x [0, c] (dims) on the uniform grid with
+    counts = (nx, ny, nz) intervals per edge direction: every face square is split into two
+    triangles along one diagonal, so n = 4 (nx ny + nx nz + ny nz) triangles sharing the
+    grid vertices (watertight).  The default is the 1.0 x 0.8 x 0.6 box with 119,912
+    triangles."""
+    nx, ny, nz = (int(c) for c in counts)
+    a, b, c = (float(d) for d in dims)
+    index = -np.ones((nx + 1, ny + 1, nz + 1), dtype=np.int64)
+    pts = []
+
+    def vid(i, j, k):
+        if index[i, j, k] < 0:
+            index[i, j, k] = len(pts)
+            pts.append((a * i / nx, b * j / ny, c * k / nz))
+        return index[i, j, k]
+
+    tris = []
+
+    def face(fix_axis, fix_val, u_axis, nu, v_axis, nv):
+        for iu in range(nu):
+            for iv in range(nv):
+                corners = []
+                for du, dv in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                    ijk = [0, 0, 0]
+                    ijk[fix_axis] = fix_val
+                    ijk[u_axis] = iu + du
+                    ijk[v_axis] = iv + dv
+                    corners.append(vid(*ijk))
+                tris.append((corners[0], corners[1], corners[2]))
+                tris.append((corners[0], corners[2], corners[3]))
+
+    for val, n_fix in ((0, None), (1, None)):
+        face(2, 0 if val == 0 else nz, 0, nx, 1, ny)
+        face(1, 0 if val == 0 else ny, 0, nx, 2, nz)
+        face(0, 0 if val == 0 else nx, 1, ny, 2, nz)
+    return np.asarray(pts, dtype=np.float64), np.asarray(tris, dtype=np.int32)
 
 
 def probe_block(n: int, m: int, seed: int) -> np.ndarray:

@@ -17,17 +17,17 @@ class DenseMesh:
         self.op = op
         self.n = op.n
 
-    def contour_moments(self, z, W, V):
+    def contour_moments(self, z, W, V, form=0):
         V = V.numpy()
         out = sum(np.asarray(W)[j][:, None, None] * self.op.dense(z[j]) @ V for j in range(len(z)))
         return torch.from_numpy(np.ascontiguousarray(out.reshape(np.asarray(W).shape[1], self.n, -1)))
 
-    def cheb_moments(self, a, b, N, L, V):
+    def cheb_moments(self, a, b, N, L, V, form=0):
         kappa, coef = M.cheb_nodes(a, b, N)
         Y = np.stack([self.op.dense(k) @ V.numpy() for k in kappa])
         return torch.from_numpy(np.einsum("lk,kam->lam", coef[:L], Y))
 
-    def rr_project(self, z, U):
+    def rr_project(self, z, U, form=0):
         U = U.numpy()
         return torch.from_numpy(np.stack([U.conj().T @ self.op.dense(zj) @ U for zj in z]))
 

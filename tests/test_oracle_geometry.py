@@ -165,3 +165,23 @@ def test_self_term_derivatives(oracle_lib):
             got = C.self_term_tri(P, k0, deriv=d)
             # roundoff of the reference scales with max|T| d!/rad^d
             assert abs(got - ref) <= 1e-13 * np.abs(vals).max() * fac / rad ** d, (d, got, ref)
+
+
+def test_box_surface_mesh():
+    """The box meshes: 4 (nx ny + nx nz + ny nz) triangles, every edge in exactly two faces,
+    Euler characteristic 2, total area 2 (ab + ac + bc), all triangles of the grid's size."""
+    for dims, counts in (((1.0, 0.8, 0.6), (10, 8, 6)), ((1.0, 0.8, 0.6), (126, 101, 76)), ((2.0, 1.0, 0.5), (3, 2, 1))):
+        xyz, tri = synth.box_surface(dims, counts)
+        nx, ny, nz = counts
+        a, b, c = dims
+        assert tri.shape[0] == 4 * (nx * ny + nx * nz + ny * nz)
+        assert synth.mesh_edges_ok(tri)
+        assert xyz.shape[0] - tri.shape[0] * 3 // 2 + tri.shape[0] == 2
+        P = xyz[tri]
+        area = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+        assert abs(area.sum() - 2 * (a * b + a * c + b * c)) < 1e-10
+        assert np.all(area > 0)
+        # every vertex lies on the box surface
+        on = np.isclose(xyz[:, 0], 0) | np.isclose(xyz[:, 0], a) | np.isclose(xyz[:, 1], 0) | \
+            np.isclose(xyz[:, 1], b) | np.isclose(xyz[:, 2], 0) | np.isclose(xyz[:, 2], c)
+        assert on.all()
