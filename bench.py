@@ -33,7 +33,7 @@ WORKLOAD = dict(name="sphere-81920", level=6, c=5.0, radius=2.0, N=64, m=64, P=2
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "devmath.h", "internal.h"):
+    for f in ("sweep.hip", "generators.h", "devmath.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_1906_03938_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -78,6 +78,73 @@ def cpu_baseline(xyz, tri, z, V, rows_per_thread=6):
     }
 
 
+PRECISION_WORKLOAD = dict(name="box-119912", dims=(1.0, 0.8, 0.6), counts=(126, 101, 76), a=2.0, b=8.0, N=48,
+                          m=128, seed=3)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}  # MI355X dense matrix peaks
+
+
+def precision_form():
+    """The precision form on the box workload (1.0 x 0.8 x 0.6 box, 126 x 101 x 76 face grid,
+    n = 119,912; Chebyshev blocks on [2, 8] with N = 48 nodes, m = 128 probes, seed 3): one
+    cheb_moments call per arithmetic after a warm-up call at FP64, timed by the library's
+    events around its sweep kernel (and wall clock for the whole call), and the eigenvalue
+    error per arithmetic on the 752-triangle box (interval [6.5, 8], N = 24), with every
+    sweep at that arithmetic ("all") and with FP64 Rayleigh-Ritz projections ("rr_f64"),
+    against the oracle's value in tests/golden/box752_interval_eigs.txt."""
+    import numpy as np
+    import torch
+
+    import paper_1906_03938_amd as bem
+    import synth
+    from paper_1906_03938_amd.eig import eigs_in_interval
+
+    w = PRECISION_WORKLOAD
+    xyz, tri = synth.box_surface(w["dims"], w["counts"])
+    n = tri.shape[0]
+    V = torch.from_numpy(synth.probe_block(n, w["m"], seed=w["seed"])).to("cuda")
+    precs = (("f64", bem.PREC_F64), ("f32", bem.PREC_F32), ("bf16", bem.PREC_BF16), ("f16", bem.PREC_F16))
+    forms = {}
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_timing(True)
+        mesh.cheb_moments(w["a"], w["b"], w["N"], w["N"], V)  # warm-up (workspace)
+        torch.cuda.synchronize()
+        for name, p in precs:
+            t0 = time.perf_counter()
+            mesh.cheb_moments(w["a"], w["b"], w["N"], w["N"], V, form=bem.FORM_AUTO | p)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            kms = mesh.last_kernel_ms()
+            form, L = mesh.last_form()
+            fl = 8.0 * L * n * n * w["m"]
+            forms[name] = {"value": w["N"] * n * n * w["m"] / wall, "unit": "kernel-entry*RHS/s",
+                           "seconds": wall, "sweep_kernel_ms": kms,
+                           "form": {bem.FORM_DIRECT: "direct", bem.FORM_EXPAND: "expand",
+                                    bem.FORM_CHEB: "cheb"}[form], "operators_generated": L,
+                           "achieved_tflops": fl / (kms * 1e-3) / 1e12, "matrix_peak_tflops": PEAK_TFLOPS[name]}
+    ref = np.loadtxt(os.path.join(ROOT, "tests", "golden", "box752_interval_eigs.txt"))
+    lam_ref = ref[0] + 1j * ref[1]
+    bx, bt = synth.box_surface(w["dims"], (10, 8, 6))
+    U0 = synth.probe_block(bt.shape[0], 8, seed=3)
+    eig = {}
+    with bem.Mesh(bx, bt) as mesh:
+        for name, p in precs:
+            for mode in ("all", "rr_f64"):
+                if name == "f64" and mode == "rr_f64":
+                    continue
+                lam, _, res, outer = eigs_in_interval(mesh, 6.5, 8.0, 24, U0, q=10, tol=1e-12, max_outer=4,
+                                                      sweep_prec=p, rr_prec=p if mode == "all" else bem.PREC_F64)
+                err = float(np.max(np.abs(lam - lam_ref)) / abs(lam_ref)) if lam.size == 1 else None
+                eig[f"{name}/{mode}"] = {"rel_err": err, "found": int(lam.size),
+                                         "max_rel_residual": float(res.max()) if res.size else None,
+                                         "outer_iterations": int(outer)}
+    base = forms["f64"]["value"]
+    for name in forms:
+        forms[name]["speedup_vs_f64"] = forms[name]["value"] / base
+    return {"workload": w["name"], "mesh": f"box 1.0x0.8x0.6, face grid 126x101x76, n={n}",
+            "interval": [w["a"], w["b"]], "nodes": w["N"], "m": w["m"], "call": "cheb_moments, all N blocks",
+            "forms": forms, "eigen_box752": eig}
+
+
 def eigen_check():
     """Eigenvalues of the sphere-1280 workload (icosphere level 3, |z - 4| < 1.5, N = 32,
     16 probes, seed 1) by the host driver on device sweeps, against the oracle's values
@@ -110,6 +177,7 @@ def main():
     ap.add_argument("--form", choices=["auto", "direct", "expand"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eigen-check", action="store_true")
+    ap.add_argument("--no-precision-form", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -211,6 +279,8 @@ def main():
     mesh.close()
     if not args.no_eigen_check:
         out["eigen_check"] = eigen_check()
+    if not args.no_precision_form:
+        out["precision_form"] = precision_form()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xyz, tri, z, Vh)
     print(json.dumps(out), flush=True)
