@@ -101,7 +101,7 @@ struct bem_mesh {
     DeviceMesh dm;
     double diameter = 0.0;  // upper bound on every distance in the operator
     double mean_area = 0.0; // mean triangle area (sets the scale of reduced-precision entries)
-    Buffer geom, gl, self, aux, Z, params, partial, probe;
+    Buffer geom, gl, self, aux, Z, params, partial, probe, vmax;
     Staging staging;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false, timed = false;
@@ -472,7 +472,7 @@ bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, 
                 "self-term expansion kernel");
     }
     // zero-padded copy of the probe block read by the sweep
-    const int64_t m_pad = bemrat::sweep_m_pad(m);
+    const int64_t m_pad = plan.prec == bemrat::Prec::F64 ? bemrat::sweep_m_pad(m) : bemrat::sweep_lp_m_pad(m);
     const size_t np = (size_t)dm.n_pad * m_pad;
     HIP_TRY(h->probe.ensure(np * sizeof(double2)), "probe copy");
     double2 *Vp2 = h->probe.as<double2>();
@@ -507,8 +507,12 @@ bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, 
     if (plan.prec == bemrat::Prec::F64) {
         HIP_TRY(bemrat::launch_sweep(plan.gen, a, s), "sweep kernel");
     } else {
-        // entries ~ A_b w_q / (4 pi r): scaled to ~ w_q / r, well inside the FP16 range
+        // entries ~ A_b w_q / (4 pi r): scaled to ~ w_q / r, well inside the FP16 range;
+        // the probe block by 1 / max |V| (a device reduction into the workspace)
         a.a_scale = 4.0 * 3.14159265358979323846 / h->mean_area;
+        HIP_TRY(h->vmax.ensure(sizeof(unsigned long long)), "probe scale");
+        HIP_TRY(bemrat::launch_absmax(a.V, ldv, dm.n, m, h->vmax.as<unsigned long long>(), s), "probe scale kernel");
+        a.vmax = h->vmax.as<unsigned long long>();
         HIP_TRY(bemrat::launch_sweep_lp(plan.prec, plan.gen, a, s), "reduced-precision sweep kernel");
         HIP_TRY(bemrat::launch_add_diag(h->self.as<double2>(), dm.n_pad, a.V, ldv, Z, ldz, zstride, dm.n, m, plan.L, s),
                 "diagonal kernel");
@@ -667,6 +671,7 @@ void bem_mesh_destroy(bem_mesh_t h) {
     h->params.release();
     h->partial.release();
     h->probe.release();
+    h->vmax.release();
     if (h->staging.host) (void)hipHostFree(h->staging.host);
     if (h->staging.done) (void)hipEventDestroy(h->staging.done);
     if (h->ev0) (void)hipEventDestroy(h->ev0);

@@ -51,6 +51,7 @@ struct SweepArgs {
     const double *inv_int;   // 1/l, l < kMaxTaylor (entry 0 unused)
     int miller_M;            // Cheb: start index of the Bessel recurrence (multiple of 8)
     double a_scale;          // reduced precision: entries are scaled by this before rounding
+    const unsigned long long *vmax;  // reduced precision: bits of max |V| (probe scale)
 };
 
 // Launchers (asynchronous on `stream`; return hipSuccess or the launch error).
@@ -61,9 +62,12 @@ hipError_t launch_self_terms(const DeviceMesh &mesh, const double2 *kappa, int64
 hipError_t launch_sweep(Gen gen, const SweepArgs &args, hipStream_t stream);
 // Reduced-precision sweep (diagonal entries zero) and the FP64 diagonal pass that completes it.
 hipError_t launch_sweep_lp(Prec prec, Gen gen, const SweepArgs &args, hipStream_t stream);
+hipError_t launch_absmax(const double2 *V, int64_t ldv, int64_t n, int64_t m, unsigned long long *out,
+                         hipStream_t stream);
 hipError_t launch_add_diag(const double2 *S, int64_t n_pad, const double2 *V, int64_t ldv, double2 *Z, int64_t ldz,
                            int64_t zstride, int64_t n, int64_t m, int L, hipStream_t stream);
-int sweep_lp_ops_per_block(Gen gen);
+int sweep_lp_ops_per_block(Gen gen, int64_t m);
+int64_t sweep_lp_m_pad(int64_t m);  // column padding of the probe copy for the reduced-precision sweep
 // Coefficient operators one sweep block generates together (they share its base terms).
 int sweep_ops_per_block(int64_t m);
 // Column padding of the probe copy the sweep reads (a multiple of its column tile).

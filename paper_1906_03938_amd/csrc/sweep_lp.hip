@@ -8,7 +8,9 @@
 //   instructions issue at the same rate when packed FP32 is not used), then scales the
 //   entries by a_scale (which keeps them inside the FP16 range) and rounds the real part,
 //   the imaginary part and their sum (Gauss's three-multiplication product) to the
-//   contraction type.  The probe rows are rounded the same way when staged.
+//   contraction type.  The probe rows are scaled by 1 / max |V| (computed on the device by
+//   absmax_kernel before the sweep, so any probe block stays inside the FP16 range) and
+//   rounded the same way when staged; the epilogue undoes both scales.
 // * Diagonal entries are stored as zero: the exact FP64 self terms are added afterwards by
 //   add_diag_kernel (Z_l[a] += T_l[a,a] V[a]), so they never pass through low precision.
 // * FP32: v_mfma_f32_16x16x4f32 per k-step of 4 triangles, entries stored [triangle][row].
@@ -17,6 +19,8 @@
 //   [column][triangle].
 // * D layout of the FP32-accumulating 16x16 MFMAs (checked on the device): register i of a
 //   lane holds row 4 (lane >> 4) + i, column lane & 15.
+#include <algorithm>
+
 #include "generators.h"
 
 namespace bemrat {
@@ -62,6 +66,13 @@ struct Lp<Prec::F16> {
     __device__ static v4f mma(V4 a, V4 b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
 };
 
+// Scale applied to the probe block: its largest modulus (the reduction result), or 1 for a
+// zero block.
+__device__ __forceinline__ double vscale_of(const unsigned long long *vmax) {
+    const double m = __longlong_as_double((long long)*vmax);
+    return m > 0.0 ? m : 1.0;
+}
+
 // LDS index of component c (0: real, 1: imaginary, 2: their sum) of the entry of operator j
 // at (row, stage triangle), and of a staged probe value at (stage triangle, column).
 template <bool K16>
@@ -98,18 +109,21 @@ __global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
         const int64_t grow = row0 + brow;
         const double4 xa = p.colloc[grow];
         const double scale = p.a_scale;
+        const float vs = (float)(1.0 / vscale_of(p.vmax));
         Generator<NOPS, GEN, DECAY> gen;
         gen.init(p, L0);
-        int64_t voff[VPT];
+        // staged probe element i of this thread: stage triangle (tid + 256 i) / NC, column
+        // tid % NC (256 is a multiple of NC); kept in FP32, as it is rounded anyway
+        static_assert(256 % NC == 0, "a producer pass covers whole rows");
+        const double2 *vbase = p.Vp2 + (int64_t)(tid / NC) * p.m_pad + col0 + tid % NC;
+        const int64_t vstep = (int64_t)(256 / NC) * p.m_pad;
+        const int64_t vstride = (int64_t)kStage * p.m_pad;
+        float2 rv[VPT];
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
-            const int idx = tid + 256 * i;
-            voff[i] = (int64_t)(idx / NC) * p.m_pad + col0 + idx % NC;
+            const double2 v = vbase[i * vstep];
+            rv[i] = make_float2((float)v.x, (float)v.y);
         }
-        const int64_t vstride = (int64_t)kStage * p.m_pad;
-        double2 rv[VPT];
-#pragma unroll
-        for (int i = 0; i < VPT; ++i) rv[i] = p.Vp2[voff[i]];
         double4 rq = make_double4(0.0, 0.0, 0.0, 0.0);
         if (tid < QN) {
             sQ[0][tid] = p.quad[tid];
@@ -123,7 +137,7 @@ __global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
                 for (int i = 0; i < VPT; ++i) {
                     const int idx = tid + 256 * i;
                     const int tri = idx / NC, col = idx % NC;
-                    const float vr = (float)rv[i].x, vi = (float)rv[i].y;
+                    const float vr = rv[i].x * vs, vi = rv[i].y * vs;
                     sV[buf][v_index<K16, NC>(0, tri, col)] = LP::cvt(vr);
                     sV[buf][v_index<K16, NC>(1, tri, col)] = LP::cvt(vi);
                     sV[buf][v_index<K16, NC>(2, tri, col)] = LP::cvt(vr + vi);
@@ -143,7 +157,10 @@ __global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
                 }
                 if (it + 1 < nstages) {
 #pragma unroll
-                    for (int i = 0; i < VPT; ++i) rv[i] = p.Vp2[voff[i] + (it + 1) * vstride];
+                    for (int i = 0; i < VPT; ++i) {
+                        const double2 v = vbase[i * vstep + (it + 1) * vstride];
+                        rv[i] = make_float2((float)v.x, (float)v.y);
+                    }
                 }
                 if (tid < QN && it + 2 < nstages) rq = p.quad[(it + 2) * QN + tid];
                 double2 a[NOPS];
@@ -225,7 +242,7 @@ __global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
             }
             __syncthreads();
         }
-        const double inv = 1.0 / p.a_scale;
+        const double inv = vscale_of(p.vmax) / p.a_scale;
         const int l0 = L0 + w * G;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -244,6 +261,30 @@ __global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
             }
         }
     }
+}
+
+// *out = max over the n x m block of max(|Re v|, |Im v|), as the bits of a non-negative
+// double (which order like unsigned integers, so a device-wide atomicMax reduces them).
+// *out must be zero beforehand (absmax_clear_kernel).
+__global__ void absmax_clear_kernel(unsigned long long *out) { *out = 0ull; }
+
+__global__ void absmax_kernel(const double2 *__restrict__ V, int64_t ldv, int64_t n, int64_t m,
+                              unsigned long long *out) {
+    __shared__ double red[256];
+    double mx = 0.0;
+    const int64_t total = n * m;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = V[(idx / m) * ldv + idx % m];
+        mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
 }
 
 // Z_l[a][c] += S_l[a] V[a][c]: the FP64 diagonal (self-term) contribution.
@@ -269,17 +310,24 @@ hipError_t launch_lp_t(const SweepArgs &p, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// Operators per consumer wave: 4 (16 per block) for the direct form, whose generation has no
-// per-point state shared across operators, 2 (8 per block) for the expansion forms, whose
-// producers would otherwise run out of registers.  The matrix work is cheap at these
-// precisions, so the block amortises its generation over as many operators and columns as
-// the registers allow.
+// Block shape: 16 CB columns with CB = 1, 2, 4 or 8 by the column count (FP32 accumulators
+// leave room for 8 column blocks of 2 operators per consumer wave), and 4 operators per
+// consumer wave for the direct form up to 64 columns (its generation shares little across
+// operators); otherwise 2.  The matrix work is cheap at these precisions, so each block
+// amortises its generation (for the expansion forms, the per-point Bessel or power
+// sequence) over as many operators and columns as the registers allow.
+int lp_cb(int64_t m) { return m <= 16 ? 1 : m <= 32 ? 2 : m <= 64 ? 4 : 8; }
+int lp_g(Gen gen, int64_t m) { return gen == Gen::Direct && lp_cb(m) <= 4 ? 4 : 2; }
+
 template <Prec P, Gen GEN, bool DECAY>
 hipError_t launch_lp_gen(const SweepArgs &p, hipStream_t stream) {
-    constexpr int G = GEN == Gen::Direct ? 4 : 2;
-    if (p.m <= 16) return launch_lp_t<P, G, 1, GEN, DECAY>(p, stream);
-    if (p.m <= 32) return launch_lp_t<P, G, 2, GEN, DECAY>(p, stream);
-    return launch_lp_t<P, G, 4, GEN, DECAY>(p, stream);
+    constexpr int G = GEN == Gen::Direct ? 4 : 2;  // lp_g up to 64 columns
+    switch (lp_cb(p.m)) {
+        case 1: return launch_lp_t<P, G, 1, GEN, DECAY>(p, stream);
+        case 2: return launch_lp_t<P, G, 2, GEN, DECAY>(p, stream);
+        case 4: return launch_lp_t<P, G, 4, GEN, DECAY>(p, stream);
+        default: return launch_lp_t<P, 2, 8, GEN, DECAY>(p, stream);
+    }
 }
 
 template <Prec P>
@@ -300,7 +348,12 @@ hipError_t launch_lp_prec(Gen gen, const SweepArgs &args, hipStream_t stream) {
 
 }  // namespace
 
-int sweep_lp_ops_per_block(Gen gen) { return gen == Gen::Direct ? 16 : 8; }
+int sweep_lp_ops_per_block(Gen gen, int64_t m) { return 4 * lp_g(gen, m); }
+
+int64_t sweep_lp_m_pad(int64_t m) {
+    const int64_t nc = 16 * lp_cb(m);
+    return (m + nc - 1) / nc * nc;
+}
 
 hipError_t launch_sweep_lp(Prec prec, Gen gen, const SweepArgs &args, hipStream_t stream) {
     switch (prec) {
@@ -309,6 +362,15 @@ hipError_t launch_sweep_lp(Prec prec, Gen gen, const SweepArgs &args, hipStream_
         case Prec::F16: return launch_lp_prec<Prec::F16>(gen, args, stream);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_absmax(const double2 *V, int64_t ldv, int64_t n, int64_t m, unsigned long long *out,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(absmax_clear_kernel, dim3(1), dim3(1), 0, stream, out);
+    const int64_t blocks = std::min<int64_t>(1024, (n * m + 255) / 256);
+    hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, stream, V, ldv, n, m,
+                       out);
+    return hipGetLastError();
 }
 
 hipError_t launch_add_diag(const double2 *S, int64_t n_pad, const double2 *V, int64_t ldv, double2 *Z, int64_t ldz,

@@ -57,3 +57,34 @@ def test_sphere1280_interval_eigenvalues_match_oracle():
     assert lam.size == lam_ref.size == 4
     err = np.abs(np.sort_complex(lam) - np.sort_complex(lam_ref)) / np.abs(lam_ref)
     assert err.max() <= 1e-10, err
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f16"])
+def test_box752_eigenvalue_per_precision(prec):
+    """The precision form in the eigensolver: interval [6.5, 8] on the 752-triangle box
+    (one eigenvalue, golden value from the oracle).  With every sweep at the reduced
+    arithmetic the eigenvalue is that of an operator perturbed by about the sweeps'
+    normwise error (<= 2u); this simple, isolated eigenvalue is well conditioned (measured
+    errors 0.02-0.07 u), so the test allows u.  With the Rayleigh-Ritz projections in FP64
+    (the subspace still built at reduced precision) the error drops further (measured
+    u/300 - u/3000); the test allows u/10.  u = 2^-24 (FP32), 2^-8 (BF16), 2^-11 (FP16)."""
+    import torch
+
+    import paper_1906_03938_amd as bem
+    from paper_1906_03938_amd.eig import eigs_in_interval
+
+    assert torch.cuda.is_available()
+    u = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}[prec]
+    p = {"f32": bem.PREC_F32, "bf16": bem.PREC_BF16, "f16": bem.PREC_F16}[prec]
+    ref = np.loadtxt(os.path.join(GOLDEN, "box752_interval_eigs.txt"))
+    lam_ref = ref[0] + 1j * ref[1]
+    xyz, tri = synth.box_surface(counts=(10, 8, 6))
+    V = synth.probe_block(752, 8, seed=3)
+    with bem.Mesh(xyz, tri) as mesh:
+        lam_a, _, res_a, _ = eigs_in_interval(mesh, 6.5, 8.0, 24, V, max_outer=4, sweep_prec=p, rr_prec=p)
+        lam_b, _, res_b, _ = eigs_in_interval(mesh, 6.5, 8.0, 24, V, max_outer=4, sweep_prec=p, rr_prec=bem.PREC_F64)
+    assert lam_a.size == lam_b.size == 1
+    ea = abs(lam_a[0] - lam_ref) / abs(lam_ref)
+    eb = abs(lam_b[0] - lam_ref) / abs(lam_ref)
+    print(prec, "eigenvalue rel err: all sweeps", ea, "FP64 projections", eb, flush=True)
+    assert ea <= u and eb <= u / 10
