@@ -149,71 +149,88 @@ struct Generator<NOPS, Gen::Cheb, DECAY> {
         L0 = L0_;
         M = p.miller_M;
     }
-    // eight steps from index l (a multiple of 8) down to l - 8; S gains 2 J at each even index
-    __device__ __forceinline__ static void steps8(int l, double tx, double &jp, double &jc, double &S) {
-        double t = l * tx;
+    // The points advance in two groups (4 and 3) whose recurrences run side by side, so the
+    // serial dependence of each is hidden by the others without running out of registers.
+    template <int Q0, int QN>
+    __device__ __forceinline__ void group(const double (&r)[kQuad], const double (&wr)[kQuad], const SweepArgs &p,
+                                          double (&gr)[NOPS], double (&gi)[NOPS]) const {
+        double tx[QN], jp[QN], jc[QN], S[QN], f[QN];
 #pragma unroll
-        for (int i = 1; i <= 8; ++i) {
-            const double jn = fma(t, jc, -jp);  // J_{l-i}
-            jp = jc;
-            jc = jn;
-            t -= tx;
-            if ((i & 1) == 0) S = fma(2.0, jc, S);
+        for (int q = 0; q < QN; ++q) {
+            const double x = p.R * r[Q0 + q];
+            // 2 / x by the reciprocal estimate and two Newton steps (x > 0)
+            double t = __builtin_amdgcn_rcp(x);
+            t = fma(fma(-x, t, 1.0), t, t);
+            tx[q] = 2.0 * fma(fma(-x, t, 1.0), t, t);
+            jp[q] = 0.0;        // J_{M+1}
+            jc[q] = 0x1p-1000;  // J_M (M even, > 0)
+            S[q] = 2.0 * jc[q];
+            f[q] = 1.0;
         }
-    }
-    __device__ __forceinline__ static double rescale(double &jp, double &jc, double &S) {
-        const double sc = fabs(jc) > 0x1p400 ? 0x1p-400 : 1.0;
-        jp *= sc;
-        jc *= sc;
-        S *= sc;
-        return sc;
+        // eight steps from index l (a multiple of 8) down to l - 8 for every point; S gains
+        // 2 J at each even index; then the rescale check
+        auto steps8 = [&](int l, bool track) {
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                double t = l * tx[q];
+#pragma unroll
+                for (int i = 1; i <= 8; ++i) {
+                    const double jn = fma(t, jc[q], -jp[q]);  // J_{l-i}
+                    jp[q] = jc[q];
+                    jc[q] = jn;
+                    t -= tx[q];
+                    if ((i & 1) == 0) S[q] = fma(2.0, jc[q], S[q]);
+                }
+                const double sc = fabs(jc[q]) > 0x1p400 ? 0x1p-400 : 1.0;
+                jp[q] *= sc;
+                jc[q] *= sc;
+                S[q] *= sc;
+                if (track) f[q] *= sc;
+            }
+        };
+        for (int l = M; l > L0 + NOPS; l -= 8) steps8(l, false);
+        // the block's indices L0 + NOPS - 1 .. L0 (jc is J_{L0+NOPS} here)
+        double jb[QN][NOPS];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            double t = (L0 + NOPS) * tx[q];
+#pragma unroll
+            for (int j = NOPS - 1; j >= 0; --j) {
+                const double jn = fma(t, jc[q], -jp[q]);
+                jp[q] = jc[q];
+                jc[q] = jn;
+                t -= tx[q];
+                jb[q][j] = jc[q];
+                if ((j & 1) == 0) S[q] = fma(2.0, jc[q], S[q]);  // L0 is even
+            }
+        }
+        for (int l = L0; l > 0; l -= 8) steps8(l, true);
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            S[q] -= jc[q];  // J_0 was counted twice
+            // f / S by the reciprocal estimate and two Newton steps (S > 0)
+            double rs = __builtin_amdgcn_rcp(S[q]);
+            rs = fma(fma(-S[q], rs, 1.0), rs, rs);
+            rs = fma(fma(-S[q], rs, 1.0), rs, rs);
+            const double nrm = f[q] * rs;
+            double sn, cs;
+            sincos_cw(p.c_re * r[Q0 + q], sn, cs);
+            const double yr = wr[Q0 + q] * cs * nrm, yi = wr[Q0 + q] * sn * nrm;
+#pragma unroll
+            for (int j = 0; j < NOPS; ++j) {
+                gr[j] = fma(yr, jb[q][j], gr[j]);
+                gi[j] = fma(yi, jb[q][j], gi[j]);
+            }
+        }
     }
     __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
                                             const SweepArgs &p, double2 (&out)[NOPS]) const {
+        static_assert(kQuad == 7, "two groups of 4 and 3 points");
         double gr[NOPS], gi[NOPS];
 #pragma unroll
         for (int j = 0; j < NOPS; ++j) gr[j] = gi[j] = 0.0;
-#pragma unroll
-        for (int q = 0; q < kQuad; ++q) {
-            const double x = p.R * r[q];
-            // 2 / x by the reciprocal estimate and two Newton steps (x > 0)
-            double tx = __builtin_amdgcn_rcp(x);
-            tx = fma(fma(-x, tx, 1.0), tx, tx);
-            tx = 2.0 * fma(fma(-x, tx, 1.0), tx, tx);
-            double sn, cs;
-            sincos_cw(p.c_re * r[q], sn, cs);
-            const double yr = wr[q] * cs, yi = wr[q] * sn;
-            double jp = 0.0, jc = 0x1p-1000, S = 2.0 * jc;  // J_{M+1}, J_M (M even, > 0)
-            for (int l = M; l > L0 + NOPS; l -= 8) {
-                steps8(l, tx, jp, jc, S);
-                rescale(jp, jc, S);
-            }
-            // the block's indices L0 + NOPS - 1 .. L0 (jc is J_{L0+NOPS} here)
-            double jb[NOPS];
-            double t = (L0 + NOPS) * tx;
-#pragma unroll
-            for (int j = NOPS - 1; j >= 0; --j) {
-                const double jn = fma(t, jc, -jp);
-                jp = jc;
-                jc = jn;
-                t -= tx;
-                jb[j] = jc;
-                if ((j & 1) == 0) S = fma(2.0, jc, S);  // L0 is even
-            }
-            double f = 1.0;
-            for (int l = L0; l > 0; l -= 8) {
-                steps8(l, tx, jp, jc, S);
-                f *= rescale(jp, jc, S);
-            }
-            S -= jc;  // J_0 was counted twice
-            const double nrm = f / S;
-#pragma unroll
-            for (int j = 0; j < NOPS; ++j) {
-                const double v = jb[j] * nrm;
-                gr[j] = fma(yr, v, gr[j]);
-                gi[j] = fma(yi, v, gi[j]);
-            }
-        }
+        group<0, 4>(r, wr, p, gr, gi);
+        group<4, 3>(r, wr, p, gr, gi);
 #pragma unroll
         for (int j = 0; j < NOPS; ++j) out[j] = make_double2(gr[j], gi[j]);
     }

@@ -31,12 +31,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16 bits, round to nearest even (finite inputs)
-__device__ __forceinline__ short bf16_bits(float f) {
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
+// FP32 -> BF16 bits, round to nearest even (the hardware conversion on gfx950)
+__device__ __forceinline__ short bf16_bits(float f) { return __builtin_bit_cast(short, (__bf16)f); }
 
 template <Prec P>
 struct Lp;

@@ -9,8 +9,9 @@ compared on.
 The paper's own meshes (a unit cube with 864 triangles, a unit sphere with 384
 triangles, an industrial pump casing) are not available; the stand-ins are seeded
 synthetic meshes of the same kind (closed, flat triangles, Dirichlet single layer):
-icospheres at subdivision level L (20*4**L triangles) and perturbed variants, and box
-surfaces meshed by uniform face grids.
+icospheres at subdivision level L (20*4**L triangles) and perturbed variants, class-I
+geodesic spheres of any frequency f (20*f**2 triangles) scaled to seeded ellipsoids, and
+box surfaces meshed by uniform face grids.
 """
 from __future__ import annotations
 
@@ -22,6 +23,8 @@ __all__ = [
     "icosphere",
     "perturbed_icosphere",
     "ellipsoid",
+    "geodesic_sphere",
+    "ellipsoid_batch",
     "probe_block",
     "mesh_edges_ok",
 ]
@@ -100,6 +103,63 @@ def ellipsoid(level: int, semi_axes):
     """Icosphere scaled to an ellipsoid with the given semi-axes (ax, ay, az)."""
     xyz, tri = icosphere(level)
     return xyz * np.asarray(semi_axes, dtype=np.float64)[None, :], tri
+
+
+def geodesic_sphere(freq: int):
+    """Class-I geodesic sphere of frequency f: every icosahedron face carries the uniform
+    triangular grid of its barycentric points (i, j, f - i - j) / f, each grid triangle
+    keeps the face's orientation, and the grid points are projected radially onto the unit
+    sphere.  Points on a shared icosahedron edge or vertex are created once (keyed by
+    their nonzero barycentric weights on the icosahedron's vertices), so the surface is
+    closed.  Returns (xyz float64 [10 f^2 + 2, 3], tri int32 [20 f^2, 3])."""
+    f = int(freq)
+    if f < 1:
+        raise ValueError("frequency must be >= 1")
+    v, faces = icosahedron()
+    index: dict[tuple, int] = {}
+    pts = []
+
+    def vid(a, b, c, i, j):
+        w = {a: f - i - j}
+        w[b] = w.get(b, 0) + i
+        w[c] = w.get(c, 0) + j
+        key = tuple(sorted((k, x) for k, x in w.items() if x))
+        k = index.get(key)
+        if k is None:
+            p = ((f - i - j) * v[a] + i * v[b] + j * v[c]) / f
+            pts.append(p / np.linalg.norm(p))
+            k = len(pts) - 1
+            index[key] = k
+        return k
+
+    tris = []
+    for a, b, c in faces:
+        for i in range(f):
+            for j in range(f - i):
+                tris.append((vid(a, b, c, i, j), vid(a, b, c, i + 1, j), vid(a, b, c, i, j + 1)))
+                if i + j < f - 1:
+                    tris.append((vid(a, b, c, i + 1, j), vid(a, b, c, i + 1, j + 1), vid(a, b, c, i, j + 1)))
+    return np.asarray(pts, dtype=np.float64), np.asarray(tris, dtype=np.int32)
+
+
+def ellipsoid_batch(count: int = 64, seed: int = 4, freq=(10, 44), axes=(0.5, 1.5), centre=(3.0, 7.0)):
+    """A seeded batch of uneven ellipsoid meshes, each with the real centre of its own
+    contour.  From NumPy's PCG64(seed), per mesh in order: the geodesic frequency
+    f ~ U{freq[0] .. freq[1]} (20 f^2 triangles), three semi-axes ~ U[axes], and the
+    centre ~ U[centre].  Returns a list of (xyz, tri, semi_axes, centre) tuples; meshes of
+    equal frequency share one geodesic sphere before scaling."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cache: dict[int, tuple] = {}
+    out = []
+    for _ in range(int(count)):
+        f = int(rng.integers(freq[0], freq[1] + 1))
+        ax = rng.uniform(axes[0], axes[1], size=3)
+        c = float(rng.uniform(centre[0], centre[1]))
+        if f not in cache:
+            cache[f] = geodesic_sphere(f)
+        xyz, tri = cache[f]
+        out.append((xyz * ax[None, :], tri, ax, c))
+    return out
 
 
 def box_surface(dims=(1.0, 0.8, 0.6), counts=(126, 101, 76)):

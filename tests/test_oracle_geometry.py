@@ -185,3 +185,42 @@ def test_box_surface_mesh():
         on = np.isclose(xyz[:, 0], 0) | np.isclose(xyz[:, 0], a) | np.isclose(xyz[:, 1], 0) | \
             np.isclose(xyz[:, 1], b) | np.isclose(xyz[:, 2], 0) | np.isclose(xyz[:, 2], c)
         assert on.all()
+
+
+def test_geodesic_sphere_mesh():
+    """Class-I geodesic spheres: 20 f^2 triangles and 10 f^2 + 2 vertices, closed, every
+    vertex on the unit sphere, every triangle oriented outward; f = 1 is the icosahedron
+    and f = 2 has exactly the vertex set of the once-split icosphere (the midpoints of flat
+    edges projected); the enclosed volume (divergence theorem) grows toward 4 pi / 3."""
+    vols = []
+    for f in (1, 2, 3, 5, 12):
+        xyz, tri = synth.geodesic_sphere(f)
+        assert tri.shape == (20 * f * f, 3) and xyz.shape == (10 * f * f + 2, 3)
+        assert synth.mesh_edges_ok(tri)
+        assert np.allclose(np.linalg.norm(xyz, axis=1), 1.0, atol=1e-14)
+        P = xyz[tri]
+        nrm = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+        assert np.all((nrm * P.mean(axis=1)).sum(axis=1) > 0)
+        vols.append((nrm * P[:, 0]).sum() / 6.0)
+    assert np.all(np.diff(vols) > 0) and vols[-1] < 4 * np.pi / 3 and vols[-1] > 0.99 * 4 * np.pi / 3
+    x1, t1 = synth.icosahedron()
+    xg, tg = synth.geodesic_sphere(1)
+    assert np.array_equal(np.sort(np.round(xg, 13), axis=0), np.sort(np.round(x1, 13), axis=0))
+    xi, _ = synth.icosphere(1)
+    x2, _ = synth.geodesic_sphere(2)
+    assert np.array_equal(np.sort(np.round(x2, 12), axis=0), np.sort(np.round(xi, 12), axis=0))
+
+
+def test_ellipsoid_batch_recipe():
+    """The seeded ellipsoid batch: deterministic, 20 f^2 triangles with f in [10, 44],
+    semi-axes in [0.5, 1.5] (the vertices satisfy the ellipsoid's equation), centres in
+    [3, 7]; a small batch is checked here, the 64-mesh default only for its size range."""
+    a = synth.ellipsoid_batch(count=3, seed=4, freq=(2, 5))
+    b = synth.ellipsoid_batch(count=3, seed=4, freq=(2, 5))
+    for (xa, ta, axa, ca), (xb, tb, axb, cb) in zip(a, b):
+        assert np.array_equal(xa, xb) and np.array_equal(ta, tb) and ca == cb
+        f = int(round((ta.shape[0] / 20) ** 0.5))
+        assert 2 <= f <= 5 and ta.shape[0] == 20 * f * f
+        assert np.all((axa >= 0.5) & (axa <= 1.5)) and 3.0 <= ca <= 7.0
+        assert np.allclose(((xa / axa[None, :]) ** 2).sum(axis=1), 1.0, atol=1e-13)
+        assert synth.mesh_edges_ok(ta)
