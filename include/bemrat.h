@@ -42,6 +42,7 @@ extern "C" {
 #endif
 
 typedef struct bem_mesh *bem_mesh_t;
+typedef struct bem_batch *bem_batch_t;
 
 typedef enum {
     BEM_OK = 0,
@@ -181,6 +182,53 @@ bem_status cheb_moments(bem_mesh_t mesh, double a, double b, int64_t N, int64_t 
 bem_status rr_project(bem_mesh_t mesh, const double *z, int64_t N, const double *U,
                       int64_t m, int64_t ldu, double *Pout, const double *W, int64_t Pw,
                       double *M, int64_t ldm, uint32_t flags, hipStream_t stream);
+
+/* ------------------------------------------------------------- batched form --- */
+
+/* A batch of meshes, each with its own node set and moment weights, whose contour moments
+ * M_i[p] = sum_j W_i[j][p] T_i(z_ij) V_i (as contour_moments, per mesh i) are computed by
+ * one persistent generate-and-contract launch over every mesh's tiles (work items taken
+ * from a device queue, longest first), followed by the per-mesh recombination.
+ * meshes [host]: count handles on the current device (they must outlive the batch and keep
+ * their geometry; the batch holds its own self terms and workspace, so calls on a mesh
+ * handle do not disturb it).  z [host]: count x N complex (row i = nodes of mesh i).
+ * W [host]: count x N x P complex.  m: probe columns of every mesh.  flags: BEM_FORM_AUTO,
+ * BEM_FORM_DIRECT or BEM_FORM_EXPAND with BEM_PREC_F64; one form serves the whole batch
+ * (AUTO: EXPAND when every mesh admits it and it generates fewer operator entries in total,
+ * else DIRECT); BEM_FORM_CHEB and reduced precision return BEM_EUNSUPPORTED.
+ * tune != 0: the column tile (16, 32 or 64 columns, at most what m fills) is chosen by
+ * timing the persistent launch on an even sample of the batch's own work; tune == 0 takes
+ * the per-call sweep's rule.  Computes every self term, uploads the parameter table and
+ * the work list, and synchronises `stream`; all device memory of the batch is allocated
+ * here.  Errors: BEM_EINVAL (null or non-finite arguments, a mesh on another device),
+ * BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE.  On error *out is NULL. */
+bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const double *z, int64_t N,
+                            const double *W, int64_t P, int64_t m, uint32_t flags, int tune,
+                            hipStream_t stream, bem_batch_t *out);
+
+/* Releases the batch and its device memory (synchronises the device first); NULL is
+ * accepted.  The meshes are not released. */
+void bem_batch_destroy(bem_batch_t batch);
+
+/* Layout of the packed blocks (any output may be NULL): rows [host] count + 1 offsets, mesh
+ * i owning packed rows rows[i] .. rows[i+1]-1 (rows[i+1] - rows[i] = its triangle count);
+ * operators [host] count generated operators per mesh; *form the form in use
+ * (BEM_FORM_DIRECT or BEM_FORM_EXPAND); *col_tile the probe columns per tile. */
+bem_status bem_batch_layout(bem_batch_t batch, int64_t *rows, int64_t *operators, uint32_t *form,
+                            int *col_tile);
+
+/* The batch's contour moments.  V: device, rows[count] x m complex, contiguous rows (mesh
+ * i's probe block is rows rows[i] .. rows[i+1]-1).  M: device; mesh i's P blocks of
+ * n_i x m (contiguous, row stride m) start at M + 2 * P * rows[i] * m doubles, block p of
+ * it at + 2 * p * n_i * m more.  Launches kernels only (no allocation, no host
+ * synchronisation, no memset), so the call may be captured into a HIP graph; the batch's
+ * workspace is shared by its calls, which must not overlap in time (one stream at a
+ * time).  Errors: BEM_EINVAL (null batch, V or M not device memory), BEM_EDEVICE. */
+bem_status bem_batch_moments(bem_batch_t batch, const double *V, double *M, hipStream_t stream);
+
+/* Timing of the persistent launch, as bem_set_timing / bem_last_kernel_ms for a mesh. */
+bem_status bem_batch_set_timing(bem_batch_t batch, int on);
+bem_status bem_batch_last_kernel_ms(bem_batch_t batch, float *ms);
 
 /* ---------------------------------------------------------------- diagnostics --- */
 

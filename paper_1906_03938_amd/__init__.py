@@ -14,6 +14,7 @@ from ._lib import (  # noqa: F401
     PREC_F16,
     PREC_F32,
     PREC_F64,
+    Batch,
     BemError,
     Mesh,
     cheb_nodes,

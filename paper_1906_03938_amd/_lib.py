@@ -27,6 +27,8 @@ EXPORTS = [
     "bem_contour_nodes", "bem_cheb_nodes", "bem_self_terms", "bem_assemble_apply",
     "contour_moments", "cheb_moments", "rr_project", "bem_last_form", "bem_set_timing",
     "bem_last_kernel_ms", "bem_stream_status", "bem_last_error",
+    "bem_batch_create", "bem_batch_destroy", "bem_batch_layout", "bem_batch_moments",
+    "bem_batch_set_timing", "bem_batch_last_kernel_ms",
 ]
 
 
@@ -72,9 +74,18 @@ def lib():
     L.bem_stream_status.argtypes = [_vp]
     L.bem_last_error.argtypes = []
     L.bem_last_error.restype = ctypes.c_char_p
+    L.bem_batch_create.argtypes = [ctypes.POINTER(_vp), _i64, _dp, _i64, _dp, _i64, _i64, _u32, ctypes.c_int, _vp,
+                                   ctypes.POINTER(_vp)]
+    L.bem_batch_destroy.argtypes = [_vp]
+    L.bem_batch_destroy.restype = None
+    L.bem_batch_layout.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_u32),
+                                   ctypes.POINTER(ctypes.c_int)]
+    L.bem_batch_moments.argtypes = [_vp, _vp, _vp, _vp]
+    L.bem_batch_set_timing.argtypes = [_vp, ctypes.c_int]
+    L.bem_batch_last_kernel_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("bem_mesh_destroy", "bem_mesh_size", "bem_last_error"):
+        if name not in ("bem_mesh_destroy", "bem_mesh_size", "bem_last_error", "bem_batch_destroy"):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -245,6 +256,82 @@ class Mesh:
     def last_kernel_ms(self):
         ms = ctypes.c_float()
         _check(lib().bem_last_kernel_ms(self._h, ctypes.byref(ms)))
+        return float(ms.value)
+
+
+class Batch:
+    """Several meshes, each with its own nodes z[i] (N complex) and moment weights W[i]
+    (N x P), whose contour moments run as one persistent launch (bem_batch_create).  The
+    probe blocks are packed: mesh i owns rows rows[i]:rows[i+1] of V (rows[-1] x m); the
+    moments come back packed the same way, P blocks per mesh (see split)."""
+
+    def __init__(self, meshes, z, W, m, form=FORM_AUTO, tune=False):
+        meshes = list(meshes)
+        count = len(meshes)
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).reshape(count, -1))
+        N = z.shape[1]
+        W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(count, N, -1))
+        handles = (_vp * count)(*[mm._h for mm in meshes])
+        h = ctypes.c_void_p()
+        _check(lib().bem_batch_create(handles, count, _hp(z), N, _hp(W), W.shape[2], int(m), form, 1 if tune else 0,
+                                      _stream(), ctypes.byref(h)))
+        self._h = h
+        self._meshes = meshes  # the batch reads their geometry
+        self.count, self.N, self.P, self.m = count, N, W.shape[2], int(m)
+        rows = np.zeros(count + 1, dtype=np.int64)
+        ops = np.zeros(count, dtype=np.int64)
+        f = _u32()
+        ct = ctypes.c_int()
+        _check(lib().bem_batch_layout(h, rows.ctypes.data_as(ctypes.POINTER(_i64)),
+                                      ops.ctypes.data_as(ctypes.POINTER(_i64)), ctypes.byref(f), ctypes.byref(ct)))
+        self.rows, self.operators, self.form, self.col_tile = rows, ops, int(f.value), int(ct.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bem_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def moments(self, V, out=None):
+        """Packed moments of the packed probe block V (rows[-1] x m complex128, contiguous)."""
+        torch = _torch()
+        if not isinstance(V, torch.Tensor) or V.dtype != torch.complex128 or not V.is_cuda:
+            raise TypeError("V must be a complex128 CUDA tensor")
+        if tuple(V.shape) != (int(self.rows[-1]), self.m) or not V.is_contiguous():
+            raise ValueError(f"V must be a contiguous ({int(self.rows[-1])}, {self.m}) tensor")
+        M = torch.empty(self.P * int(self.rows[-1]) * self.m, dtype=torch.complex128, device="cuda") \
+            if out is None else out
+        if M.numel() != self.P * int(self.rows[-1]) * self.m or not M.is_contiguous() or not M.is_cuda:
+            raise ValueError("out has the wrong size or layout")
+        _check(lib().bem_batch_moments(self._h, ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(M.data_ptr()),
+                                       _stream()))
+        return M
+
+    def split(self, M):
+        """Views of the packed moments: a list of (P, n_i, m) blocks, one per mesh."""
+        out = []
+        for i in range(self.count):
+            a, b = int(self.rows[i]), int(self.rows[i + 1])
+            out.append(M[self.P * a * self.m:self.P * b * self.m].view(self.P, b - a, self.m))
+        return out
+
+    def set_timing(self, on=True):
+        _check(lib().bem_batch_set_timing(self._h, 1 if on else 0))
+
+    def last_kernel_ms(self):
+        ms = ctypes.c_float()
+        _check(lib().bem_batch_last_kernel_ms(self._h, ctypes.byref(ms)))
         return float(ms.value)
 
 

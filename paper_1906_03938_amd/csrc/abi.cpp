@@ -392,11 +392,10 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
     return plan;
 }
 
-// Self terms for the plan's operators into h->self (L x n_pad).
-bem_status build_self(bem_mesh *h, const Plan &plan, Params &prm, size_t &off_self_kappa,
-                      size_t &off_dft, int &K, hipStream_t s) {
-    const int64_t n_pad = h->dm.n_pad;
-    HIP_TRY(h->self.ensure(sizeof(double2) * (size_t)plan.L * n_pad), "self-term table");
+// Host part of the self terms of the plan's operators: the wavenumbers the self-term kernel
+// evaluates (the nodes for DIRECT; K sample points for the expansion forms, with the DFT
+// weights that turn the samples into expansion coefficients).
+void self_params(const Plan &plan, Params &prm, size_t &off_self_kappa, size_t &off_dft, int &K) {
     if (plan.gen == bemrat::Gen::Direct) {
         std::vector<double> k(2 * plan.L);
         for (int l = 0; l < plan.L; ++l) {
@@ -405,7 +404,7 @@ bem_status build_self(bem_mesh *h, const Plan &plan, Params &prm, size_t &off_se
         }
         off_self_kappa = prm.add(k.data(), k.size());
         K = 0;
-        return BEM_OK;
+        return;
     }
     if (plan.gen == bemrat::Gen::Cheb) {
         // Chebyshev coefficients of T_aa(alpha + beta xi) from K first-kind points (DCT-II),
@@ -427,8 +426,7 @@ bem_status build_self(bem_mesh *h, const Plan &plan, Params &prm, size_t &off_se
         }
         off_self_kappa = prm.add(k.data(), k.size());
         off_dft = prm.add(F.data(), F.size());
-        HIP_TRY(h->aux.ensure(sizeof(double2) * (size_t)K * n_pad), "self-term samples");
-        return BEM_OK;
+        return;
     }
     // Expansion: sample T_aa on K points of the circle |kappa - c| = R and take the
     // Taylor coefficients by the trapezoidal (DFT) rule: S_l = (1/K) sum_k T_aa(c + R e^{i phi_k}) e^{-i l phi_k}.
@@ -448,50 +446,40 @@ bem_status build_self(bem_mesh *h, const Plan &plan, Params &prm, size_t &off_se
     }
     off_self_kappa = prm.add(k.data(), k.size());
     off_dft = prm.add(F.data(), F.size());
-    HIP_TRY(h->aux.ensure(sizeof(double2) * (size_t)K * n_pad), "self-term samples");
+}
+
+// Self terms for the plan's operators into h->self (L x n_pad).
+bem_status build_self(bem_mesh *h, const Plan &plan, Params &prm, size_t &off_self_kappa,
+                      size_t &off_dft, int &K, hipStream_t) {
+    const int64_t n_pad = h->dm.n_pad;
+    HIP_TRY(h->self.ensure(sizeof(double2) * (size_t)plan.L * n_pad), "self-term table");
+    self_params(plan, prm, off_self_kappa, off_dft, K);
+    if (K > 0) HIP_TRY(h->aux.ensure(sizeof(double2) * (size_t)K * n_pad), "self-term samples");
     return BEM_OK;
 }
 
-// Runs self terms + sweep for `plan` on probe block V; Z receives L blocks (zstride, ldz).
-bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, int64_t ldv,
-                     double2 *Z, int64_t ldz, int64_t zstride, Params &prm, size_t off_self_kappa,
-                     size_t off_dft, int K, size_t off_tables, hipStream_t s) {
-    const DeviceMesh &dm = h->dm;
-    const double *pbase = h->params.as<double>();
-    if (plan.gen == bemrat::Gen::Direct) {
-        HIP_TRY(bemrat::launch_self_terms(dm, reinterpret_cast<const double2 *>(pbase + off_self_kappa),
-                                          plan.L, h->self.as<double2>(), dm.n_pad, s),
-                "self-term kernel");
-    } else {
-        HIP_TRY(bemrat::launch_self_terms(dm, reinterpret_cast<const double2 *>(pbase + off_self_kappa), K,
-                                          h->aux.as<double2>(), dm.n_pad, s),
-                "self-term kernel");
-        HIP_TRY(bemrat::launch_coef_dft(h->aux.as<double2>(), dm.n_pad, K,
-                                        reinterpret_cast<const double2 *>(pbase + off_dft), plan.L,
-                                        h->self.as<double2>(), s),
-                "self-term expansion kernel");
-    }
-    // zero-padded copy of the probe block read by the sweep
-    const int64_t m_pad = plan.prec == bemrat::Prec::F64 ? bemrat::sweep_m_pad(m) : bemrat::sweep_lp_m_pad(m);
-    const size_t np = (size_t)dm.n_pad * m_pad;
-    HIP_TRY(h->probe.ensure(np * sizeof(double2)), "probe copy");
-    double2 *Vp2 = h->probe.as<double2>();
-    HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V), ldv, dm.n, m, dm.n_pad, m_pad, Vp2, s),
-            "probe copy kernel");
+// Launches the self-term kernels of a plan (parameters at pbase, see self_params): the
+// L x n_pad table `self`, through the K x n_pad samples `aux` for the expansion forms.
+hipError_t launch_self(const DeviceMesh &dm, const Plan &plan, const double *pbase, size_t off_self_kappa,
+                       size_t off_dft, int K, double2 *aux, double2 *self, hipStream_t s) {
+    const double2 *kap = reinterpret_cast<const double2 *>(pbase + off_self_kappa);
+    if (plan.gen == bemrat::Gen::Direct) return bemrat::launch_self_terms(dm, kap, plan.L, self, dm.n_pad, s);
+    hipError_t e = bemrat::launch_self_terms(dm, kap, K, aux, dm.n_pad, s);
+    if (e != hipSuccess) return e;
+    return bemrat::launch_coef_dft(aux, dm.n_pad, K, reinterpret_cast<const double2 *>(pbase + off_dft), plan.L, self,
+                                   s);
+}
+
+// Sweep arguments of a plan on one mesh (probe copy, output and precision fields are
+// filled by the caller).
+bemrat::SweepArgs sweep_args(const DeviceMesh &dm, const Plan &plan, const double *pbase, size_t off_self_kappa,
+                             size_t off_tables, const double2 *self) {
     bemrat::SweepArgs a{};
-    a.Vp2 = Vp2;
-    a.m_pad = m_pad;
     a.colloc = dm.colloc;
     a.quad = dm.quad;
-    a.self = h->self.as<double2>();
-    a.V = reinterpret_cast<const double2 *>(V);
-    a.ldv = ldv;
-    a.Z = Z;
-    a.ldz = ldz;
-    a.zstride = zstride;
+    a.self = self;
     a.n = dm.n;
     a.n_pad = dm.n_pad;
-    a.m = m;
     a.L = plan.L;
     a.kappa = reinterpret_cast<const double2 *>(pbase + off_self_kappa);
     a.c_re = plan.c.real();
@@ -503,6 +491,33 @@ bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, 
     a.inv_fact = pbase + off_tables;
     a.inv_int = pbase + off_tables + bemrat::kMaxTaylor;
     a.miller_M = plan.miller_M;
+    return a;
+}
+
+// Runs self terms + sweep for `plan` on probe block V; Z receives L blocks (zstride, ldz).
+bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, int64_t ldv,
+                     double2 *Z, int64_t ldz, int64_t zstride, Params &prm, size_t off_self_kappa,
+                     size_t off_dft, int K, size_t off_tables, hipStream_t s) {
+    const DeviceMesh &dm = h->dm;
+    const double *pbase = h->params.as<double>();
+    HIP_TRY(launch_self(dm, plan, pbase, off_self_kappa, off_dft, K, h->aux.as<double2>(), h->self.as<double2>(), s),
+            "self-term kernel");
+    // zero-padded copy of the probe block read by the sweep
+    const int64_t m_pad = plan.prec == bemrat::Prec::F64 ? bemrat::sweep_m_pad(m) : bemrat::sweep_lp_m_pad(m);
+    const size_t np = (size_t)dm.n_pad * m_pad;
+    HIP_TRY(h->probe.ensure(np * sizeof(double2)), "probe copy");
+    double2 *Vp2 = h->probe.as<double2>();
+    HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V), ldv, dm.n, m, dm.n_pad, m_pad, Vp2, s),
+            "probe copy kernel");
+    bemrat::SweepArgs a = sweep_args(dm, plan, pbase, off_self_kappa, off_tables, h->self.as<double2>());
+    a.Vp2 = Vp2;
+    a.m_pad = m_pad;
+    a.V = reinterpret_cast<const double2 *>(V);
+    a.ldv = ldv;
+    a.Z = Z;
+    a.ldz = ldz;
+    a.zstride = zstride;
+    a.m = m;
     if (h->timing) HIP_TRY(hipEventRecord(h->ev0, s), "event record");
     if (plan.prec == bemrat::Prec::F64) {
         HIP_TRY(bemrat::launch_sweep(plan.gen, a, s), "sweep kernel");
@@ -973,6 +988,331 @@ bem_status bem_last_kernel_ms(bem_mesh_t h, float *ms) {
     DeviceGuard guard(h->device);
     HIP_TRY(hipEventSynchronize(h->ev1), "event synchronize");
     HIP_TRY(hipEventElapsedTime(ms, h->ev0, h->ev1), "event elapsed time");
+    return BEM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched form ---
+
+struct bem_batch {
+    int device = 0;
+    int64_t count = 0, N = 0, P = 0, m = 0, m_pad = 0;
+    int variant = 0;   // bemrat::BatchVariant shared by every mesh
+    int cb = 0;        // 16-column groups per tile
+    int grid = 0;      // persistent blocks (one per compute unit)
+    uint32_t form = 0; // BEM_FORM_DIRECT or BEM_FORM_EXPAND
+    std::vector<bem_mesh *> meshes;
+    std::vector<int64_t> rows;   // count + 1: first packed row of each mesh
+    std::vector<int64_t> ops;    // generated operators per mesh
+    std::vector<size_t> off_coef, off_probe, off_Z;
+    int64_t nitems = 0;
+    Buffer params, self, probe, Z, table, items, counter;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timing = false, timed = false;
+};
+
+namespace {
+
+// Work items (mesh, row block, column block, operator block) of a batch for a column tile of
+// cb 16-column groups: meshes with the most source triangles first (their tiles run longest),
+// and within a mesh the row block varies fastest, as in the per-call grid.
+std::vector<int4> batch_items(const bem_batch *b, int cb) {
+    std::vector<int64_t> order(b->count);
+    for (int64_t i = 0; i < b->count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        return b->meshes[x]->dm.n_pad > b->meshes[y]->dm.n_pad;
+    });
+    const int64_t cblocks = (b->m + 16 * cb - 1) / (16 * cb);
+    std::vector<int4> items;
+    for (int64_t i : order) {
+        const int64_t rblocks = b->meshes[i]->dm.n_pad / 16;
+        const int64_t oblocks = (b->ops[i] + 7) / 8;
+        for (int64_t ob = 0; ob < oblocks; ++ob)
+            for (int64_t c = 0; c < cblocks; ++c)
+                for (int64_t r = 0; r < rblocks; ++r) items.push_back(make_int4((int)i, (int)r, (int)c, (int)ob));
+    }
+    return items;
+}
+
+bem_status batch_upload_items(bem_batch *b, const std::vector<int4> &items, hipStream_t s) {
+    HIP_TRY(b->items.ensure(sizeof(int4) * std::max<size_t>(items.size(), 1)), "work items");
+    HIP_TRY(hipMemcpyAsync(b->items.ptr, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s),
+            "work item upload");
+    HIP_TRY(hipStreamSynchronize(s), "work item upload");
+    b->nitems = (int64_t)items.size();
+    return BEM_OK;
+}
+
+// Tile autotuner: times the persistent sweep for every admissible column tile on an even
+// sample of the batch's own work (whole (mesh, row block, operator block) groups, so every
+// candidate does the same arithmetic), after one untimed pass, and keeps the fastest.
+bem_status batch_tune(bem_batch *b, hipStream_t s) {
+    const int max_cb = bemrat::batch_col_tile(b->m);
+    int best_cb = max_cb;
+    float best = 0.0f;
+    for (int cb = 1; cb <= max_cb; cb *= 2) {
+        const std::vector<int4> all = batch_items(b, cb);
+        const int64_t cblocks = (b->m + 16 * cb - 1) / (16 * cb);
+        // items come in runs of rblocks per (mesh, operator block, column block); take every
+        // stride-th row of the cb-independent (mesh, operator block, row block) groups
+        const int64_t groups = (int64_t)all.size() / cblocks;
+        const int64_t want = 4 * (int64_t)b->grid;
+        const int64_t stride = std::max<int64_t>(1, groups / want);
+        std::vector<int4> sample;
+        for (const int4 &it : all) {
+            const int64_t key = (int64_t)it.y + 1000003LL * ((int64_t)it.x * 64 + it.w);
+            if (key % stride == 0) sample.push_back(it);
+        }
+        bem_status st = batch_upload_items(b, sample, s);
+        if (st != BEM_OK) return st;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(hipEventRecord(b->ev0, s), "event record");
+            HIP_TRY(bemrat::launch_sweep_batch(b->variant, cb, b->table.as<bemrat::BatchEntry>(), b->items.as<int4>(),
+                                               (int)b->nitems, b->counter.as<unsigned>(), b->grid, s),
+                    "batched sweep kernel");
+            HIP_TRY(hipEventRecord(b->ev1, s), "event record");
+            HIP_TRY(hipEventSynchronize(b->ev1), "event synchronize");
+            HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1), "event elapsed time");
+        }
+        if (cb == 1 || ms < best) {
+            best = ms;
+            best_cb = cb;
+        }
+    }
+    b->cb = best_cb;
+    return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bem_batch_destroy(bem_batch_t b) {
+    if (!b) return;
+    DeviceGuard guard(b->device);
+    (void)hipDeviceSynchronize();
+    b->params.release();
+    b->self.release();
+    b->probe.release();
+    b->Z.release();
+    b->table.release();
+    b->items.release();
+    b->counter.release();
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    delete b;
+}
+
+bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const double *z, int64_t N, const double *W,
+                            int64_t P, int64_t m, uint32_t flags, int tune, hipStream_t stream, bem_batch_t *out) {
+    if (!out) return fail(BEM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!meshes || count < 1) return fail(BEM_EINVAL, "need count >= 1 meshes");
+    if (count > (1 << 20)) return fail(BEM_EINVAL, "too many meshes");
+    bem_status st = check_flags(flags);
+    if (st != BEM_OK) return st;
+    const uint32_t form = flags & BEM_FORM_MASK;
+    if (prec_of(flags) != bemrat::Prec::F64) return fail(BEM_EUNSUPPORTED, "the batched form runs in FP64 only");
+    if (form == BEM_FORM_CHEB) return fail(BEM_EUNSUPPORTED, "the batched form takes the DIRECT or EXPAND form");
+    if (!z || N < 1) return fail(BEM_EINVAL, "need z and N >= 1");
+    if (!W || P < 1) return fail(BEM_EINVAL, "need W and P >= 1");
+    if (m < 1) return fail(BEM_EINVAL, "m must be positive");
+    if (!finite_c(W, count * N * P)) return fail(BEM_EINVAL, "W has a non-finite value");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "current device");
+    for (int64_t i = 0; i < count; ++i) {
+        if (!meshes[i]) return fail(BEM_EINVAL, "a mesh is NULL");
+        if (meshes[i]->device != dev) return fail(BEM_EINVAL, "every mesh must live on the current device");
+        if ((st = check_kappas(meshes[i], z + 2 * i * N, N, "z")) != BEM_OK) return st;
+    }
+    // one operator family for the launch: EXPAND for every mesh when every mesh admits it
+    // (and, for AUTO, when it generates fewer operator entries than DIRECT), else DIRECT
+    std::vector<Plan> plans(count);
+    bool all_expand = form != BEM_FORM_DIRECT;
+    double cost_e = 0.0, cost_d = 0.0;
+    for (int64_t i = 0; i < count && all_expand; ++i) {
+        plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_EXPAND);
+        const double n = (double)meshes[i]->dm.n;
+        all_expand = plans[i].gen == bemrat::Gen::Taylor;
+        cost_e += plans[i].L * n * n;
+        cost_d += (double)N * n * n;
+    }
+    if (form == BEM_FORM_AUTO && all_expand && !(cost_e < cost_d)) all_expand = false;
+    if (!all_expand)
+        for (int64_t i = 0; i < count; ++i) plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_DIRECT);
+    bool decay = false;
+    for (const Plan &p : plans) {
+        if (p.gen == bemrat::Gen::Taylor) decay |= p.c.imag() != 0.0;
+        for (const cplx &k : p.kappa) decay |= k.imag() != 0.0;
+    }
+
+    auto *b = new (std::nothrow) bem_batch;
+    if (!b) return fail(BEM_ENOMEM, "host allocation failed");
+    b->device = dev;
+    b->count = count;
+    b->N = N;
+    b->P = P;
+    b->m = m;
+    b->form = all_expand ? BEM_FORM_EXPAND : BEM_FORM_DIRECT;
+    b->variant = bemrat::batch_variant(all_expand ? bemrat::Gen::Taylor : bemrat::Gen::Direct, decay);
+    b->meshes.assign(meshes, meshes + count);
+    const int max_cb = bemrat::batch_col_tile(m);
+    b->cb = max_cb;
+    b->m_pad = (m + 16 * max_cb - 1) / (16 * max_cb) * (16 * max_cb);
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    b->grid = e == hipSuccess && cus > 0 ? cus : 256;
+
+    // parameters: tables, then per mesh the self-term wavenumbers and combine coefficients
+    Params prm;
+    const size_t off_tables = add_tables(prm);
+    std::vector<size_t> off_k(count), off_dft(count), off_self(count);
+    std::vector<int> K(count);
+    b->rows.assign(count + 1, 0);
+    b->ops.resize(count);
+    b->off_coef.resize(count);
+    b->off_probe.resize(count);
+    b->off_Z.resize(count);
+    size_t self_total = 0, probe_total = 0, z_total = 0, aux_need = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const Plan &plan = plans[i];
+        const DeviceMesh &dm = meshes[i]->dm;
+        self_params(plan, prm, off_k[i], off_dft[i], K[i]);
+        std::vector<cplx> coef((size_t)plan.L * P, 0.0);
+        const double *Wi = W + 2 * i * N * P;
+        for (int64_t j = 0; j < N; ++j)
+            for (int l = 0; l < plan.L; ++l) {
+                const cplx cf = plan.Cf[j * plan.L + l];
+                if (cf == cplx(0.0, 0.0)) continue;
+                for (int64_t p = 0; p < P; ++p)
+                    coef[l * P + p] += cf * cplx(Wi[2 * (j * P + p)], Wi[2 * (j * P + p) + 1]);
+            }
+        b->off_coef[i] = add_complex(prm, coef);
+        b->ops[i] = plan.L;
+        b->rows[i + 1] = b->rows[i] + dm.n;
+        off_self[i] = self_total;
+        self_total += (size_t)plan.L * dm.n_pad;
+        b->off_probe[i] = probe_total;
+        probe_total += (size_t)dm.n_pad * b->m_pad;
+        b->off_Z[i] = z_total;
+        z_total += (size_t)plan.L * dm.n * m;
+        aux_need = std::max(aux_need, (size_t)K[i] * dm.n_pad);
+    }
+    Buffer aux;
+    st = BEM_OK;
+    auto step = [&](hipError_t err, const char *what) {
+        if (st == BEM_OK && err != hipSuccess) st = hip_fail(err, what);
+        return st == BEM_OK;
+    };
+    const size_t pbytes = prm.d.size() * sizeof(double);
+    if (step(b->params.ensure(pbytes), "batch parameters") &&
+        step(hipMemcpy(b->params.ptr, prm.d.data(), pbytes, hipMemcpyHostToDevice), "parameter upload") &&
+        step(b->self.ensure(sizeof(double2) * self_total), "batch self terms") &&
+        step(b->probe.ensure(sizeof(double2) * probe_total), "batch probe copy") &&
+        step(b->Z.ensure(sizeof(double2) * z_total), "batch sweep workspace") &&
+        step(b->table.ensure(sizeof(bemrat::BatchEntry) * count), "batch table") &&
+        step(b->counter.ensure(sizeof(unsigned)), "work counter") &&
+        step(aux.ensure(sizeof(double2) * std::max<size_t>(aux_need, 1)), "self-term samples") &&
+        step(hipEventCreate(&b->ev0), "event") && step(hipEventCreate(&b->ev1), "event")) {
+        const double *pbase = b->params.as<double>();
+        std::vector<bemrat::BatchEntry> table(count);
+        for (int64_t i = 0; i < count && st == BEM_OK; ++i) {
+            const DeviceMesh &dm = meshes[i]->dm;
+            double2 *self = b->self.as<double2>() + off_self[i];
+            if (!step(launch_self(dm, plans[i], pbase, off_k[i], off_dft[i], K[i], aux.as<double2>(), self, stream),
+                      "self-term kernel"))
+                break;
+            bemrat::SweepArgs a = sweep_args(dm, plans[i], pbase, off_k[i], off_tables, self);
+            a.Vp2 = b->probe.as<double2>() + b->off_probe[i];
+            a.m_pad = b->m_pad;
+            a.Z = b->Z.as<double2>() + b->off_Z[i];
+            a.ldz = m;
+            a.zstride = dm.n * m;
+            a.m = m;
+            table[i].args = a;
+            table[i].variant = b->variant;
+        }
+        if (st == BEM_OK &&
+            step(hipMemcpyAsync(b->table.ptr, table.data(), sizeof(bemrat::BatchEntry) * count, hipMemcpyHostToDevice,
+                                stream),
+                 "batch table upload") &&
+            step(hipStreamSynchronize(stream), "batch set-up")) {
+            if (tune) {
+                // the sample runs read the probe copy: give it defined (zero) contents
+                if (step(hipMemsetAsync(b->probe.ptr, 0, sizeof(double2) * probe_total, stream), "probe clear"))
+                    st = batch_tune(b, stream);
+            }
+            if (st == BEM_OK) st = batch_upload_items(b, batch_items(b, b->cb), stream);
+        }
+    }
+    (void)hipStreamSynchronize(stream);
+    aux.release();
+    if (st != BEM_OK) {
+        bem_batch_destroy(b);
+        return st;
+    }
+    if (b->nitems > INT32_MAX) {
+        bem_batch_destroy(b);
+        return fail(BEM_EINVAL, "too many work items");
+    }
+    *out = b;
+    return BEM_OK;
+}
+
+bem_status bem_batch_layout(bem_batch_t b, int64_t *rows, int64_t *operators, uint32_t *form, int *col_tile) {
+    if (!b) return fail(BEM_EINVAL, "batch is NULL");
+    if (rows) std::copy(b->rows.begin(), b->rows.end(), rows);
+    if (operators) std::copy(b->ops.begin(), b->ops.end(), operators);
+    if (form) *form = b->form;
+    if (col_tile) *col_tile = 16 * b->cb;
+    return BEM_OK;
+}
+
+bem_status bem_batch_moments(bem_batch_t b, const double *V, double *M, hipStream_t stream) {
+    if (!b) return fail(BEM_EINVAL, "batch is NULL");
+    DeviceGuard guard(b->device);
+    if (!V || !is_device_ptr(V)) return fail(BEM_EINVAL, "V is not device memory");
+    if (!M || !is_device_ptr(M)) return fail(BEM_EINVAL, "M is not device memory");
+    const int64_t m = b->m;
+    for (int64_t i = 0; i < b->count; ++i) {
+        const DeviceMesh &dm = b->meshes[i]->dm;
+        HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V) + b->rows[i] * m, m, dm.n, m, dm.n_pad,
+                                          b->m_pad, b->probe.as<double2>() + b->off_probe[i], stream),
+                "probe copy kernel");
+    }
+    if (b->timing) HIP_TRY(hipEventRecord(b->ev0, stream), "event record");
+    HIP_TRY(bemrat::launch_sweep_batch(b->variant, b->cb, b->table.as<bemrat::BatchEntry>(), b->items.as<int4>(),
+                                       (int)b->nitems, b->counter.as<unsigned>(), b->grid, stream),
+            "batched sweep kernel");
+    if (b->timing) {
+        HIP_TRY(hipEventRecord(b->ev1, stream), "event record");
+        b->timed = true;
+    }
+    const double *pbase = b->params.as<double>();
+    for (int64_t i = 0; i < b->count; ++i) {
+        const int64_t n = b->meshes[i]->dm.n;
+        HIP_TRY(bemrat::launch_combine(b->Z.as<double2>() + b->off_Z[i], n * m, m, (int)b->ops[i],
+                                       reinterpret_cast<const double2 *>(pbase + b->off_coef[i]), (int)b->P, n, m,
+                                       reinterpret_cast<double2 *>(M) + b->P * b->rows[i] * m, m, stream),
+                "combine kernel");
+    }
+    return BEM_OK;
+}
+
+bem_status bem_batch_set_timing(bem_batch_t b, int on) {
+    if (!b) return fail(BEM_EINVAL, "batch is NULL");
+    b->timing = on != 0;
+    return BEM_OK;
+}
+
+bem_status bem_batch_last_kernel_ms(bem_batch_t b, float *ms) {
+    if (!b || !ms) return fail(BEM_EINVAL, "batch or ms is NULL");
+    if (!b->timed) return fail(BEM_EINVAL, "no timed batch call yet");
+    DeviceGuard guard(b->device);
+    HIP_TRY(hipEventSynchronize(b->ev1), "event synchronize");
+    HIP_TRY(hipEventElapsedTime(ms, b->ev0, b->ev1), "event elapsed time");
     return BEM_OK;
 }
 

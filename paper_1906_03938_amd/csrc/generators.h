@@ -9,6 +9,27 @@
 namespace bemrat {
 namespace {
 
+// Loads and stores through the global address space, for pointers read from a table in
+// device memory (the batched form): the compiler takes those as generic, and generic (flat)
+// accesses also count against the LDS wait counter, so the producers' LDS waits would wait
+// for their prefetches too.  Kernel-argument pointers are known to be global already.
+typedef double gv2 __attribute__((ext_vector_type(2)));
+typedef double gv4 __attribute__((ext_vector_type(4)));
+#define BEMRAT_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ double gld(const double *p, int64_t i) { return ((const BEMRAT_GLOBAL double *)p)[i]; }
+__device__ __forceinline__ double2 gld(const double2 *p, int64_t i) {
+    const gv2 v = ((const BEMRAT_GLOBAL gv2 *)p)[i];
+    return make_double2(v[0], v[1]);
+}
+__device__ __forceinline__ double4 gld(const double4 *p, int64_t i) {
+    const gv4 v = ((const BEMRAT_GLOBAL gv4 *)p)[i];
+    return make_double4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void gst(double2 *p, int64_t i, double2 v) {
+    ((BEMRAT_GLOBAL gv2 *)p)[i] = gv2{v.x, v.y};
+}
+#undef BEMRAT_GLOBAL
+
 constexpr int kStage = 16;               // source triangles per stage
 constexpr int kStageSteps = kStage / 4;  // k-steps per stage
 

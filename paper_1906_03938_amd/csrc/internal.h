@@ -54,6 +54,20 @@ struct SweepArgs {
     const unsigned long long *vmax;  // reduced precision: bits of max |V| (probe scale)
 };
 
+// One mesh of the persistent batched sweep: its arguments (the operator family, a
+// BatchVariant, is common to the launch; `variant` records it per mesh for checking).
+enum BatchVariant : int {
+    kBatchDirectDecay = 0,
+    kBatchDirect = 1,
+    kBatchTaylorDecay = 2,
+    kBatchTaylor = 3,
+};
+struct BatchEntry {
+    SweepArgs args;
+    int variant;  // BatchVariant
+    int pad_;
+};
+
 // Launchers (asynchronous on `stream`; return hipSuccess or the launch error).
 hipError_t launch_prepare_mesh(const double *xyz, const int32_t *tri, int64_t n, int64_t n_pad,
                                DeviceMesh mesh, const double *rule, hipStream_t stream);
@@ -70,6 +84,14 @@ int sweep_lp_ops_per_block(Gen gen, int64_t m);
 int64_t sweep_lp_m_pad(int64_t m);  // column padding of the probe copy for the reduced-precision sweep
 // Coefficient operators one sweep block generates together (they share its base terms).
 int sweep_ops_per_block(int64_t m);
+// Persistent batched FP64 sweep: clears `counter` (a kernel, not a memset), then `grid` blocks
+// take the `nitems` items (mesh, row block, column block, operator block) of `table` meshes,
+// all of operator family `variant`.
+// cb = 16-column groups per tile (1, 2 or 4; batch_col_tile(m) is the per-call kernel's choice).
+hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, const int4 *items, int nitems,
+                              unsigned *counter, int grid, hipStream_t stream);
+int batch_variant(Gen gen, bool decay);  // BatchVariant of an operator family, -1 if none
+int batch_col_tile(int64_t m);
 // Column padding of the probe copy the sweep reads (a multiple of its column tile).
 int64_t sweep_m_pad(int64_t m);
 hipError_t launch_prep_probe(const double2 *V, int64_t ldv, int64_t n, int64_t m, int64_t n_pad, int64_t m_pad,

@@ -46,19 +46,41 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
 // each kind, so the vector work of one fills the gaps of the other's MFMA stream on the
 // shared FP64 pipe.  Both kinds pass one barrier before their loop and run the same
 // nstages + 1 iterations, each ending in exactly one barrier (and none after the loop).
-template <int G, int CB, Gen GEN, bool DECAY>
-__global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
+// LDS of one tile (double-buffered probe rows, entries and quadrature points).
+template <int G, int CB>
+struct TileLds {
+    double2 sV[2][kStage * 16 * CB];      // (Vr, Vi) [triangle][column]
+    double2 sA[2][4 * G * kStage * 16];   // entries [(operator * kStage + triangle) * 16 + row]
+    double4 sQ[2][kStage * kQuad];        // quadrature points [triangle][q]
+};
+
+// Memory accesses of the tile: plain for kernel-argument pointers, explicitly global for
+// pointers taken from the batched form's table (CAST).
+template <bool CAST, class T>
+__device__ __forceinline__ T ld(const T *p, int64_t i) {
+    if constexpr (CAST) return gld(p, i);
+    else return p[i];
+}
+template <bool CAST>
+__device__ __forceinline__ void st(double2 *p, int64_t i, double2 v) {
+    if constexpr (CAST) gst(p, i, v);
+    else p[i] = v;
+}
+
+// One tile: 16 target rows from row0, 16 CB columns from col0, operators L0 .. L0 + 4 G - 1,
+// by the 512 threads of the block.  Used by the per-call kernel (one tile per block) and by
+// the batched persistent kernel (tiles of several meshes taken from a work queue).
+template <int G, int CB, Gen GEN, bool DECAY, bool CAST>
+__device__ __forceinline__ void sweep_tile(const SweepArgs &p, int64_t row0, int64_t col0, int L0,
+                                           TileLds<G, CB> &lds) {
     constexpr int NC = 16 * CB;
     constexpr int NOPS = 4 * G;
     constexpr int VPT = kStage * NC / 256;  // staged probe elements per producer thread (1, 2, 4)
-    __shared__ double2 sV[2][kStage * NC];         // (Vr, Vi) [triangle][column]
-    __shared__ double2 sA[2][NOPS * kStage * 16];  // entries [(operator * kStage + triangle) * 16 + row]
-    __shared__ double4 sQ[2][kStage * kQuad];      // quadrature points [triangle][q]
+    auto &sV = lds.sV;
+    auto &sA = lds.sA;
+    auto &sQ = lds.sQ;
 
     const int tid = threadIdx.x;
-    const int64_t row0 = (int64_t)blockIdx.x * 16;
-    const int64_t col0 = (int64_t)blockIdx.y * NC;
-    const int L0 = blockIdx.z * NOPS;
     const int64_t nstages = p.n_pad / kStage;
 
     if (tid < 256) {
@@ -66,7 +88,7 @@ __global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
         constexpr int QN = kStage * kQuad;  // quadrature points per stage (112)
         const int brow = tid & 15, btri = tid >> 4;
         const int64_t grow = row0 + brow;
-        const double4 xa = p.colloc[grow];
+        const double4 xa = ld<CAST>(p.colloc, grow);
         Generator<NOPS, GEN, DECAY> gen;
         gen.init(p, L0);
         int64_t voff[VPT];
@@ -80,11 +102,11 @@ __global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
         // of stage 1 in registers
         double2 rv[VPT];
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) rv[i] = p.Vp2[voff[i]];
+        for (int i = 0; i < VPT; ++i) rv[i] = ld<CAST>(p.Vp2, voff[i]);
         double4 rq = make_double4(0.0, 0.0, 0.0, 0.0);
         if (tid < QN) {
-            sQ[0][tid] = p.quad[tid];
-            if (nstages > 1) rq = p.quad[QN + tid];
+            sQ[0][tid] = ld<CAST>(p.quad, tid);
+            if (nstages > 1) rq = ld<CAST>(p.quad, QN + tid);
         }
         __syncthreads();
         for (int64_t it = 0; it <= nstages; ++it) {
@@ -109,14 +131,14 @@ __global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
                 // during the generation below
                 if (it + 1 < nstages) {
 #pragma unroll
-                    for (int i = 0; i < VPT; ++i) rv[i] = p.Vp2[voff[i] + (it + 1) * vstride];
+                    for (int i = 0; i < VPT; ++i) rv[i] = ld<CAST>(p.Vp2, voff[i] + (it + 1) * vstride);
                 }
-                if (tid < QN && it + 2 < nstages) rq = p.quad[(it + 2) * QN + tid];
+                if (tid < QN && it + 2 < nstages) rq = ld<CAST>(p.quad, (it + 2) * QN + tid);
                 double2 a[NOPS];
                 gen.entries(r, wr, p, a);
                 if (diag) {
 #pragma unroll
-                    for (int j = 0; j < NOPS; ++j) a[j] = p.self[(int64_t)min(L0 + j, p.L - 1) * p.n_pad + grow];
+                    for (int j = 0; j < NOPS; ++j) a[j] = ld<CAST>(p.self, (int64_t)min(L0 + j, p.L - 1) * p.n_pad + grow);
                 }
 #pragma unroll
                 for (int j = 0; j < NOPS; ++j) sA[buf][(j * kStage + btri) * 16 + brow] = a[j];
@@ -181,11 +203,18 @@ __global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
                 for (int i = 0; i < 4; ++i) {
                     const int64_t row = row0 + ck + 4 * i;
                     const double p1 = P1[g][cb][i], p2 = P2[g][cb][i], p3 = P3[g][cb][i];
-                    if (row < p.n && col < p.m) Z[row * p.ldz + col] = make_double2(p1 - p2, p3 - p1 - p2);
+                    if (row < p.n && col < p.m) st<CAST>(Z, row * p.ldz + col, make_double2(p1 - p2, p3 - p1 - p2));
                 }
             }
         }
     }
+}
+
+template <int G, int CB, Gen GEN, bool DECAY>
+__global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
+    __shared__ TileLds<G, CB> lds;
+    sweep_tile<G, CB, GEN, DECAY, false>(p, (int64_t)blockIdx.x * 16, (int64_t)blockIdx.y * 16 * CB,
+                                  (int)blockIdx.z * 4 * G, lds);
 }
 
 template <int G, int CB, Gen GEN, bool DECAY>
@@ -203,6 +232,37 @@ hipError_t launch_gen(const SweepArgs &p, hipStream_t stream) {
     if (p.m <= 16) return launch_t<2, 1, GEN, DECAY>(p, stream);
     if (p.m <= 32) return launch_t<2, 2, GEN, DECAY>(p, stream);
     return launch_t<2, 4, GEN, DECAY>(p, stream);
+}
+
+// Persistent batched form: one block per compute unit takes tiles of several meshes from a
+// work queue (an atomic counter cleared by batch_reset_kernel before the launch); each item
+// names (mesh, row block, column block, operator block) and the mesh's arguments come from
+// a table in device memory.  Every mesh of one launch uses the same operator family.  Items are ordered longest first by
+// the host, so the tail of the launch holds the shortest tiles.  Every block leaves the
+// loop once the counter passes the item count.
+template <int CB, Gen GEN, bool DECAY>
+__global__ __launch_bounds__(512, 1) void sweep_batch_kernel(const BatchEntry *__restrict__ table,
+                                                             const int4 *__restrict__ items, int nitems,
+                                                             unsigned *__restrict__ counter) {
+    __shared__ TileLds<2, CB> lds;
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(counter, 1u);
+        // the tile's own barriers keep this write behind every read of the previous value
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(s_next);
+        if (idx >= nitems) break;
+        const int4 item = items[idx];
+        const int mesh = __builtin_amdgcn_readfirstlane(item.x);
+        const SweepArgs p = table[mesh].args;
+        sweep_tile<2, CB, GEN, DECAY, true>(p, (int64_t)__builtin_amdgcn_readfirstlane(item.y) * 16,
+                                      (int64_t)__builtin_amdgcn_readfirstlane(item.z) * 16 * CB,
+                                      __builtin_amdgcn_readfirstlane(item.w) * 8, lds);
+    }
+}
+
+__global__ void batch_reset_kernel(unsigned *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
 // Zero-padded copy of the probe block: Vp2[b][c] = V[b][c] for b < n_pad, c < m_pad
@@ -230,6 +290,43 @@ hipError_t launch_prep_probe(const double2 *V, int64_t ldv, int64_t n, int64_t m
     const unsigned grid = (unsigned)((n_pad * m_pad + bs - 1) / bs);
     hipLaunchKernelGGL(prep_probe_kernel, dim3(grid), dim3(bs), 0, stream, V, ldv, n, m, n_pad, m_pad, Vp2);
     return hipGetLastError();
+}
+
+int batch_variant(Gen gen, bool decay) {
+    switch (gen) {
+        case Gen::Direct: return decay ? kBatchDirectDecay : kBatchDirect;
+        case Gen::Taylor: return decay ? kBatchTaylorDecay : kBatchTaylor;
+        default: return -1;
+    }
+}
+
+int batch_col_tile(int64_t m) { return m <= 16 ? 1 : (m <= 32 ? 2 : 4); }
+
+template <Gen GEN, bool DECAY>
+hipError_t launch_batch_gen(int cb, const BatchEntry *table, const int4 *items, int nitems, unsigned *counter,
+                            int grid, hipStream_t stream) {
+    switch (cb) {
+        case 1: hipLaunchKernelGGL((sweep_batch_kernel<1, GEN, DECAY>), dim3(grid), dim3(512), 0, stream, table, items, nitems, counter); break;
+        case 2: hipLaunchKernelGGL((sweep_batch_kernel<2, GEN, DECAY>), dim3(grid), dim3(512), 0, stream, table, items, nitems, counter); break;
+        case 4: hipLaunchKernelGGL((sweep_batch_kernel<4, GEN, DECAY>), dim3(grid), dim3(512), 0, stream, table, items, nitems, counter); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, const int4 *items, int nitems,
+                              unsigned *counter, int grid, hipStream_t stream) {
+    if (grid < 1 || nitems < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (variant) {
+        case kBatchDirectDecay: return launch_batch_gen<Gen::Direct, true>(cb, table, items, nitems, counter, grid, stream);
+        case kBatchDirect: return launch_batch_gen<Gen::Direct, false>(cb, table, items, nitems, counter, grid, stream);
+        case kBatchTaylorDecay: return launch_batch_gen<Gen::Taylor, true>(cb, table, items, nitems, counter, grid, stream);
+        case kBatchTaylor: return launch_batch_gen<Gen::Taylor, false>(cb, table, items, nitems, counter, grid, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_sweep(Gen gen, const SweepArgs &args, hipStream_t stream) {
