@@ -145,6 +145,87 @@ def precision_form():
             "forms": forms, "eigen_box752": eig}
 
 
+BATCH_WORKLOAD = dict(name="ellipsoids-64", count=64, seed=4, freq=(10, 44), axes=(0.5, 1.5), centre=(3.0, 7.0),
+                      radius=1.0, N=32, m=32, P=2)
+
+
+def batched_form():
+    """The batched persistent form on 64 seeded ellipsoids (class-I geodesic frequencies
+    10..44, i.e. 2,000-38,720 triangles, semi-axes in [0.5, 1.5], seed 4), each with its
+    own circle |z - c_i| = 1, c_i in [3, 7], N = 32 nodes, P = 2 moments and m = 32 probes
+    (seeds 4000 + i): one bem_batch_moments call (after the batch's set-up with the tile
+    autotuner and one warm-up call), timed by wall clock and by the library's events around
+    the persistent kernel, beside the same moments by 64 per-mesh contour_moments calls in
+    the same form on the same stream."""
+    import numpy as np
+    import torch
+
+    import paper_1906_03938_amd as bem
+    import synth
+
+    w = BATCH_WORKLOAD
+    spec = synth.ellipsoid_batch(count=w["count"], seed=w["seed"], freq=w["freq"], axes=w["axes"],
+                                 centre=w["centre"])
+    sizes = np.array([t.shape[0] for _, t, _, _ in spec], dtype=np.float64)
+    meshes = [bem.Mesh(x, t) for x, t, _, _ in spec]
+    z, W = [], []
+    for _, _, _, c in spec:
+        zi, _, Wi = bem.contour_nodes(c, w["radius"], w["N"], P=w["P"])
+        z.append(zi)
+        W.append(Wi)
+    z, W = np.array(z), np.array(W)
+    V = [synth.probe_block(int(n), w["m"], seed=4000 + i) for i, n in enumerate(sizes)]
+    Vd = torch.from_numpy(np.concatenate(V, axis=0)).to("cuda")
+    t0 = time.perf_counter()
+    batch = bem.Batch(meshes, z, W, w["m"], tune=True)
+    setup = time.perf_counter() - t0
+    batch.set_timing(True)
+    out = torch.empty(w["P"] * int(batch.rows[-1]) * w["m"], dtype=torch.complex128, device="cuda")
+    batch.moments(Vd, out=out)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.moments(Vd, out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = batch.last_kernel_ms()
+    L = batch.operators.astype(np.float64)
+    units = float(np.sum(w["N"] * sizes ** 2 * w["m"]))
+    flops = float(np.sum(8.0 * L * sizes ** 2 * w["m"]))
+    achieved = flops / (kms * 1e-3) / 1e12
+    # the same moments by one call per mesh
+    Vs = [torch.from_numpy(v).to("cuda") for v in V]
+    outs = [torch.empty((w["P"], int(n), w["m"]), dtype=torch.complex128, device="cuda") for n in sizes]
+    for i, mesh in enumerate(meshes):  # warm-up (workspaces)
+        mesh.contour_moments(z[i], W[i], Vs[i], out=outs[i], form=batch.form)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, mesh in enumerate(meshes):
+        mesh.contour_moments(z[i], W[i], Vs[i], out=outs[i], form=batch.form)
+    torch.cuda.synchronize()
+    wall_seq = time.perf_counter() - t0
+    parts = batch.split(out)
+    same = all(torch.equal(parts[i], outs[i]) for i in range(len(meshes)))
+    res = {
+        "workload": w["name"],
+        "meshes": f"{w['count']} ellipsoids, geodesic frequency U{{{w['freq'][0]}..{w['freq'][1]}}}, "
+                  f"n = {int(sizes.min())}..{int(sizes.max())} (total {int(sizes.sum())}), semi-axes U[0.5, 1.5]",
+        "contours": f"|z - c_i| = {w['radius']}, c_i ~ U[3, 7], N = {w['N']}", "m": w["m"], "moments": w["P"],
+        "form": {bem.FORM_DIRECT: "direct", bem.FORM_EXPAND: "expand"}[batch.form],
+        "operators_generated": [int(x) for x in batch.operators], "col_tile": batch.col_tile,
+        "value": units / wall, "unit": "kernel-entry*RHS/s", "seconds": wall,
+        "persistent_kernel_ms": kms, "setup_seconds_incl_autotune": setup,
+        "achieved_tflops": achieved, "fp64_mfma_peak_tflops": PEAK_FP64_MFMA_TFLOPS,
+        "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+        "per_mesh_calls": {"seconds": wall_seq, "value": units / wall_seq},
+        "speedup_vs_per_mesh_calls": wall_seq / wall,
+        "bitwise_equal_to_per_mesh_calls": bool(same),
+    }
+    batch.close()
+    for mm in meshes:
+        mm.close()
+    return res
+
+
 def eigen_check():
     """Eigenvalues of the sphere-1280 workload (icosphere level 3, |z - 4| < 1.5, N = 32,
     16 probes, seed 1) by the host driver on device sweeps, against the oracle's values
@@ -178,6 +259,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eigen-check", action="store_true")
     ap.add_argument("--no-precision-form", action="store_true")
+    ap.add_argument("--no-batched-form", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -281,6 +363,8 @@ def main():
         out["eigen_check"] = eigen_check()
     if not args.no_precision_form:
         out["precision_form"] = precision_form()
+    if not args.no_batched_form:
+        out["batched_form"] = batched_form()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xyz, tri, z, Vh)
     print(json.dumps(out), flush=True)

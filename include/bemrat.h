@@ -183,6 +183,19 @@ bem_status rr_project(bem_mesh_t mesh, const double *z, int64_t N, const double 
                       int64_t m, int64_t ldu, double *Pout, const double *W, int64_t Pw,
                       double *M, int64_t ldm, uint32_t flags, hipStream_t stream);
 
+/* Dense node combination S = sum_j c_j T(z_j), n x n row-major (row stride lds >= n): the
+ * matrix the inverse iteration solves with -- for the Cauchy form the Schur complement
+ * S = sum_j w_j T(z_j)/(z_j - s) of the linearisation at the shift s (paper, eq. sc2-sc5:
+ * c_j = W[j][0] of bem_contour_nodes), for the Chebyshev form G = sum_l B_l T_l(s) (c_j the
+ * DCT weights times T_l(s), summed over l).  Each entry is generated once on the device
+ * from the same operators as the sweep (flags: BEM_FORM_* as for contour_moments, FP64
+ * only), so S V equals contour_moments with the weights c to rounding.  z, c [host]: N
+ * complex.  S: device, n x lds complex.  Timed by bem_set_timing like a sweep.  Errors:
+ * BEM_EINVAL, BEM_EUNSUPPORTED (reduced precision, CHEB on complex nodes), BEM_ENOMEM,
+ * BEM_EDEVICE. */
+bem_status bem_assemble_sum(bem_mesh_t mesh, const double *z, int64_t N, const double *c, double *S,
+                            int64_t lds, uint32_t flags, hipStream_t stream);
+
 /* ------------------------------------------------------------- batched form --- */
 
 /* A batch of meshes, each with its own node set and moment weights, whose contour moments

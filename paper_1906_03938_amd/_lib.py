@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbemrat.so")
 BEM_OK, BEM_EINVAL, BEM_EMESH, BEM_ENOMEM, BEM_EDEVICE, BEM_EUNSUPPORTED = range(6)
 FORM_AUTO, FORM_DIRECT, FORM_EXPAND, FORM_CHEB = 0, 1, 2, 3
 PREC_F64, PREC_F32, PREC_BF16, PREC_F16 = 0x00, 0x10, 0x20, 0x30
+FORM_MASK, PREC_MASK = 0x03, 0xF0
 STATUS_NAMES = {0: "BEM_OK", 1: "BEM_EINVAL", 2: "BEM_EMESH", 3: "BEM_ENOMEM", 4: "BEM_EDEVICE",
                 5: "BEM_EUNSUPPORTED"}
 
@@ -27,7 +28,7 @@ EXPORTS = [
     "bem_contour_nodes", "bem_cheb_nodes", "bem_self_terms", "bem_assemble_apply",
     "contour_moments", "cheb_moments", "rr_project", "bem_last_form", "bem_set_timing",
     "bem_last_kernel_ms", "bem_stream_status", "bem_last_error",
-    "bem_batch_create", "bem_batch_destroy", "bem_batch_layout", "bem_batch_moments",
+    "bem_assemble_sum", "bem_batch_create", "bem_batch_destroy", "bem_batch_layout", "bem_batch_moments",
     "bem_batch_set_timing", "bem_batch_last_kernel_ms",
 ]
 
@@ -74,6 +75,7 @@ def lib():
     L.bem_stream_status.argtypes = [_vp]
     L.bem_last_error.argtypes = []
     L.bem_last_error.restype = ctypes.c_char_p
+    L.bem_assemble_sum.argtypes = [_vp, _dp, _i64, _dp, _vp, _i64, _u32, _vp]
     L.bem_batch_create.argtypes = [ctypes.POINTER(_vp), _i64, _dp, _i64, _dp, _i64, _i64, _u32, ctypes.c_int, _vp,
                                    ctypes.POINTER(_vp)]
     L.bem_batch_destroy.argtypes = [_vp]
@@ -243,6 +245,18 @@ class Mesh:
             _check(lib().rr_project(self._h, _hp(z), z.size, pu, m, ldu, ctypes.c_void_p(Pout.data_ptr()), None, 0,
                                     None, m, form, _stream()))
         return (Pout, M) if W is not None else Pout
+
+    def assemble_sum(self, z, c, out=None, form=FORM_AUTO):
+        """Dense S = sum_j c_j T(z_j) (n x n complex128 on the device)."""
+        torch = _torch()
+        z = _host_complex(z)
+        c = _host_complex(c)
+        if c.size != z.size:
+            raise ValueError("z and c must have the same length")
+        S = torch.empty((self.n, self.n), dtype=torch.complex128, device="cuda") if out is None else out
+        _check(lib().bem_assemble_sum(self._h, _hp(z), z.size, _hp(c), ctypes.c_void_p(S.data_ptr()), S.stride(0),
+                                      form, _stream()))
+        return S
 
     def last_form(self):
         f = _u32()

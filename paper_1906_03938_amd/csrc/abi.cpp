@@ -969,6 +969,49 @@ bem_status rr_project(bem_mesh_t h, const double *z, int64_t N, const double *U,
     return BEM_OK;
 }
 
+bem_status bem_assemble_sum(bem_mesh_t h, const double *z, int64_t N, const double *c, double *S, int64_t lds,
+                            uint32_t flags, hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_flags(flags);
+    if (st != BEM_OK) return st;
+    if (prec_of(flags) != bemrat::Prec::F64) return fail(BEM_EUNSUPPORTED, "dense assembly runs in FP64 only");
+    if ((st = check_kappas(h, z, N, "z")) != BEM_OK) return st;
+    if (!c) return fail(BEM_EINVAL, "c is NULL");
+    if (!finite_c(c, N)) return fail(BEM_EINVAL, "c has a non-finite value");
+    if ((st = check_block(S, h->dm.n, lds, "S")) != BEM_OK) return st;
+    Plan plan = make_plan(h, z, N, 1, flags);
+    if (plan.unsupported) return fail(BEM_EUNSUPPORTED, "the Chebyshev form needs real nodes in a bounded interval");
+    Params prm;
+    const size_t off_tables = add_tables(prm);
+    size_t off_k = 0, off_dft = 0;
+    int K = 0;
+    if ((st = build_self(h, plan, prm, off_k, off_dft, K, stream)) != BEM_OK) return st;
+    // d_l = sum_j c_j Cf[j][l]
+    std::vector<cplx> d(plan.L, 0.0);
+    for (int64_t j = 0; j < N; ++j)
+        for (int l = 0; l < plan.L; ++l) d[l] += cplx(c[2 * j], c[2 * j + 1]) * plan.Cf[j * plan.L + l];
+    const size_t off_d = add_complex(prm, d);
+    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
+    const double *pbase = h->params.as<double>();
+    HIP_TRY(launch_self(h->dm, plan, pbase, off_k, off_dft, K, h->aux.as<double2>(), h->self.as<double2>(), stream),
+            "self-term kernel");
+    bemrat::SweepArgs a = sweep_args(h->dm, plan, pbase, off_k, off_tables, h->self.as<double2>());
+    if (h->timing) HIP_TRY(hipEventRecord(h->ev0, stream), "event record");
+    HIP_TRY(bemrat::launch_assemble_sum(plan.gen, a, reinterpret_cast<const double2 *>(pbase + off_d),
+                                        reinterpret_cast<double2 *>(S), lds, stream),
+            "assembly kernel");
+    if (h->timing) {
+        HIP_TRY(hipEventRecord(h->ev1, stream), "event record");
+        h->timed = true;
+    }
+    h->last_form = plan.gen == bemrat::Gen::Direct ? BEM_FORM_DIRECT
+                   : plan.gen == bemrat::Gen::Taylor ? BEM_FORM_EXPAND
+                                                     : BEM_FORM_CHEB;
+    h->last_ops = plan.L;
+    return BEM_OK;
+}
+
 bem_status bem_last_form(bem_mesh_t h, uint32_t *form, int64_t *operators) {
     if (!h) return fail(BEM_EINVAL, "mesh is NULL");
     if (form) *form = h->last_form;

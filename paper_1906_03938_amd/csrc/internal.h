@@ -99,6 +99,12 @@ hipError_t launch_prep_probe(const double2 *V, int64_t ldv, int64_t n, int64_t m
 hipError_t launch_combine(const double2 *Z, int64_t zstride, int64_t ldz, int L,
                           const double2 *coef, int P, int64_t n, int64_t m, double2 *out,
                           int64_t ldo, hipStream_t stream);
+// Dense S[a][b] = sum_l d[l] T_l[a][b] (a != b), S[a][a] = sum_l d[l] self_l[a], for the
+// plan's generated operators (row stride lds); operators are generated in blocks of
+// assemble_ops_per_block(), so the plan's L must be a multiple of it for the expansion forms.
+hipError_t launch_assemble_sum(Gen gen, const SweepArgs &p, const double2 *d, double2 *S, int64_t lds,
+                               hipStream_t stream);
+int assemble_ops_per_block();
 hipError_t launch_coef_dft(const double2 *samples, int64_t n_pad, int K, const double2 *F,
                            int L, double2 *out, hipStream_t stream);
 hipError_t launch_project_partial(const double2 *U, int64_t ldu, const double2 *Z,

@@ -10,8 +10,11 @@ residual ||T(lambda) x|| / ||x|| is at most `tol`, otherwise the next outer iter
 restarts from them.
 
 Every application of the BEM operator is a library sweep (contour_moments, cheb_moments, rr_project,
-bem_assemble_apply).  The host only does small dense algebra with LAPACK through SciPy: one
-LU of the n x n Schur complement, QR of n x nu blocks and QZ of the (N+1) nu pencil.
+bem_assemble_apply), and the n x n matrix of the inverse iteration (the Schur complement S,
+or G for the Chebyshev form) is generated densely on the device by bem_assemble_sum.  Its
+LU factorisation runs on the host through SciPy (LAPACK) for small n, or on the device
+through torch.linalg (the ROCm solver library) for large n, where the host would need hours;
+the rest of the host algebra is QR of n x nu blocks and QZ of the (N+1) nu pencil.
 
 Inverse iteration without storing the N v-blocks.  With shift s = c, d_i = z_i - s,
 B_i = w_i T(z_i) and the moment blocks M_p = sum_i B_i d_i^-p, one step of Algorithm 1 --
@@ -34,12 +37,56 @@ import scipy.linalg as sla
 
 from . import _lib
 
+# n above which the inverse iteration's LU runs on the device ("auto")
+DEVICE_LU_MIN_N = 4096
+
+
+class DenseFactor:
+    """LU factorisation of a dense n x n complex matrix held on the device, with solves for
+    host right-hand sides: on the host through SciPy ("host") or on the device through
+    torch.linalg ("device", in place: the matrix passed in is overwritten by its factors);
+    "auto" takes the device above DEVICE_LU_MIN_N unknowns."""
+
+    def __init__(self, S, mode="auto"):
+        import torch
+
+        self.torch = torch
+        n = S.shape[0]
+        self.mode = ("device" if n > DEVICE_LU_MIN_N else "host") if mode == "auto" else mode
+        if self.mode == "device":
+            # factorised in place (S is overwritten): at n = 81920 one complex matrix is 107 GB
+            self.piv = torch.empty(n, dtype=torch.int32, device=S.device)
+            torch.linalg.lu_factor(S, out=(S, self.piv))
+            self.LU = S
+        elif self.mode == "host":
+            self.lu = sla.lu_factor(S.cpu().numpy())
+        else:
+            raise ValueError(f"unknown LU mode {mode!r}")
+
+    def solve(self, B):
+        B = np.asarray(B, dtype=np.complex128)
+        if self.mode == "host":
+            return sla.lu_solve(self.lu, B)
+        Bd = self.torch.from_numpy(np.ascontiguousarray(B)).to("cuda")
+        return self.torch.linalg.lu_solve(self.LU, self.piv, Bd).cpu().numpy()
+
+
+def _assemble(mesh, z, c, flags):
+    """sum_j c_j T(z_j) on the device: generated directly in FP64 (bem_assemble_sum), or, when
+    the sweeps run at reduced precision, by one sweep of the identity at that precision."""
+    if flags & _lib.PREC_MASK:
+        import torch
+
+        eye = torch.eye(mesh.n, dtype=torch.complex128, device="cuda")
+        return mesh.contour_moments(z, np.asarray(c, dtype=np.complex128)[:, None], eye, form=flags)[0]
+    return mesh.assemble_sum(z, c, form=flags)
+
 
 class ContourSolver:
     """Cauchy-approximation eigensolver for T(kappa) x = 0 inside |kappa - c| < radius,
     with N trapezoidal nodes, q inverse-iteration steps per outer iteration."""
 
-    def __init__(self, mesh, c, radius, N, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0):
+    def __init__(self, mesh, c, radius, N, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0, lu="auto"):
         import torch
 
         self.torch = torch
@@ -55,6 +102,7 @@ class ContourSolver:
         self.sweep_flags = int(sweep_prec)  # arithmetic of the subspace sweeps (moments, S)
         self.rr_flags = int(rr_prec)        # arithmetic of the Rayleigh-Ritz projections
         self._S_lu = None
+        self.lu_mode = lu
         self.history = []
 
     def _dev(self, a):
@@ -72,10 +120,11 @@ class ContourSolver:
         return self.mesh.contour_moments(self.z, W, self._dev(x.reshape(-1, 1)), form=self.sweep_flags).cpu().numpy()[0, :, 0]
 
     def schur_lu(self):
-        """LU of S = M_1 = sum_i B_i/(z_i - c), assembled by one sweep of the identity."""
+        """LU of S = M_1 = sum_i B_i/(z_i - c), assembled on the device."""
         if self._S_lu is None:
-            S = self.moments(np.eye(self.n, dtype=np.complex128), [1])[0]
-            self._S_lu = sla.lu_factor(S)
+            S = _assemble(self.mesh, self.z, self.W[:, 0], self.sweep_flags)
+            self._S_lu = DenseFactor(S, self.lu_mode)
+            del S
         return self._S_lu
 
     # -- Algorithm 1, q steps -------------------------------------------------------
@@ -102,7 +151,7 @@ class ContourSolver:
                     acc += swept[k][j - k]                               # M_{j-k+2} a_1^(k)
             if restart:
                 acc += base * rho[None, :] ** (j + 1)
-            u = sla.lu_solve(lu, acc)
+            u = lu.solve(acc)
             if j + 1 < q:
                 a1 = -u
                 orders = list(range(2, q - j + 1))                       # still needed by steps j+1 .. q-1
@@ -171,13 +220,14 @@ class ContourSolver:
         return lam_in[order], X[:, order], res[order], self.max_outer
 
 
-def eigs_in_contour(mesh, c, radius, N, U0, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0):
+def eigs_in_contour(mesh, c, radius, N, U0, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0, lu="auto"):
     """(eigenvalues, eigenvectors, relative residuals, outer iterations) of T(kappa) x = 0
     inside |kappa - c| < radius; U0 is the n x nu starting block.  sweep_prec / rr_prec are
     the library's precision flags (PREC_*) for the subspace sweeps and for the Rayleigh-Ritz
-    projections; residuals are always evaluated in FP64."""
+    projections; residuals are always evaluated in FP64.  lu: where the Schur complement is
+    factorised ("host", "device" or "auto", see DenseFactor)."""
     return ContourSolver(mesh, c, radius, N, q=q, tol=tol, max_outer=max_outer, sweep_prec=sweep_prec,
-                         rr_prec=rr_prec).solve(U0)
+                         rr_prec=rr_prec, lu=lu).solve(U0)
 
 
 class IntervalSolver:
@@ -199,7 +249,7 @@ class IntervalSolver:
     g[l] = T_l(xi_k); it is swept once by cheb_moments (all B_l x) and combined on the host."""
 
     def __init__(self, mesh, a, b, N, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2, sweep_prec=0,
-                 rr_prec=0):
+                 rr_prec=0, lu="auto"):
         import torch
 
         if N < 3:
@@ -227,6 +277,7 @@ class IntervalSolver:
             self.W_age[:, age] = -(self.coef.T @ p)
             g = p[:self.d]
         self._G_lu = None
+        self.lu_mode = lu
         self.history = []
 
     def _tvals(self, xi):
@@ -256,12 +307,13 @@ class IntervalSolver:
         return self.mesh.contour_moments(self.z, W, self._dev(X), form=self.sweep_flags).cpu().numpy()
 
     def g_lu(self):
-        """LU of G = sum_l B_l T_l(s) = sum_j T(kappa_j) sum_l coef[l, j] T_l(s), assembled by
-        one sweep of the identity."""
+        """LU of G = sum_l B_l T_l(s) = sum_j T(kappa_j) sum_l coef[l, j] T_l(s), assembled on
+        the device."""
         if self._G_lu is None:
-            wg = (self.coef.T @ self.t_s)[:, None]
-            G = self.mesh.contour_moments(self.z, wg, self._dev(np.eye(self.n)), form=self.sweep_flags).cpu().numpy()[0]
-            self._G_lu = sla.lu_factor(G)
+            wg = self.coef.T @ self.t_s
+            G = _assemble(self.mesh, self.z, wg, self.sweep_flags)
+            self._G_lu = DenseFactor(G, self.lu_mode)
+            del G
         return self._G_lu
 
     def inverse_iteration(self, u0, xi=None):
@@ -291,7 +343,7 @@ class IntervalSolver:
                     rhs += swept[k][j - k]
             if restart is not None:
                 rhs += restart[j]
-            u = sla.lu_solve(lu, rhs)
+            u = lu.solve(rhs)
             if j + 1 < q:
                 swept.append(self.sweep(u, range(q - 1 - j)))
         return u
@@ -364,10 +416,10 @@ class IntervalSolver:
 
 
 def eigs_in_interval(mesh, a, b, N, U0, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2, sweep_prec=0,
-                     rr_prec=0):
+                     rr_prec=0, lu="auto"):
     """(eigenvalues, eigenvectors, relative residuals, outer iterations) of T(kappa) x = 0
     with kappa in [a, b] (|Im kappa| <= imag_tol (b - a)), from the Chebyshev interpolant
-    with N first-kind nodes; U0 is the n x nu starting block.  sweep_prec / rr_prec as for
-    eigs_in_contour."""
+    with N first-kind nodes; U0 is the n x nu starting block.  sweep_prec / rr_prec / lu as
+    for eigs_in_contour."""
     return IntervalSolver(mesh, a, b, N, q=q, tol=tol, max_outer=max_outer, shift=shift,
-                          imag_tol=imag_tol, sweep_prec=sweep_prec, rr_prec=rr_prec).solve(U0)
+                          imag_tol=imag_tol, sweep_prec=sweep_prec, rr_prec=rr_prec, lu=lu).solve(U0)

@@ -35,6 +35,9 @@ class DenseMesh:
         V = V.numpy()
         return torch.from_numpy(np.stack([self.op.dense(k) @ V for k in kappas]))
 
+    def assemble_sum(self, z, c, form=0):
+        return torch.from_numpy(sum(c[j] * self.op.dense(z[j]) for j in range(len(z))))
+
 
 class CpuSolver(ContourSolver):
     def _dev(self, a):
