@@ -226,6 +226,67 @@ def batched_form():
     return res
 
 
+def large_eigen(freq):
+    """Eigen-extraction at large n (opt-in, --large-eigen F): the class-I geodesic unit sphere of
+    frequency F (n = 20 F^2; F = 45 gives n = 40500, near the largest n the device LU takes),
+    circle |z - 5| = 2, N = 64 nodes, 32 probes (seed 2), q = 10, tol 1e-12; the Schur
+    complement generated densely on the device and factorised there (in place).  Reports the
+    eigenvalues with their relative residuals, the outer iterations, the times of the
+    assembly, of assembly + factorisation and of the whole solve, and the distance of each
+    eigenvalue to the nearest interior Dirichlet eigenvalue of the unit sphere (the
+    discretisation error)."""
+    import numpy as np
+    import torch
+
+    import paper_1906_03938_amd as bem
+    import synth
+    from paper_1906_03938_amd.eig import ContourSolver
+
+    phase = {"inverse_iteration": 0.0, "rayleigh_ritz": 0.0, "residuals": 0.0}
+
+    class Progress(ContourSolver):
+        def _timed(self, name, f, *a):
+            t = time.perf_counter()
+            out = f(*a)
+            phase[name] += time.perf_counter() - t
+            return out
+
+        def inverse_iteration(self, u0, lam=None):
+            return self._timed("inverse_iteration", super().inverse_iteration, u0, lam)
+
+        def rayleigh_ritz(self, U):
+            return self._timed("rayleigh_ritz", super().rayleigh_ritz, U)
+
+        def residuals(self, lam, X):
+            res = self._timed("residuals", super().residuals, lam, X)
+            print(f"large_eigen: outer iteration {len(self.history) + 1}, {lam.size} Ritz values inside, "
+                  f"max residual {res.max() if res.size else float('nan'):.2e}, {time.perf_counter() - t0:.0f} s "
+                  f"({', '.join(f'{k} {v:.0f} s' for k, v in phase.items())})", file=sys.stderr, flush=True)
+            return res
+
+    xyz, tri = synth.geodesic_sphere(freq)
+    n = tri.shape[0]
+    tab = np.loadtxt(os.path.join(ROOT, "tests", "golden", "sphere_dirichlet_eigs.txt"))
+    t0 = time.perf_counter()
+    with bem.Mesh(xyz, tri) as mesh:
+        solver = Progress(mesh, 5.0, 2.0, 64, q=10, tol=1e-12, max_outer=40, lu="device")
+        mesh.set_timing(True)
+        solver.schur_lu()
+        torch.cuda.synchronize()
+        t_asm = mesh.last_kernel_ms() * 1e-3
+        t_lu = time.perf_counter() - t0
+        print(f"large_eigen: n = {n}, assembly {t_asm:.2f} s, assembly + LU {t_lu:.1f} s", file=sys.stderr, flush=True)
+        lam, X, res, outer = solver.solve(synth.probe_block(n, 32, seed=2))
+        torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    dist = [float(np.min(np.abs(l - tab[:, 0]))) for l in lam]
+    return {"workload": f"geodesic unit sphere, frequency {freq}, n={n}", "contour": "|z - 5| = 2, N = 64", "m": 32,
+            "eigenvalues": [[float(l.real), float(l.imag)] for l in lam], "count": int(lam.size),
+            "max_rel_residual": float(res.max()) if res.size else None, "outer_iterations": int(outer),
+            "assembly_seconds": t_asm, "assembly_plus_device_lu_seconds": t_lu, "total_seconds": total,
+            "phase_seconds": phase, "max_distance_to_sphere_eigenvalue": max(dist) if dist else None}
+
+
 def eigen_check():
     """Eigenvalues of the sphere-1280 workload (icosphere level 3, |z - 4| < 1.5, N = 32,
     16 probes, seed 1) by the host driver on device sweeps, against the oracle's values
@@ -260,6 +321,9 @@ def main():
     ap.add_argument("--no-eigen-check", action="store_true")
     ap.add_argument("--no-precision-form", action="store_true")
     ap.add_argument("--no-batched-form", action="store_true")
+    ap.add_argument("--large-eigen", type=int, default=0, metavar="F",
+                    help="also run the eigen-extraction on the geodesic sphere of frequency F (n = 20 F^2) "
+                         "with the LU on the device")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -365,6 +429,8 @@ def main():
         out["precision_form"] = precision_form()
     if not args.no_batched_form:
         out["batched_form"] = batched_form()
+    if args.large_eigen:
+        out["large_eigen"] = large_eigen(args.large_eigen)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xyz, tri, z, Vh)
     print(json.dumps(out), flush=True)

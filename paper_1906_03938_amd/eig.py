@@ -39,6 +39,8 @@ from . import _lib
 
 # n above which the inverse iteration's LU runs on the device ("auto")
 DEVICE_LU_MIN_N = 4096
+# size of the Cauchy pencil above which Rayleigh-Ritz takes the shift-invert Arnoldi route
+DENSE_QZ_MAX = 1200
 
 
 class DenseFactor:
@@ -54,7 +56,11 @@ class DenseFactor:
         n = S.shape[0]
         self.mode = ("device" if n > DEVICE_LU_MIN_N else "host") if mode == "auto" else mode
         if self.mode == "device":
-            # factorised in place (S is overwritten): at n = 81920 one complex matrix is 107 GB
+            if n * n >= 2 ** 31:
+                # the solver library takes 32-bit sizes and leading dimensions; element offsets
+                # of a larger matrix are not guaranteed to be formed in 64 bits
+                raise ValueError(f"device LU supports n <= 46340 (n^2 < 2^31), got n = {n}")
+            # factorised in place (S is overwritten): the factors need no second n x n array
             self.piv = torch.empty(n, dtype=torch.int32, device=S.device)
             torch.linalg.lu_factor(S, out=(S, self.piv))
             self.LU = S
@@ -115,9 +121,13 @@ class ContourSolver:
         return self.mesh.contour_moments(self.z, W, self._dev(X), form=self.sweep_flags).cpu().numpy()
 
     def r_lam(self, x, lam):
-        """R_lam x = sum_i w_i T(z_i) x / (lam - z_i), one column."""
-        W = (self.w / (lam - self.z))[:, None]
-        return self.mesh.contour_moments(self.z, W, self._dev(x.reshape(-1, 1)), form=self.sweep_flags).cpu().numpy()[0, :, 0]
+        """Columns R_lam_k x_k = sum_i w_i T(z_i) x_k / (lam_k - z_i), k < x.shape[1]: one sweep
+        of the block with one weight set per column (column k of weight set k is kept)."""
+        lam = np.atleast_1d(np.asarray(lam, dtype=np.complex128))
+        W = np.ascontiguousarray(self.w[:, None] / (lam[None, :] - self.z[:, None]))
+        R = self.mesh.contour_moments(self.z, W, self._dev(x), form=self.sweep_flags)
+        k = self.torch.arange(lam.size, device=R.device)
+        return R[k, :, k].T.cpu().numpy()
 
     def schur_lu(self):
         """LU of S = M_1 = sum_i B_i/(z_i - c), assembled on the device."""
@@ -138,7 +148,7 @@ class ContourSolver:
             rho = 1.0 / (np.asarray(lam, dtype=np.complex128) - self.c)  # per column
             x = np.asarray(u0, dtype=np.complex128)
             Mx = self.moments(x, list(range(1, q + 2)))                  # M_1 x .. M_{q+1} x
-            Rx = np.stack([self.r_lam(x[:, k], lam[k]) for k in range(x.shape[1])], axis=1)
+            Rx = self.r_lam(x, lam)
             base = Mx[0] + Rx                                            # (M_1 + R_lam) x
             swept.append(None)                                           # no a_1^(0) on restarts
         else:
@@ -176,13 +186,44 @@ class ContourSolver:
             M[sl, sl] = eye
         return A, M
 
+    def ritz_shift_invert(self, Bhat, k):
+        """The k eigenvalues of the reduced pencil closest to the centre c and their y-parts,
+        without the dense QZ (whose cost grows as ((N+1) m)^3).  Shift-invert at c:
+        (A - c M)^-1 M has the finite eigenvalues theta = 1/(lam - c), and on the v-part it is
+        D^-1 - D^-1 E G^-1 B D^-1 with D = (Z - c) (x) I, E = 1 (x) I, B = [B^_0 .. B^_{N-1}]
+        and G = sum_j B^_j/(z_j - c) (block elimination of the arrow-shaped pencil), so a
+        product costs O(N m^2); ARPACK takes the k largest |theta|.  The y-part of the pencil
+        eigenvector belonging to v is G^-1 B D^-1 v."""
+        from scipy.sparse.linalg import LinearOperator, eigs
+
+        N, m = len(Bhat), Bhat[0].shape[0]
+        d = 1.0 / (self.z - self.c)
+        Bh = np.stack(Bhat)
+        G_lu = sla.lu_factor(np.einsum("j,jab->ab", d, Bh))
+
+        def y_of(F):  # G^-1 B D^-1 v for block rows F (N x m x cols)
+            return sla.lu_solve(G_lu, np.einsum("jab,jbc->ac", Bh, d[:, None, None] * F))
+
+        def matvec(f):
+            F = f.reshape(N, m, 1)
+            DF = d[:, None, None] * F
+            y = y_of(F)
+            return (DF - d[:, None, None] * y[None, :, :]).reshape(-1)
+
+        op = LinearOperator((N * m, N * m), matvec=matvec, dtype=np.complex128)
+        theta, Xv = eigs(op, k=k, which="LM", ncv=min(N * m, max(2 * k + 1, 40)), tol=0.0)
+        Y = y_of(Xv.reshape(N, m, k))
+        return self.c + 1.0 / theta, Y
+
     def rayleigh_ritz(self, U):
         P = self.mesh.rr_project(self.z, self._dev(U), form=self.rr_flags).cpu().numpy()
         Bhat = [self.w[j] * P[j] for j in range(self.N)]
+        m = U.shape[1]
+        if (self.N + 1) * m > DENSE_QZ_MAX:
+            return self.ritz_shift_invert(Bhat, min(m, self.N * m - 2))
         A, M = self.reduced_pencil(Bhat)
         with np.errstate(invalid="ignore", divide="ignore"):
             lam, V = sla.eig(A, M)
-        m = U.shape[1]
         Y = V[-m:, :]
         return lam, Y
 

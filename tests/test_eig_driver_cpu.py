@@ -3,6 +3,7 @@ reduced pencil) against the oracle's step-by-step Algorithm 1, using a stand-in 
 sweeps are dense products with the oracle's operator (no GPU involved)."""
 import numpy as np
 import pytest
+import scipy.linalg as sla
 import torch
 
 import synth
@@ -150,3 +151,32 @@ def test_interval_driver_matches_oracle(setup):
     lo, _, reso, _, _ = M.cheb_subspace_iteration(op, 2.5, 5.0, 16, V, q=10, tol=1e-12, imag_tol=1e-2)
     assert res.max() <= 1e-12 and lam.size == lo.size == 4
     assert np.abs(np.sort_complex(lam) - np.sort_complex(lo)).max() <= 1e-10 * np.abs(lo).max()
+
+
+def test_shift_invert_ritz_equals_dense_qz():
+    """The structured shift-invert Ritz step returns the eigenvalues of the reduced Cauchy
+    pencil closest to the centre that the dense QZ returns, with y-parts of the same
+    pencil eigenvectors (up to scale), on random projected blocks."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    c, r, N, m = 4.0, 1.5, 24, 6
+    s, w = M.circle_nodes(c, r, N)
+
+    class Stub(ContourSolver):
+        def __init__(self):
+            self.c, self.N, self.z, self.w = c, N, s, w
+
+    st = Stub()
+    base = [rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)) for _ in range(3)]
+    Bhat = [w[j] * (base[0] + (s[j] - c) * base[1] + (s[j] - c) ** 2 * base[2]) for j in range(N)]
+    A, Mm = st.reduced_pencil(Bhat)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        lam_d, V = sla.eig(A, Mm)
+    fin = np.isfinite(lam_d)
+    order = np.flatnonzero(fin)[np.argsort(np.abs(lam_d[fin] - c))][:m]
+    lam_s, Y = st.ritz_shift_invert(Bhat, m)
+    assert np.allclose(np.sort_complex(lam_s), np.sort_complex(lam_d[order]), rtol=1e-11, atol=1e-11)
+    for k in range(m):
+        j = order[np.argmin(np.abs(lam_d[order] - lam_s[k]))]
+        yd, ys = V[-m:, j], Y[:, k]
+        cos = abs(np.vdot(yd, ys)) / (np.linalg.norm(yd) * np.linalg.norm(ys))
+        assert cos > 1 - 1e-9, (k, cos)
