@@ -206,12 +206,14 @@ bem_status bem_assemble_sum(bem_mesh_t mesh, const double *z, int64_t N, const d
  * their geometry; the batch holds its own self terms and workspace, so calls on a mesh
  * handle do not disturb it).  z [host]: count x N complex (row i = nodes of mesh i).
  * W [host]: count x N x P complex.  m: probe columns of every mesh.  flags: BEM_FORM_AUTO,
- * BEM_FORM_DIRECT or BEM_FORM_EXPAND with BEM_PREC_F64; one form serves the whole batch
- * (AUTO: EXPAND when every mesh admits it and it generates fewer operator entries in total,
- * else DIRECT); BEM_FORM_CHEB and reduced precision return BEM_EUNSUPPORTED.
- * tune != 0: the column tile (16, 32 or 64 columns, at most what m fills) is chosen by
- * timing the persistent launch on an even sample of the batch's own work; tune == 0 takes
- * the per-call sweep's rule.  Computes every self term, uploads the parameter table and
+ * BEM_FORM_DIRECT or BEM_FORM_EXPAND with any BEM_PREC_*; one form serves the whole batch
+ * (AUTO in FP64: EXPAND when every mesh admits it and it generates fewer operator entries in
+ * total, else DIRECT; AUTO at reduced precision: DIRECT); BEM_FORM_CHEB returns
+ * BEM_EUNSUPPORTED.  At reduced precision each mesh's probe block is scaled by its own
+ * largest modulus and its self terms are added in FP64, as in the per-mesh calls.
+ * tune != 0: the column tile (16 to 64 columns in FP64, 16 to 128 at reduced precision, at
+ * most what m fills) is chosen by timing the persistent launch on an even sample of the
+ * batch's own work; tune == 0 takes the per-call sweep's rule.  Computes every self term, uploads the parameter table and
  * the work list, and synchronises `stream`; all device memory of the batch is allocated
  * here.  Errors: BEM_EINVAL (null or non-finite arguments, a mesh on another device),
  * BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE.  On error *out is NULL. */

@@ -1042,6 +1042,7 @@ struct bem_batch {
     int device = 0;
     int64_t count = 0, N = 0, P = 0, m = 0, m_pad = 0;
     int variant = 0;   // bemrat::BatchVariant shared by every mesh
+    bemrat::Prec prec = bemrat::Prec::F64;
     int cb = 0;        // 16-column groups per tile
     int grid = 0;      // persistent blocks (one per compute unit)
     uint32_t form = 0; // BEM_FORM_DIRECT or BEM_FORM_EXPAND
@@ -1050,12 +1051,33 @@ struct bem_batch {
     std::vector<int64_t> ops;    // generated operators per mesh
     std::vector<size_t> off_coef, off_probe, off_Z;
     int64_t nitems = 0;
-    Buffer params, self, probe, Z, table, items, counter;
+    std::vector<size_t> off_self;
+    Buffer params, self, probe, Z, table, items, counter, vmax;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false, timed = false;
 };
 
 namespace {
+
+// Operators one work item generates (FP64: 8; reduced precision: 16 for the direct form up
+// to 64 columns, else 8).
+int batch_ops_per_item(const bem_batch *b, int cb) {
+    if (b->prec == bemrat::Prec::F64) return 8;
+    const bool direct = b->variant == bemrat::kBatchDirect || b->variant == bemrat::kBatchDirectDecay;
+    return bemrat::lp_batch_ops_per_block(direct ? bemrat::Gen::Direct : bemrat::Gen::Taylor, cb);
+}
+
+int batch_max_col_tile(const bem_batch *b) {
+    return b->prec == bemrat::Prec::F64 ? bemrat::batch_col_tile(b->m) : bemrat::lp_batch_col_tile(b->m);
+}
+
+hipError_t batch_launch(const bem_batch *b, int cb, int nitems, hipStream_t s) {
+    if (b->prec == bemrat::Prec::F64)
+        return bemrat::launch_sweep_batch(b->variant, cb, b->table.as<bemrat::BatchEntry>(), b->items.as<int4>(),
+                                          nitems, b->counter.as<unsigned>(), b->grid, s);
+    return bemrat::launch_sweep_lp_batch(b->prec, b->variant, cb, b->table.as<bemrat::BatchEntry>(),
+                                         b->items.as<int4>(), nitems, b->counter.as<unsigned>(), b->grid, s);
+}
 
 // Work items (mesh, row block, column block, operator block) of a batch for a column tile of
 // cb 16-column groups: meshes with the most source triangles first (their tiles run longest),
@@ -1070,7 +1092,8 @@ std::vector<int4> batch_items(const bem_batch *b, int cb) {
     std::vector<int4> items;
     for (int64_t i : order) {
         const int64_t rblocks = b->meshes[i]->dm.n_pad / 16;
-        const int64_t oblocks = (b->ops[i] + 7) / 8;
+        const int ops = batch_ops_per_item(b, cb);
+        const int64_t oblocks = (b->ops[i] + ops - 1) / ops;
         for (int64_t ob = 0; ob < oblocks; ++ob)
             for (int64_t c = 0; c < cblocks; ++c)
                 for (int64_t r = 0; r < rblocks; ++r) items.push_back(make_int4((int)i, (int)r, (int)c, (int)ob));
@@ -1091,7 +1114,7 @@ bem_status batch_upload_items(bem_batch *b, const std::vector<int4> &items, hipS
 // sample of the batch's own work (whole (mesh, row block, operator block) groups, so every
 // candidate does the same arithmetic), after one untimed pass, and keeps the fastest.
 bem_status batch_tune(bem_batch *b, hipStream_t s) {
-    const int max_cb = bemrat::batch_col_tile(b->m);
+    const int max_cb = batch_max_col_tile(b);
     int best_cb = max_cb;
     float best = 0.0f;
     for (int cb = 1; cb <= max_cb; cb *= 2) {
@@ -1112,9 +1135,7 @@ bem_status batch_tune(bem_batch *b, hipStream_t s) {
         float ms = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {
             HIP_TRY(hipEventRecord(b->ev0, s), "event record");
-            HIP_TRY(bemrat::launch_sweep_batch(b->variant, cb, b->table.as<bemrat::BatchEntry>(), b->items.as<int4>(),
-                                               (int)b->nitems, b->counter.as<unsigned>(), b->grid, s),
-                    "batched sweep kernel");
+            HIP_TRY(batch_launch(b, cb, (int)b->nitems, s), "batched sweep kernel");
             HIP_TRY(hipEventRecord(b->ev1, s), "event record");
             HIP_TRY(hipEventSynchronize(b->ev1), "event synchronize");
             HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1), "event elapsed time");
@@ -1143,6 +1164,7 @@ void bem_batch_destroy(bem_batch_t b) {
     b->table.release();
     b->items.release();
     b->counter.release();
+    b->vmax.release();
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     delete b;
@@ -1157,7 +1179,8 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
     bem_status st = check_flags(flags);
     if (st != BEM_OK) return st;
     const uint32_t form = flags & BEM_FORM_MASK;
-    if (prec_of(flags) != bemrat::Prec::F64) return fail(BEM_EUNSUPPORTED, "the batched form runs in FP64 only");
+    const bemrat::Prec prec = prec_of(flags);
+    const bool lp = prec != bemrat::Prec::F64;
     if (form == BEM_FORM_CHEB) return fail(BEM_EUNSUPPORTED, "the batched form takes the DIRECT or EXPAND form");
     if (!z || N < 1) return fail(BEM_EINVAL, "need z and N >= 1");
     if (!W || P < 1) return fail(BEM_EINVAL, "need W and P >= 1");
@@ -1171,12 +1194,15 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
         if ((st = check_kappas(meshes[i], z + 2 * i * N, N, "z")) != BEM_OK) return st;
     }
     // one operator family for the launch: EXPAND for every mesh when every mesh admits it
-    // (and, for AUTO, when it generates fewer operator entries than DIRECT), else DIRECT
+    // (and, for AUTO in FP64, when it generates fewer operator entries than DIRECT), else
+    // DIRECT; at reduced precision AUTO means DIRECT (the expansion's recombination amplifies
+    // rounding errors)
+    const uint32_t pbits = flags & BEM_PREC_MASK;
     std::vector<Plan> plans(count);
-    bool all_expand = form != BEM_FORM_DIRECT;
+    bool all_expand = form == BEM_FORM_EXPAND || (form == BEM_FORM_AUTO && !lp);
     double cost_e = 0.0, cost_d = 0.0;
     for (int64_t i = 0; i < count && all_expand; ++i) {
-        plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_EXPAND);
+        plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_EXPAND | pbits);
         const double n = (double)meshes[i]->dm.n;
         all_expand = plans[i].gen == bemrat::Gen::Taylor;
         cost_e += plans[i].L * n * n;
@@ -1184,7 +1210,7 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
     }
     if (form == BEM_FORM_AUTO && all_expand && !(cost_e < cost_d)) all_expand = false;
     if (!all_expand)
-        for (int64_t i = 0; i < count; ++i) plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_DIRECT);
+        for (int64_t i = 0; i < count; ++i) plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_DIRECT | pbits);
     bool decay = false;
     for (const Plan &p : plans) {
         if (p.gen == bemrat::Gen::Taylor) decay |= p.c.imag() != 0.0;
@@ -1200,8 +1226,9 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
     b->m = m;
     b->form = all_expand ? BEM_FORM_EXPAND : BEM_FORM_DIRECT;
     b->variant = bemrat::batch_variant(all_expand ? bemrat::Gen::Taylor : bemrat::Gen::Direct, decay);
+    b->prec = prec;
     b->meshes.assign(meshes, meshes + count);
-    const int max_cb = bemrat::batch_col_tile(m);
+    const int max_cb = batch_max_col_tile(b);
     b->cb = max_cb;
     b->m_pad = (m + 16 * max_cb - 1) / (16 * max_cb) * (16 * max_cb);
     int cus = 0;
@@ -1211,7 +1238,9 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
     // parameters: tables, then per mesh the self-term wavenumbers and combine coefficients
     Params prm;
     const size_t off_tables = add_tables(prm);
-    std::vector<size_t> off_k(count), off_dft(count), off_self(count);
+    std::vector<size_t> off_k(count), off_dft(count);
+    std::vector<size_t> &off_self = b->off_self;
+    off_self.resize(count);
     std::vector<int> K(count);
     b->rows.assign(count + 1, 0);
     b->ops.resize(count);
@@ -1257,6 +1286,7 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
         step(b->Z.ensure(sizeof(double2) * z_total), "batch sweep workspace") &&
         step(b->table.ensure(sizeof(bemrat::BatchEntry) * count), "batch table") &&
         step(b->counter.ensure(sizeof(unsigned)), "work counter") &&
+        step(b->vmax.ensure(sizeof(unsigned long long) * count), "probe scales") &&
         step(aux.ensure(sizeof(double2) * std::max<size_t>(aux_need, 1)), "self-term samples") &&
         step(hipEventCreate(&b->ev0), "event") && step(hipEventCreate(&b->ev1), "event")) {
         const double *pbase = b->params.as<double>();
@@ -1274,6 +1304,10 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
             a.ldz = m;
             a.zstride = dm.n * m;
             a.m = m;
+            // reduced precision: entries ~ A_b w_q / (4 pi r) scaled to ~ w_q / r; the probe
+            // block by 1 / max |V_i| (reduced per call into the mesh's slot)
+            a.a_scale = 4.0 * 3.14159265358979323846 / meshes[i]->mean_area;
+            a.vmax = b->vmax.as<unsigned long long>() + i;
             table[i].args = a;
             table[i].variant = b->variant;
         }
@@ -1283,8 +1317,10 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
                  "batch table upload") &&
             step(hipStreamSynchronize(stream), "batch set-up")) {
             if (tune) {
-                // the sample runs read the probe copy: give it defined (zero) contents
-                if (step(hipMemsetAsync(b->probe.ptr, 0, sizeof(double2) * probe_total, stream), "probe clear"))
+                // the sample runs read the probe copy and the probe scales: give them defined
+                // contents (zeros; a zero scale reads as 1)
+                if (step(hipMemsetAsync(b->probe.ptr, 0, sizeof(double2) * probe_total, stream), "probe clear") &&
+                    step(hipMemsetAsync(b->vmax.ptr, 0, sizeof(unsigned long long) * count, stream), "scale clear"))
                     st = batch_tune(b, stream);
             }
             if (st == BEM_OK) st = batch_upload_items(b, batch_items(b, b->cb), stream);
@@ -1319,16 +1355,19 @@ bem_status bem_batch_moments(bem_batch_t b, const double *V, double *M, hipStrea
     if (!V || !is_device_ptr(V)) return fail(BEM_EINVAL, "V is not device memory");
     if (!M || !is_device_ptr(M)) return fail(BEM_EINVAL, "M is not device memory");
     const int64_t m = b->m;
+    const bool lp = b->prec != bemrat::Prec::F64;
+    const double2 *V2 = reinterpret_cast<const double2 *>(V);
     for (int64_t i = 0; i < b->count; ++i) {
         const DeviceMesh &dm = b->meshes[i]->dm;
-        HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V) + b->rows[i] * m, m, dm.n, m, dm.n_pad,
-                                          b->m_pad, b->probe.as<double2>() + b->off_probe[i], stream),
+        HIP_TRY(bemrat::launch_prep_probe(V2 + b->rows[i] * m, m, dm.n, m, dm.n_pad, b->m_pad,
+                                          b->probe.as<double2>() + b->off_probe[i], stream),
                 "probe copy kernel");
+        if (lp)
+            HIP_TRY(bemrat::launch_absmax(V2 + b->rows[i] * m, m, dm.n, m, b->vmax.as<unsigned long long>() + i, stream),
+                    "probe scale kernel");
     }
     if (b->timing) HIP_TRY(hipEventRecord(b->ev0, stream), "event record");
-    HIP_TRY(bemrat::launch_sweep_batch(b->variant, b->cb, b->table.as<bemrat::BatchEntry>(), b->items.as<int4>(),
-                                       (int)b->nitems, b->counter.as<unsigned>(), b->grid, stream),
-            "batched sweep kernel");
+    HIP_TRY(batch_launch(b, b->cb, (int)b->nitems, stream), "batched sweep kernel");
     if (b->timing) {
         HIP_TRY(hipEventRecord(b->ev1, stream), "event record");
         b->timed = true;
@@ -1336,6 +1375,11 @@ bem_status bem_batch_moments(bem_batch_t b, const double *V, double *M, hipStrea
     const double *pbase = b->params.as<double>();
     for (int64_t i = 0; i < b->count; ++i) {
         const int64_t n = b->meshes[i]->dm.n;
+        if (lp)
+            HIP_TRY(bemrat::launch_add_diag(b->self.as<double2>() + b->off_self[i], b->meshes[i]->dm.n_pad,
+                                            V2 + b->rows[i] * m, m, b->Z.as<double2>() + b->off_Z[i], m, n * m, n, m,
+                                            (int)b->ops[i], stream),
+                    "diagonal kernel");
         HIP_TRY(bemrat::launch_combine(b->Z.as<double2>() + b->off_Z[i], n * m, m, (int)b->ops[i],
                                        reinterpret_cast<const double2 *>(pbase + b->off_coef[i]), (int)b->P, n, m,
                                        reinterpret_cast<double2 *>(M) + b->P * b->rows[i] * m, m, stream),

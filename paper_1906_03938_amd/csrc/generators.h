@@ -30,6 +30,19 @@ __device__ __forceinline__ void gst(double2 *p, int64_t i, double2 v) {
 }
 #undef BEMRAT_GLOBAL
 
+// Memory accesses of a sweep tile: plain for kernel-argument pointers, explicitly global for
+// pointers taken from the batched form's table (CAST).
+template <bool CAST, class T>
+__device__ __forceinline__ T ld(const T *p, int64_t i) {
+    if constexpr (CAST) return gld(p, i);
+    else return p[i];
+}
+template <bool CAST>
+__device__ __forceinline__ void st(double2 *p, int64_t i, double2 v) {
+    if constexpr (CAST) gst(p, i, v);
+    else p[i] = v;
+}
+
 constexpr int kStage = 16;               // source triangles per stage
 constexpr int kStageSteps = kStage / 4;  // k-steps per stage
 

@@ -91,6 +91,12 @@ int sweep_ops_per_block(int64_t m);
 hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, const int4 *items, int nitems,
                               unsigned *counter, int grid, hipStream_t stream);
 int batch_variant(Gen gen, bool decay);  // BatchVariant of an operator family, -1 if none
+// The same at reduced precision (each table entry carries its mesh's a_scale and probe-scale
+// pointer); cb = 1, 2, 4 or 8 16-column groups, operators per item lp_batch_ops_per_block.
+hipError_t launch_sweep_lp_batch(Prec prec, int variant, int cb, const BatchEntry *table, const int4 *items,
+                                 int nitems, unsigned *counter, int grid, hipStream_t stream);
+int lp_batch_col_tile(int64_t m);              // the per-call reduced-precision column rule
+int lp_batch_ops_per_block(Gen gen, int cb);   // operators per work item
 int batch_col_tile(int64_t m);
 // Column padding of the probe copy the sweep reads (a multiple of its column tile).
 int64_t sweep_m_pad(int64_t m);

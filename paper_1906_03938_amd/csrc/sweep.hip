@@ -54,19 +54,6 @@ struct TileLds {
     double4 sQ[2][kStage * kQuad];        // quadrature points [triangle][q]
 };
 
-// Memory accesses of the tile: plain for kernel-argument pointers, explicitly global for
-// pointers taken from the batched form's table (CAST).
-template <bool CAST, class T>
-__device__ __forceinline__ T ld(const T *p, int64_t i) {
-    if constexpr (CAST) return gld(p, i);
-    else return p[i];
-}
-template <bool CAST>
-__device__ __forceinline__ void st(double2 *p, int64_t i, double2 v) {
-    if constexpr (CAST) gst(p, i, v);
-    else p[i] = v;
-}
-
 // One tile: 16 target rows from row0, 16 CB columns from col0, operators L0 .. L0 + 4 G - 1,
 // by the 512 threads of the block.  Used by the per-call kernel (one tile per block) and by
 // the batched persistent kernel (tiles of several meshes taken from a work queue).

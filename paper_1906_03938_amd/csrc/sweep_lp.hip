@@ -80,22 +80,32 @@ __device__ __forceinline__ int v_index(int c, int tri, int col) {
     return K16 ? (c * NC + col) * kStage + tri : (c * kStage + tri) * NC + col;
 }
 
-template <Prec P, int G, int CB, Gen GEN, bool DECAY>
-__global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
+// LDS of one tile: double-buffered entries (3 components per operator), probe rows and
+// quadrature points.
+template <Prec P, int G, int CB>
+struct LpLds {
+    typedef typename Lp<P>::T T;
+    __attribute__((aligned(16))) T sA[2][4 * G * 3 * kStage * 16];
+    __attribute__((aligned(16))) T sV[2][3 * kStage * 16 * CB];
+    double4 sQ[2][kStage * kQuad];
+};
+
+// One tile: 16 target rows from row0, 16 CB columns from col0, operators L0 .. L0 + 4 G - 1,
+// by the 512 threads of the block (per-call kernel: one tile per block; batched kernel: tiles
+// of several meshes from a work queue, CAST = accesses through the global address space).
+template <Prec P, int G, int CB, Gen GEN, bool DECAY, bool CAST>
+__device__ __forceinline__ void sweep_lp_tile(const SweepArgs &p, int64_t row0, int64_t col0, int L0,
+                                              LpLds<P, G, CB> &lds) {
     typedef Lp<P> LP;
-    typedef typename LP::T T;
     constexpr bool K16 = LP::k16;
     constexpr int NC = 16 * CB;
     constexpr int NOPS = 4 * G;
     constexpr int VPT = kStage * NC / 256;
-    __shared__ __attribute__((aligned(16))) T sA[2][NOPS * 3 * kStage * 16];
-    __shared__ __attribute__((aligned(16))) T sV[2][3 * kStage * NC];
-    __shared__ double4 sQ[2][kStage * kQuad];
+    auto &sA = lds.sA;
+    auto &sV = lds.sV;
+    auto &sQ = lds.sQ;
 
     const int tid = threadIdx.x;
-    const int64_t row0 = (int64_t)blockIdx.x * 16;
-    const int64_t col0 = (int64_t)blockIdx.y * NC;
-    const int L0 = blockIdx.z * NOPS;
     const int64_t nstages = p.n_pad / kStage;
 
     if (tid < 256) {
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
         constexpr int QN = kStage * kQuad;
         const int brow = tid & 15, btri = tid >> 4;
         const int64_t grow = row0 + brow;
-        const double4 xa = p.colloc[grow];
+        const double4 xa = ld<CAST>(p.colloc, grow);
         const double scale = p.a_scale;
         const float vs = (float)(1.0 / vscale_of(p.vmax));
         Generator<NOPS, GEN, DECAY> gen;
@@ -117,13 +127,13 @@ __global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
         float2 rv[VPT];
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
-            const double2 v = vbase[i * vstep];
+            const double2 v = ld<CAST>(vbase, i * vstep);
             rv[i] = make_float2((float)v.x, (float)v.y);
         }
         double4 rq = make_double4(0.0, 0.0, 0.0, 0.0);
         if (tid < QN) {
-            sQ[0][tid] = p.quad[tid];
-            if (nstages > 1) rq = p.quad[QN + tid];
+            sQ[0][tid] = ld<CAST>(p.quad, tid);
+            if (nstages > 1) rq = ld<CAST>(p.quad, QN + tid);
         }
         __syncthreads();
         for (int64_t it = 0; it <= nstages; ++it) {
@@ -154,11 +164,11 @@ __global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
                 if (it + 1 < nstages) {
 #pragma unroll
                     for (int i = 0; i < VPT; ++i) {
-                        const double2 v = vbase[i * vstep + (it + 1) * vstride];
+                        const double2 v = ld<CAST>(vbase, i * vstep + (it + 1) * vstride);
                         rv[i] = make_float2((float)v.x, (float)v.y);
                     }
                 }
-                if (tid < QN && it + 2 < nstages) rq = p.quad[(it + 2) * QN + tid];
+                if (tid < QN && it + 2 < nstages) rq = ld<CAST>(p.quad, (it + 2) * QN + tid);
                 double2 a[NOPS];
                 gen.entries(r, wr, p, a);
                 const double s = diag ? 0.0 : scale;
@@ -252,11 +262,47 @@ __global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
                     const int64_t row = row0 + 4 * ck + i;
                     const double p1 = P1[g][cb][i], p2 = P2[g][cb][i], p3 = P3[g][cb][i];
                     if (row < p.n && col < p.m)
-                        Z[row * p.ldz + col] = make_double2((p1 - p2) * inv, (p3 - p1 - p2) * inv);
+                        st<CAST>(Z, row * p.ldz + col, make_double2((p1 - p2) * inv, (p3 - p1 - p2) * inv));
                 }
             }
         }
     }
+}
+
+template <Prec P, int G, int CB, Gen GEN, bool DECAY>
+__global__ __launch_bounds__(512, 1) void sweep_lp_kernel(SweepArgs p) {
+    __shared__ LpLds<P, G, CB> lds;
+    sweep_lp_tile<P, G, CB, GEN, DECAY, false>(p, (int64_t)blockIdx.x * 16, (int64_t)blockIdx.y * 16 * CB,
+                                               (int)blockIdx.z * 4 * G, lds);
+}
+
+// Persistent batched form at reduced precision: as sweep_batch_kernel (work items
+// (mesh, row block, column block, operator block) from a queue cleared by a kernel, one
+// operator family per launch), with each mesh's entry scale and probe scale in its table
+// entry.
+template <Prec P, int G, int CB, Gen GEN, bool DECAY>
+__global__ __launch_bounds__(512, 1) void sweep_lp_batch_kernel(const BatchEntry *__restrict__ table,
+                                                                const int4 *__restrict__ items, int nitems,
+                                                                unsigned *__restrict__ counter) {
+    __shared__ LpLds<P, G, CB> lds;
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(counter, 1u);
+        // the tile's own barriers keep this write behind every read of the previous value
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(s_next);
+        if (idx >= nitems) break;
+        const int4 item = items[idx];
+        const int mesh = __builtin_amdgcn_readfirstlane(item.x);
+        const SweepArgs p = table[mesh].args;
+        sweep_lp_tile<P, G, CB, GEN, DECAY, true>(p, (int64_t)__builtin_amdgcn_readfirstlane(item.y) * 16,
+                                                  (int64_t)__builtin_amdgcn_readfirstlane(item.z) * 16 * CB,
+                                                  __builtin_amdgcn_readfirstlane(item.w) * 4 * G, lds);
+    }
+}
+
+__global__ void lp_batch_reset_kernel(unsigned *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
 // *out = max over the n x m block of max(|Re v|, |Im v|), as the bits of a non-negative
@@ -342,9 +388,58 @@ hipError_t launch_lp_prec(Gen gen, const SweepArgs &args, hipStream_t stream) {
     }
 }
 
+template <Prec P, int G, int CB, Gen GEN, bool DECAY>
+hipError_t launch_lp_batch_t(const BatchEntry *table, const int4 *items, int nitems, unsigned *counter, int grid,
+                             hipStream_t stream) {
+    hipLaunchKernelGGL((sweep_lp_batch_kernel<P, G, CB, GEN, DECAY>), dim3(grid), dim3(512), 0, stream, table, items,
+                       nitems, counter);
+    return hipGetLastError();
+}
+
+// Direct (with decay: complex nodes) and Taylor families; the operator-per-wave count G
+// follows lp_g: 4 for the direct form up to 64 columns, else 2.
+template <Prec P>
+hipError_t launch_lp_batch_prec(int variant, int cb, const BatchEntry *table, const int4 *items, int nitems,
+                                unsigned *counter, int grid, hipStream_t stream) {
+#define BEMRAT_LP_BATCH_CB(GEN, DECAY, G4)                                                                      \
+    switch (cb) {                                                                                             \
+        case 1: return launch_lp_batch_t<P, G4, 1, GEN, DECAY>(table, items, nitems, counter, grid, stream);  \
+        case 2: return launch_lp_batch_t<P, G4, 2, GEN, DECAY>(table, items, nitems, counter, grid, stream);  \
+        case 4: return launch_lp_batch_t<P, G4, 4, GEN, DECAY>(table, items, nitems, counter, grid, stream);  \
+        case 8: return launch_lp_batch_t<P, 2, 8, GEN, DECAY>(table, items, nitems, counter, grid, stream);   \
+        default: return hipErrorInvalidValue;                                                                 \
+    }
+    switch (variant) {
+        case kBatchDirectDecay: BEMRAT_LP_BATCH_CB(Gen::Direct, true, 4)
+        case kBatchDirect: BEMRAT_LP_BATCH_CB(Gen::Direct, false, 4)
+        case kBatchTaylorDecay: BEMRAT_LP_BATCH_CB(Gen::Taylor, true, 2)
+        case kBatchTaylor: BEMRAT_LP_BATCH_CB(Gen::Taylor, false, 2)
+        default: return hipErrorInvalidValue;
+    }
+#undef BEMRAT_LP_BATCH_CB
+}
+
 }  // namespace
 
 int sweep_lp_ops_per_block(Gen gen, int64_t m) { return 4 * lp_g(gen, m); }
+
+int lp_batch_col_tile(int64_t m) { return lp_cb(m); }
+
+int lp_batch_ops_per_block(Gen gen, int cb) { return gen == Gen::Direct && cb <= 4 ? 16 : 8; }
+
+hipError_t launch_sweep_lp_batch(Prec prec, int variant, int cb, const BatchEntry *table, const int4 *items,
+                                 int nitems, unsigned *counter, int grid, hipStream_t stream) {
+    if (grid < 1 || nitems < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lp_batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (prec) {
+        case Prec::F32: return launch_lp_batch_prec<Prec::F32>(variant, cb, table, items, nitems, counter, grid, stream);
+        case Prec::BF16: return launch_lp_batch_prec<Prec::BF16>(variant, cb, table, items, nitems, counter, grid, stream);
+        case Prec::F16: return launch_lp_batch_prec<Prec::F16>(variant, cb, table, items, nitems, counter, grid, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 int64_t sweep_lp_m_pad(int64_t m) {
     const int64_t nc = 16 * lp_cb(m);

@@ -107,11 +107,54 @@ def test_batch_graph_capture_replays(small):
             assert torch.equal(out, ref), rep
 
 
+U_ROUND = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+U_FACTOR = {"f32": 40.0, "bf16": 2.0, "f16": 2.0}  # as for the per-mesh reduced-precision calls
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f16"])
+def test_batch_reduced_precision(small, prec):
+    """Reduced-precision batch (AUTO = direct form): bitwise equal to the per-mesh calls at the
+    same arithmetic (same tiles, same per-mesh probe scale), and within the arithmetic's
+    tolerance of the oracle."""
+    bem, torch, spec, meshes, z, W, V, N, P, m = small
+    from oracle import method as M
+
+    p = {"f32": bem.PREC_F32, "bf16": bem.PREC_BF16, "f16": bem.PREC_F16}[prec]
+    with bem.Batch(meshes, z, W, m, form=bem.FORM_AUTO | p) as b:
+        assert b.form == bem.FORM_DIRECT
+        Mb = b.split(b.moments(_packed(torch, V)))
+        print(prec, "col tile", b.col_tile, "operators", b.operators, flush=True)
+        errs = []
+        for i, (x, t, _, c) in enumerate(spec):
+            Mi = meshes[i].contour_moments(z[i], W[i], torch.from_numpy(V[i]).to("cuda"), form=bem.FORM_AUTO | p)
+            assert torch.equal(Mi, Mb[i]), i
+            op = M.Operator(x, t)
+            zo, wo = M.circle_nodes(c, 1.0, N)
+            Mo = M.contour_moments(op, zo, M.moment_weights(zo, wo, c, P), V[i])
+            errs += [_rel(Mb[i][q].cpu().numpy(), Mo[q]) for q in range(P)]
+    print(prec, "max rel err vs oracle", max(errs), flush=True)
+    assert max(errs) <= U_FACTOR[prec] * U_ROUND[prec]
+
+
+def test_batch_reduced_precision_tuned_expand(small):
+    """FP32 with the expansion form on request and the autotuned column tile: still bitwise
+    equal to the per-mesh calls in that form."""
+    bem, torch, spec, meshes, z, W, V, N, P, m = small
+    f = bem.FORM_EXPAND | bem.PREC_F32
+    with bem.Batch(meshes, z, W, m, form=f, tune=True) as b:
+        assert b.form == bem.FORM_EXPAND
+        Mb = b.split(b.moments(_packed(torch, V)))
+        print("f32 expand col tile", b.col_tile, flush=True)
+        for i in range(len(meshes)):
+            Mi = meshes[i].contour_moments(z[i], W[i], torch.from_numpy(V[i]).to("cuda"), form=f)
+            assert torch.equal(Mi, Mb[i]), i
+
+
 def test_batch_error_paths(small):
     bem, torch, spec, meshes, z, W, V, N, P, m = small
     from paper_1906_03938_amd import _lib
 
-    for flags in (bem.FORM_CHEB, bem.FORM_AUTO | bem.PREC_F32):
+    for flags in (bem.FORM_CHEB, bem.FORM_CHEB | bem.PREC_F32, bem.FORM_AUTO | 0x40):
         with pytest.raises(bem.BemError) as e:
             bem.Batch(meshes, z, W, m, form=flags)
         assert e.value.status == _lib.BEM_EUNSUPPORTED
