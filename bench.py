@@ -156,7 +156,9 @@ def batched_form():
     (seeds 4000 + i): one bem_batch_moments call (after the batch's set-up with the tile
     autotuner and one warm-up call), timed by wall clock and by the library's events around
     the persistent kernel, beside the same moments by 64 per-mesh contour_moments calls in
-    the same form on the same stream."""
+    the same form on the same stream, and the batch with an FP32 contraction (autotuned; the
+    direct form that AUTO takes at reduced precision, and the expansion form on request) with
+    its error against the FP64 result."""
     import numpy as np
     import torch
 
@@ -205,6 +207,30 @@ def batched_form():
     wall_seq = time.perf_counter() - t0
     parts = batch.split(out)
     same = all(torch.equal(parts[i], outs[i]) for i in range(len(meshes)))
+    # FP32 contraction (AUTO at reduced precision: the direct form), against the FP64 result
+    lp = {}
+    for name, flags in (("f32", bem.FORM_AUTO | bem.PREC_F32), ("f32_expand", bem.FORM_EXPAND | bem.PREC_F32)):
+        b32 = bem.Batch(meshes, z, W, w["m"], form=flags, tune=True)
+        b32.set_timing(True)
+        o32 = torch.empty_like(out)
+        b32.moments(Vd, out=o32)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b32.moments(Vd, out=o32)
+        torch.cuda.synchronize()
+        wall32 = time.perf_counter() - t0
+        k32 = b32.last_kernel_ms()
+        p32 = b32.split(o32)
+        err = max(float(torch.linalg.vector_norm(p32[i][q] - parts[i][q]) / torch.linalg.vector_norm(parts[i][q]))
+                  for i in range(len(meshes)) for q in range(w["P"]))
+        ops32 = b32.operators.astype(np.float64)
+        lp[name] = {"form": {bem.FORM_DIRECT: "direct", bem.FORM_EXPAND: "expand"}[b32.form],
+                    "operators_generated": int(ops32.max()), "col_tile": b32.col_tile,
+                    "value": units / wall32, "seconds": wall32, "persistent_kernel_ms": k32,
+                    "achieved_tflops": float(np.sum(8.0 * ops32 * sizes ** 2 * w["m"])) / (k32 * 1e-3) / 1e12,
+                    "fp32_matrix_peak_tflops": 157.3, "max_rel_err_vs_fp64": err,
+                    "speedup_vs_fp64_batch": wall / wall32}
+        b32.close()
     res = {
         "workload": w["name"],
         "meshes": f"{w['count']} ellipsoids, geodesic frequency U{{{w['freq'][0]}..{w['freq'][1]}}}, "
@@ -219,6 +245,7 @@ def batched_form():
         "per_mesh_calls": {"seconds": wall_seq, "value": units / wall_seq},
         "speedup_vs_per_mesh_calls": wall_seq / wall,
         "bitwise_equal_to_per_mesh_calls": bool(same),
+        "reduced_precision": lp,
     }
     batch.close()
     for mm in meshes:
