@@ -20,10 +20,10 @@ namespace bemrat {
 
 // sin(x), cos(x): reduce by pi to |y| <= pi/2, k = round(x / pi); then
 // sin x = (-1)^k sin y and cos x = (-1)^k cos y, so the quadrant costs one sign flip of
-// both results instead of a swap and two sign selections.  The series are longer than on
-// |y| <= pi/4 (absolute error about 1.2 ulp of 1 instead of 0.6, checked on the host
-// against long-double sin/cos for |x| <= 1e6), which is what the kernel sums need: every
-// use multiplies them by a weight and adds them to other terms.
+// both results instead of a swap and two sign selections.  Absolute error 1.0-1.8 ulp of 1
+// (checked on the host against long-double sin/cos for |x| <= 1e6; 0.6 ulp with a reduction
+// by pi/2 and its quadrant selects), which is what the kernel sums need: every use
+// multiplies them by a weight and adds them to other terms.
 __device__ __forceinline__ void sincos_cw(double x, double &s, double &c) {
     constexpr double one_over_pi = 0.3183098861837907;
     constexpr double pi_1 = 3.1415926534682512;      // 33 significant bits (2 x the pi/2 parts)
@@ -34,29 +34,27 @@ __device__ __forceinline__ void sincos_cw(double x, double &s, double &c) {
     y = fma(-kd, pi_2, y);
     y = fma(-kd, pi_3, y);
     const double y2 = y * y;
-    // sin y = y + y^3 sum_{j=1..10} (-1)^j y^{2j-2}/(2j+1)!   (remainder (pi/2)^23/23! < 2e-18)
-    double ps = 1.0 / 51090942171709440000.0;       //  1/21!
-    ps = fma(ps, y2, -1.0 / 121645100408832000.0);  // -1/19!
-    ps = fma(ps, y2, 1.0 / 355687428096000.0);      //  1/17!
-    ps = fma(ps, y2, -1.0 / 1307674368000.0);       // -1/15!
-    ps = fma(ps, y2, 1.0 / 6227020800.0);           //  1/13!
-    ps = fma(ps, y2, -1.0 / 39916800.0);            // -1/11!
-    ps = fma(ps, y2, 1.0 / 362880.0);               //  1/9!
-    ps = fma(ps, y2, -1.0 / 5040.0);                // -1/7!
-    ps = fma(ps, y2, 1.0 / 120.0);                  //  1/5!
-    ps = fma(ps, y2, -1.0 / 6.0);                   // -1/3!
+    // sin y = y + y^3 P(y^2), cos y = 1 + y^2 Q(y^2): the Taylor series (to degree 31 and 32)
+    // economised on |y| <= pi/2 by Chebyshev polynomials down to degree 17 and 16 (Lanczos'
+    // economisation; coefficients computed in exact rational arithmetic, error bounds
+    // 2e-19 and 4e-18, leading coefficients 1 - 2e-18 and 1 - 4e-18 rounded to 1)
+    double ps = 2.7166581648246254e-15;
+    ps = fma(ps, y2, -7.642510917660842e-13);
+    ps = fma(ps, y2, 1.6058918611181144e-10);
+    ps = fma(ps, y2, -2.505210638033204e-08);
+    ps = fma(ps, y2, 2.7557319204570754e-06);
+    ps = fma(ps, y2, -0.00019841269841159377);
+    ps = fma(ps, y2, 0.008333333333332993);
+    ps = fma(ps, y2, -0.16666666666666663);
     const double sy = fma(y * y2, ps, y);
-    // cos y = 1 + y^2 sum_{j=1..10} (-1)^j y^{2j-2}/(2j)!   (remainder (pi/2)^22/22! < 2e-17)
-    double pc = 1.0 / 2432902008176640000.0;        //  1/20!
-    pc = fma(pc, y2, -1.0 / 6402373705728000.0);    // -1/18!
-    pc = fma(pc, y2, 1.0 / 20922789888000.0);       //  1/16!
-    pc = fma(pc, y2, -1.0 / 87178291200.0);         // -1/14!
-    pc = fma(pc, y2, 1.0 / 479001600.0);            //  1/12!
-    pc = fma(pc, y2, -1.0 / 3628800.0);             // -1/10!
-    pc = fma(pc, y2, 1.0 / 40320.0);                //  1/8!
-    pc = fma(pc, y2, -1.0 / 720.0);                 // -1/6!
-    pc = fma(pc, y2, 1.0 / 24.0);                   //  1/4!
-    pc = fma(pc, y2, -0.5);                         // -1/2!
+    double pc = 4.608992189914223e-14;
+    pc = fma(pc, y2, -1.1462903400770852e-11);
+    pc = fma(pc, y2, 2.087656190004232e-09);
+    pc = fma(pc, y2, -2.755731639228085e-07);
+    pc = fma(pc, y2, 2.4801587277429444e-05);
+    pc = fma(pc, y2, -0.0013888888888773081);
+    pc = fma(pc, y2, 0.04166666666666388);
+    pc = fma(pc, y2, -0.4999999999999997);
     const double cy = fma(y2, pc, 1.0);
     // (-1)^k: flip the sign bits when k is odd
     const unsigned long long flip = (unsigned long long)((int)kd & 1) << 63;
