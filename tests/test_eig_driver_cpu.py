@@ -180,3 +180,19 @@ def test_shift_invert_ritz_equals_dense_qz():
         yd, ys = V[-m:, j], Y[:, k]
         cos = abs(np.vdot(yd, ys)) / (np.linalg.norm(yd) * np.linalg.norm(ys))
         assert cos > 1 - 1e-9, (k, cos)
+
+
+def test_device_lu_size_guard():
+    """The device factorisation refuses matrices whose element count reaches 2^31 (the
+    solver library takes 32-bit sizes) before touching the matrix; the host mode and
+    unknown modes are checked the same way."""
+    from paper_1906_03938_amd.eig import DenseFactor
+
+    S = torch.empty((46341, 1), dtype=torch.complex128)  # only the shape is read
+    with pytest.raises(ValueError, match="46340"):
+        DenseFactor(S, "device")
+    with pytest.raises(ValueError, match="unknown"):
+        DenseFactor(torch.eye(4, dtype=torch.complex128), "gpu")
+    A = torch.from_numpy(np.array([[2.0, 1.0], [1.0, 3.0]], dtype=np.complex128))
+    x = DenseFactor(A, "host").solve(np.array([[3.0], [4.0]]))
+    assert np.allclose(x, [[1.0], [1.0]])

@@ -208,3 +208,46 @@ def test_batch_ellipsoids64_sampled_rows():
                 assert e <= TOL
     for mm in meshes:
         mm.close()
+
+
+@pytest.mark.parametrize("m", [1, 33])
+def test_batch_edge_shapes(m):
+    """A batch mixing the 20-triangle icosahedron (one row block, mostly padding), a ragged
+    open subset (n = 777) and one of the small ellipsoids, with a single probe column and
+    with a ragged column count: bitwise equal to the per-mesh calls and to the oracle."""
+    import torch
+
+    import paper_1906_03938_amd as bem
+    from oracle import method as M
+
+    x0, t0 = synth.icosahedron()
+    xs, ts = synth.icosphere(3)
+    keep = ts[:777]
+    used = np.unique(keep)
+    remap = -np.ones(xs.shape[0], dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    x1, t1 = xs[used], remap[keep].astype(np.int32)
+    x2, t2, _, _ = synth.ellipsoid_batch(count=1, seed=9, freq=(4, 4))[0]
+    geo = [(x0, t0, 4.0), (x1, t1, 4.5), (x2, t2, 3.5)]
+    meshes = [bem.Mesh(x, t) for x, t, _ in geo]
+    N, P = 12, 2
+    z, W = [], []
+    for _, _, c in geo:
+        zi, _, Wi = bem.contour_nodes(c, 1.0, N, P=P)
+        z.append(zi)
+        W.append(Wi)
+    V = [synth.probe_block(t.shape[0], m, seed=50 + i) for i, (_, t, _) in enumerate(geo)]
+    try:
+        with bem.Batch(meshes, np.array(z), np.array(W), m) as b:
+            Mb = b.split(b.moments(torch.from_numpy(np.concatenate(V)).to("cuda")))
+            for i, (x, t, c) in enumerate(geo):
+                Mi = meshes[i].contour_moments(z[i], W[i], torch.from_numpy(V[i]).to("cuda"), form=b.form)
+                assert torch.equal(Mi, Mb[i]), i
+                op = M.Operator(x, t)
+                zo, wo = M.circle_nodes(c, 1.0, N)
+                Mo = M.contour_moments(op, zo, M.moment_weights(zo, wo, c, P), V[i])
+                for q in range(P):
+                    assert _rel(Mb[i][q].cpu().numpy(), Mo[q]) <= TOL, (i, q)
+    finally:
+        for mm in meshes:
+            mm.close()
