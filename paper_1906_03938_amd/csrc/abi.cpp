@@ -320,8 +320,10 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
     double hmax = 0.0;
     if (R > 0.0)
         for (auto &v : zs) hmax = std::max(hmax, (v - c).imag() / R);
-    const int block = bemrat::sweep_ops_per_block(m);
     const bemrat::Prec prec = prec_of(flags);
+    // expansion lengths are whole multiples of the sweep's length unit
+    const int block = bemrat::sweep_ops_per_block(bemrat::Gen::Taylor, m);
+    const int cblock = bemrat::sweep_ops_per_block(bemrat::Gen::Cheb, m);
     plan.prec = prec;
     const double tol = trunc_tol(prec);
     int L = R > 0.0 ? taylor_length(R * h->diameter, hmax, block, tol) : bemrat::kMaxTaylor;
@@ -329,7 +331,7 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
     // Chebyshev form: every node real (then c is real and R is the half-width)
     const bool real_nodes = imin == 0.0 && imax == 0.0;
     int need = 0;
-    const int Lc = real_nodes && R > 0.0 ? cheb_length(R * h->diameter, block, &need, tol) : bemrat::kMaxTaylor;
+    const int Lc = real_nodes && R > 0.0 ? cheb_length(R * h->diameter, cblock, &need, tol) : bemrat::kMaxTaylor;
     const bool cheb_ok = real_nodes && R > 0.0 && Lc + 10 < bemrat::kMaxTaylor;
     if (form == BEM_FORM_CHEB && !cheb_ok) {
         plan.unsupported = true;
@@ -1059,10 +1061,13 @@ struct bem_batch {
 
 namespace {
 
-// Operators one work item generates (FP64: 8; reduced precision: 16 for the direct form up
-// to 64 columns, else 8).
+// Operators one work item generates (FP64: 16 for the expansion form up to 32 columns, else 8;
+// reduced precision: 16 for the direct form up to 64 columns, else 8).
 int batch_ops_per_item(const bem_batch *b, int cb) {
-    if (b->prec == bemrat::Prec::F64) return 8;
+    if (b->prec == bemrat::Prec::F64) {
+        const bool taylor = b->variant == bemrat::kBatchTaylor || b->variant == bemrat::kBatchTaylorDecay;
+        return bemrat::batch_ops_per_item_f64(taylor ? bemrat::Gen::Taylor : bemrat::Gen::Direct, cb);
+    }
     const bool direct = b->variant == bemrat::kBatchDirect || b->variant == bemrat::kBatchDirectDecay;
     return bemrat::lp_batch_ops_per_block(direct ? bemrat::Gen::Direct : bemrat::Gen::Taylor, cb);
 }

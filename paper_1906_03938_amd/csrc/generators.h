@@ -166,6 +166,83 @@ struct Generator<NOPS, Gen::Taylor, DECAY> {
     }
 };
 
+// Sixteen Taylor operators per block (L0 a multiple of 16) in two passes of eight that share
+// each point's distance, exp(i c r) and x^L0 / L0!: after the first pass the point term is
+// advanced by x^8 (the chain's last power times x) and the factorial ratios continue, so
+// the transcendental work per point is paid once for 16 operators.  When the second half
+// lies beyond L (L a multiple of 8) it is skipped and returned as zeros.
+template <bool DECAY>
+struct Generator<16, Gen::Taylor, DECAY> {
+    int z, L0;
+    double inv_fact;  // 1 / L0!
+    __device__ void init(const SweepArgs &p, int L0_) {
+        L0 = L0_;
+        z = L0 / 16;
+        inv_fact = p.inv_fact[min(L0, kMaxTaylor - 1)];
+    }
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &p, double2 (&out)[16]) const {
+        double xq[kQuad], yr[kQuad], yi[kQuad];
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+            const double x = p.R * r[q];
+            const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
+            double base = x8 * x8, pw = inv_fact;
+            for (int zz = z; zz != 0; zz >>= 1) {  // z is uniform: no divergence
+                if (zz & 1) pw *= base;
+                base *= base;
+            }
+            const double e = (DECAY ? exp_cw(-p.c_im * r[q]) * wr[q] : wr[q]) * pw;
+            double sn, cs;
+            sincos_cw(p.c_re * r[q], sn, cs);
+            xq[q] = x;
+            yr[q] = e * cs;
+            yi[q] = e * sn;
+        }
+        double c = 1.0;  // L0! / (L0 + 8 h + j)!
+        const int passes = L0 + 8 < p.L ? 2 : 1;  // uniform over the block
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= passes) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) out[8 * h + j] = make_double2(0.0, 0.0);
+                break;
+            }
+            double gr[8], gi[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) gr[j] = gi[j] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kQuad; ++q) {
+                const double x = xq[q];
+                double xp = x;
+                gr[0] += yr[q];
+                gi[0] += yi[q];
+#pragma unroll
+                for (int j = 1; j < 8; ++j) {
+                    gr[j] = fma(yr[q], xp, gr[j]);
+                    gi[j] = fma(yi[q], xp, gi[j]);
+                    xp *= x;
+                }
+                if (h == 0) {  // advance the point term to x^(L0 + 8)
+                    yr[q] *= xp;
+                    yi[q] *= xp;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (h + j > 0) c *= p.inv_int[min(L0 + 8 * h + j, kMaxTaylor - 1)];
+                const double a = gr[j] * c, b = gi[j] * c;
+                switch (j & 3) {  // times i^(8 h + j) = i^j
+                    case 0: out[8 * h + j] = make_double2(a, b); break;
+                    case 1: out[8 * h + j] = make_double2(-b, a); break;
+                    case 2: out[8 * h + j] = make_double2(-a, -b); break;
+                    default: out[8 * h + j] = make_double2(b, -a); break;
+                }
+            }
+        }
+    }
+};
+
 // Chebyshev (Jacobi-Anger) form for real nodes kappa = alpha + beta xi, xi in [-1, 1]:
 // exp(i kappa r) = exp(i alpha r) sum_l eps_l i^l J_l(beta r) T_l(xi), so with the factors
 // eps_l i^l left to the host's recombination, operator l has entries

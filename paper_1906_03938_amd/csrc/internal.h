@@ -82,8 +82,10 @@ hipError_t launch_add_diag(const double2 *S, int64_t n_pad, const double2 *V, in
                            int64_t zstride, int64_t n, int64_t m, int L, hipStream_t stream);
 int sweep_lp_ops_per_block(Gen gen, int64_t m);
 int64_t sweep_lp_m_pad(int64_t m);  // column padding of the probe copy for the reduced-precision sweep
-// Coefficient operators one sweep block generates together (they share its base terms).
-int sweep_ops_per_block(int64_t m);
+// Length unit of the expansion forms (their L is a multiple of it): 8.  The FP64 sweep
+// generates 8 operators per block, or 16 for the expansion form up to 32 columns.
+int sweep_ops_per_block(Gen gen, int64_t m);
+int batch_ops_per_item_f64(Gen gen, int cb);  // the same for a batched work item of cb column groups
 // Persistent batched FP64 sweep: clears `counter` (a kernel, not a memset), then `grid` blocks
 // take the `nitems` items (mesh, row block, column block, operator block) of `table` meshes,
 // all of operator family `variant`.

@@ -54,6 +54,12 @@ struct TileLds {
     double4 sQ[2][kStage * kQuad];        // quadrature points [triangle][q]
 };
 
+// Operators per consumer wave: 2 (8 per block), except for the expansion form up to 32
+// columns: 4 (16 per block, the two-pass generator), where the matrix work per generated
+// entry is small and sharing each point's transcendental work over 16 operators pays; with
+// 64 columns the 16-operator tiles would not fit the LDS.
+constexpr int ops_g(Gen gen, int cb) { return gen == Gen::Taylor && cb <= 2 ? 4 : 2; }
+
 // One tile: 16 target rows from row0, 16 CB columns from col0, operators L0 .. L0 + 4 G - 1,
 // by the 512 threads of the block.  Used by the per-call kernel (one tile per block) and by
 // the batched persistent kernel (tiles of several meshes taken from a work queue).
@@ -147,8 +153,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &p, int64_t row0, int
                 P3[g][cb] = v4d{0.0, 0.0, 0.0, 0.0};
             }
         __syncthreads();  // pairs with the producers' prologue barrier
+        // with 16-operator blocks, a wave whose operators all lie beyond L (the last block of
+        // an odd number of 8-operator halves) only keeps the barrier rhythm
+        const bool active = G == 2 || L0 + w * G < p.L;
         for (int64_t it = 0; it <= nstages; ++it) {
-            if (it >= 1) {
+            if (it >= 1 && active) {
                 const int buf = (int)((it - 1) & 1);
 #pragma unroll 2
                 for (int ks = 0; ks < kStageSteps; ++ks) {
@@ -212,26 +221,25 @@ hipError_t launch_t(const SweepArgs &p, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// Operators per consumer wave: 2 (8 per block) for every column count; the producer's
-// generation of 8 operators fits two waves per SIMD without spilling.
 template <Gen GEN, bool DECAY>
 hipError_t launch_gen(const SweepArgs &p, hipStream_t stream) {
-    if (p.m <= 16) return launch_t<2, 1, GEN, DECAY>(p, stream);
-    if (p.m <= 32) return launch_t<2, 2, GEN, DECAY>(p, stream);
+    if (p.m <= 16) return launch_t<ops_g(GEN, 1), 1, GEN, DECAY>(p, stream);
+    if (p.m <= 32) return launch_t<ops_g(GEN, 2), 2, GEN, DECAY>(p, stream);
     return launch_t<2, 4, GEN, DECAY>(p, stream);
 }
 
 // Persistent batched form: one block per compute unit takes tiles of several meshes from a
 // work queue (an atomic counter cleared by batch_reset_kernel before the launch); each item
 // names (mesh, row block, column block, operator block) and the mesh's arguments come from
-// a table in device memory.  Every mesh of one launch uses the same operator family.  Items are ordered longest first by
-// the host, so the tail of the launch holds the shortest tiles.  Every block leaves the
+// a table in device memory.  Every mesh of one launch uses the same operator family.  Items
+// are ordered longest first by the host, so the tail of the launch holds the shortest tiles.  Every block leaves the
 // loop once the counter passes the item count.
 template <int CB, Gen GEN, bool DECAY>
 __global__ __launch_bounds__(512, 1) void sweep_batch_kernel(const BatchEntry *__restrict__ table,
                                                              const int4 *__restrict__ items, int nitems,
                                                              unsigned *__restrict__ counter) {
-    __shared__ TileLds<2, CB> lds;
+    constexpr int G = ops_g(GEN, CB);
+    __shared__ TileLds<G, CB> lds;
     __shared__ int s_next;
     for (;;) {
         if (threadIdx.x == 0) s_next = (int)atomicAdd(counter, 1u);
@@ -242,9 +250,9 @@ __global__ __launch_bounds__(512, 1) void sweep_batch_kernel(const BatchEntry *_
         const int4 item = items[idx];
         const int mesh = __builtin_amdgcn_readfirstlane(item.x);
         const SweepArgs p = table[mesh].args;
-        sweep_tile<2, CB, GEN, DECAY, true>(p, (int64_t)__builtin_amdgcn_readfirstlane(item.y) * 16,
-                                      (int64_t)__builtin_amdgcn_readfirstlane(item.z) * 16 * CB,
-                                      __builtin_amdgcn_readfirstlane(item.w) * 8, lds);
+        sweep_tile<G, CB, GEN, DECAY, true>(p, (int64_t)__builtin_amdgcn_readfirstlane(item.y) * 16,
+                                            (int64_t)__builtin_amdgcn_readfirstlane(item.z) * 16 * CB,
+                                            __builtin_amdgcn_readfirstlane(item.w) * 4 * G, lds);
     }
 }
 
@@ -264,7 +272,13 @@ __global__ void prep_probe_kernel(const double2 *__restrict__ V, int64_t ldv, in
 
 }  // namespace
 
-int sweep_ops_per_block(int64_t) { return 8; }
+// Expansion lengths are whole multiples of 8 whatever the block: a 16-operator block whose
+// second half lies beyond L skips that half (generator pass and contraction).  Rounding L up
+// to 16 instead would add terms whose self-term coefficients are rounding noise, which the
+// Chebyshev eigen-route's highest coefficient blocks are sensitive to.
+int sweep_ops_per_block(Gen, int64_t) { return 8; }
+
+int batch_ops_per_item_f64(Gen gen, int cb) { return 4 * ops_g(gen, cb); }
 
 int64_t sweep_m_pad(int64_t m) {
     const int nc = m <= 16 ? 16 : (m <= 32 ? 32 : 64);
