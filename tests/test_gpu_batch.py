@@ -81,11 +81,14 @@ def test_batch_bitwise_equals_per_mesh(small, form, tune):
             assert torch.equal(Mi, Mb[i]), i
 
 
-def test_batch_graph_capture_replays(small):
-    """The moments call only launches kernels: captured once, every replay (with other
-    work and synchronisations in between) reproduces the eager result bitwise."""
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_graph_capture_replays(small, prec):
+    """The moments call only launches kernels (at reduced precision also the per-mesh probe
+    scale reductions, cleared by a kernel): captured once, every replay (with other work and
+    synchronisations in between) reproduces the eager result bitwise."""
     bem, torch, spec, meshes, z, W, V, N, P, m = small
-    with bem.Batch(meshes, z, W, m) as b:
+    flags = bem.FORM_AUTO | (bem.PREC_F32 if prec == "f32" else bem.PREC_F64)
+    with bem.Batch(meshes, z, W, m, form=flags) as b:
         Vd = _packed(torch, V)
         ref = b.moments(Vd).clone()
         out = torch.empty_like(ref)
