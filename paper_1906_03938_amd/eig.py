@@ -88,6 +88,21 @@ def _assemble(mesh, z, c, flags):
     return mesh.assemble_sum(z, c, form=flags)
 
 
+def _residuals(mesh, dev, lam, X, chunk=16):
+    """Relative residuals ||T(lam_k) x_k|| / ||x_k||.  Up to `chunk` pairs share one
+    bem_assemble_apply call (all their wavenumbers applied to all their vectors, the diagonal
+    kept): the direct sweep generates its operators in blocks of 8, so one call per pair would
+    generate 8 operators for each."""
+    lam = np.asarray(lam, dtype=np.complex128)
+    out = np.empty(lam.size)
+    for k0 in range(0, lam.size, chunk):
+        k1 = min(lam.size, k0 + chunk)
+        Y = mesh.assemble_apply(lam[k0:k1], dev(X[:, k0:k1])).cpu().numpy()
+        for k in range(k0, k1):
+            out[k] = np.linalg.norm(Y[k - k0, :, k - k0]) / np.linalg.norm(X[:, k])
+    return out
+
+
 class ContourSolver:
     """Cauchy-approximation eigensolver for T(kappa) x = 0 inside |kappa - c| < radius,
     with N trapezoidal nodes, q inverse-iteration steps per outer iteration."""
@@ -228,11 +243,7 @@ class ContourSolver:
         return lam, Y
 
     def residuals(self, lam, X):
-        out = np.empty(lam.size)
-        for k in range(lam.size):
-            y = self.mesh.assemble_apply([lam[k]], self._dev(X[:, k:k + 1])).cpu().numpy()[0, :, 0]
-            out[k] = np.linalg.norm(y) / np.linalg.norm(X[:, k])
-        return out
+        return _residuals(self.mesh, self._dev, lam, X)
 
     # -- Algorithm 3 with restarts -------------------------------------------------------
     def solve(self, U0):
@@ -421,11 +432,7 @@ class IntervalSolver:
         return kap, V[:U.shape[1], :]
 
     def residuals(self, lam, X):
-        out = np.empty(lam.size)
-        for k in range(lam.size):
-            y = self.mesh.assemble_apply([lam[k]], self._dev(X[:, k:k + 1])).cpu().numpy()[0, :, 0]
-            out[k] = np.linalg.norm(y) / np.linalg.norm(X[:, k])
-        return out
+        return _residuals(self.mesh, self._dev, lam, X)
 
     def solve(self, U0):
         u0 = np.asarray(U0, dtype=np.complex128)
