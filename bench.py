@@ -156,7 +156,7 @@ def batched_form():
     (seeds 4000 + i): one bem_batch_moments call (after the batch's set-up with the tile
     autotuner and one warm-up call), timed by wall clock and by the library's events around
     the persistent kernel, beside the same moments by 64 per-mesh contour_moments calls in
-    the same form on the same stream, and the batch with an FP32 contraction (autotuned; the
+    the same form on the same stream (which fold their two weight sets into the sweep), and the batch with an FP32 contraction (autotuned; the
     direct form that AUTO takes at reduced precision, and the expansion form on request) with
     its error against the FP64 result."""
     import numpy as np
@@ -206,7 +206,8 @@ def batched_form():
     torch.cuda.synchronize()
     wall_seq = time.perf_counter() - t0
     parts = batch.split(out)
-    same = all(torch.equal(parts[i], outs[i]) for i in range(len(meshes)))
+    diff = max(float(torch.linalg.vector_norm(parts[i] - outs[i]) / torch.linalg.vector_norm(outs[i]))
+               for i in range(len(meshes)))
     # FP32 contraction (AUTO at reduced precision: the direct form), against the FP64 result
     lp = {}
     for name, flags in (("f32", bem.FORM_AUTO | bem.PREC_F32), ("f32_expand", bem.FORM_EXPAND | bem.PREC_F32)):
@@ -244,7 +245,7 @@ def batched_form():
         "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
         "per_mesh_calls": {"seconds": wall_seq, "value": units / wall_seq},
         "speedup_vs_per_mesh_calls": wall_seq / wall,
-        "bitwise_equal_to_per_mesh_calls": bool(same),
+        "max_rel_diff_vs_per_mesh_calls": diff,
         "reduced_precision": lp,
     }
     batch.close()
@@ -448,6 +449,20 @@ def main():
             "kernel_ms": kms,
             "kernel_hash": khash,
         },
+    }
+    # the folded form: contour_moments with P = 2 weight sets generates every operator of each
+    # entry but contracts only the two folds (reported beside, not as, the per-node sweep)
+    z2, _, W2 = bem.contour_nodes(w["c"], w["radius"], w["N"], P=w["P"])
+    mesh.contour_moments(z2, W2, U, out=Mout, form=form)
+    fold_ms = []
+    for _ in range(2):
+        mesh.contour_moments(z2, W2, U, out=Mout, form=form)
+        fold_ms.append(mesh.last_kernel_ms())
+    out["folded_moments"] = {
+        "call": f"contour_moments, P = {w['P']} weight sets on the headline mesh, nodes and probes",
+        "kernel_ms": float(np.mean(fold_ms)), "value": units / (float(np.mean(fold_ms)) * 1e-3),
+        "unit": "kernel-entry*RHS/s", "contractions": w["P"], "operators_generated": L,
+        "speedup_vs_per_node_sweep_kernel": kms / float(np.mean(fold_ms)),
     }
     mesh.close()
     if not args.no_eigen_check:

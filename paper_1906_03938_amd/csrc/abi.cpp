@@ -101,7 +101,7 @@ struct bem_mesh {
     DeviceMesh dm;
     double diameter = 0.0;  // upper bound on every distance in the operator
     double mean_area = 0.0; // mean triangle area (sets the scale of reduced-precision entries)
-    Buffer geom, gl, self, aux, Z, params, partial, probe, vmax;
+    Buffer geom, gl, self, aux, Z, params, partial, probe, vmax, fself;
     Staging staging;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false, timed = false;
@@ -689,6 +689,7 @@ void bem_mesh_destroy(bem_mesh_t h) {
     h->partial.release();
     h->probe.release();
     h->vmax.release();
+    h->fself.release();
     if (h->staging.host) (void)hipHostFree(h->staging.host);
     if (h->staging.done) (void)hipEventDestroy(h->staging.done);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -824,6 +825,52 @@ bem_status bem_assemble_apply(bem_mesh_t h, const double *kappa, int64_t nk, con
 }
 
 
+// Folded moments (FP64, direct or expansion plans, P <= kFoldMax): the sweep generates every
+// operator of each entry and contracts only the P combinations sum_l coef[l][p] T_l, written
+// straight to M; the diagonal is the same combination of the self terms.
+bem_status folded_moments(bem_mesh *h, const Plan &plan, Params &prm, size_t off_k, size_t off_dft, int K,
+                          size_t off_tables, size_t off_coef, int P, const double *V, int64_t m, int64_t ldv,
+                          double *M, int64_t ldm, hipStream_t s) {
+    bem_status st = upload(h, prm, s);
+    if (st != BEM_OK) return st;
+    const DeviceMesh &dm = h->dm;
+    const double *pbase = h->params.as<double>();
+    const double2 *coef = reinterpret_cast<const double2 *>(pbase + off_coef);
+    HIP_TRY(launch_self(dm, plan, pbase, off_k, off_dft, K, h->aux.as<double2>(), h->self.as<double2>(), s),
+            "self-term kernel");
+    HIP_TRY(h->fself.ensure(sizeof(double2) * (size_t)P * dm.n_pad), "folded self terms");
+    // fself[p][a] = sum_l coef[l][p] self_l[a]: the recombination kernel with one column
+    HIP_TRY(bemrat::launch_combine(h->self.as<double2>(), dm.n_pad, 1, plan.L, coef, P, dm.n_pad, 1,
+                                   h->fself.as<double2>(), 1, s),
+            "folded self-term kernel");
+    const int64_t m_pad = bemrat::sweep_m_pad(m);
+    HIP_TRY(h->probe.ensure((size_t)dm.n_pad * m_pad * sizeof(double2)), "probe copy");
+    double2 *Vp2 = h->probe.as<double2>();
+    HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V), ldv, dm.n, m, dm.n_pad, m_pad, Vp2, s),
+            "probe copy kernel");
+    bemrat::SweepArgs a = sweep_args(dm, plan, pbase, off_k, off_tables, h->fself.as<double2>());
+    a.L = P;
+    a.Lgen = plan.L;
+    a.fcoef = coef;
+    a.Vp2 = Vp2;
+    a.m_pad = m_pad;
+    a.V = reinterpret_cast<const double2 *>(V);
+    a.ldv = ldv;
+    a.Z = reinterpret_cast<double2 *>(M);
+    a.ldz = ldm;
+    a.zstride = dm.n * ldm;
+    a.m = m;
+    if (h->timing) HIP_TRY(hipEventRecord(h->ev0, s), "event record");
+    HIP_TRY(bemrat::launch_sweep_fold(plan.gen, a, s), "folded sweep kernel");
+    if (h->timing) {
+        HIP_TRY(hipEventRecord(h->ev1, s), "event record");
+        h->timed = true;
+    }
+    h->last_form = plan.gen == bemrat::Gen::Direct ? BEM_FORM_DIRECT : BEM_FORM_EXPAND;
+    h->last_ops = plan.L;
+    return BEM_OK;
+}
+
 bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const double *W, int64_t P, const double *V,
                            int64_t m, int64_t ldv, double *M, int64_t ldm, uint32_t flags, hipStream_t stream) {
     if (!h) return fail(BEM_EINVAL, "mesh is NULL");
@@ -851,6 +898,11 @@ bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const doubl
             for (int64_t p = 0; p < P; ++p) coef[l * P + p] += cf * cplx(W[2 * (j * P + p)], W[2 * (j * P + p) + 1]);
         }
     const size_t off_coef = add_complex(prm, coef);
+    // the folded sweep pays off for one or two weight sets (measured at n = 81920: 1.47x at
+    // m = 64, 1.05x at m = 32 for P = 2; slower than the unfolded sweep at P = 8, where the
+    // producer's folding work outweighs the saved contractions)
+    if (plan.prec == bemrat::Prec::F64 && plan.gen != bemrat::Gen::Cheb && P <= 2)
+        return folded_moments(h, plan, prm, off_k, off_dft, K, off_tables, off_coef, (int)P, V, m, ldv, M, ldm, stream);
     const size_t zstride = (size_t)h->dm.n * m;
     HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * plan.L), "sweep workspace");
     if ((st = upload(h, prm, stream)) != BEM_OK) return st;

@@ -3,6 +3,8 @@
 // of NOPS consecutive coefficient operators (Direct, Taylor or Chebyshev family), in FP64.
 #pragma once
 
+#include <type_traits>
+
 #include "devmath.h"
 #include "internal.h"
 
@@ -240,6 +242,119 @@ struct Generator<16, Gen::Taylor, DECAY> {
                 }
             }
         }
+    }
+};
+
+// Folded generators: all p.Lgen operators of one entry, combined into the NOPS outputs
+// out[k] = sum_l fcoef[l][k] T_l (k < p.L; zero beyond).  The Taylor form computes each
+// point's distance, exp(i c r) and weight once and runs the power chain through all the
+// operators in passes of eight (the point term advanced by x^8 between passes, the factorial
+// ratios continuing); the direct form generates its nodes in passes of eight.
+template <int NOPS, Gen GEN, bool DECAY>
+struct FoldGenerator;
+
+template <int NOPS, bool DECAY>
+struct FoldGenerator<NOPS, Gen::Taylor, DECAY> {
+    __device__ void init(const SweepArgs &, int) {}
+    __device__ __forceinline__ void fold(const SweepArgs &p, int l, double er, double ei, double (&ar)[NOPS],
+                                         double (&ai)[NOPS]) const {
+#pragma unroll
+        for (int k = 0; k < NOPS; ++k) {
+            if (k < p.L) {
+                const double2 w = p.fcoef[(int64_t)l * p.L + k];
+                ar[k] = fma(w.x, er, fma(-w.y, ei, ar[k]));
+                ai[k] = fma(w.x, ei, fma(w.y, er, ai[k]));
+            }
+        }
+    }
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &p, double2 (&out)[NOPS]) const {
+        double xq[kQuad], yr[kQuad], yi[kQuad];
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+            const double e = DECAY ? exp_cw(-p.c_im * r[q]) * wr[q] : wr[q];
+            double sn, cs;
+            sincos_cw(p.c_re * r[q], sn, cs);
+            xq[q] = p.R * r[q];
+            yr[q] = e * cs;
+            yi[q] = e * sn;
+        }
+        double ar[NOPS], ai[NOPS];
+#pragma unroll
+        for (int k = 0; k < NOPS; ++k) ar[k] = ai[k] = 0.0;
+        double c = 1.0;  // 1 / l!
+        for (int h = 0; h < p.Lgen; h += 8) {  // uniform over the block
+            double gr[8], gi[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) gr[j] = gi[j] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kQuad; ++q) {
+                const double x = xq[q];
+                double xp = x;
+                gr[0] += yr[q];
+                gi[0] += yi[q];
+#pragma unroll
+                for (int j = 1; j < 8; ++j) {
+                    gr[j] = fma(yr[q], xp, gr[j]);
+                    gi[j] = fma(yi[q], xp, gi[j]);
+                    xp *= x;
+                }
+                yr[q] *= xp;  // x^8: the next pass starts at x^(h + 8)
+                yi[q] *= xp;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (h + j > 0) c *= p.inv_int[min(h + j, kMaxTaylor - 1)];
+                const double a = gr[j] * c, b = gi[j] * c;
+                double er, ei;
+                switch (j & 3) {  // times i^(h + j) = i^j (h a multiple of 8)
+                    case 0: er = a; ei = b; break;
+                    case 1: er = -b; ei = a; break;
+                    case 2: er = -a; ei = -b; break;
+                    default: er = b; ei = -a; break;
+                }
+                fold(p, h + j, er, ei, ar, ai);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NOPS; ++k) out[k] = make_double2(ar[k], ai[k]);
+    }
+};
+
+template <int NOPS, bool DECAY>
+struct FoldGenerator<NOPS, Gen::Direct, DECAY> {
+    __device__ void init(const SweepArgs &, int) {}
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &p, double2 (&out)[NOPS]) const {
+        double ar[NOPS], ai[NOPS];
+#pragma unroll
+        for (int k = 0; k < NOPS; ++k) ar[k] = ai[k] = 0.0;
+        for (int h = 0; h < p.Lgen; h += 8) {  // uniform over the block
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (h + j >= p.Lgen) break;
+                const double2 kap = p.kappa[h + j];
+                double gr = 0.0, gi = 0.0;
+#pragma unroll
+                for (int q = 0; q < kQuad; ++q) {
+                    const double e = DECAY ? exp_cw(-kap.y * r[q]) * wr[q] : wr[q];
+                    double sn, cs;
+                    sincos_cw(kap.x * r[q], sn, cs);
+                    gr = fma(e, cs, gr);
+                    gi = fma(e, sn, gi);
+                }
+#pragma unroll
+                for (int k = 0; k < NOPS; ++k) {
+                    if (k < p.L) {
+                        const double2 w = p.fcoef[(int64_t)(h + j) * p.L + k];
+                        ar[k] = fma(w.x, gr, fma(-w.y, gi, ar[k]));
+                        ai[k] = fma(w.x, gi, fma(w.y, gr, ai[k]));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NOPS; ++k) out[k] = make_double2(ar[k], ai[k]);
     }
 };
 

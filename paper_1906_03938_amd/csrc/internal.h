@@ -52,6 +52,10 @@ struct SweepArgs {
     int miller_M;            // Cheb: start index of the Bessel recurrence (multiple of 8)
     double a_scale;          // reduced precision: entries are scaled by this before rounding
     const unsigned long long *vmax;  // reduced precision: bits of max |V| (probe scale)
+    // Folded form (the sweep contracts L folded operators sum_l fcoef[l][p] T_l, p < L, out of
+    // Lgen generated ones; self then holds the folded diagonal)
+    int Lgen;
+    const double2 *fcoef;  // Lgen x L
 };
 
 // One mesh of the persistent batched sweep: its arguments (the operator family, a
@@ -82,6 +86,12 @@ hipError_t launch_add_diag(const double2 *S, int64_t n_pad, const double2 *V, in
                            int64_t zstride, int64_t n, int64_t m, int L, hipStream_t stream);
 int sweep_lp_ops_per_block(Gen gen, int64_t m);
 int64_t sweep_lp_m_pad(int64_t m);  // column padding of the probe copy for the reduced-precision sweep
+// Folded FP64 sweep for the moments of Direct or Taylor plans: the producer generates all
+// args.Lgen operators of each entry and folds them into args.L <= kFoldMax combinations
+// (args.fcoef), the consumers contract only those and write them to args.Z like operators.
+constexpr int kFoldMax = 8;
+hipError_t launch_sweep_fold(Gen gen, const SweepArgs &args, hipStream_t stream);
+
 // Length unit of the expansion forms (their L is a multiple of it): 8.  The FP64 sweep
 // generates 8 operators per block, or 16 for the expansion form up to 32 columns.
 int sweep_ops_per_block(Gen gen, int64_t m);

@@ -63,7 +63,7 @@ constexpr int ops_g(Gen gen, int cb) { return gen == Gen::Taylor && cb <= 2 ? 4 
 // One tile: 16 target rows from row0, 16 CB columns from col0, operators L0 .. L0 + 4 G - 1,
 // by the 512 threads of the block.  Used by the per-call kernel (one tile per block) and by
 // the batched persistent kernel (tiles of several meshes taken from a work queue).
-template <int G, int CB, Gen GEN, bool DECAY, bool CAST>
+template <int G, int CB, Gen GEN, bool DECAY, bool CAST, bool FOLD = false>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &p, int64_t row0, int64_t col0, int L0,
                                            TileLds<G, CB> &lds) {
     constexpr int NC = 16 * CB;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &p, int64_t row0, int
         const int brow = tid & 15, btri = tid >> 4;
         const int64_t grow = row0 + brow;
         const double4 xa = ld<CAST>(p.colloc, grow);
-        Generator<NOPS, GEN, DECAY> gen;
+        std::conditional_t<FOLD, FoldGenerator<NOPS, GEN, DECAY>, Generator<NOPS, GEN, DECAY>> gen;
         gen.init(p, L0);
         int64_t voff[VPT];
 #pragma unroll
@@ -213,6 +213,39 @@ __global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
                                   (int)blockIdx.z * 4 * G, lds);
 }
 
+// Folded form: one block per (row block, column block) generates every operator of its
+// entries and contracts the p.L <= 4 G folds.
+template <int G, int CB, Gen GEN, bool DECAY>
+__global__ __launch_bounds__(512, 1) void sweep_fold_kernel(SweepArgs p) {
+    __shared__ TileLds<G, CB> lds;
+    sweep_tile<G, CB, GEN, DECAY, false, true>(p, (int64_t)blockIdx.x * 16, (int64_t)blockIdx.y * 16 * CB, 0, lds);
+}
+
+template <int G, int CB, Gen GEN, bool DECAY>
+hipError_t launch_fold_t(const SweepArgs &p, hipStream_t stream) {
+    constexpr int NC = 16 * CB;
+    dim3 grid((unsigned)(p.n_pad / 16), (unsigned)((p.m + NC - 1) / NC), 1u);
+    hipLaunchKernelGGL((sweep_fold_kernel<G, CB, GEN, DECAY>), grid, dim3(512), 0, stream, p);
+    return hipGetLastError();
+}
+
+template <Gen GEN, bool DECAY>
+hipError_t launch_fold_gen(const SweepArgs &p, hipStream_t stream) {
+    const int cb = p.m <= 16 ? 1 : (p.m <= 32 ? 2 : 4);
+    if (p.L <= 4) {
+        switch (cb) {
+            case 1: return launch_fold_t<1, 1, GEN, DECAY>(p, stream);
+            case 2: return launch_fold_t<1, 2, GEN, DECAY>(p, stream);
+            default: return launch_fold_t<1, 4, GEN, DECAY>(p, stream);
+        }
+    }
+    switch (cb) {
+        case 1: return launch_fold_t<2, 1, GEN, DECAY>(p, stream);
+        case 2: return launch_fold_t<2, 2, GEN, DECAY>(p, stream);
+        default: return launch_fold_t<2, 4, GEN, DECAY>(p, stream);
+    }
+}
+
 template <int G, int CB, Gen GEN, bool DECAY>
 hipError_t launch_t(const SweepArgs &p, hipStream_t stream) {
     constexpr int NC = 16 * CB;
@@ -326,6 +359,18 @@ hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, cons
         case kBatchDirect: return launch_batch_gen<Gen::Direct, false>(cb, table, items, nitems, counter, grid, stream);
         case kBatchTaylorDecay: return launch_batch_gen<Gen::Taylor, true>(cb, table, items, nitems, counter, grid, stream);
         case kBatchTaylor: return launch_batch_gen<Gen::Taylor, false>(cb, table, items, nitems, counter, grid, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_fold(Gen gen, const SweepArgs &args, hipStream_t stream) {
+    if (args.L < 1 || args.L > kFoldMax || args.Lgen < 1) return hipErrorInvalidValue;
+    const bool decay = args.decay != 0;
+    switch (gen) {
+        case Gen::Direct:
+            return decay ? launch_fold_gen<Gen::Direct, true>(args, stream) : launch_fold_gen<Gen::Direct, false>(args, stream);
+        case Gen::Taylor:
+            return decay ? launch_fold_gen<Gen::Taylor, true>(args, stream) : launch_fold_gen<Gen::Taylor, false>(args, stream);
         default: return hipErrorInvalidValue;
     }
 }

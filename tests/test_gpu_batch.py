@@ -76,7 +76,9 @@ def test_batch_bitwise_equals_per_mesh(small, form, tune):
         Mb = b.split(b.moments(_packed(torch, V)))
         print(form, "tune", tune, "col tile", b.col_tile, flush=True)
         for i, mesh in enumerate(meshes):
-            Mi = mesh.contour_moments(z[i], W[i], torch.from_numpy(V[i]).to("cuda"), form=f)
+            # the per-mesh unfolded path (rr_project's fused moments: the same sweep tiles and
+            # recombination; contour_moments itself folds one or two weight sets)
+            _, Mi = mesh.rr_project(z[i], torch.from_numpy(V[i]).to("cuda"), W=W[i], form=f)
             assert mesh.last_form()[0] == b.form and mesh.last_form()[1] == b.operators[i]
             assert torch.equal(Mi, Mb[i]), i
 
@@ -149,7 +151,7 @@ def test_batch_reduced_precision_tuned_expand(small):
         Mb = b.split(b.moments(_packed(torch, V)))
         print("f32 expand col tile", b.col_tile, flush=True)
         for i in range(len(meshes)):
-            Mi = meshes[i].contour_moments(z[i], W[i], torch.from_numpy(V[i]).to("cuda"), form=f)
+            _, Mi = meshes[i].rr_project(z[i], torch.from_numpy(V[i]).to("cuda"), W=W[i], form=f)
             assert torch.equal(Mi, Mb[i]), i
 
 
@@ -244,7 +246,7 @@ def test_batch_edge_shapes(m):
         with bem.Batch(meshes, np.array(z), np.array(W), m) as b:
             Mb = b.split(b.moments(torch.from_numpy(np.concatenate(V)).to("cuda")))
             for i, (x, t, c) in enumerate(geo):
-                Mi = meshes[i].contour_moments(z[i], W[i], torch.from_numpy(V[i]).to("cuda"), form=b.form)
+                _, Mi = meshes[i].rr_project(z[i], torch.from_numpy(V[i]).to("cuda"), W=W[i], form=b.form)
                 assert torch.equal(Mi, Mb[i]), i
                 op = M.Operator(x, t)
                 zo, wo = M.circle_nodes(c, 1.0, N)

@@ -241,3 +241,29 @@ def test_bitwise_deterministic(sphere3, torch, bem):
     P1, M1 = mesh.rr_project(s, U, W=W)
     P2, M2 = mesh.rr_project(s, U, W=W)
     assert torch.equal(P1, P2) and torch.equal(M1, M2)
+
+
+@pytest.mark.parametrize("form", ["direct", "expand"])
+@pytest.mark.parametrize("P,m", [(1, 5), (2, 33), (2, 70)])
+def test_folded_moments_match_unfolded(bem, torch, sphere3, form, P, m):
+    """contour_moments folds one or two weight sets into the sweep (every operator of an
+    entry generated, only the folds contracted); rr_project's fused moments take the
+    unfolded route (every operator contracted, then recombined).  Both evaluate the same sums
+    in FP64: they agree to rounding, and the folded result matches the oracle."""
+    from oracle import method as M
+
+    mesh, op, xyz, tri = sphere3
+    f = {"direct": bem.FORM_DIRECT, "expand": bem.FORM_EXPAND}[form]
+    z, w, W = bem.contour_nodes(4.0, 1.5, 24, P=P)
+    Vm = synth.probe_block(op.n, m, seed=30 + m)
+    Vmd = torch.from_numpy(Vm).to("cuda")
+    Mf = mesh.contour_moments(z, W, Vmd, form=f).cpu().numpy()
+    _, Mu = mesh.rr_project(z, Vmd, W=W, form=f)
+    Mu = Mu.cpu().numpy()
+    zo, wo = M.circle_nodes(4.0, 1.5, 24)
+    Mo = M.contour_moments(op, zo, M.moment_weights(zo, wo, 4.0, P), Vm)
+    for p in range(P):
+        d = np.linalg.norm(Mf[p] - Mu[p]) / np.linalg.norm(Mu[p])
+        e = np.linalg.norm(Mf[p] - Mo[p]) / np.linalg.norm(Mo[p])
+        print(form, P, m, p, "folded vs unfolded", d, "vs oracle", e, flush=True)
+        assert d <= 1e-13 and e <= TOL
