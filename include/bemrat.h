@@ -159,7 +159,10 @@ bem_status bem_assemble_apply(bem_mesh_t mesh, const double *kappa, int64_t nk,
  * W[j][0] = w_j/(z_j - c) the sum is -S V, S = T~(c) the Schur complement).
  * z [host]: N complex nodes; W [host]: N x P complex.  V: device n x m (ldv >= m).
  * M: device, P blocks of n x m; block p starts at M + 2*p*n*ldm doubles, row stride
- * ldm >= m.  Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE. */
+ * ldm >= m.  In FP64 with one or two weight sets and the DIRECT or EXPAND form, the sweep
+ * folds the weights into the generated entries and contracts only the P combinations (same
+ * sums, different rounding order); otherwise every generated operator is contracted and the
+ * results recombined.  Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE. */
 bem_status contour_moments(bem_mesh_t mesh, const double *z, int64_t N, const double *W,
                            int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
                            int64_t ldm, uint32_t flags, hipStream_t stream);
