@@ -53,6 +53,13 @@ def lib():
                                     ctypes.c_int, _i64p, _i64, _dp, _i64, _i64, _dp]
         L.or_apply_rows.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
+        L.or_tri_integral.argtypes = [_dp, _dp, _dp, _i64, ctypes.c_double, _dp]
+        L.or_tri_integral.restype = ctypes.c_int
+        L.or_near_pairs.argtypes = [_dp, _i64, _i32p, _i64, ctypes.c_double, _i64p, _i32p, _i64]
+        L.or_near_pairs.restype = ctypes.c_int64
+        L.or_nearfield_correction.argtypes = [_dp, _i64, _i32p, _i64, _i64p, _i32p, _dp, _i64,
+                                              ctypes.c_double, _dp]
+        L.or_nearfield_correction.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -152,3 +159,45 @@ def apply_rows(xyz, tri, kappa, V, rows=None, deriv: int = 0) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def tri_integral(x, P, kappas, rtol: float = 1e-15) -> np.ndarray:
+    """Adaptive integral of exp(i k |x - y|)/(4 pi |x - y|) over triangle P (3 x 3), one
+    value per wavenumber."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(3)
+    P = np.ascontiguousarray(P, dtype=np.float64).reshape(9)
+    k = np.ascontiguousarray(np.atleast_1d(np.asarray(kappas, dtype=np.complex128)))
+    out = np.zeros(k.size, dtype=np.complex128)
+    _check(lib().or_tri_integral(_d(x), _d(P), k.view(np.float64).ctypes.data_as(_dp), k.size,
+                                 float(rtol), out.view(np.float64).ctypes.data_as(_dp)))
+    return out
+
+
+def near_pairs(xyz, tri, eta: float):
+    """Near-pair list (rowptr[n + 1], col[nnz]) by brute force over all pairs."""
+    xyz, tri = _mesh(xyz, tri)
+    n = tri.shape[0]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    args = (_d(xyz), xyz.shape[0], tri.ctypes.data_as(_i32p), n, float(eta), rowptr.ctypes.data_as(_i64p))
+    cnt = lib().or_near_pairs(*args, None, 0)
+    _check(int(min(cnt, 0)))
+    col = np.zeros(max(cnt, 1), dtype=np.int32)
+    cnt2 = lib().or_near_pairs(*args, col.ctypes.data_as(_i32p), col.size)
+    _check(int(min(cnt2, 0)))
+    return rowptr, col[:cnt]
+
+
+def nearfield_correction(xyz, tri, eta: float, kappas, rtol: float = 1e-15):
+    """(rowptr, col, dT): the near-pair list and dT[j, i] = integral - 7-point value of pair
+    i at wavenumber kappas[j]."""
+    xyz, tri = _mesh(xyz, tri)
+    n = tri.shape[0]
+    rowptr, col = near_pairs(xyz, tri, eta)
+    k = np.ascontiguousarray(np.atleast_1d(np.asarray(kappas, dtype=np.complex128)))
+    dT = np.zeros((k.size, col.size), dtype=np.complex128)
+    if col.size:
+        _check(lib().or_nearfield_correction(_d(xyz), xyz.shape[0], tri.ctypes.data_as(_i32p), n,
+                                             rowptr.ctypes.data_as(_i64p), col.ctypes.data_as(_i32p),
+                                             k.view(np.float64).ctypes.data_as(_dp), k.size, float(rtol),
+                                             dT.view(np.float64).ctypes.data_as(_dp)))
+    return rowptr, col, dT

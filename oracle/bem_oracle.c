@@ -29,6 +29,7 @@
  *   count is doubled until two successive values agree to 1e-15 relative.
  */
 #include <complex.h>
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -398,6 +399,225 @@ int or_apply_rows(const double *xyz, int64_t nv, const int32_t *tri, int64_t n,
     }
     geom_free(&g);
     return bad ? -3 : 0;
+}
+
+/* ---------------------------------------------------------------- near field --- */
+/*
+ * Near-field quadrature: the entries T_ab, a != b, whose collocation point x_a is close
+ * to triangle b are redefined as the integral itself,
+ *     T_ab(k) = integral over triangle b of g(|x_a - y|) dA_y,
+ * instead of its 7-point approximation (the same boundary integral of Section 1, eq.
+ * GreenFun, that the 7-point rule approximates; the rule loses accuracy when x_a is
+ * within a few triangle diameters of triangle b).  A pair (a, b), a != b, is near when
+ *     |x_a - x_b|^2 < eta^2 h_b^2,
+ * with h_b the longest edge of triangle b; every quantity in that test is formed in the
+ * order written below (centroid ((P0 + P1) + P2)/3 per coordinate, squared lengths as
+ * dx*dx + dy*dy + dz*dz, then (eta*eta)*h2), so the list is reproducible bit for bit.
+ *
+ * The integral is evaluated by adaptive cubature: a collapsed Gauss-Legendre product
+ * rule (Stroud's conical product, 10 x 10 points, exact for polynomials of degree 18 on
+ * the triangle) on a triangle and on its four midpoint children; where the two estimates
+ * differ by more than the tolerance (an absolute bound, the relative tolerance times the
+ * first estimate, the same at every level) the children are refined in turn.  All wavenumbers
+ * share one refinement (the near-singularity at x_a does not depend on k), and the
+ * acceptance test takes the largest difference over them.
+ */
+
+#define NQ_COLLAPSED 10
+#define ADAPT_DEPTH 40
+
+static double cq_x[NQ_COLLAPSED], cq_w[NQ_COLLAPSED];
+static int cq_ready = 0;
+
+static void cq_init(void)
+{
+    if (!cq_ready) {
+        or_gauss_legendre(NQ_COLLAPSED, cq_x, cq_w);
+        cq_ready = 1;
+    }
+}
+
+/* Collapsed product rule on triangle (V0, V1, V2): y = V0 + s (V1 - V0) + t (V2 - V0) with
+ * s = u (1 - v), t = u v on the unit square, dA = 2 A u du dv.  out[j] = sum of g over
+ * the rule for wavenumber k[j]. */
+static void collapsed_rule(const double x[3], const double V0[3], const double V1[3],
+                           const double V2[3], const cplx *k, int nk, cplx *out)
+{
+    double e1[3], e2[3];
+    for (int c = 0; c < 3; ++c) { e1[c] = V1[c] - V0[c]; e2[c] = V2[c] - V0[c]; }
+    double cr0 = e1[1] * e2[2] - e1[2] * e2[1];
+    double cr1 = e1[2] * e2[0] - e1[0] * e2[2];
+    double cr2 = e1[0] * e2[1] - e1[1] * e2[0];
+    double twoA = sqrt(cr0 * cr0 + cr1 * cr1 + cr2 * cr2);
+    for (int j = 0; j < nk; ++j) out[j] = 0.0;
+    for (int i = 0; i < NQ_COLLAPSED; ++i) {
+        double u = 0.5 * (1.0 + cq_x[i]);
+        for (int l = 0; l < NQ_COLLAPSED; ++l) {
+            double v = 0.5 * (1.0 + cq_x[l]);
+            double s = u * (1.0 - v), t = u * v;
+            double w = twoA * u * 0.25 * cq_w[i] * cq_w[l];
+            double dx = x[0] - (V0[0] + s * e1[0] + t * e2[0]);
+            double dy = x[1] - (V0[1] + s * e1[1] + t * e2[1]);
+            double dz = x[2] - (V0[2] + s * e1[2] + t * e2[2]);
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double wr = w / (4.0 * PI * r);
+            for (int j = 0; j < nk; ++j) out[j] += wr * cexp(I * k[j] * r);
+        }
+    }
+}
+
+/* Refines triangle (V0, V1, V2) whose rule value is `whole`; adds the accepted value of
+ * every leaf to acc.  work holds 5 nk complex values per remaining level. */
+static void adapt_tri(const double x[3], const double V0[3], const double V1[3], const double V2[3],
+                      const cplx *k, int nk, const cplx *whole, double tol, int depth, cplx *work,
+                      cplx *acc)
+{
+    double m01[3], m12[3], m20[3];
+    for (int c = 0; c < 3; ++c) {
+        m01[c] = 0.5 * (V0[c] + V1[c]);
+        m12[c] = 0.5 * (V1[c] + V2[c]);
+        m20[c] = 0.5 * (V2[c] + V0[c]);
+    }
+    const double *ch[4][3] = {{V0, m01, m20}, {m01, V1, m12}, {m20, m12, V2}, {m01, m12, m20}};
+    cplx *cv = work, *sum = work + 4 * nk;
+    for (int q = 0; q < 4; ++q) collapsed_rule(x, ch[q][0], ch[q][1], ch[q][2], k, nk, cv + q * nk);
+    double err = 0.0, mag = 0.0;
+    for (int j = 0; j < nk; ++j) {
+        sum[j] = cv[j] + cv[nk + j] + cv[2 * nk + j] + cv[3 * nk + j];
+        double e = cabs(sum[j] - whole[j]);
+        if (e > err) err = e;
+        for (int q = 0; q < 4; ++q)
+            if (cabs(cv[q * nk + j]) > mag) mag = cabs(cv[q * nk + j]);
+    }
+    /* accept below the tolerance, or once the difference is at the rounding level of the
+     * children's own sums (further refinement cannot reduce it) */
+    if (err <= tol || err <= 256.0 * DBL_EPSILON * mag || depth >= ADAPT_DEPTH) {
+        for (int j = 0; j < nk; ++j) acc[j] += sum[j];
+        return;
+    }
+    for (int q = 0; q < 4; ++q)
+        adapt_tri(x, ch[q][0], ch[q][1], ch[q][2], k, nk, cv + q * nk, tol, depth + 1,
+                  work + 5 * nk, acc);
+}
+
+/* Integral of g(|x - y|) over triangle P (9 doubles) for the nk wavenumbers k (interleaved
+ * complex); out is nk complex.  The refinement stops where the children change the value
+ * by at most rtol times the largest first estimate.  Returns 0 or -3 (allocation). */
+int or_tri_integral(const double *x, const double *P9, const double *kappa, int64_t nk, double rtol,
+                    double *out)
+{
+    cq_init();
+    cplx *k = malloc(sizeof(cplx) * (size_t)(nk > 0 ? nk : 1));
+    cplx *work = malloc(sizeof(cplx) * (size_t)(nk > 0 ? nk : 1) * (5 * (ADAPT_DEPTH + 1) + 2));
+    if (!k || !work) { free(k); free(work); return -3; }
+    for (int64_t j = 0; j < nk; ++j) k[j] = kappa[2 * j] + I * kappa[2 * j + 1];
+    const double *V0 = P9, *V1 = P9 + 3, *V2 = P9 + 6;
+    cplx *whole = work + 5 * (ADAPT_DEPTH + 1) * nk, *acc = whole + nk;
+    collapsed_rule(x, V0, V1, V2, k, (int)nk, whole);
+    double scale = 0.0;
+    for (int64_t j = 0; j < nk; ++j) {
+        acc[j] = 0.0;
+        if (cabs(whole[j]) > scale) scale = cabs(whole[j]);
+    }
+    adapt_tri(x, V0, V1, V2, k, (int)nk, whole, rtol * scale, 0, work, acc);
+    for (int64_t j = 0; j < nk; ++j) {
+        out[2 * j] = creal(acc[j]);
+        out[2 * j + 1] = cimag(acc[j]);
+    }
+    free(k);
+    free(work);
+    return 0;
+}
+
+/* Centroids and squared longest edges in the order stated above. */
+static void near_geometry(const double *xyz, const int32_t *tri, int64_t n, double *cen, double *h2)
+{
+    for (int64_t b = 0; b < n; ++b) {
+        const double *P[3];
+        for (int v = 0; v < 3; ++v) P[v] = xyz + 3 * (int64_t)tri[3 * b + v];
+        for (int c = 0; c < 3; ++c) cen[3 * b + c] = ((P[0][c] + P[1][c]) + P[2][c]) / 3.0;
+        double best = 0.0;
+        for (int e = 0; e < 3; ++e) {
+            const double *A = P[e], *B = P[(e + 1) % 3];
+            double dx = B[0] - A[0], dy = B[1] - A[1], dz = B[2] - A[2];
+            double l2 = dx * dx + dy * dy + dz * dz;
+            if (l2 > best) best = l2;
+        }
+        h2[b] = best;
+    }
+}
+
+/* Near pairs by brute force over all (a, b): row a lists its near b in increasing order.
+ * rowptr has n + 1 entries; col (capacity cap) may be NULL to count only.  Returns the
+ * number of pairs, -1 on a bad index, -3 on allocation failure, -4 if cap is too small. */
+int64_t or_near_pairs(const double *xyz, int64_t nv, const int32_t *tri, int64_t n, double eta,
+                      int64_t *rowptr, int32_t *col, int64_t cap)
+{
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (tri[i] < 0 || tri[i] >= nv) return -1;
+    double *cen = malloc(sizeof(double) * 3 * (size_t)n), *h2 = malloc(sizeof(double) * (size_t)n);
+    if (!cen || !h2) { free(cen); free(h2); return -3; }
+    near_geometry(xyz, tri, n, cen, h2);
+    int64_t count = 0;
+    rowptr[0] = 0;
+    for (int64_t a = 0; a < n; ++a) {
+        for (int64_t b = 0; b < n; ++b) {
+            if (b == a) continue;
+            double dx = cen[3 * a] - cen[3 * b], dy = cen[3 * a + 1] - cen[3 * b + 1],
+                   dz = cen[3 * a + 2] - cen[3 * b + 2];
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < eta * eta * h2[b]) {
+                if (col) {
+                    if (count >= cap) { free(cen); free(h2); return -4; }
+                    col[count] = (int32_t)b;
+                }
+                ++count;
+            }
+        }
+        rowptr[a + 1] = count;
+    }
+    free(cen);
+    free(h2);
+    return count;
+}
+
+/* Near-field corrections dT[j][i] = (integral - 7-point value) for pair i = (a, col[i]) of
+ * the list (rowptr, col) and wavenumber kappa[j]; dT is nk x nnz complex.  rtol as in
+ * or_tri_integral.  Returns 0, -1 (bad index or list), -3 (allocation). */
+int or_nearfield_correction(const double *xyz, int64_t nv, const int32_t *tri, int64_t n,
+                            const int64_t *rowptr, const int32_t *col, const double *kappa, int64_t nk,
+                            double rtol, double *dT)
+{
+    geom_t g;
+    int rc = geom_build(xyz, nv, tri, n, &g);
+    if (rc) return rc;
+    const int64_t nnz = rowptr[n];
+    for (int64_t i = 0; i < nnz; ++i)
+        if (col[i] < 0 || col[i] >= n) { geom_free(&g); return -1; }
+    int bad = 0;
+#pragma omp parallel
+    {
+        double *res = malloc(sizeof(double) * 2 * (size_t)(nk > 0 ? nk : 1));
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t a = 0; a < n; ++a) {
+            for (int64_t i = rowptr[a]; i < rowptr[a + 1]; ++i) {
+                int64_t b = col[i];
+                if (!res || b == a || or_tri_integral(g.cen + 3 * a, g.vtx + 9 * b, kappa, nk, rtol, res)) {
+#pragma omp atomic write
+                    bad = 1;
+                    continue;
+                }
+                for (int64_t j = 0; j < nk; ++j) {
+                    cplx seven = offdiag(&g, a, b, kappa[2 * j] + I * kappa[2 * j + 1], 0);
+                    dT[2 * (j * nnz + i)] = res[2 * j] - creal(seven);
+                    dT[2 * (j * nnz + i) + 1] = res[2 * j + 1] - cimag(seven);
+                }
+            }
+        }
+        free(res);
+    }
+    geom_free(&g);
+    return bad ? -1 : 0;
 }
 
 int or_num_threads(void)
