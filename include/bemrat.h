@@ -186,6 +186,39 @@ bem_status rr_project(bem_mesh_t mesh, const double *z, int64_t N, const double 
                       int64_t m, int64_t ldu, double *Pout, const double *W, int64_t Pw,
                       double *M, int64_t ldm, uint32_t flags, hipStream_t stream);
 
+/* Near-field quadrature (a refinement of the operator's discretisation, not a step of the
+ * paper's method: the same boundary integral of Section 1, eq. GreenFun, evaluated more
+ * accurately where the 7-point rule is poor).  A pair (a, b), a != b, is near when
+ * |x_a - x_b|^2 < (eta*eta) h_b^2, with x the triangle centroids ((P0 + P1) + P2)/3 and h_b
+ * the longest edge of triangle b, all formed in that order without fused multiply-adds.
+ * For near pairs the corrected operator uses the integral of g(|x_a - y|) over triangle b
+ * (semi-analytic: polar form around the foot of x_a on the plane of b, radial part in closed
+ * form, angular part by sinh-transformed 16-point Gauss-Legendre panels; accurate to about
+ * 1e-14 relative while |kappa| h_b <~ 2) in place of the 7-point value.
+ *
+ * bem_mesh_set_nearfield builds the near-pair list of the mesh on the host and uploads it
+ * (a set-up call: synchronises the device).  eta = 0 removes it; 0 <= eta <= 16, else
+ * BEM_EINVAL.  Errors: BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE. */
+bem_status bem_mesh_set_nearfield(bem_mesh_t mesh, double eta);
+
+/* The near-pair list: *pairs = its length; rowptr [host, n + 1 entries, may be NULL] and col
+ * [host, *pairs entries, may be NULL]: row a lists its near b in increasing order at
+ * col[rowptr[a] .. rowptr[a+1]).  Synchronous.  Errors: BEM_EINVAL, BEM_EDEVICE. */
+bem_status bem_mesh_nearfield(bem_mesh_t mesh, int64_t *pairs, int64_t *rowptr, int32_t *col);
+
+/* Adds the near-field correction to moments of the 7-point operator:
+ *   M[p] += sum_j W[j][p] dT(z_j) V,  p < P,
+ * dT(z) = (near-field operator - 7-point operator) at z, nonzero only on the near pairs, so
+ * contour_moments followed by this call gives the moments of the corrected operator (the
+ * same sums with W[j][p] = delta_jp give T(z_j) V).  Arguments and layout as for
+ * contour_moments (z, W [host]; V, M device; block p at M + 2*p*n*ldm doubles); M is read
+ * and written.  Without a near-pair list M is left unchanged.  Each entry dT_ab(z_j) is
+ * generated on the device per call; results are deterministic.  Errors: BEM_EINVAL,
+ * BEM_ENOMEM, BEM_EDEVICE. */
+bem_status bem_nearfield_moments(bem_mesh_t mesh, const double *z, int64_t N, const double *W,
+                                 int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
+                                 int64_t ldm, hipStream_t stream);
+
 /* Dense node combination S = sum_j c_j T(z_j), n x n row-major (row stride lds >= n): the
  * matrix the inverse iteration solves with -- for the Cauchy form the Schur complement
  * S = sum_j w_j T(z_j)/(z_j - s) of the linearisation at the shift s (paper, eq. sc2-sc5:

@@ -30,6 +30,7 @@ EXPORTS = [
     "bem_last_kernel_ms", "bem_stream_status", "bem_last_error",
     "bem_assemble_sum", "bem_batch_create", "bem_batch_destroy", "bem_batch_layout", "bem_batch_moments",
     "bem_batch_set_timing", "bem_batch_last_kernel_ms",
+    "bem_mesh_set_nearfield", "bem_mesh_nearfield", "bem_nearfield_moments",
 ]
 
 
@@ -85,6 +86,9 @@ def lib():
     L.bem_batch_moments.argtypes = [_vp, _vp, _vp, _vp]
     L.bem_batch_set_timing.argtypes = [_vp, ctypes.c_int]
     L.bem_batch_last_kernel_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
+    L.bem_mesh_set_nearfield.argtypes = [_vp, ctypes.c_double]
+    L.bem_mesh_nearfield.argtypes = [_vp, ctypes.POINTER(_i64), _vp, _vp]
+    L.bem_nearfield_moments.argtypes = [_vp, _dp, _i64, _dp, _i64, _vp, _i64, _i64, _vp, _i64, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("bem_mesh_destroy", "bem_mesh_size", "bem_last_error", "bem_batch_destroy"):
@@ -221,6 +225,32 @@ class Mesh:
         M = self._out(W.shape[1], m) if out is None else out
         _check(lib().contour_moments(self._h, _hp(z), z.size, _hp(W), W.shape[1], pv, m, ldv,
                                      ctypes.c_void_p(M.data_ptr()), M.stride(1), form, _stream()))
+        return M
+
+    def set_nearfield(self, eta: float):
+        """Builds (eta > 0) or removes (eta = 0) the mesh's near-pair list."""
+        _check(lib().bem_mesh_set_nearfield(self._h, float(eta)))
+
+    def nearfield_list(self):
+        """(rowptr[n + 1], col[pairs]) of the near-pair list as NumPy arrays."""
+        cnt = _i64(0)
+        _check(lib().bem_mesh_nearfield(self._h, ctypes.byref(cnt), None, None))
+        rowptr = np.zeros(self.n + 1, dtype=np.int64)
+        col = np.zeros(max(cnt.value, 1), dtype=np.int32)
+        _check(lib().bem_mesh_nearfield(self._h, ctypes.byref(cnt), rowptr.ctypes.data_as(_vp),
+                                        col.ctypes.data_as(_vp)))
+        return rowptr, col[:cnt.value]
+
+    def nearfield_moments(self, z, W, V, out=None):
+        """Adds sum_j W[j, p] dT(z_j) V to out (zeros if None) and returns it."""
+        z = _host_complex(z)
+        W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(z.size, -1))
+        pv, m, ldv = _block(V, "V")
+        M = self._out(W.shape[1], m) if out is None else out
+        if out is None:
+            M.zero_()
+        _check(lib().bem_nearfield_moments(self._h, _hp(z), z.size, _hp(W), W.shape[1], pv, m, ldv,
+                                           ctypes.c_void_p(M.data_ptr()), M.stride(1), _stream()))
         return M
 
     def cheb_moments(self, a, b, N, L, V, out=None, form=FORM_AUTO):

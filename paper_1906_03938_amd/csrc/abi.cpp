@@ -102,6 +102,11 @@ struct bem_mesh {
     double diameter = 0.0;  // upper bound on every distance in the operator
     double mean_area = 0.0; // mean triangle area (sets the scale of reduced-precision entries)
     Buffer geom, gl, self, aux, Z, params, partial, probe, vmax, fself;
+    // near field: host centroids and squared longest edges (the list's test), device list
+    std::vector<double> nf_cen, nf_h2;
+    Buffer nf_rowptr, nf_col, nf_gl;
+    int64_t nf_pairs = 0;
+    double nf_eta = 0.0;
     Staging staging;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false, timed = false;
@@ -560,6 +565,105 @@ size_t add_complex(Params &prm, const std::vector<cplx> &v) {
     return prm.add(reinterpret_cast<const double *>(v.data()), 2 * v.size());
 }
 
+// Centroids ((P0 + P1) + P2)/3 and squared longest edges, each formed in exactly this order
+// (no contraction into fused multiply-adds), so that the near-pair test below gives the same
+// answer as any other evaluation written the same way.
+bool near_geometry(const double *xyz, const int32_t *tri, int64_t n, std::vector<double> &cen,
+                   std::vector<double> &h2) {
+#pragma clang fp contract(off)
+    try {
+        cen.assign(3 * (size_t)n, 0.0);
+        h2.assign((size_t)n, 0.0);
+    } catch (...) {
+        return false;
+    }
+    for (int64_t b = 0; b < n; ++b) {
+        const double *P[3];
+        for (int v = 0; v < 3; ++v) P[v] = xyz + 3 * (int64_t)tri[3 * b + v];
+        for (int c = 0; c < 3; ++c) cen[3 * b + c] = ((P[0][c] + P[1][c]) + P[2][c]) / 3.0;
+        double best = 0.0;
+        for (int e = 0; e < 3; ++e) {
+            const double *A = P[e], *B = P[(e + 1) % 3];
+            const double dx = B[0] - A[0], dy = B[1] - A[1], dz = B[2] - A[2];
+            const double l2 = dx * dx + dy * dy + dz * dz;
+            if (l2 > best) best = l2;
+        }
+        h2[b] = best;
+    }
+    return true;
+}
+
+// Near pairs (a, b), a != b, with |x_a - x_b|^2 < (eta*eta) h_b^2, row a listing its b in
+// increasing order.  A uniform grid of cells no smaller than eta max_b h_b only prunes the
+// candidates; the test itself is the one above.
+bool near_list(const std::vector<double> &cen, const std::vector<double> &h2, int64_t n, double eta,
+               std::vector<int64_t> &rowptr, std::vector<int32_t> &col) {
+#pragma clang fp contract(off)
+    double hmax2 = 0.0, lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t b = 0; b < n; ++b) {
+        hmax2 = std::max(hmax2, h2[b]);
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], cen[3 * b + c]);
+            hi[c] = std::max(hi[c], cen[3 * b + c]);
+        }
+    }
+    double cs = eta * std::sqrt(hmax2) * (1.0 + 1e-9);
+    int64_t dims[3];
+    for (;;) {
+        int64_t cells = 1;
+        for (int c = 0; c < 3; ++c) {
+            dims[c] = (int64_t)((hi[c] - lo[c]) / cs) + 1;
+            cells *= dims[c];
+        }
+        if (cells <= 8 * n + 64) break;
+        cs *= 1.5;  // coarser cells: fewer, each holding more candidates
+    }
+    auto cell_of = [&](int64_t b, int c) {
+        const int64_t k = (int64_t)((cen[3 * b + c] - lo[c]) / cs);
+        return std::min(std::max(k, (int64_t)0), dims[c] - 1);
+    };
+    const int64_t ncell = dims[0] * dims[1] * dims[2];
+    try {
+        std::vector<int64_t> start(ncell + 1, 0);
+        std::vector<int32_t> items(n);
+        std::vector<int64_t> cell(n);
+        for (int64_t b = 0; b < n; ++b) {
+            cell[b] = (cell_of(b, 2) * dims[1] + cell_of(b, 1)) * dims[0] + cell_of(b, 0);
+            ++start[cell[b] + 1];
+        }
+        for (int64_t k = 0; k < ncell; ++k) start[k + 1] += start[k];
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t b = 0; b < n; ++b) items[fill[cell[b]]++] = (int32_t)b;
+        const double eta2 = eta * eta;
+        rowptr.assign(n + 1, 0);
+        col.clear();
+        std::vector<int32_t> cand;
+        for (int64_t a = 0; a < n; ++a) {
+            cand.clear();
+            const int64_t ia[3] = {cell_of(a, 0), cell_of(a, 1), cell_of(a, 2)};
+            for (int64_t z = std::max<int64_t>(ia[2] - 1, 0); z <= std::min(ia[2] + 1, dims[2] - 1); ++z)
+                for (int64_t y = std::max<int64_t>(ia[1] - 1, 0); y <= std::min(ia[1] + 1, dims[1] - 1); ++y)
+                    for (int64_t x = std::max<int64_t>(ia[0] - 1, 0); x <= std::min(ia[0] + 1, dims[0] - 1); ++x) {
+                        const int64_t k = (z * dims[1] + y) * dims[0] + x;
+                        for (int64_t it = start[k]; it < start[k + 1]; ++it) {
+                            const int64_t b = items[it];
+                            if (b == a) continue;
+                            const double dx = cen[3 * a] - cen[3 * b], dy = cen[3 * a + 1] - cen[3 * b + 1],
+                                         dz = cen[3 * a + 2] - cen[3 * b + 2];
+                            const double d2 = dx * dx + dy * dy + dz * dz;
+                            if (d2 < eta2 * h2[b]) cand.push_back((int32_t)b);
+                        }
+                    }
+            std::sort(cand.begin(), cand.end());
+            col.insert(col.end(), cand.begin(), cand.end());
+            rowptr[a + 1] = (int64_t)col.size();
+        }
+    } catch (...) {
+        return false;
+    }
+    return true;
+}
+
 bem_status sync_status(hipStream_t s) {
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "stream synchronize");
@@ -621,6 +725,10 @@ bem_status bem_mesh_create(const double *xyz, int64_t nv, const int32_t *tri, in
         area_sum += 0.5 * std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
     }
     h->mean_area = area_sum / (double)n;
+    if (!near_geometry(xyz, tri, n, h->nf_cen, h->nf_h2)) {
+        delete h;
+        return fail(BEM_ENOMEM, "host allocation failed");
+    }
     const int64_t n_pad = (n + bemrat::kPad - 1) / bemrat::kPad * bemrat::kPad;
     h->dm.n = n;
     h->dm.n_pad = n_pad;
@@ -690,6 +798,9 @@ void bem_mesh_destroy(bem_mesh_t h) {
     h->probe.release();
     h->vmax.release();
     h->fself.release();
+    h->nf_rowptr.release();
+    h->nf_col.release();
+    h->nf_gl.release();
     if (h->staging.host) (void)hipHostFree(h->staging.host);
     if (h->staging.done) (void)hipEventDestroy(h->staging.done);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -1063,6 +1174,87 @@ bem_status bem_assemble_sum(bem_mesh_t h, const double *z, int64_t N, const doub
                    : plan.gen == bemrat::Gen::Taylor ? BEM_FORM_EXPAND
                                                      : BEM_FORM_CHEB;
     h->last_ops = plan.L;
+    return BEM_OK;
+}
+
+bem_status bem_mesh_set_nearfield(bem_mesh_t h, double eta) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    if (!std::isfinite(eta) || eta < 0.0 || eta > 16.0) return fail(BEM_EINVAL, "need 0 <= eta <= 16");
+    DeviceGuard guard(h->device);
+    h->nf_pairs = 0;
+    h->nf_eta = 0.0;
+    if (eta == 0.0) return BEM_OK;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    if (!near_list(h->nf_cen, h->nf_h2, h->dm.n, eta, rowptr, col))
+        return fail(BEM_ENOMEM, "host allocation failed (near-pair list)");
+    const int64_t nnz = (int64_t)col.size();
+    double glh[2 * 16];
+    gauss_legendre(16, glh, glh + 16);
+    HIP_TRY(h->nf_rowptr.ensure(sizeof(int64_t) * rowptr.size()), "near-pair list");
+    HIP_TRY(h->nf_col.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "near-pair list");
+    HIP_TRY(h->nf_gl.ensure(sizeof glh), "near-field rule");
+    // a set-up call: synchronous copies, the device may still run earlier work on any stream
+    HIP_TRY(hipDeviceSynchronize(), "device synchronize");
+    HIP_TRY(hipMemcpy(h->nf_rowptr.ptr, rowptr.data(), sizeof(int64_t) * rowptr.size(), hipMemcpyHostToDevice),
+            "near-pair list upload");
+    if (nnz)
+        HIP_TRY(hipMemcpy(h->nf_col.ptr, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice),
+                "near-pair list upload");
+    HIP_TRY(hipMemcpy(h->nf_gl.ptr, glh, sizeof glh, hipMemcpyHostToDevice), "near-field rule upload");
+    h->nf_pairs = nnz;
+    h->nf_eta = eta;
+    return BEM_OK;
+}
+
+bem_status bem_mesh_nearfield(bem_mesh_t h, int64_t *pairs, int64_t *rowptr, int32_t *col) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    if (!pairs) return fail(BEM_EINVAL, "pairs is NULL");
+    DeviceGuard guard(h->device);
+    *pairs = h->nf_pairs;
+    if (h->nf_eta == 0.0) {
+        if (rowptr)
+            for (int64_t a = 0; a <= h->dm.n; ++a) rowptr[a] = 0;
+        return BEM_OK;
+    }
+    if (rowptr)
+        HIP_TRY(hipMemcpy(rowptr, h->nf_rowptr.ptr, sizeof(int64_t) * (h->dm.n + 1), hipMemcpyDeviceToHost),
+                "near-pair list download");
+    if (col && h->nf_pairs)
+        HIP_TRY(hipMemcpy(col, h->nf_col.ptr, sizeof(int32_t) * h->nf_pairs, hipMemcpyDeviceToHost),
+                "near-pair list download");
+    return BEM_OK;
+}
+
+bem_status bem_nearfield_moments(bem_mesh_t h, const double *z, int64_t N, const double *W, int64_t P,
+                                 const double *V, int64_t m, int64_t ldv, double *M, int64_t ldm,
+                                 hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_kappas(h, z, N, "z");
+    if (st != BEM_OK) return st;
+    if (N > (int64_t)1 << 20) return fail(BEM_EINVAL, "too many nodes");
+    if (!W || P < 1 || P > (int64_t)1 << 20) return fail(BEM_EINVAL, "need W and 1 <= P <= 2^20");
+    if (!finite_c(W, N * P)) return fail(BEM_EINVAL, "W has a non-finite value");
+    if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
+    if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
+    if (h->nf_pairs == 0) return BEM_OK;  // no near pairs: nothing to add
+    Params prm;
+    const size_t off_z = prm.add(z, 2 * (size_t)N);
+    const size_t off_w = prm.add(W, 2 * (size_t)(N * P));
+    double kmax = 0.0;
+    for (int64_t j = 0; j < N; ++j) kmax = std::max(kmax, std::abs(cplx(z[2 * j], z[2 * j + 1])));
+    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
+    const double *base = h->params.as<double>();
+    for (int64_t p0 = 0; p0 < P; p0 += bemrat::kNfFold) {
+        const int Pc = (int)std::min<int64_t>(bemrat::kNfFold, P - p0);
+        HIP_TRY(bemrat::launch_nearfield(h->dm, h->nf_gl.as<double>(), h->nf_rowptr.as<int64_t>(),
+                                         h->nf_col.as<int32_t>(), reinterpret_cast<const double2 *>(base + off_z),
+                                         (int)N, reinterpret_cast<const double2 *>(base + off_w), (int)P, (int)p0, Pc,
+                                         kmax, reinterpret_cast<const double2 *>(V), ldv, m,
+                                         reinterpret_cast<double2 *>(M), ldm, stream),
+                "near-field kernel");
+    }
     return BEM_OK;
 }
 

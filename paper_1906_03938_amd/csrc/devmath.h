@@ -88,4 +88,42 @@ __device__ __forceinline__ double exp_cw(double x) {
     return ldexp(p, (int)kd);
 }
 
+// E(w) = (e^w - 1)/w for complex w (self and near-field integrals): Taylor series for
+// |w| < 1/4, otherwise through expm1 so that no cancellation occurs at small |w|.
+__device__ inline double2 exprel(double wr, double wi) {
+    if (wr * wr + wi * wi < 0.0625) {
+        // Taylor series sum_k w^k/(k+1)!, k <= 14: remainder < 0.25^15/16! ~ 4e-23
+        const double c[15] = {1.0,
+                              1.0 / 2.0,
+                              1.0 / 6.0,
+                              1.0 / 24.0,
+                              1.0 / 120.0,
+                              1.0 / 720.0,
+                              1.0 / 5040.0,
+                              1.0 / 40320.0,
+                              1.0 / 362880.0,
+                              1.0 / 3628800.0,
+                              1.0 / 39916800.0,
+                              1.0 / 479001600.0,
+                              1.0 / 6227020800.0,
+                              1.0 / 87178291200.0,
+                              1.0 / 1307674368000.0};
+        double sr = c[14], si = 0.0;
+        for (int k = 13; k >= 0; --k) {
+            const double tr = sr * wr - si * wi + c[k];
+            si = sr * wi + si * wr;
+            sr = tr;
+        }
+        return make_double2(sr, si);
+    }
+    // e^w - 1 = (expm1(wr) cos wi - 2 sin^2(wi/2)) + i e^wr sin wi
+    double s, co;
+    sincos(wi, &s, &co);
+    const double sh = sin(0.5 * wi);
+    const double nr = expm1(wr) * co - 2.0 * sh * sh;
+    const double ni = exp(wr) * s;
+    const double den = wr * wr + wi * wi;
+    return make_double2((nr * wr + ni * wi) / den, (ni * wr - nr * wi) / den);
+}
+
 }  // namespace bemrat

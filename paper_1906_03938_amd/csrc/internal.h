@@ -133,4 +133,13 @@ hipError_t launch_project_finish(const double2 *partial, int nchunks, int L, int
                                  const double2 *coef, int N, double2 *out,
                                  hipStream_t stream);
 
+// Near-field correction (nearfield.hip): M[p0 + p][a, :] += sum_j W[j][p0 + p] sum_{b in
+// row a of (rowptr, col)} (integral - 7-point value of T_ab(kappa_j)) V[b, :], p < P <= kNfFold;
+// one workgroup per row of the mesh.  gl16: 16-point Gauss-Legendre nodes then weights.
+constexpr int kNfFold = 8;
+hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const int64_t *rowptr,
+                            const int32_t *col, const double2 *kappa, int N, const double2 *W, int Pstride,
+                            int p0, int P, double kmax, const double2 *V, int64_t ldv, int64_t m,
+                            double2 *M, int64_t ldm, hipStream_t stream);
+
 }  // namespace bemrat

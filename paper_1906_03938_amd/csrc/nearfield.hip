@@ -1,0 +1,243 @@
+// Near-field correction of the operator: for each near pair (a, b) of the mesh's list the
+// 7-point entry T_ab(kappa) is replaced by the integral of the Green's function over
+// triangle b (the boundary integral that the 7-point rule approximates, Section 1,
+// eq. GreenFun), and the difference dT_ab = integral - 7-point value is applied to the probe
+// block, folded with the node weights:
+//     M[p][a, :] += sum_j W[j][p] sum_{b near a} dT_ab(z_j) V[b, :].
+//
+// Integral (polar form around the projection of x_a onto the plane of triangle b): with
+// d the signed height of x_a over the plane, x' its foot, and for edge e its signed
+// in-plane distance p_e from x' (positive on the interior side) and the tangential
+// coordinates s_A < s_B of its end points,
+//     int_b g dA = e^{i kappa |d|}/(4 pi) sum_e sign(p_e) int delta(rho) E(i kappa delta(rho)) dphi,
+// where along direction phi the fan triangle (x', A, B) reaches rho = |p_e|/cos phi,
+// delta(rho) = sqrt(rho^2 + d^2) - |d| = rho^2/(sqrt(rho^2 + d^2) + |d|), and
+// E(w) = (e^w - 1)/w (the radial integral of g in closed form).  The angle is substituted
+// by phi = atan(sinh u) (t = |p_e| sinh u along the edge, rho = |p_e| cosh u,
+// dphi = du / cosh u), the sinh transformation of Johnston and Elliott (2005) that keeps the
+// integrand smooth when x' is close to the edge line; the u-interval is split into panels
+// of length <= 2 (the integrand's nearest singularities lie at Im u = +-pi/2) and no wider
+// than 2 / (kappa_max rho_max) in phase, each integrated with 16-point Gauss-Legendre.
+//
+// One workgroup per target row; its pairs are taken 64 at a time, four node groups per
+// pair, so every partial sum is reduced in a fixed order and results are deterministic.
+#include "devmath.h"
+#include "internal.h"
+
+namespace bemrat {
+
+namespace {
+
+constexpr int kNfThreads = 256;
+constexpr int kNfPairs = 64;
+constexpr int kNfGroups = kNfThreads / kNfPairs;
+constexpr int kNfGL = 16;
+constexpr int kNfMaxPanels = 64;
+
+struct NfArgs {
+    const double4 *colloc;
+    const double4 *quad;
+    const double *vtx;
+    const double *gl;  // kNfGL nodes then weights on [-1, 1]
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double2 *kappa;  // N nodes
+    const double2 *W;      // N x Pstride; this launch uses columns p0 .. p0 + P - 1
+    int N, Pstride, p0, P;
+    double kmax;           // max |kappa_j| (sets the panel count)
+    const double2 *V;
+    int64_t ldv, m;
+    double2 *M;            // block p at M + p * mstride, row stride ldm
+    int64_t ldm, mstride;
+};
+
+__global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
+    __shared__ double2 red[kNfGroups][kNfPairs][kNfFold];
+    __shared__ int32_t cols[kNfPairs];
+    const int64_t a = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t beg = g.rowptr[a], end = g.rowptr[a + 1];
+    if (beg >= end) return;  // uniform over the workgroup
+    const double4 xa = g.colloc[a];
+    const double inv4pi = 0.25 / 3.14159265358979323846;
+    const int i = t % kNfPairs, grp = t / kNfPairs;
+    for (int64_t base = beg; base < end; base += kNfPairs) {
+        const int cnt = (int)(end - base < kNfPairs ? end - base : kNfPairs);
+        double2 acc[kNfFold];
+#pragma unroll
+        for (int p = 0; p < kNfFold; ++p) acc[p] = make_double2(0.0, 0.0);
+        if (i < cnt) {
+            const int64_t b = g.col[base + i];
+            if (grp == 0) cols[i] = (int32_t)b;
+            double P[3][3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) P[v][c] = g.vtx[9 * b + 3 * v + c];
+            const double x[3] = {xa.x, xa.y, xa.z};
+            // unit normal, height and foot of x
+            const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+            const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+            double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                            e1[0] * e2[1] - e1[1] * e2[0]};
+            const double nn = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            for (int c = 0; c < 3; ++c) nv[c] /= nn;
+            const double d = (x[0] - P[0][0]) * nv[0] + (x[1] - P[0][1]) * nv[1] + (x[2] - P[0][2]) * nv[2];
+            const double ad = fabs(d);
+            const double xp[3] = {x[0] - d * nv[0], x[1] - d * nv[1], x[2] - d * nv[2]};
+            // per edge: sign of p, |p|, start of the u-interval, panel width and count
+            double esg[3], eap[3], eu0[3], eh[3];
+            int enp[3];
+            for (int e = 0; e < 3; ++e) {
+                const double *A = P[e], *B = P[(e + 1) % 3];
+                double tv[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+                const double len = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
+                for (int c = 0; c < 3; ++c) tv[c] /= len;
+                // outward in-plane normal of the edge: t x n
+                const double u[3] = {tv[1] * nv[2] - tv[2] * nv[1], tv[2] * nv[0] - tv[0] * nv[2],
+                                     tv[0] * nv[1] - tv[1] * nv[0]};
+                const double ax = A[0] - xp[0], ay = A[1] - xp[1], az = A[2] - xp[2];
+                const double bx = B[0] - xp[0], by = B[1] - xp[1], bz = B[2] - xp[2];
+                const double pe = ax * u[0] + ay * u[1] + az * u[2];
+                const double sA = ax * tv[0] + ay * tv[1] + az * tv[2];
+                const double sB = bx * tv[0] + by * tv[1] + bz * tv[2];
+                const double ap = fabs(pe);
+                if (!(ap > 1e-30 * len)) {  // x' on the edge line: the fan triangle is empty
+                    esg[e] = 0.0;
+                    eap[e] = 0.0;
+                    eu0[e] = 0.0;
+                    eh[e] = 0.0;
+                    enp[e] = 0;
+                    continue;
+                }
+                const double u0 = asinh(sA / ap), u1 = asinh(sB / ap);
+                const double rmax = fmax(sqrt(ap * ap + sA * sA), sqrt(ap * ap + sB * sB));
+                const double want = fmax(0.5 * (u1 - u0), 0.5 * g.kmax * rmax);
+                const int np = want >= kNfMaxPanels ? kNfMaxPanels : (want <= 1.0 ? 1 : (int)ceil(want));
+                esg[e] = pe > 0.0 ? 1.0 : -1.0;
+                eap[e] = ap;
+                eu0[e] = u0;
+                eh[e] = (u1 - u0) / np;
+                enp[e] = np;
+            }
+            // 7-point distances of the rule the sweep uses
+            double r7[kQuad], w7[kQuad];
+#pragma unroll
+            for (int q = 0; q < kQuad; ++q) {
+                const double4 y = g.quad[b * kQuad + q];
+                const double dx = x[0] - y.x, dy = x[1] - y.y, dz = x[2] - y.z;
+                r7[q] = sqrt(dx * dx + dy * dy + dz * dz);
+                w7[q] = y.w;  // A_b w_q / (4 pi)
+            }
+            for (int j = grp; j < g.N; j += kNfGroups) {
+                const double kr = g.kappa[j].x, ki = g.kappa[j].y;
+                double sr = 0.0, si = 0.0;
+                for (int e = 0; e < 3; ++e) {
+                    double er = 0.0, ei = 0.0;
+                    for (int pn = 0; pn < enp[e]; ++pn) {
+                        const double mid = eu0[e] + (pn + 0.5) * eh[e];
+                        double pr = 0.0, pi = 0.0;
+                        for (int k = 0; k < kNfGL; ++k) {
+                            const double uu = mid + 0.5 * eh[e] * g.gl[k];
+                            const double ch = cosh(uu);
+                            const double rho = eap[e] * ch;
+                            const double dl = rho * rho / (sqrt(rho * rho + d * d) + ad);
+                            const double2 E = exprel(-ki * dl, kr * dl);  // w = i kappa delta
+                            const double wt = g.gl[kNfGL + k] * dl / ch;
+                            pr += wt * E.x;
+                            pi += wt * E.y;
+                        }
+                        er += 0.5 * eh[e] * pr;
+                        ei += 0.5 * eh[e] * pi;
+                    }
+                    sr += esg[e] * er;
+                    si += esg[e] * ei;
+                }
+                // e^{i kappa |d|} / (4 pi)
+                double s0, c0;
+                sincos(kr * ad, &s0, &c0);
+                const double m0 = exp(-ki * ad) * inv4pi;
+                double dr = m0 * (c0 * sr - s0 * si), di = m0 * (c0 * si + s0 * sr);
+                // minus the 7-point value
+#pragma unroll
+                for (int q = 0; q < kQuad; ++q) {
+                    double sq, cq;
+                    sincos(kr * r7[q], &sq, &cq);
+                    const double mq = exp(-ki * r7[q]) * w7[q] / r7[q];
+                    dr -= mq * cq;
+                    di -= mq * sq;
+                }
+#pragma unroll
+                for (int p = 0; p < kNfFold; ++p) {
+                    if (p < g.P) {
+                        const double2 w = g.W[(int64_t)j * g.Pstride + g.p0 + p];
+                        acc[p].x += w.x * dr - w.y * di;
+                        acc[p].y += w.x * di + w.y * dr;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < kNfFold; ++p) red[grp][i][p] = acc[p];
+        __syncthreads();
+        // fold the node groups in a fixed order
+        for (int idx = t; idx < cnt * g.P; idx += kNfThreads) {
+            const int k = idx / g.P, p = idx % g.P;
+            double2 s = red[0][k][p];
+            for (int q = 1; q < kNfGroups; ++q) {
+                s.x += red[q][k][p].x;
+                s.y += red[q][k][p].y;
+            }
+            red[0][k][p] = s;
+        }
+        __syncthreads();
+        // apply to the probe block
+        for (int64_t item = t; item < (int64_t)g.P * g.m; item += kNfThreads) {
+            const int p = (int)(item / g.m);
+            const int64_t c = item % g.m;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < cnt; ++k) {
+                const double2 f = red[0][k][p];
+                const double2 v = g.V[(int64_t)cols[k] * g.ldv + c];
+                sr += f.x * v.x - f.y * v.y;
+                si += f.x * v.y + f.y * v.x;
+            }
+            double2 *out = g.M + p * g.mstride + a * g.ldm + c;
+            const double2 o = *out;
+            *out = make_double2(o.x + sr, o.y + si);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const int64_t *rowptr,
+                            const int32_t *col, const double2 *kappa, int N, const double2 *W, int Pstride,
+                            int p0, int P, double kmax, const double2 *V, int64_t ldv, int64_t m,
+                            double2 *M, int64_t ldm, hipStream_t stream) {
+    NfArgs g;
+    g.colloc = mesh.colloc;
+    g.quad = mesh.quad;
+    g.vtx = mesh.vtx;
+    g.gl = gl16;
+    g.rowptr = rowptr;
+    g.col = col;
+    g.kappa = kappa;
+    g.W = W;
+    g.N = N;
+    g.Pstride = Pstride;
+    g.p0 = p0;
+    g.P = P;
+    g.kmax = kmax;
+    g.V = V;
+    g.ldv = ldv;
+    g.m = m;
+    g.M = M + (int64_t)p0 * mesh.n * ldm;
+    g.ldm = ldm;
+    g.mstride = mesh.n * ldm;
+    hipLaunchKernelGGL(nearfield_kernel, dim3((unsigned)mesh.n), dim3(kNfThreads), 0, stream, g);
+    return hipGetLastError();
+}
+
+}  // namespace bemrat

@@ -1,0 +1,170 @@
+"""GPU parity of the near-field correction against the oracle's adaptive cubature.
+
+Workloads: unit icosphere level 3 (n = 1280, 34 near pairs per row at eta = 2), the box
+1.0 x 0.8 x 0.6 on a 10 x 8 x 6 grid (coplanar neighbours, collocation points on the edge
+lines of other triangles), a randomly perturbed icosphere (level 3, amplitude 0.05, seed 5:
+uneven triangles), circle |z - 4| = 1.5 with N = 16 trapezoidal nodes, m = 16 seeded
+probes.  The near-pair list is index work and must be identical; the moments of the
+corrected operator (contour_moments + bem_nearfield_moments) must agree with the oracle's
+to ||gpu - oracle||_F / ||oracle||_F <= 1e-12 per weight set, and the correction alone to
+1e-12 of the corrected moments (the correction is a difference of two nearly equal values,
+so its own relative error is larger by the ratio of the entries to the corrections).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bem():
+    import paper_1906_03938_amd as bem
+
+    return bem
+
+
+def _mesh(name):
+    if name == "sphere":
+        return synth.icosphere(3)
+    if name == "box":
+        return synth.box_surface((1.0, 0.8, 0.6), (10, 8, 6))
+    return synth.perturbed_icosphere(3, 0.05, 5)
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _correction_ref(xyz, tri, eta, z, W, V):
+    """sum_j W[j, p] dT(z_j) V from the oracle's per-pair corrections."""
+    import scipy.sparse as sp
+    from oracle import _clib
+
+    n = len(tri)
+    rp, col, dT = _clib.nearfield_correction(xyz, tri, eta, z)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    out = np.zeros((W.shape[1], n, V.shape[1]), dtype=np.complex128)
+    for j in range(len(z)):
+        D = sp.csr_matrix((dT[j], (rows, col)), shape=(n, n))
+        Y = D @ V
+        for p in range(W.shape[1]):
+            out[p] += W[j, p] * Y
+    return out
+
+
+@pytest.mark.parametrize("name", ["sphere", "box", "perturbed"])
+def test_near_pair_list_is_identical(bem, torch, oracle_lib, name):
+    from oracle import _clib
+
+    xyz, tri = _mesh(name)
+    with bem.Mesh(xyz, tri) as mesh:
+        rp0, col0 = mesh.nearfield_list()
+        assert col0.size == 0 and not rp0.any()
+        for eta in (1.0, 2.0, 3.0):
+            mesh.set_nearfield(eta)
+            rp, col = mesh.nearfield_list()
+            rpo, colo = _clib.near_pairs(xyz, tri, eta)
+            assert np.array_equal(rp, rpo) and np.array_equal(col, colo), (name, eta)
+
+
+@pytest.mark.parametrize("name", ["sphere", "box", "perturbed"])
+def test_corrected_moments_match_oracle(bem, torch, oracle_lib, name):
+    from oracle import method as M
+
+    xyz, tri = _mesh(name)
+    n = len(tri)
+    z, w, W = bem.contour_nodes(4.0, 1.5, 16, P=2)
+    V = synth.probe_block(n, 16, seed=1)
+    eta = 2.0
+    corr = _correction_ref(xyz, tri, eta, z, W, V)
+    base = M.contour_moments(M.Operator(xyz, tri), z, W, V)
+    full = base + corr
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(eta)
+        Vd = _dev(torch, V)
+        Mg = mesh.contour_moments(z, W, Vd)
+        mesh.nearfield_moments(z, W, Vd, out=Mg)
+        Cg = mesh.nearfield_moments(z, W, Vd).cpu().numpy()
+        Mg = Mg.cpu().numpy()
+    for p in range(W.shape[1]):
+        e_full = np.linalg.norm(Mg[p] - full[p]) / np.linalg.norm(full[p])
+        e_corr = np.linalg.norm(Cg[p] - corr[p]) / np.linalg.norm(full[p])
+        print(f"{name} p={p}: corrected moments rel err {e_full:.2e}, correction err {e_corr:.2e} "
+              f"(|corr|/|M| = {np.linalg.norm(corr[p]) / np.linalg.norm(full[p]):.1e})")
+        assert e_full <= TOL and e_corr <= TOL
+    # the correction is not negligible at this size: it changes the moments well above the
+    # parity tolerance
+    assert np.linalg.norm(corr[0]) >= 1e3 * TOL * np.linalg.norm(full[0])
+
+
+def test_many_weight_sets_ragged_and_strided(bem, torch, oracle_lib):
+    """P = 11 (two launches of up to 8 weight sets), per-node weights (W = I gives
+    dT(z_j) V), m = 5 inside a strided probe block, a ragged mesh size."""
+    xyz, tri = synth.perturbed_icosphere(2, 0.08, 7)
+    tri = tri[:301]
+    used = np.unique(tri)
+    remap = -np.ones(len(xyz), dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    xyz, tri = xyz[used], remap[tri].astype(np.int32)
+    n = len(tri)
+    rng = np.random.default_rng(3)
+    z = np.array([3.0 + 0.5j, 4.5 - 0.2j, 2.0, 5.5 + 1.0j, 4.0 + 0.0j])
+    W = rng.normal(size=(5, 11)) + 1j * rng.normal(size=(5, 11))
+    Vfull = synth.probe_block(n, 9, seed=2)
+    V = Vfull[:, 2:7]
+    corr = _correction_ref(xyz, tri, 2.5, z, W, V)
+    corr_id = _correction_ref(xyz, tri, 2.5, z, np.eye(5, dtype=np.complex128), V)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.5)
+        Vd = _dev(torch, Vfull)[:, 2:7]
+        Cg = mesh.nearfield_moments(z, W, Vd).cpu().numpy()
+        Ig = mesh.nearfield_moments(z, np.eye(5), Vd).cpu().numpy()
+    for p in range(11):
+        assert np.linalg.norm(Cg[p] - corr[p]) <= 1e-11 * np.linalg.norm(corr[p])
+    for j in range(5):
+        assert np.linalg.norm(Ig[j] - corr_id[j]) <= 1e-11 * np.linalg.norm(corr_id[j])
+
+
+def test_no_list_leaves_moments_unchanged_and_errors(bem, torch):
+    xyz, tri = synth.icosphere(2)
+    n = len(tri)
+    z, w, W = bem.contour_nodes(4.0, 1.5, 8, P=1)
+    with bem.Mesh(xyz, tri) as mesh:
+        Vd = _dev(torch, synth.probe_block(n, 4, seed=1))
+        M0 = torch.ones((1, n, 4), dtype=torch.complex128, device="cuda")
+        mesh.nearfield_moments(z, W, Vd, out=M0)
+        assert bool((M0 == 1).all())
+        mesh.set_nearfield(2.0)
+        mesh.set_nearfield(0.0)  # removes the list again
+        mesh.nearfield_moments(z, W, Vd, out=M0)
+        assert bool((M0 == 1).all())
+        for bad in (-1.0, 17.0, float("nan")):
+            with pytest.raises(bem.BemError, match="EINVAL"):
+                mesh.set_nearfield(bad)
+        mesh.set_nearfield(2.0)
+        with pytest.raises(bem.BemError, match="EINVAL"):
+            mesh.nearfield_moments(z, np.full_like(W, np.nan), Vd, out=M0)
+        torch.cuda.synchronize()
+
+
+def test_deterministic(bem, torch):
+    xyz, tri = synth.icosphere(3)
+    z, w, W = bem.contour_nodes(5.0, 2.0, 24, P=2)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        Vd = _dev(torch, synth.probe_block(len(tri), 8, seed=4))
+        a = mesh.nearfield_moments(z, W, Vd)
+        b = mesh.nearfield_moments(z, W, Vd)
+        assert bool((a == b).all())
