@@ -315,6 +315,54 @@ def large_eigen(freq):
             "phase_seconds": phase, "max_distance_to_sphere_eigenvalue": max(dist) if dist else None}
 
 
+def near_field(mesh, U, z, W, sweep_kernel_ms, eta=2.0, freq=158):
+    """Near-field correction (bem_nearfield_moments, eta = 2): on the headline mesh beside the
+    per-node sweep it corrects, and on the harmonic sphere of 20 freq^2 triangles
+    (radius 1 + 0.1 sum_{l<=6} c_lm Y_lm, seed 5) with the same nodes, weights and m."""
+    import numpy as np
+    import torch
+
+    import paper_1906_03938_amd as bem
+    import synth
+
+    def timed(msh, V, reps=3):
+        out = torch.zeros((W.shape[1], msh.n, V.shape[1]), dtype=torch.complex128, device="cuda")
+        msh.nearfield_moments(z, W, V, out=out)  # warm-up
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            msh.nearfield_moments(z, W, V, out=out)
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        bem.stream_status()
+        return float(np.median(ms))
+
+    res = {"eta": eta, "nodes": len(z), "weight_sets": int(W.shape[1]), "m": int(U.shape[1])}
+    t0 = time.perf_counter()
+    mesh.set_nearfield(eta)
+    res["headline_list_s"] = time.perf_counter() - t0
+    res["headline_pairs"] = int(mesh.nearfield_list()[1].size)
+    res["headline_ms"] = timed(mesh, U)
+    res["headline_fraction_of_sweep_kernel"] = res["headline_ms"] / sweep_kernel_ms
+    mesh.set_nearfield(0.0)
+    xyz, tri = synth.harmonic_sphere(freq, seed=5)
+    n = len(tri)
+    V = torch.from_numpy(synth.probe_block(n, U.shape[1], seed=5)).to("cuda")
+    with bem.Mesh(xyz, tri) as big:
+        t0 = time.perf_counter()
+        big.set_nearfield(eta)
+        res["harmonic_list_s"] = time.perf_counter() - t0
+        pairs = int(big.nearfield_list()[1].size)
+        ms = timed(big, V)
+    res.update({"harmonic_mesh": f"harmonic sphere f={freq}, n={n}", "harmonic_pairs": pairs,
+                "harmonic_ms": ms, "pair_node_evaluations_per_s": pairs * len(z) / (ms * 1e-3)})
+    del V
+    torch.cuda.empty_cache()
+    return res
+
+
 def eigen_check():
     """Eigenvalues of the sphere-1280 workload (icosphere level 3, |z - 4| < 1.5, N = 32,
     16 probes, seed 1) by the host driver on device sweeps, against the oracle's values
@@ -349,6 +397,7 @@ def main():
     ap.add_argument("--no-eigen-check", action="store_true")
     ap.add_argument("--no-precision-form", action="store_true")
     ap.add_argument("--no-batched-form", action="store_true")
+    ap.add_argument("--no-near-field", action="store_true")
     ap.add_argument("--large-eigen", type=int, default=0, metavar="F",
                     help="also run the eigen-extraction on the geodesic sphere of frequency F (n = 20 F^2) "
                          "with the LU on the device")
@@ -464,6 +513,8 @@ def main():
         "unit": "kernel-entry*RHS/s", "contractions": w["P"], "operators_generated": L,
         "speedup_vs_per_node_sweep_kernel": kms / float(np.mean(fold_ms)),
     }
+    if not args.no_near_field:
+        out["near_field"] = near_field(mesh, U, z2, W2, kms)
     mesh.close()
     if not args.no_eigen_check:
         out["eigen_check"] = eigen_check()

@@ -33,6 +33,7 @@ constexpr int kNfPairs = 64;
 constexpr int kNfGroups = kNfThreads / kNfPairs;
 constexpr int kNfGL = 16;
 constexpr int kNfMaxPanels = 64;
+constexpr int kNfNodes = 4;  // nodes per thread evaluated together
 
 struct NfArgs {
     const double4 *colloc;
@@ -63,7 +64,8 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
     const int i = t % kNfPairs, grp = t / kNfPairs;
     for (int64_t base = beg; base < end; base += kNfPairs) {
         const int cnt = (int)(end - base < kNfPairs ? end - base : kNfPairs);
-        double2 acc[kNfFold];
+        // this thread's folded sums live in its own LDS slots (fewer live registers)
+        double2 *acc = red[grp][i];
 #pragma unroll
         for (int p = 0; p < kNfFold; ++p) acc[p] = make_double2(0.0, 0.0);
         if (i < cnt) {
@@ -120,65 +122,71 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
                 eh[e] = (u1 - u0) / np;
                 enp[e] = np;
             }
-            // 7-point distances of the rule the sweep uses
-            double r7[kQuad], w7[kQuad];
+            // this thread's nodes j = grp + kNfGroups * t, taken kNfNodes at a time: the
+            // geometry of each quadrature point is computed once per chunk, and the chunk's
+            // independent series evaluations overlap in the pipeline
+            for (int j0 = grp; j0 < g.N; j0 += kNfGroups * kNfNodes) {
+                double kr[kNfNodes], ki[kNfNodes], sr[kNfNodes], si[kNfNodes];
 #pragma unroll
-            for (int q = 0; q < kQuad; ++q) {
-                const double4 y = g.quad[b * kQuad + q];
-                const double dx = x[0] - y.x, dy = x[1] - y.y, dz = x[2] - y.z;
-                r7[q] = sqrt(dx * dx + dy * dy + dz * dz);
-                w7[q] = y.w;  // A_b w_q / (4 pi)
-            }
-            for (int j = grp; j < g.N; j += kNfGroups) {
-                const double kr = g.kappa[j].x, ki = g.kappa[j].y;
-                double sr = 0.0, si = 0.0;
+                for (int s = 0; s < kNfNodes; ++s) {
+                    const int j = j0 + s * kNfGroups;
+                    const double2 kj = j < g.N ? g.kappa[j] : make_double2(0.0, 0.0);
+                    kr[s] = kj.x;
+                    ki[s] = kj.y;
+                    sr[s] = 0.0;
+                    si[s] = 0.0;
+                }
                 for (int e = 0; e < 3; ++e) {
-                    double er = 0.0, ei = 0.0;
                     for (int pn = 0; pn < enp[e]; ++pn) {
                         const double mid = eu0[e] + (pn + 0.5) * eh[e];
-                        double pr = 0.0, pi = 0.0;
+                        const double scale = 0.5 * eh[e] * esg[e];
                         for (int k = 0; k < kNfGL; ++k) {
                             const double uu = mid + 0.5 * eh[e] * g.gl[k];
                             const double ch = cosh(uu);
                             const double rho = eap[e] * ch;
                             const double dl = rho * rho / (sqrt(rho * rho + d * d) + ad);
-                            const double2 E = exprel(-ki * dl, kr * dl);  // w = i kappa delta
-                            const double wt = g.gl[kNfGL + k] * dl / ch;
-                            pr += wt * E.x;
-                            pi += wt * E.y;
+                            const double wt = scale * g.gl[kNfGL + k] * dl / ch;
+#pragma unroll
+                            for (int s = 0; s < kNfNodes; ++s) {
+                                const double2 E = exprel(-ki[s] * dl, kr[s] * dl);  // w = i kappa delta
+                                sr[s] += wt * E.x;
+                                si[s] += wt * E.y;
+                            }
                         }
-                        er += 0.5 * eh[e] * pr;
-                        ei += 0.5 * eh[e] * pi;
                     }
-                    sr += esg[e] * er;
-                    si += esg[e] * ei;
-                }
-                // e^{i kappa |d|} / (4 pi)
-                double s0, c0;
-                sincos(kr * ad, &s0, &c0);
-                const double m0 = exp(-ki * ad) * inv4pi;
-                double dr = m0 * (c0 * sr - s0 * si), di = m0 * (c0 * si + s0 * sr);
-                // minus the 7-point value
-#pragma unroll
-                for (int q = 0; q < kQuad; ++q) {
-                    double sq, cq;
-                    sincos(kr * r7[q], &sq, &cq);
-                    const double mq = exp(-ki * r7[q]) * w7[q] / r7[q];
-                    dr -= mq * cq;
-                    di -= mq * sq;
                 }
 #pragma unroll
-                for (int p = 0; p < kNfFold; ++p) {
-                    if (p < g.P) {
-                        const double2 w = g.W[(int64_t)j * g.Pstride + g.p0 + p];
-                        acc[p].x += w.x * dr - w.y * di;
-                        acc[p].y += w.x * di + w.y * dr;
+                for (int s = 0; s < kNfNodes; ++s) {
+                    const int j = j0 + s * kNfGroups;
+                    if (j >= g.N) break;
+                    // e^{i kappa |d|} / (4 pi)
+                    double s0, c0;
+                    sincos(kr[s] * ad, &s0, &c0);
+                    const double m0 = exp(-ki[s] * ad) * inv4pi;
+                    double dr = m0 * (c0 * sr[s] - s0 * si[s]), di = m0 * (c0 * si[s] + s0 * sr[s]);
+                    // minus the 7-point value of the rule the sweep uses
+#pragma unroll
+                    for (int q = 0; q < kQuad; ++q) {
+                        const double4 y = g.quad[b * kQuad + q];
+                        const double qx = x[0] - y.x, qy = x[1] - y.y, qz = x[2] - y.z;
+                        const double rq = sqrt(qx * qx + qy * qy + qz * qz);
+                        double sq, cq;
+                        sincos(kr[s] * rq, &sq, &cq);
+                        const double mq = exp(-ki[s] * rq) * y.w / rq;  // y.w = A_b w_q / (4 pi)
+                        dr -= mq * cq;
+                        di -= mq * sq;
+                    }
+#pragma unroll
+                    for (int p = 0; p < kNfFold; ++p) {
+                        if (p < g.P) {
+                            const double2 w = g.W[(int64_t)j * g.Pstride + g.p0 + p];
+                            acc[p].x += w.x * dr - w.y * di;
+                            acc[p].y += w.x * di + w.y * dr;
+                        }
                     }
                 }
             }
         }
-#pragma unroll
-        for (int p = 0; p < kNfFold; ++p) red[grp][i][p] = acc[p];
         __syncthreads();
         // fold the node groups in a fixed order
         for (int idx = t; idx < cnt * g.P; idx += kNfThreads) {

@@ -142,6 +142,33 @@ def geodesic_sphere(freq: int):
     return np.asarray(pts, dtype=np.float64), np.asarray(tris, dtype=np.int32)
 
 
+def harmonic_sphere(freq: int = 158, seed: int = 5, amplitude: float = 0.1, lmax: int = 6):
+    """Class-I geodesic sphere of frequency f (20 f^2 triangles; f = 158 gives 499,280) with
+    each vertex moved radially to r = 1 + amplitude sum_{l <= lmax, |m| <= l} c_lm Y_lm, the
+    Y_lm real orthonormal spherical harmonics and c_lm ~ N(0, 1)/sqrt(#terms) drawn from
+    PCG64(seed) in (l, m) order: a smooth star-shaped closed surface of uneven curvature."""
+    from scipy.special import sph_harm_y
+
+    xyz, tri = geodesic_sphere(freq)
+    theta = np.arccos(np.clip(xyz[:, 2], -1.0, 1.0))
+    phi = np.arctan2(xyz[:, 1], xyz[:, 0])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    terms = (lmax + 1) ** 2
+    r = np.ones(len(xyz))
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            c = rng.standard_normal() / np.sqrt(terms)
+            Y = sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                y = np.sqrt(2.0) * Y.real
+            elif m < 0:
+                y = np.sqrt(2.0) * Y.imag
+            else:
+                y = Y.real
+            r += amplitude * c * y
+    return xyz * r[:, None], tri
+
+
 def ellipsoid_batch(count: int = 64, seed: int = 4, freq=(10, 44), axes=(0.5, 1.5), centre=(3.0, 7.0)):
     """A seeded batch of uneven ellipsoid meshes, each with the real centre of its own
     contour.  From NumPy's PCG64(seed), per mesh in order: the geodesic frequency

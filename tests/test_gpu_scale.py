@@ -72,3 +72,50 @@ def test_cheb_moments_at_scale(big):
     err = max(np.linalg.norm(C[l] - Co[l]) for l in range(L)) / scale
     print(f"chebyshev blocks: max error / |C_0| = {err:.2e}", flush=True)
     assert err <= TOL
+
+
+def test_nearfield_at_scale():
+    """Workload "harmonic-499280": the harmonic sphere of 499,280 triangles (geodesic f = 158,
+    radius 1 + 0.1 sum_{l<=6} c_lm Y_lm, seed 5), eta = 2, circle |z - 5| = 2 with N = 64
+    nodes, P = 2 weight sets, m = 16 probes (seed 5).  Sampled rows: the near-pair list
+    against a brute-force scan over every source triangle, and the correction rows against
+    the oracle's adaptive integrals minus its 7-point entries, 1e-12 of the row's near-field
+    part (the sum of the same rows with the 7-point values of the near pairs added back)."""
+    import torch
+
+    import paper_1906_03938_amd as bem
+    from oracle import _clib
+
+    xyz, tri = synth.harmonic_sphere(158, seed=5)
+    n = len(tri)
+    rows = np.array([0, 1, 12345, 249639, 400000, n - 2, n - 1], dtype=np.int64)
+    z, w, W = bem.contour_nodes(5.0, 2.0, 64, P=2)
+    V = synth.probe_block(n, 16, seed=5)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        rp, col = mesh.nearfield_list()
+        Cg = mesh.nearfield_moments(z, W, torch.from_numpy(V).to("cuda"))[:, torch.from_numpy(rows).to("cuda")]
+        Cg = Cg.cpu().numpy()
+    P = xyz[tri]
+    cen = ((P[:, 0] + P[:, 1]) + P[:, 2]) / 3.0
+    h2 = np.zeros(n)
+    for e in range(3):
+        d = P[:, (e + 1) % 3] - P[:, e]
+        h2 = np.maximum(h2, d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2])
+    area, cen_o, qp, qw = _clib.geometry(xyz, tri)
+    for r, a in enumerate(rows):
+        dx, dy, dz = cen[a, 0] - cen[:, 0], cen[a, 1] - cen[:, 1], cen[a, 2] - cen[:, 2]
+        near = np.nonzero(dx * dx + dy * dy + dz * dz < (2.0 * 2.0) * h2)[0]
+        near = near[near != a]
+        assert np.array_equal(col[rp[a]:rp[a + 1]], near.astype(np.int32)), a
+        corr = np.zeros((2, 16), dtype=np.complex128)
+        part = np.zeros((2, 16), dtype=np.complex128)
+        for b in near:
+            exact = _clib.tri_integral(cen_o[a], P[b], z)
+            rq = np.linalg.norm(cen_o[a][None, :] - qp[b], axis=1)
+            seven = np.array([np.sum(qw[b] * np.exp(1j * k * rq) / (4 * np.pi * rq)) for k in z])
+            corr += (W.T @ (exact - seven))[:, None] * V[b][None, :]
+            part += (W.T @ exact)[:, None] * V[b][None, :]
+        for p in range(2):
+            err = np.linalg.norm(Cg[p, r] - corr[p]) / np.linalg.norm(part[p])
+            assert err <= TOL, (a, p, err)

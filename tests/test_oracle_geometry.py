@@ -224,3 +224,20 @@ def test_ellipsoid_batch_recipe():
         assert np.all((axa >= 0.5) & (axa <= 1.5)) and 3.0 <= ca <= 7.0
         assert np.allclose(((xa / axa[None, :]) ** 2).sum(axis=1), 1.0, atol=1e-13)
         assert synth.mesh_edges_ok(ta)
+
+
+def test_harmonic_sphere_shape():
+    """20 f^2 triangles, closed (every edge in two faces), radius within 1 +- 0.1 sum |c Y|,
+    seeded (same seed, same mesh) and star-shaped around the origin."""
+    import synth
+
+    xyz, tri = synth.harmonic_sphere(9, seed=5)
+    assert tri.shape == (20 * 81, 3) and xyz.shape == (10 * 81 + 2, 3)
+    assert synth.mesh_edges_ok(tri)
+    r = np.linalg.norm(xyz, axis=1)
+    assert 0.8 < r.min() < 1.0 < r.max() < 1.2
+    xyz2, tri2 = synth.harmonic_sphere(9, seed=5)
+    assert np.array_equal(xyz, xyz2) and np.array_equal(tri, tri2)
+    P = xyz[tri]
+    vol6 = np.einsum("ij,ij->i", P[:, 0], np.cross(P[:, 1], P[:, 2]))
+    assert (vol6 > 0).all()  # every face sees the origin on the same side
