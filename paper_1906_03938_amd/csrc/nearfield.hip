@@ -19,8 +19,9 @@
 // of length <= 2 (the integrand's nearest singularities lie at Im u = +-pi/2) and no wider
 // than 2 / (kappa_max rho_max) in phase, each integrated with 16-point Gauss-Legendre.
 //
-// One workgroup per target row; its pairs are taken 64 at a time, four node groups per
-// pair, so every partial sum is reduced in a fixed order and results are deterministic.
+// One workgroup per target row; its pairs are taken 64 at a time, with 256 / (pairs in the
+// chunk) node groups per pair, and every partial sum is reduced in a fixed order, so results
+// are deterministic.
 #include "devmath.h"
 #include "internal.h"
 
@@ -30,7 +31,6 @@ namespace {
 
 constexpr int kNfThreads = 256;
 constexpr int kNfPairs = 64;
-constexpr int kNfGroups = kNfThreads / kNfPairs;
 constexpr int kNfGL = 16;
 constexpr int kNfMaxPanels = 64;
 constexpr int kNfNodes = 4;  // nodes per thread evaluated together
@@ -53,7 +53,7 @@ struct NfArgs {
 };
 
 __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
-    __shared__ double2 red[kNfGroups][kNfPairs][kNfFold];
+    __shared__ double2 red[kNfThreads][kNfFold];
     __shared__ int32_t cols[kNfPairs];
     const int64_t a = blockIdx.x;
     const int t = threadIdx.x;
@@ -61,14 +61,17 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
     if (beg >= end) return;  // uniform over the workgroup
     const double4 xa = g.colloc[a];
     const double inv4pi = 0.25 / 3.14159265358979323846;
-    const int i = t % kNfPairs, grp = t / kNfPairs;
     for (int64_t base = beg; base < end; base += kNfPairs) {
         const int cnt = (int)(end - base < kNfPairs ? end - base : kNfPairs);
+        // as many node groups per pair as the workgroup holds (at least 4): thread t takes
+        // pair t % cnt and node group t / cnt, so rows with few pairs still fill the lanes
+        const int G = kNfThreads / cnt;
+        const int i = t % cnt, grp = t / cnt;
         // this thread's folded sums live in its own LDS slots (fewer live registers)
-        double2 *acc = red[grp][i];
+        double2 *acc = red[t];
 #pragma unroll
         for (int p = 0; p < kNfFold; ++p) acc[p] = make_double2(0.0, 0.0);
-        if (i < cnt) {
+        if (grp < G) {
             const int64_t b = g.col[base + i];
             if (grp == 0) cols[i] = (int32_t)b;
             double P[3][3];
@@ -122,14 +125,14 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
                 eh[e] = (u1 - u0) / np;
                 enp[e] = np;
             }
-            // this thread's nodes j = grp + kNfGroups * t, taken kNfNodes at a time: the
+            // this thread's nodes j = grp + G * s, s = 0, 1, ..., taken kNfNodes at a time: the
             // geometry of each quadrature point is computed once per chunk, and the chunk's
             // independent series evaluations overlap in the pipeline
-            for (int j0 = grp; j0 < g.N; j0 += kNfGroups * kNfNodes) {
+            for (int j0 = grp; j0 < g.N; j0 += G * kNfNodes) {
                 double kr[kNfNodes], ki[kNfNodes], sr[kNfNodes], si[kNfNodes];
 #pragma unroll
                 for (int s = 0; s < kNfNodes; ++s) {
-                    const int j = j0 + s * kNfGroups;
+                    const int j = j0 + s * G;
                     const double2 kj = j < g.N ? g.kappa[j] : make_double2(0.0, 0.0);
                     kr[s] = kj.x;
                     ki[s] = kj.y;
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
                 }
 #pragma unroll
                 for (int s = 0; s < kNfNodes; ++s) {
-                    const int j = j0 + s * kNfGroups;
+                    const int j = j0 + s * G;
                     if (j >= g.N) break;
                     // e^{i kappa |d|} / (4 pi)
                     double s0, c0;
@@ -191,12 +194,12 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
         // fold the node groups in a fixed order
         for (int idx = t; idx < cnt * g.P; idx += kNfThreads) {
             const int k = idx / g.P, p = idx % g.P;
-            double2 s = red[0][k][p];
-            for (int q = 1; q < kNfGroups; ++q) {
-                s.x += red[q][k][p].x;
-                s.y += red[q][k][p].y;
+            double2 s = red[k][p];
+            for (int q = 1; q < G; ++q) {
+                s.x += red[q * cnt + k][p].x;
+                s.y += red[q * cnt + k][p].y;
             }
-            red[0][k][p] = s;
+            red[k][p] = s;
         }
         __syncthreads();
         // apply to the probe block
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
             const int64_t c = item % g.m;
             double sr = 0.0, si = 0.0;
             for (int k = 0; k < cnt; ++k) {
-                const double2 f = red[0][k][p];
+                const double2 f = red[k][p];
                 const double2 v = g.V[(int64_t)cols[k] * g.ldv + c];
                 sr += f.x * v.x - f.y * v.y;
                 si += f.x * v.y + f.y * v.x;
