@@ -193,7 +193,7 @@ bem_status rr_project(bem_mesh_t mesh, const double *z, int64_t N, const double 
  * the longest edge of triangle b, all formed in that order without fused multiply-adds.
  * For near pairs the corrected operator uses the integral of g(|x_a - y|) over triangle b
  * (semi-analytic: polar form around the foot of x_a on the plane of b, radial part in closed
- * form, angular part by sinh-transformed 16-point Gauss-Legendre panels; accurate to about
+ * form, angular part by sinh-transformed Gauss-Legendre panels of 16 or 10 points; accurate to about
  * 1e-14 relative while |kappa| h_b <~ 2) in place of the 7-point value.
  *
  * bem_mesh_set_nearfield builds the near-pair list of the mesh on the host and uploads it

@@ -1189,8 +1189,9 @@ bem_status bem_mesh_set_nearfield(bem_mesh_t h, double eta) {
     if (!near_list(h->nf_cen, h->nf_h2, h->dm.n, eta, rowptr, col))
         return fail(BEM_ENOMEM, "host allocation failed (near-pair list)");
     const int64_t nnz = (int64_t)col.size();
-    double glh[2 * 16];
+    double glh[2 * 16 + 2 * 10];  // 16-point rule, then the 10-point rule (nodes, weights)
     gauss_legendre(16, glh, glh + 16);
+    gauss_legendre(10, glh + 32, glh + 42);
     HIP_TRY(h->nf_rowptr.ensure(sizeof(int64_t) * rowptr.size()), "near-pair list");
     HIP_TRY(h->nf_col.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "near-pair list");
     HIP_TRY(h->nf_gl.ensure(sizeof glh), "near-field rule");

@@ -135,7 +135,8 @@ hipError_t launch_project_finish(const double2 *partial, int nchunks, int L, int
 
 // Near-field correction (nearfield.hip): M[p0 + p][a, :] += sum_j W[j][p0 + p] sum_{b in
 // row a of (rowptr, col)} (integral - 7-point value of T_ab(kappa_j)) V[b, :], p < P <= kNfFold;
-// one workgroup per row of the mesh.  gl16: 16-point Gauss-Legendre nodes then weights.
+// one workgroup per row of the mesh.  gl16: 16-point Gauss-Legendre nodes then weights,
+// followed by the 10-point rule's nodes then weights.
 constexpr int kNfFold = 8;
 hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const int64_t *rowptr,
                             const int32_t *col, const double2 *kappa, int N, const double2 *W, int Pstride,
