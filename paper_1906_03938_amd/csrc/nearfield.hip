@@ -56,6 +56,7 @@ struct NfArgs {
 
 __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
     __shared__ double2 red[kNfThreads][kNfFold];
+    __shared__ double2 fold[kNfPairs][kNfFold];
     __shared__ int32_t cols[kNfPairs];
     const int64_t a = blockIdx.x;
     const int t = threadIdx.x;
@@ -65,15 +66,16 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
     const double inv4pi = 0.25 / 3.14159265358979323846;
     for (int64_t base = beg; base < end; base += kNfPairs) {
         const int cnt = (int)(end - base < kNfPairs ? end - base : kNfPairs);
-        // as many node groups per pair as the workgroup holds (at least 4): thread t takes
-        // pair t % cnt and node group t / cnt, so rows with few pairs still fill the lanes
+        // as many node groups per pair as the workgroup holds (at least 4), so rows with few
+        // pairs still fill the lanes; thread t takes pair t / G and node group t % G, so the
+        // G lanes of one pair follow the same panel loops
         const int G = kNfThreads / cnt;
-        const int i = t % cnt, grp = t / cnt;
+        const int i = t / G, grp = t % G;
         // this thread's folded sums live in its own LDS slots (fewer live registers)
         double2 *acc = red[t];
 #pragma unroll
         for (int p = 0; p < kNfFold; ++p) acc[p] = make_double2(0.0, 0.0);
-        if (grp < G) {
+        if (i < cnt) {
             const int64_t b = g.col[base + i];
             if (grp == 0) cols[i] = (int32_t)b;
             double P[3][3];
@@ -202,12 +204,12 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
         // fold the node groups in a fixed order
         for (int idx = t; idx < cnt * g.P; idx += kNfThreads) {
             const int k = idx / g.P, p = idx % g.P;
-            double2 s = red[k][p];
+            double2 s = red[k * G][p];
             for (int q = 1; q < G; ++q) {
-                s.x += red[q * cnt + k][p].x;
-                s.y += red[q * cnt + k][p].y;
+                s.x += red[k * G + q][p].x;
+                s.y += red[k * G + q][p].y;
             }
-            red[k][p] = s;
+            fold[k][p] = s;
         }
         __syncthreads();
         // apply to the probe block
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
             const int64_t c = item % g.m;
             double sr = 0.0, si = 0.0;
             for (int k = 0; k < cnt; ++k) {
-                const double2 f = red[k][p];
+                const double2 f = fold[k][p];
                 const double2 v = g.V[(int64_t)cols[k] * g.ldv + c];
                 sr += f.x * v.x - f.y * v.y;
                 si += f.x * v.y + f.y * v.x;
