@@ -168,3 +168,37 @@ def test_deterministic(bem, torch):
         a = mesh.nearfield_moments(z, W, Vd)
         b = mesh.nearfield_moments(z, W, Vd)
         assert bool((a == b).all())
+
+
+@pytest.mark.parametrize("eta,level", [(4.0, 2), (16.0, 1)])
+def test_rows_longer_than_one_chunk(bem, torch, oracle_lib, eta, level):
+    """Rows with more than 64 near pairs are taken in several chunks of different lengths
+    (eta = 4: about 130 pairs per row, chunks of 64, 64 and the rest; eta = 16 on 80
+    triangles: every other triangle is near, chunks of 64 and 15)."""
+    xyz, tri = synth.perturbed_icosphere(level, 0.05, 9)
+    n = len(tri)
+    z = np.array([3.0 + 0.4j, 5.0 - 0.3j, 4.2, 6.1 + 0.8j, 2.5 + 0.1j, 3.3 - 0.9j])
+    rng = np.random.default_rng(8)
+    W = rng.normal(size=(6, 3)) + 1j * rng.normal(size=(6, 3))
+    V = synth.probe_block(n, 7, seed=3)
+    corr = _correction_ref(xyz, tri, eta, z, W, V)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(eta)
+        rp, _ = mesh.nearfield_list()
+        assert np.diff(rp).max() > 64
+        Cg = mesh.nearfield_moments(z, W, _dev(torch, V)).cpu().numpy()
+    for p in range(3):
+        assert np.linalg.norm(Cg[p] - corr[p]) <= 1e-11 * np.linalg.norm(corr[p])
+
+
+def test_single_node_weight_and_column(bem, torch, oracle_lib):
+    xyz, tri = synth.icosphere(2)
+    n = len(tri)
+    z = np.array([4.5 + 0.2j])
+    W = np.array([[0.7 - 0.3j]])
+    V = synth.probe_block(n, 1, seed=6)
+    corr = _correction_ref(xyz, tri, 2.0, z, W, V)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        Cg = mesh.nearfield_moments(z, W, _dev(torch, V)).cpu().numpy()
+    assert np.linalg.norm(Cg[0] - corr[0]) <= 1e-11 * np.linalg.norm(corr[0])
