@@ -219,6 +219,15 @@ bem_status bem_nearfield_moments(bem_mesh_t mesh, const double *z, int64_t N, co
                                  int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
                                  int64_t ldm, hipStream_t stream);
 
+/* Adds the near-field correction to a dense node combination: S[a][b] += sum_j c_j
+ * dT_ab(z_j) for every near pair (a, b) of the mesh's list, so that bem_assemble_sum followed
+ * by this call gives sum_j c_j T(z_j) of the corrected operator (the matrix the inverse
+ * iteration solves with).  z, c [host]: N complex.  S: device, n x lds complex (lds >= n), read
+ * and written.  Without a near-pair list S is left unchanged.  Errors: BEM_EINVAL, BEM_ENOMEM,
+ * BEM_EDEVICE. */
+bem_status bem_nearfield_sum(bem_mesh_t mesh, const double *z, int64_t N, const double *c, double *S,
+                             int64_t lds, hipStream_t stream);
+
 /* Dense node combination S = sum_j c_j T(z_j), n x n row-major (row stride lds >= n): the
  * matrix the inverse iteration solves with -- for the Cauchy form the Schur complement
  * S = sum_j w_j T(z_j)/(z_j - s) of the linearisation at the shift s (paper, eq. sc2-sc5:

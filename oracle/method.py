@@ -94,12 +94,17 @@ def cheb_eval(coefs, xi):
 
 
 class Operator:
-    """T(kappa) of a closed triangle mesh; caches dense matrices for small meshes."""
+    """T(kappa) of a closed triangle mesh; caches dense matrices for small meshes.
 
-    def __init__(self, xyz, tri):
+    nearfield_eta > 0 selects the near-field-corrected operator: the entries of the near
+    pairs (|x_a - x_b| < eta h_b) are the adaptive integrals over the source triangle instead
+    of their 7-point values (dense matrices only, no derivatives)."""
+
+    def __init__(self, xyz, tri, nearfield_eta: float = 0.0):
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self.tri = np.ascontiguousarray(tri, dtype=np.int32)
         self.n = self.tri.shape[0]
+        self.nearfield_eta = float(nearfield_eta)
         self._dense = {}
 
     def dense(self, kappa, deriv: int = 0):
@@ -107,6 +112,12 @@ class Operator:
         T = self._dense.get(key)
         if T is None:
             T = _clib.dense(self.xyz, self.tri, kappa, deriv)
+            if self.nearfield_eta > 0.0:
+                if deriv:
+                    raise NotImplementedError("no derivatives of the near-field-corrected operator")
+                rp, col, dT = _clib.nearfield_correction(self.xyz, self.tri, self.nearfield_eta, [kappa])
+                rows = np.repeat(np.arange(self.n), np.diff(rp))
+                T[rows, col] += dT[0]
             if self.n <= 2048:
                 self._dense[key] = T
         return T
@@ -117,6 +128,8 @@ class Operator:
         V = np.asarray(V, dtype=np.complex128)
         if rows is None and self.n <= 2048:
             return self.dense(kappa, deriv) @ V
+        if self.nearfield_eta > 0.0:
+            raise NotImplementedError("the near-field-corrected operator is dense only")
         return _clib.apply_rows(self.xyz, self.tri, kappa, V, rows, deriv)
 
 

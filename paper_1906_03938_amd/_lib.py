@@ -30,7 +30,7 @@ EXPORTS = [
     "bem_last_kernel_ms", "bem_stream_status", "bem_last_error",
     "bem_assemble_sum", "bem_batch_create", "bem_batch_destroy", "bem_batch_layout", "bem_batch_moments",
     "bem_batch_set_timing", "bem_batch_last_kernel_ms",
-    "bem_mesh_set_nearfield", "bem_mesh_nearfield", "bem_nearfield_moments",
+    "bem_mesh_set_nearfield", "bem_mesh_nearfield", "bem_nearfield_moments", "bem_nearfield_sum",
 ]
 
 
@@ -89,6 +89,7 @@ def lib():
     L.bem_mesh_set_nearfield.argtypes = [_vp, ctypes.c_double]
     L.bem_mesh_nearfield.argtypes = [_vp, ctypes.POINTER(_i64), _vp, _vp]
     L.bem_nearfield_moments.argtypes = [_vp, _dp, _i64, _dp, _i64, _vp, _i64, _i64, _vp, _i64, _vp]
+    L.bem_nearfield_sum.argtypes = [_vp, _dp, _i64, _dp, _vp, _i64, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("bem_mesh_destroy", "bem_mesh_size", "bem_last_error", "bem_batch_destroy"):
@@ -252,6 +253,18 @@ class Mesh:
         _check(lib().bem_nearfield_moments(self._h, _hp(z), z.size, _hp(W), W.shape[1], pv, m, ldv,
                                            ctypes.c_void_p(M.data_ptr()), M.stride(1), _stream()))
         return M
+
+    def nearfield_sum(self, z, c, S):
+        """Adds sum_j c_j dT(z_j) to the dense n x n matrix S (device, complex128) in place."""
+        z = _host_complex(z)
+        c = _host_complex(c)
+        if c.size != z.size:
+            raise ValueError("need one coefficient per node")
+        if S.dim() != 2 or S.shape[0] != self.n or S.shape[1] < self.n or S.stride(1) != 1:
+            raise ValueError("S must be an n x n (row stride >= n) complex128 device matrix")
+        _check(lib().bem_nearfield_sum(self._h, _hp(z), z.size, _hp(c), ctypes.c_void_p(S.data_ptr()), S.stride(0),
+                                       _stream()))
+        return S
 
     def cheb_moments(self, a, b, N, L, V, out=None, form=FORM_AUTO):
         pv, m, ldv = _block(V, "V")

@@ -1253,9 +1253,35 @@ bem_status bem_nearfield_moments(bem_mesh_t h, const double *z, int64_t N, const
                                          h->nf_col.as<int32_t>(), reinterpret_cast<const double2 *>(base + off_z),
                                          (int)N, reinterpret_cast<const double2 *>(base + off_w), (int)P, (int)p0, Pc,
                                          kmax, reinterpret_cast<const double2 *>(V), ldv, m,
-                                         reinterpret_cast<double2 *>(M), ldm, stream),
+                                         reinterpret_cast<double2 *>(M), ldm, nullptr, 0, stream),
                 "near-field kernel");
     }
+    return BEM_OK;
+}
+
+bem_status bem_nearfield_sum(bem_mesh_t h, const double *z, int64_t N, const double *c, double *S, int64_t lds,
+                             hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_kappas(h, z, N, "z");
+    if (st != BEM_OK) return st;
+    if (N > (int64_t)1 << 20) return fail(BEM_EINVAL, "too many nodes");
+    if (!c || !finite_c(c, N)) return fail(BEM_EINVAL, "c is NULL or has a non-finite value");
+    if (!S || lds < h->dm.n) return fail(BEM_EINVAL, "need S and lds >= n");
+    if (!is_device_ptr(S)) return fail(BEM_EINVAL, "S is not device memory");
+    if (h->nf_pairs == 0) return BEM_OK;
+    Params prm;
+    const size_t off_z = prm.add(z, 2 * (size_t)N);
+    const size_t off_c = prm.add(c, 2 * (size_t)N);
+    double kmax = 0.0;
+    for (int64_t j = 0; j < N; ++j) kmax = std::max(kmax, std::abs(cplx(z[2 * j], z[2 * j + 1])));
+    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
+    const double *base = h->params.as<double>();
+    HIP_TRY(bemrat::launch_nearfield(h->dm, h->nf_gl.as<double>(), h->nf_rowptr.as<int64_t>(), h->nf_col.as<int32_t>(),
+                                     reinterpret_cast<const double2 *>(base + off_z), (int)N,
+                                     reinterpret_cast<const double2 *>(base + off_c), 1, 0, 1, kmax, nullptr, 0, 0,
+                                     nullptr, 0, reinterpret_cast<double2 *>(S), lds, stream),
+            "near-field kernel");
     return BEM_OK;
 }
 

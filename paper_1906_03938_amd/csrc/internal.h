@@ -136,11 +136,13 @@ hipError_t launch_project_finish(const double2 *partial, int nchunks, int L, int
 // Near-field correction (nearfield.hip): M[p0 + p][a, :] += sum_j W[j][p0 + p] sum_{b in
 // row a of (rowptr, col)} (integral - 7-point value of T_ab(kappa_j)) V[b, :], p < P <= kNfFold;
 // one workgroup per row of the mesh.  gl16: 16-point Gauss-Legendre nodes then weights,
-// followed by the 10-point rule's nodes then weights.
+// followed by the 10-point rule's nodes then weights.  With S non-null (and P = 1) the folded
+// corrections are added to the dense matrix S (row stride lds) instead: S[a][b] += sum_j
+// W[j][p0] dT_ab(kappa_j); V and M are then unused.
 constexpr int kNfFold = 8;
 hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const int64_t *rowptr,
                             const int32_t *col, const double2 *kappa, int N, const double2 *W, int Pstride,
                             int p0, int P, double kmax, const double2 *V, int64_t ldv, int64_t m,
-                            double2 *M, int64_t ldm, hipStream_t stream);
+                            double2 *M, int64_t ldm, double2 *S, int64_t lds, hipStream_t stream);
 
 }  // namespace bemrat

@@ -52,6 +52,8 @@ struct NfArgs {
     int64_t ldv, m;
     double2 *M;            // block p at M + p * mstride, row stride ldm
     int64_t ldm, mstride;
+    double2 *S;            // dense mode (P = 1): S[a][b] += folded correction, row stride lds
+    int64_t lds;
 };
 
 __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
@@ -212,6 +214,16 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
             fold[k][p] = s;
         }
         __syncthreads();
+        if (g.S) {
+            // dense mode: add the folded corrections to the matrix (one thread per pair)
+            if (t < cnt) {
+                double2 *out = g.S + a * g.lds + cols[t];
+                const double2 o = *out;
+                *out = make_double2(o.x + fold[t][0].x, o.y + fold[t][0].y);
+            }
+            __syncthreads();
+            continue;
+        }
         // apply to the probe block
         for (int64_t item = t; item < (int64_t)g.P * g.m; item += kNfThreads) {
             const int p = (int)(item / g.m);
@@ -236,7 +248,7 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
 hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const int64_t *rowptr,
                             const int32_t *col, const double2 *kappa, int N, const double2 *W, int Pstride,
                             int p0, int P, double kmax, const double2 *V, int64_t ldv, int64_t m,
-                            double2 *M, int64_t ldm, hipStream_t stream) {
+                            double2 *M, int64_t ldm, double2 *S, int64_t lds, hipStream_t stream) {
     NfArgs g;
     g.colloc = mesh.colloc;
     g.quad = mesh.quad;
@@ -254,9 +266,11 @@ hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const in
     g.V = V;
     g.ldv = ldv;
     g.m = m;
-    g.M = M + (int64_t)p0 * mesh.n * ldm;
+    g.M = M ? M + (int64_t)p0 * mesh.n * ldm : nullptr;
     g.ldm = ldm;
     g.mstride = mesh.n * ldm;
+    g.S = S;
+    g.lds = lds;
     hipLaunchKernelGGL(nearfield_kernel, dim3((unsigned)mesh.n), dim3(kNfThreads), 0, stream, g);
     return hipGetLastError();
 }

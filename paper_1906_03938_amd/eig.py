@@ -88,16 +88,21 @@ def _assemble(mesh, z, c, flags):
     return mesh.assemble_sum(z, c, form=flags)
 
 
-def _residuals(mesh, dev, lam, X, chunk=16):
+def _residuals(mesh, dev, lam, X, chunk=16, nearfield=False):
     """Relative residuals ||T(lam_k) x_k|| / ||x_k||.  Up to `chunk` pairs share one
     bem_assemble_apply call (all their wavenumbers applied to all their vectors, the diagonal
     kept): the direct sweep generates its operators in blocks of 8, so one call per pair would
-    generate 8 operators for each."""
+    generate 8 operators for each.  nearfield: T is the operator with the mesh's near-field
+    correction (bem_nearfield_moments with per-node weights adds dT(lam_k) X)."""
     lam = np.asarray(lam, dtype=np.complex128)
     out = np.empty(lam.size)
     for k0 in range(0, lam.size, chunk):
         k1 = min(lam.size, k0 + chunk)
-        Y = mesh.assemble_apply(lam[k0:k1], dev(X[:, k0:k1])).cpu().numpy()
+        Xd = dev(X[:, k0:k1])
+        Y = mesh.assemble_apply(lam[k0:k1], Xd)
+        if nearfield:
+            mesh.nearfield_moments(lam[k0:k1], np.eye(k1 - k0), Xd, out=Y)
+        Y = Y.cpu().numpy()
         for k in range(k0, k1):
             out[k] = np.linalg.norm(Y[k - k0, :, k - k0]) / np.linalg.norm(X[:, k])
     return out
@@ -107,11 +112,13 @@ class ContourSolver:
     """Cauchy-approximation eigensolver for T(kappa) x = 0 inside |kappa - c| < radius,
     with N trapezoidal nodes, q inverse-iteration steps per outer iteration."""
 
-    def __init__(self, mesh, c, radius, N, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0, lu="auto"):
+    def __init__(self, mesh, c, radius, N, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0, lu="auto",
+                 nearfield=False):
         import torch
 
         self.torch = torch
         self.mesh = mesh
+        self.nearfield = bool(nearfield)  # solve with the mesh's near-field-corrected operator
         self.n = mesh.n
         self.c = complex(c)
         self.radius = float(radius)
@@ -133,14 +140,21 @@ class ContourSolver:
     def moments(self, X, orders):
         """M_p X for moment orders p >= 1: one contour_moments sweep of X."""
         W = np.ascontiguousarray(self.W[:, [p - 1 for p in orders]])
-        return self.mesh.contour_moments(self.z, W, self._dev(X), form=self.sweep_flags).cpu().numpy()
+        Xd = self._dev(X)
+        M = self.mesh.contour_moments(self.z, W, Xd, form=self.sweep_flags)
+        if self.nearfield:
+            self.mesh.nearfield_moments(self.z, W, Xd, out=M)
+        return M.cpu().numpy()
 
     def r_lam(self, x, lam):
         """Columns R_lam_k x_k = sum_i w_i T(z_i) x_k / (lam_k - z_i), k < x.shape[1]: one sweep
         of the block with one weight set per column (column k of weight set k is kept)."""
         lam = np.atleast_1d(np.asarray(lam, dtype=np.complex128))
         W = np.ascontiguousarray(self.w[:, None] / (lam[None, :] - self.z[:, None]))
-        R = self.mesh.contour_moments(self.z, W, self._dev(x), form=self.sweep_flags)
+        xd = self._dev(x)
+        R = self.mesh.contour_moments(self.z, W, xd, form=self.sweep_flags)
+        if self.nearfield:
+            self.mesh.nearfield_moments(self.z, W, xd, out=R)
         k = self.torch.arange(lam.size, device=R.device)
         return R[k, :, k].T.cpu().numpy()
 
@@ -148,6 +162,8 @@ class ContourSolver:
         """LU of S = M_1 = sum_i B_i/(z_i - c), assembled on the device."""
         if self._S_lu is None:
             S = _assemble(self.mesh, self.z, self.W[:, 0], self.sweep_flags)
+            if self.nearfield:
+                self.mesh.nearfield_sum(self.z, self.W[:, 0], S)
             self._S_lu = DenseFactor(S, self.lu_mode)
             del S
         return self._S_lu
@@ -231,7 +247,13 @@ class ContourSolver:
         return self.c + 1.0 / theta, Y
 
     def rayleigh_ritz(self, U):
-        P = self.mesh.rr_project(self.z, self._dev(U), form=self.rr_flags).cpu().numpy()
+        Ud = self._dev(U)
+        P = self.mesh.rr_project(self.z, Ud, form=self.rr_flags)
+        if self.nearfield:
+            # U^H dT(z_j) U from the per-node corrections dT(z_j) U
+            dY = self.mesh.nearfield_moments(self.z, np.eye(self.N), Ud)
+            P = P + self.torch.matmul(Ud.conj().T.contiguous(), dY)
+        P = P.cpu().numpy()
         Bhat = [self.w[j] * P[j] for j in range(self.N)]
         m = U.shape[1]
         if (self.N + 1) * m > DENSE_QZ_MAX:
@@ -243,7 +265,7 @@ class ContourSolver:
         return lam, Y
 
     def residuals(self, lam, X):
-        return _residuals(self.mesh, self._dev, lam, X)
+        return _residuals(self.mesh, self._dev, lam, X, nearfield=self.nearfield)
 
     # -- Algorithm 3 with restarts -------------------------------------------------------
     def solve(self, U0):
@@ -272,14 +294,17 @@ class ContourSolver:
         return lam_in[order], X[:, order], res[order], self.max_outer
 
 
-def eigs_in_contour(mesh, c, radius, N, U0, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0, lu="auto"):
+def eigs_in_contour(mesh, c, radius, N, U0, q=10, tol=1e-12, max_outer=30, sweep_prec=0, rr_prec=0, lu="auto",
+                    nearfield=False):
     """(eigenvalues, eigenvectors, relative residuals, outer iterations) of T(kappa) x = 0
     inside |kappa - c| < radius; U0 is the n x nu starting block.  sweep_prec / rr_prec are
     the library's precision flags (PREC_*) for the subspace sweeps and for the Rayleigh-Ritz
     projections; residuals are always evaluated in FP64.  lu: where the Schur complement is
-    factorised ("host", "device" or "auto", see DenseFactor)."""
+    factorised ("host", "device" or "auto", see DenseFactor).  nearfield: solve with the
+    operator corrected on the mesh's near-pair list (Mesh.set_nearfield) in every sweep, in S,
+    the projections and the residuals."""
     return ContourSolver(mesh, c, radius, N, q=q, tol=tol, max_outer=max_outer, sweep_prec=sweep_prec,
-                         rr_prec=rr_prec, lu=lu).solve(U0)
+                         rr_prec=rr_prec, lu=lu, nearfield=nearfield).solve(U0)
 
 
 class IntervalSolver:

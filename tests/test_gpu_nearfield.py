@@ -202,3 +202,41 @@ def test_single_node_weight_and_column(bem, torch, oracle_lib):
         mesh.set_nearfield(2.0)
         Cg = mesh.nearfield_moments(z, W, _dev(torch, V)).cpu().numpy()
     assert np.linalg.norm(Cg[0] - corr[0]) <= 1e-11 * np.linalg.norm(corr[0])
+
+
+def test_nearfield_sum_matches_oracle(bem, torch, oracle_lib):
+    """bem_assemble_sum + bem_nearfield_sum = sum_j c_j T_nf(z_j), the dense matrix of the
+    corrected operator, against the oracle's dense corrected operators."""
+    from oracle import method as M
+
+    xyz, tri = synth.perturbed_icosphere(2, 0.05, 5)
+    z, w, W = bem.contour_nodes(4.0, 1.5, 12, P=1)
+    c = W[:, 0]
+    op = M.Operator(xyz, tri, nearfield_eta=2.0)
+    So = sum(c[j] * op.dense(z[j]) for j in range(len(z)))
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        S = mesh.assemble_sum(z, c)
+        mesh.nearfield_sum(z, c, S)
+        S = S.cpu().numpy()
+    assert np.linalg.norm(S - So) <= TOL * np.linalg.norm(So)
+
+
+def test_eigs_of_corrected_operator_match_golden(bem, torch, oracle_lib):
+    """The Cauchy route on the corrected operator (every sweep, S, the projections and the
+    residuals corrected) against the oracle's Algorithm 3 on the dense corrected operator:
+    sphere-1280, |z - 4| < 1.5, N = 32, 16 probes (seed 1), eigenvalues to 1e-10."""
+    import os
+
+    from paper_1906_03938_amd.eig import eigs_in_contour
+
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "sphere1280_nearfield_eigs.txt"))
+    lam_o = gold[:, 0] + 1j * gold[:, 1]
+    xyz, tri = synth.icosphere(3)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        lam, X, res, outer = eigs_in_contour(mesh, 4.0, 1.5, 32, synth.probe_block(len(tri), 16, seed=1),
+                                             nearfield=True)
+    assert lam.size == lam_o.size and res.max() <= 1e-12
+    for lo in lam_o:
+        assert np.min(np.abs(lam - lo)) <= 1e-10 * abs(lo)

@@ -231,3 +231,19 @@ def test_correction_vanishes_beyond_a_few_diameters(oracle_lib):
                 outer_worst = max(outer_worst, rel)
     assert 0.0 < outer_worst <= 1e-5, outer_worst
     assert inner_worst >= 100.0 * outer_worst, (inner_worst, outer_worst)
+
+
+def test_corrected_operator_differs_only_on_near_pairs(oracle_lib):
+    from oracle import _clib
+    from oracle import method as M
+    import synth
+
+    xyz, tri = synth.icosphere(1)
+    k = 3.5 + 0.2j
+    T = M.Operator(xyz, tri).dense(k)
+    Tn = M.Operator(xyz, tri, nearfield_eta=2.0).dense(k)
+    rp, col, dT = _clib.nearfield_correction(xyz, tri, 2.0, [k])
+    D = np.zeros_like(T)
+    D[np.repeat(np.arange(len(tri)), np.diff(rp)), col] = dT[0]
+    assert np.array_equal(Tn - T == 0, D == 0)
+    assert np.abs((Tn - T) - D).max() <= 1e-17 * np.abs(T).max() * 10
