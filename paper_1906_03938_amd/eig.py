@@ -108,6 +108,15 @@ def _residuals(mesh, dev, lam, X, chunk=16, nearfield=False):
     return out
 
 
+def _project_correction(mesh, z, Ud):
+    """U^H dT(z_j) U for every node (N x m x m, device), dT the mesh's near-field correction:
+    from the per-node corrections dT(z_j) U (bem_nearfield_moments with identity weights)."""
+    import torch
+
+    dY = mesh.nearfield_moments(z, np.eye(len(z)), Ud)
+    return torch.matmul(Ud.conj().T.contiguous(), dY)
+
+
 class ContourSolver:
     """Cauchy-approximation eigensolver for T(kappa) x = 0 inside |kappa - c| < radius,
     with N trapezoidal nodes, q inverse-iteration steps per outer iteration."""
@@ -250,9 +259,7 @@ class ContourSolver:
         Ud = self._dev(U)
         P = self.mesh.rr_project(self.z, Ud, form=self.rr_flags)
         if self.nearfield:
-            # U^H dT(z_j) U from the per-node corrections dT(z_j) U
-            dY = self.mesh.nearfield_moments(self.z, np.eye(self.N), Ud)
-            P = P + self.torch.matmul(Ud.conj().T.contiguous(), dY)
+            P = P + _project_correction(self.mesh, self.z, Ud)
         P = P.cpu().numpy()
         Bhat = [self.w[j] * P[j] for j in range(self.N)]
         m = U.shape[1]
@@ -326,13 +333,14 @@ class IntervalSolver:
     g[l] = T_l(xi_k); it is swept once by cheb_moments (all B_l x) and combined on the host."""
 
     def __init__(self, mesh, a, b, N, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2, sweep_prec=0,
-                 rr_prec=0, lu="auto"):
+                 rr_prec=0, lu="auto", nearfield=False):
         import torch
 
         if N < 3:
             raise ValueError("the Chebyshev pencil needs N >= 3 nodes")
         self.torch = torch
         self.mesh = mesh
+        self.nearfield = bool(nearfield)  # solve with the mesh's near-field-corrected operator
         self.n = mesh.n
         self.a, self.b, self.N = float(a), float(b), int(N)
         self.alpha, self.beta = 0.5 * (self.a + self.b), 0.5 * (self.b - self.a)
@@ -381,7 +389,11 @@ class IntervalSolver:
 
     def sweep(self, X, ages):
         W = np.ascontiguousarray(self.W_age[:, list(ages)])
-        return self.mesh.contour_moments(self.z, W, self._dev(X), form=self.sweep_flags).cpu().numpy()
+        Xd = self._dev(X)
+        M = self.mesh.contour_moments(self.z, W, Xd, form=self.sweep_flags)
+        if self.nearfield:
+            self.mesh.nearfield_moments(self.z, W, Xd, out=M)
+        return M.cpu().numpy()
 
     def g_lu(self):
         """LU of G = sum_l B_l T_l(s) = sum_j T(kappa_j) sum_l coef[l, j] T_l(s), assembled on
@@ -389,6 +401,8 @@ class IntervalSolver:
         if self._G_lu is None:
             wg = self.coef.T @ self.t_s
             G = _assemble(self.mesh, self.z, wg, self.sweep_flags)
+            if self.nearfield:
+                self.mesh.nearfield_sum(self.z, wg, G)
             self._G_lu = DenseFactor(G, self.lu_mode)
             del G
         return self._G_lu
@@ -404,7 +418,11 @@ class IntervalSolver:
         if xi is None:
             swept.append(self.sweep(u0, range(q)))
         else:
-            Cx = self.mesh.cheb_moments(self.a, self.b, self.N, self.N, self._dev(u0), form=self.sweep_flags).cpu().numpy()
+            u0d = self._dev(u0)
+            Cx = self.mesh.cheb_moments(self.a, self.b, self.N, self.N, u0d, form=self.sweep_flags)
+            if self.nearfield:  # C_l += sum_k coef[l, k] dT(kappa_k) u0
+                self.mesh.nearfield_moments(self.z, np.ascontiguousarray(self.coef.T), u0d, out=Cx)
+            Cx = Cx.cpu().numpy()
             g = self._tvals(np.asarray(xi, dtype=np.complex128))[:self.d]   # d x m
             restart = []
             for _ in range(q):
@@ -448,7 +466,11 @@ class IntervalSolver:
 
     def rayleigh_ritz(self, U):
         """kappa and y of the reduced pencil with B_hat_l = sum_j coef[l, j] U^H T(kappa_j) U."""
-        P = self.mesh.rr_project(self.z, self._dev(U), form=self.rr_flags).cpu().numpy()
+        Ud = self._dev(U)
+        P = self.mesh.rr_project(self.z, Ud, form=self.rr_flags)
+        if self.nearfield:
+            P = P + _project_correction(self.mesh, self.z, Ud)
+        P = P.cpu().numpy()
         Bhat = np.einsum("lj,jab->lab", self.coef, P)
         A, M = self.reduced_pencil(Bhat)
         with np.errstate(invalid="ignore", divide="ignore"):
@@ -457,7 +479,7 @@ class IntervalSolver:
         return kap, V[:U.shape[1], :]
 
     def residuals(self, lam, X):
-        return _residuals(self.mesh, self._dev, lam, X)
+        return _residuals(self.mesh, self._dev, lam, X, nearfield=self.nearfield)
 
     def solve(self, U0):
         u0 = np.asarray(U0, dtype=np.complex128)
@@ -489,10 +511,11 @@ class IntervalSolver:
 
 
 def eigs_in_interval(mesh, a, b, N, U0, q=10, tol=1e-12, max_outer=30, shift=0.0, imag_tol=1e-2, sweep_prec=0,
-                     rr_prec=0, lu="auto"):
+                     rr_prec=0, lu="auto", nearfield=False):
     """(eigenvalues, eigenvectors, relative residuals, outer iterations) of T(kappa) x = 0
     with kappa in [a, b] (|Im kappa| <= imag_tol (b - a)), from the Chebyshev interpolant
-    with N first-kind nodes; U0 is the n x nu starting block.  sweep_prec / rr_prec / lu as
-    for eigs_in_contour."""
+    with N first-kind nodes; U0 is the n x nu starting block.  sweep_prec / rr_prec / lu /
+    nearfield as for eigs_in_contour."""
     return IntervalSolver(mesh, a, b, N, q=q, tol=tol, max_outer=max_outer, shift=shift,
-                          imag_tol=imag_tol, sweep_prec=sweep_prec, rr_prec=rr_prec, lu=lu).solve(U0)
+                          imag_tol=imag_tol, sweep_prec=sweep_prec, rr_prec=rr_prec, lu=lu,
+                          nearfield=nearfield).solve(U0)

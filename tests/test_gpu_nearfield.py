@@ -240,3 +240,28 @@ def test_eigs_of_corrected_operator_match_golden(bem, torch, oracle_lib):
     assert lam.size == lam_o.size and res.max() <= 1e-12
     for lo in lam_o:
         assert np.min(np.abs(lam - lo)) <= 1e-10 * abs(lo)
+
+
+def test_interval_eigs_of_corrected_operator_match_golden(bem, torch, oracle_lib):
+    """The Chebyshev route on the corrected operator (sweeps, G, restart blocks, projections
+    and residuals corrected) against the oracle's Chebyshev route on the dense corrected
+    operator: sphere-1280, kappa in [2.5, 5], N = 32, 16 probes (seed 1), eigenvalues to
+    1e-10; the two golden files (Cauchy and Chebyshev routes) also agree with each other."""
+    import os
+
+    from paper_1906_03938_amd.eig import eigs_in_interval
+
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    gold = np.loadtxt(os.path.join(here, "sphere1280_nearfield_interval_eigs.txt"))
+    lam_o = gold[:, 0] + 1j * gold[:, 1]
+    gold_c = np.loadtxt(os.path.join(here, "sphere1280_nearfield_eigs.txt"))
+    for lo in gold_c[:, 0] + 1j * gold_c[:, 1]:
+        assert np.min(np.abs(lam_o - lo)) <= 1e-10 * abs(lo)
+    xyz, tri = synth.icosphere(3)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        lam, X, res, outer = eigs_in_interval(mesh, 2.5, 5.0, 32, synth.probe_block(len(tri), 16, seed=1),
+                                              nearfield=True)
+    assert lam.size == lam_o.size and res.max() <= 1e-12
+    for lo in lam_o:
+        assert np.min(np.abs(lam - lo)) <= 1e-10 * abs(lo)
