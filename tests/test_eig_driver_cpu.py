@@ -196,3 +196,51 @@ def test_device_lu_size_guard():
     A = torch.from_numpy(np.array([[2.0, 1.0], [1.0, 3.0]], dtype=np.complex128))
     x = DenseFactor(A, "host").solve(np.array([[3.0], [4.0]]))
     assert np.allclose(x, [[1.0], [1.0]])
+
+
+class SplitMesh(DenseMesh):
+    """Stand-in whose sweeps use the plain operator and whose near-field calls add the
+    correction (corrected minus plain dense operator), as the library splits them."""
+
+    def __init__(self, op, op_nf):
+        super().__init__(op)
+        self.nf = op_nf
+
+    def _d(self, k):
+        return self.nf.dense(k) - self.op.dense(k)
+
+    def nearfield_moments(self, z, W, V, out=None):
+        W = np.asarray(W, dtype=np.complex128).reshape(len(z), -1)
+        Vn = V.numpy()
+        add = sum(W[j][:, None, None] * (self._d(z[j]) @ Vn)[None] for j in range(len(z)))
+        add = torch.from_numpy(np.ascontiguousarray(add))
+        if out is None:
+            return add
+        out += add
+        return out
+
+    def nearfield_sum(self, z, c, S):
+        S += torch.from_numpy(sum(c[j] * self._d(z[j]) for j in range(len(z))))
+        return S
+
+
+@pytest.mark.parametrize("route", ["contour", "interval"])
+def test_nearfield_option_corrects_every_sweep(route):
+    """With nearfield=True both drivers reach the oracle's eigenvalues of the corrected
+    operator (which differ from the plain operator's by far more than the tolerance, so a
+    sweep left uncorrected would show)."""
+    xyz, tri = synth.icosphere(1)
+    op, op_nf = M.Operator(xyz, tri), M.Operator(xyz, tri, nearfield_eta=2.0)
+    mesh = SplitMesh(op, op_nf)
+    V = synth.probe_block(op.n, 8, seed=1)
+    if route == "contour":
+        lam, X, res, _ = CpuSolver(mesh, 4.0, 1.5, 32, q=10, tol=1e-12, nearfield=True).solve(V)
+        lo, _, _, _, _ = M.subspace_iteration(op_nf, 4.0, 1.5, 32, V, q=10, tol=1e-12)
+        lp, _, _, _, _ = M.subspace_iteration(op, 4.0, 1.5, 32, V, q=10, tol=1e-12)
+    else:
+        lam, X, res, _ = CpuIntervalSolver(mesh, 2.5, 5.0, 16, q=10, tol=1e-12, nearfield=True).solve(V)
+        lo, _, _, _, _ = M.cheb_subspace_iteration(op_nf, 2.5, 5.0, 16, V, q=10, tol=1e-12, imag_tol=1e-2)
+        lp, _, _, _, _ = M.cheb_subspace_iteration(op, 2.5, 5.0, 16, V, q=10, tol=1e-12, imag_tol=1e-2)
+    assert res.max() <= 1e-12 and lam.size == lo.size
+    assert np.abs(np.sort_complex(lam) - np.sort_complex(lo)).max() <= 1e-10 * np.abs(lo).max()
+    assert np.abs(np.sort_complex(lp) - np.sort_complex(lo)).max() >= 1e-6 * np.abs(lo).max()
