@@ -16,13 +16,16 @@
 // by phi = atan(sinh u) (t = |p_e| sinh u along the edge, rho = |p_e| cosh u,
 // dphi = du / cosh u), the sinh transformation of Johnston and Elliott (2005) that keeps the
 // integrand smooth when x' is close to the edge line; the u-interval is split into panels
-// of length <= 2 (the integrand's nearest singularities lie at Im u = +-pi/2) and no wider
-// than 2 / (kappa_max rho_max) in phase, each integrated with 16-point Gauss-Legendre (10
-// points where one panel of half that size covers the interval).
+// of length <= 2 (the integrand's nearest singularities lie at Im u = +-pi/2), and into at
+// least kappa_max rho_max / 2 of them (rho_max the distance to the farther end point, so that
+// a panel spans about two radians of phase), each integrated with 16-point Gauss-Legendre;
+// an interval that needs half of both (length <= 1, kappa_max rho_max <= 1) takes a single
+// 10-point panel.
 //
 // One workgroup per target row; its pairs are taken 64 at a time, with 256 / (pairs in the
 // chunk) node groups per pair, and every partial sum is reduced in a fixed order, so results
-// are deterministic.
+// are deterministic.  In the dense mode (S non-null, one weight set) the folded corrections
+// are added to the matrix entries S[a][b] instead of being applied to a probe block.
 #include "devmath.h"
 #include "internal.h"
 
