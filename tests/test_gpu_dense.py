@@ -157,3 +157,28 @@ def test_large_n_eigenvalues_device_lu():
     lam = np.sort_complex(lam)
     assert abs(lam[0] - tab[0, 0]) < 5e-3 and np.all(np.abs(lam[1:] - tab[1, 0]) < 5e-3)
     assert np.ptp(lam[1:].real) < 1e-8 * abs(lam[1])
+
+
+def test_large_n_eigenvalues_device_lu_nearfield():
+    """The same at n = 20480 with the near-field-corrected operator (eta = 2, 33 pairs per
+    row): S corrected on the device (bem_nearfield_sum, 6.7 GB matrix), device LU, corrected
+    sweeps, projections and residuals.  Properties: four eigenvalues with residuals below
+    1e-12, the triple degenerate to 1e-7 (the pair list follows the mesh's symmetry up to
+    rounding at the boundary of the near test), each within 5e-3 of the continuum value."""
+    import torch
+
+    import paper_1906_03938_amd as bem
+    from paper_1906_03938_amd.eig import ContourSolver
+
+    assert torch.cuda.is_available()
+    xyz, tri = synth.icosphere(5)
+    tab = np.loadtxt(os.path.join(GOLDEN, "sphere_dirichlet_eigs.txt"))
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        solver = ContourSolver(mesh, 4.0, 1.5, 32, q=10, tol=1e-12, lu="device", nearfield=True)
+        lam, X, res, outer = solver.solve(synth.probe_block(tri.shape[0], 16, seed=1))
+    print(f"n = {tri.shape[0]} near field: outer {outer}; eigenvalues {lam}, residuals {res}", flush=True)
+    assert lam.size == 4 and res.max() <= 1e-12
+    lam = np.sort_complex(lam)
+    assert abs(lam[0] - tab[0, 0]) < 5e-3 and np.all(np.abs(lam[1:] - tab[1, 0]) < 5e-3)
+    assert np.ptp(lam[1:].real) < 1e-7 * abs(lam[1])
