@@ -5,12 +5,16 @@ Workload "sphere-81920" (the headline configuration): unit icosphere at subdivis
 exp(i kappa r)/(4 pi r), 7-point rule plus exact self terms), circular contour
 |z - 5| = 2 with N = 64 trapezoidal nodes, probe block of m = 64 seeded complex Gaussian
 columns (seed 2).  One step = the nodes and moment weights (host) plus one rr_project
-call with fused moments: the per-node projections U^H T(z_j) U for all 64 nodes and the
-first P = 2 contour moments sum_j w_j (z_j - c)^-p T(z_j) U, with the self terms, the
-sweep, the combination and the projection all on the device.
+call with fused moments in the per-node (direct) form: every operator T(z_j) regenerated
+and contracted with the probe block, i.e. all N n^2 m complex multiply-adds, giving the
+projections U^H T(z_j) U for all 64 nodes and the first P = 2 contour moments
+sum_j w_j (z_j - c)^-p T(z_j) U; self terms, sweep, combination and projection all run on
+the device.
 
-Metric: kernel-entry x RHS per second, N n^2 m / t_step (operator entries at every node
-times probe columns, whatever form evaluates them).
+Metric: kernel-entry x RHS per second, N n^2 m / t_step, t_step the device time of one step.
+Beside it ("taylor_form") the same call in the Taylor-expansion form, which generates and
+contracts L < N coefficient operators and recombines them per node: its rate in the same
+units is an effective one (N n^2 m / t), reported with the L n^2 m entries it contracts.
 
 Prints one JSON line (see the repository's design notes for every field).
 """
@@ -39,10 +43,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_hash: str):
-    """HBM bytes per launch measured by rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE), if the
-    committed summary was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "sweep_sphere81920_traffic.json")
+def load_traffic(name: str, kernel_hash: str):
+    """HBM bytes per launch measured by rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE) for the kernel
+    summarised in profiles/<name>, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -53,28 +57,30 @@ def load_traffic(kernel_hash: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(xyz, tri, z, V, rows_per_thread=6):
+def cpu_baseline(xyz, tri, z, V, rows=256):
     """The oracle (plain FP64 C, OpenMP over target rows) on a bounded sample: the full
-    N-node sweep of T(z_j) V for a few target rows, scaled to entry x RHS per second."""
+    N-node sweep of T(z_j) V for a fixed slice of `rows` target rows spread evenly over the
+    mesh (all sources, all probe columns), scaled to entry x RHS per second."""
     import numpy as np
 
     from oracle import _clib
 
     threads = _clib.num_threads()
     n = tri.shape[0]
-    rows = np.linspace(0, n - 1, max(1, rows_per_thread * threads)).astype(np.int64)
+    sel = np.linspace(0, n - 1, rows).astype(np.int64)
     t0 = time.perf_counter()
     for zj in z:
-        _clib.apply_rows(xyz, tri, zj, V, rows)
+        _clib.apply_rows(xyz, tri, zj, V, sel)
     dt = time.perf_counter() - t0
-    units = rows.size * n * len(z) * V.shape[1]
+    units = sel.size * n * len(z) * V.shape[1]
     return {
         "value": units / dt,
         "unit": "kernel-entry*RHS/s",
-        "cores": int(min(threads, rows.size)),
+        "cores": int(min(threads, sel.size)),
         "kind": "oracle",
-        "sample": f"{rows.size} of {n} target rows x all {n} source triangles x {len(z)} nodes x "
-                  f"{V.shape[1]} probes ({dt:.1f} s), scaled by entry*RHS count",
+        "sample": f"{sel.size} of {n} target rows (evenly spaced) x all {n} source triangles x {len(z)} nodes x "
+                  f"{V.shape[1]} probes ({dt:.1f} s), scaled by entry*RHS count; the full sweep would be "
+                  f"{n / sel.size:.0f}x this sample",
     }
 
 
@@ -392,7 +398,6 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", choices=["auto", "direct", "expand"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eigen-check", action="store_true")
     ap.add_argument("--no-precision-form", action="store_true")
@@ -434,46 +439,78 @@ def main():
     n = tri.shape[0]
     Vh = synth.probe_block(n, w["m"], seed=w["seed"])
     U = torch.from_numpy(Vh).to("cuda")
-    form = {"auto": bem.FORM_AUTO, "direct": bem.FORM_DIRECT, "expand": bem.FORM_EXPAND}[args.form]
     mesh = bem.Mesh(xyz, tri)
     mesh.set_timing(True)
     Pout = torch.empty((w["N"], w["m"], w["m"]), dtype=torch.complex128, device="cuda")
     Mout = torch.empty((w["P"], n, w["m"]), dtype=torch.complex128, device="cuda")
+    units = w["N"] * n * n * w["m"]
+    khash = kernel_source_hash()
 
-    def step():
+    def step(form):
         z, _, W = bem.contour_nodes(w["c"], w["radius"], w["N"], P=w["P"])
         mesh.rr_project(z, U, W=W, out=Pout, moments_out=Mout, form=form)
         return z
 
+    def run(form, steps, warmup):
+        """warm-up steps, then `steps` timed ones: wall clock over all of them (bracketed by
+        device synchronisations), HIP events around each step on the call's stream (torch's
+        current stream) and the library's events around each sweep kernel."""
+        for _ in range(warmup):
+            step(form)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        kernel_ms = []
+        t0 = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record()
+            z = step(form)
+            e1.record()
+            kernel_ms.append(mesh.last_kernel_ms())  # waits for this step's sweep kernel only
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        bem.stream_status()
+        step_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+        used, L = mesh.last_form()
+        return z, elapsed, step_ms, kernel_ms, used, L
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    kernel_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        z = step()
-        kernel_ms.append(mesh.last_kernel_ms())  # waits for this step's sweep kernel only
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    used_form, L = mesh.last_form()
-    bem.stream_status()
+    def roofline(L, kernel_ms, traffic_file):
+        flops = 8.0 * L * n * n * w["m"]  # 8 real flops per complex multiply-add of each contracted operator
+        kms = float(np.mean(kernel_ms))
+        achieved = flops / (kms * 1e-3) / 1e12
+        return {
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+            "traffic": load_traffic(traffic_file, khash),
+            "kernel": "sweep_kernel",
+            "kernel_ms": kms,
+            "kernel_ms_median": float(np.median(kernel_ms)),
+            "flops_per_launch": flops,
+            # the kernel forms each complex product with three real multiplications (Gauss):
+            # the matrix cores execute 6 of the 8 flops counted above
+            "mfma_issued_frac": 0.75 * achieved / PEAK_FP64_MFMA_TFLOPS,
+            "kernel_hash": khash,
+        }
 
+    def progress(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+    # the headline: the per-node sweep
+    z, elapsed, step_ms, kernel_ms, used_form, L = run(bem.FORM_DIRECT, args.steps, args.warmup)
+    progress(f"per-node sweep {1e3 * elapsed / args.steps:.0f} ms per step")
+    assert used_form == bem.FORM_DIRECT and L == w["N"]
     ms_per_step = 1e3 * elapsed / args.steps
-    units = w["N"] * n * n * w["m"]
-    value = units / (elapsed / args.steps)
-    kms = float(np.mean(kernel_ms))
-    flops = 8.0 * L * n * n * w["m"]  # 8 real flops per complex MAC of the generated operators
-    achieved = flops / (kms * 1e-3) / 1e12
-    khash = kernel_source_hash()
     out = {
-        "metric": "kernel-entry*RHS/s of sum_j T(z_j)V sweep (rr_project + fused moments)",
-        "value": value,
+        "metric": "kernel-entry*RHS/s of sum_j T(z_j)V sweep (rr_project + fused moments, per-node form)",
+        "value": units / (elapsed / args.steps),
         "unit": "kernel-entry*RHS/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "step_ms_median_events": float(np.median(step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -484,48 +521,65 @@ def main():
             "mesh": f"unit icosphere level {w['level']}, n={n} triangles",
             "contour": f"circle c={w['c']} r={w['radius']}, N={w['N']} trapezoidal nodes",
             "m": w["m"], "moments": w["P"], "seed": w["seed"],
-            "form": "expand" if used_form == bem.FORM_EXPAND else "direct",
+            "form": "direct",
             "operators_generated": L,
         },
-        "roofline": {
-            "bound": "mfma",
-            "achieved": achieved,
-            "peak": PEAK_FP64_MFMA_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
-            "traffic": load_traffic(khash),
-            "kernel": "sweep_kernel",
-            "kernel_ms": kms,
-            "kernel_hash": khash,
-        },
+        "roofline": roofline(L, kernel_ms, "sweep_direct_sphere81920_traffic.json"),
+    }
+    # the Taylor-expansion form of the same call (what FORM_AUTO takes here)
+    reps = max(3, min(args.steps, 5))
+    _, el_t, step_t, kms_t, used_t, L_t = run(bem.FORM_AUTO, reps, 1)
+    t_step = el_t / reps
+    progress(f"Taylor form {1e3 * t_step:.0f} ms per step")
+    out["taylor_form"] = {
+        "call": "rr_project with 2 fused moments, FORM_AUTO (Taylor expansion about the contour centre)",
+        "form": "expand" if used_t == bem.FORM_EXPAND else "direct",
+        "operators_generated": L_t,
+        "steps": reps,
+        "ms_per_step": 1e3 * t_step,
+        "step_ms_median_events": float(np.median(step_t)),
+        "effective_value": units / t_step,
+        "effective_unit": "kernel-entry*RHS/s counted as N n^2 m (N = 64 nodes) although L n^2 m are contracted",
+        "contracted_value": L_t * n * n * w["m"] / t_step,
+        "contracted_unit": "contracted operator entry*RHS/s (L n^2 m)",
+        "speedup_vs_per_node_step": ms_per_step / (1e3 * t_step),
+        "roofline": roofline(L_t, kms_t, "sweep_sphere81920_traffic.json"),
     }
     # the folded form: contour_moments with P = 2 weight sets generates every operator of each
     # entry but contracts only the two folds (reported beside, not as, the per-node sweep)
+    form = bem.FORM_AUTO
     z2, _, W2 = bem.contour_nodes(w["c"], w["radius"], w["N"], P=w["P"])
     mesh.contour_moments(z2, W2, U, out=Mout, form=form)
     fold_ms = []
     for _ in range(2):
         mesh.contour_moments(z2, W2, U, out=Mout, form=form)
         fold_ms.append(mesh.last_kernel_ms())
+    kms = out["roofline"]["kernel_ms"]
     out["folded_moments"] = {
         "call": f"contour_moments, P = {w['P']} weight sets on the headline mesh, nodes and probes",
         "kernel_ms": float(np.mean(fold_ms)), "value": units / (float(np.mean(fold_ms)) * 1e-3),
-        "unit": "kernel-entry*RHS/s", "contractions": w["P"], "operators_generated": L,
+        "unit": "kernel-entry*RHS/s (effective: N n^2 m)", "contractions": w["P"],
+        "operators_generated": mesh.last_form()[1],
         "speedup_vs_per_node_sweep_kernel": kms / float(np.mean(fold_ms)),
     }
     if not args.no_near_field:
         out["near_field"] = near_field(mesh, U, z2, W2, kms)
+        progress("near field done")
     mesh.close()
     if not args.no_eigen_check:
         out["eigen_check"] = eigen_check()
+        progress("eigen check done")
     if not args.no_precision_form:
         out["precision_form"] = precision_form()
+        progress("precision form done")
     if not args.no_batched_form:
         out["batched_form"] = batched_form()
+        progress("batched form done")
     if args.large_eigen:
         out["large_eigen"] = large_eigen(args.large_eigen)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xyz, tri, z, Vh)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -132,6 +132,29 @@ def _block(t, name):
     return ctypes.c_void_p(t.data_ptr()), t.shape[1], t.stride(0)
 
 
+def _out_blocks(t, blocks, n, m, name):
+    """Checks a caller-supplied output of `blocks` blocks of n x m complex128 on the device,
+    laid out as the C ABI expects (block p at 2*p*n*ld doubles, row stride ld >= m)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if t.dim() != 3 or t.shape[0] < blocks or t.shape[1] != n or t.shape[2] != m:
+        raise ValueError(f"{name} must have shape ({blocks}, {n}, {m}), got {tuple(t.shape)}")
+    if t.stride(2) != 1 or t.stride(0) != n * t.stride(1):
+        raise ValueError(f"{name} must have unit column stride and blocks of n rows back to back")
+    return t
+
+
+def _dense_out(t, n, name):
+    """Checks an n x n (row stride >= n) complex128 device matrix."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if t.dim() != 2 or t.shape[0] != n or t.shape[1] < n or t.stride(1) != 1 or t.stride(0) < n:
+        raise ValueError(f"{name} must be an n x n (row stride >= n) complex128 device matrix")
+    return t
+
+
 # ------------------------------------------------------------------- host routines
 
 
@@ -214,7 +237,7 @@ class Mesh:
     def assemble_apply(self, kappas, V, out=None, form=FORM_DIRECT):
         k = _host_complex(kappas)
         pv, m, ldv = _block(V, "V")
-        Y = self._out(k.size, m) if out is None else out
+        Y = self._out(k.size, m) if out is None else _out_blocks(out, k.size, self.n, m, "out")
         _check(lib().bem_assemble_apply(self._h, _hp(k), k.size, pv, m, ldv, ctypes.c_void_p(Y.data_ptr()),
                                         Y.stride(1), form, _stream()))
         return Y
@@ -223,7 +246,7 @@ class Mesh:
         z = _host_complex(z)
         W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(z.size, -1))
         pv, m, ldv = _block(V, "V")
-        M = self._out(W.shape[1], m) if out is None else out
+        M = self._out(W.shape[1], m) if out is None else _out_blocks(out, W.shape[1], self.n, m, "out")
         _check(lib().contour_moments(self._h, _hp(z), z.size, _hp(W), W.shape[1], pv, m, ldv,
                                      ctypes.c_void_p(M.data_ptr()), M.stride(1), form, _stream()))
         return M
@@ -247,7 +270,7 @@ class Mesh:
         z = _host_complex(z)
         W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(z.size, -1))
         pv, m, ldv = _block(V, "V")
-        M = self._out(W.shape[1], m) if out is None else out
+        M = self._out(W.shape[1], m) if out is None else _out_blocks(out, W.shape[1], self.n, m, "out")
         if out is None:
             M.zero_()
         _check(lib().bem_nearfield_moments(self._h, _hp(z), z.size, _hp(W), W.shape[1], pv, m, ldv,
@@ -260,15 +283,14 @@ class Mesh:
         c = _host_complex(c)
         if c.size != z.size:
             raise ValueError("need one coefficient per node")
-        if S.dim() != 2 or S.shape[0] != self.n or S.shape[1] < self.n or S.stride(1) != 1:
-            raise ValueError("S must be an n x n (row stride >= n) complex128 device matrix")
+        _dense_out(S, self.n, "S")
         _check(lib().bem_nearfield_sum(self._h, _hp(z), z.size, _hp(c), ctypes.c_void_p(S.data_ptr()), S.stride(0),
                                        _stream()))
         return S
 
     def cheb_moments(self, a, b, N, L, V, out=None, form=FORM_AUTO):
         pv, m, ldv = _block(V, "V")
-        C = self._out(L, m) if out is None else out
+        C = self._out(L, m) if out is None else _out_blocks(out, L, self.n, m, "out")
         _check(lib().cheb_moments(self._h, float(a), float(b), N, L, pv, m, ldv, ctypes.c_void_p(C.data_ptr()),
                                   C.stride(1), form, _stream()))
         return C
@@ -278,10 +300,15 @@ class Mesh:
         z = _host_complex(z)
         pu, m, ldu = _block(U, "U")
         Pout = torch.empty((z.size, m, m), dtype=torch.complex128, device="cuda") if out is None else out
+        if out is not None:
+            _out_blocks(out, z.size, m, m, "out")
+            if not out.is_contiguous():
+                raise ValueError("out must be a contiguous (N, m, m) tensor")
         M = None
         if W is not None:
             W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(z.size, -1))
-            M = self._out(W.shape[1], m) if moments_out is None else moments_out
+            M = self._out(W.shape[1], m) if moments_out is None else \
+                _out_blocks(moments_out, W.shape[1], self.n, m, "moments_out")
             _check(lib().rr_project(self._h, _hp(z), z.size, pu, m, ldu, ctypes.c_void_p(Pout.data_ptr()), _hp(W),
                                     W.shape[1], ctypes.c_void_p(M.data_ptr()), M.stride(1), form, _stream()))
         else:
@@ -296,7 +323,8 @@ class Mesh:
         c = _host_complex(c)
         if c.size != z.size:
             raise ValueError("z and c must have the same length")
-        S = torch.empty((self.n, self.n), dtype=torch.complex128, device="cuda") if out is None else out
+        S = torch.empty((self.n, self.n), dtype=torch.complex128, device="cuda") if out is None else \
+            _dense_out(out, self.n, "out")
         _check(lib().bem_assemble_sum(self._h, _hp(z), z.size, _hp(c), ctypes.c_void_p(S.data_ptr()), S.stride(0),
                                       form, _stream()))
         return S
@@ -369,7 +397,9 @@ class Batch:
             raise ValueError(f"V must be a contiguous ({int(self.rows[-1])}, {self.m}) tensor")
         M = torch.empty(self.P * int(self.rows[-1]) * self.m, dtype=torch.complex128, device="cuda") \
             if out is None else out
-        if M.numel() != self.P * int(self.rows[-1]) * self.m or not M.is_contiguous() or not M.is_cuda:
+        if not isinstance(M, torch.Tensor) or M.dtype != torch.complex128 or not M.is_cuda:
+            raise TypeError("out must be a complex128 CUDA tensor")
+        if M.numel() != self.P * int(self.rows[-1]) * self.m or not M.is_contiguous():
             raise ValueError("out has the wrong size or layout")
         _check(lib().bem_batch_moments(self._h, ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(M.data_ptr()),
                                        _stream()))

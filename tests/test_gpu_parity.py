@@ -3,7 +3,9 @@
 Workload "sphere-1280": unit icosphere level 3 (n = 1280), circle |z - 4| = 1.5 with
 N = 32 trapezoidal nodes, m = 16 seeded complex Gaussian probes (seed 1).  Edge cases:
 ragged n and m, strided probe blocks, single columns, complex and real wavenumbers.
-Tolerance: ||gpu - oracle||_F / ||oracle||_F <= 1e-12 per node or weight set.
+Tolerance: ||gpu - oracle||_F / ||oracle||_F <= 1e-12 per node or weight set, and row by row
+||gpu[r] - oracle[r]|| / ||oracle[r]|| <= 1e-12 for the per-node products and projections (a
+single wrong row cannot hide below the block's norm).
 """
 import numpy as np
 import pytest
@@ -45,6 +47,12 @@ def _rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
 
 
+def _row_rel(a, b):
+    """Largest relative error of a row: max_r ||a[r] - b[r]|| / ||b[r]||."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)))
+
+
 def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
@@ -79,7 +87,9 @@ def test_assemble_apply_matches_oracle(sphere3, torch, bem):
     kappas = [4.0, 5.5 - 1.5j, 2.5 + 1.0j, 3.14159]
     Y = mesh.assemble_apply(kappas, _dev(torch, V)).cpu().numpy()
     for k, Yk in zip(kappas, Y):
-        assert _rel(Yk, op.apply(k, V)) <= TOL, k
+        Yo = op.apply(k, V)
+        assert _rel(Yk, Yo) <= TOL, k
+        assert _row_rel(Yk, Yo) <= TOL, (k, _row_rel(Yk, Yo))
 
 
 @pytest.mark.parametrize("form", ["direct", "expand", "auto"])
@@ -117,10 +127,12 @@ def test_rr_project_matches_oracle(sphere3, torch, bem, form):
     Po = M.rr_project(op, s, U)
     for j in range(32):
         assert _rel(P[j], Po[j]) <= TOL, (form, j, _rel(P[j], Po[j]))
+        assert _row_rel(P[j], Po[j]) <= TOL, (form, j, _row_rel(P[j], Po[j]))
     Mo = M.contour_moments(op, s, W, U)
     Mg = Mg.cpu().numpy()
     for p in range(2):
         assert _rel(Mg[p], Mo[p]) <= TOL
+        assert _row_rel(Mg[p], Mo[p]) <= TOL, (form, p, _row_rel(Mg[p], Mo[p]))
 
 
 @pytest.mark.parametrize("form", ["direct", "expand", "cheb"])
@@ -224,6 +236,15 @@ def test_error_paths(torch, bem):
                                            ctypes.c_void_p(h.ctypes.data), 4, 4, ctypes.c_void_p(Y.data_ptr()), 4, 0,
                                            None)
         assert st == _lib.BEM_EINVAL
+        # caller-supplied outputs are checked before anything is launched
+        with pytest.raises(TypeError):
+            mesh.assemble_apply([4.0], V, out=torch.zeros((1, 80, 4), dtype=torch.complex64, device="cuda"))
+        with pytest.raises(ValueError):
+            mesh.contour_moments(z, W, V, out=torch.zeros((1, 79, 4), dtype=torch.complex128, device="cuda"))
+        with pytest.raises(ValueError):
+            mesh.rr_project(z, V, out=torch.zeros((7, 4, 4), dtype=torch.complex128, device="cuda"))
+        with pytest.raises(TypeError):
+            mesh.assemble_sum(z, W[:, 0], out=torch.zeros((80, 80), dtype=torch.complex128))
     bad = np.array([[0, 1, 2], [0, 0, 1]], dtype=np.int32)
     with pytest.raises(bem.BemError) as e:
         bem.Mesh(xyz, bad)

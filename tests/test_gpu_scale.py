@@ -4,7 +4,12 @@ bench.py times (rr_project with 2 fused moments, automatic form).  The oracle ev
 sampled target rows one by one; quantities that need every row (the projections) are
 checked through the identity P_j = U^H Y_j against per-node products Y_j that are
 themselves checked on the sampled rows.  Also the Chebyshev blocks on [2, 8] with N = 48.
-Tolerance: 1e-12 normwise per node / weight set over the sampled rows."""
+Tolerance: 1e-12 normwise per node / weight set over the sampled rows, and row by row.
+
+The projections are also checked against the oracle directly: with U supported on a row set S
+(zero elsewhere), U^H T(z_j) U = U_S^H T(z_j)[S, S] U_S, and T(z_j)[S, S] is the oracle's dense
+operator of the sub-mesh made of the triangles in S (an entry T_ab depends on triangles a and b
+only), while the kernel still sweeps every one of the 81920 source triangles."""
 import numpy as np
 import pytest
 
@@ -47,20 +52,63 @@ def test_rr_project_and_moments_at_scale(big):
     Mo = M.contour_moments(op, zo, Wo, V, rows=ROWS)
     for p in range(2):
         e = _rel(Mg[p], Mo[p])
-        print(f"moment {p + 1}: rel err {e:.2e}", flush=True)
-        assert e <= TOL
+        er = _row_rel(Mg[p], Mo[p])
+        print(f"moment {p + 1}: rel err {e:.2e}, row {er:.2e}", flush=True)
+        assert e <= TOL and er <= TOL
     # per-node products (direct form) on sampled rows, and P_j = U^H Y_j
     sel = [0, 21, 47]
     Y = mesh.assemble_apply(z[sel], Vd)
     Yh = Y.cpu().numpy()[:, ROWS]
     for t, j in enumerate(sel):
-        e = _rel(Yh[t], op.apply(zo[j], V, rows=ROWS))
-        print(f"node {j}: rel err {e:.2e}", flush=True)
-        assert e <= TOL
+        Yo = op.apply(zo[j], V, rows=ROWS)
+        e, er = _rel(Yh[t], Yo), _row_rel(Yh[t], Yo)
+        print(f"node {j}: rel err {e:.2e}, row {er:.2e}", flush=True)
+        assert e <= TOL and er <= TOL
         Pj = (Vd.conj().T @ Y[t]).cpu().numpy()
         e = _rel(P[j].cpu().numpy(), Pj)
         print(f"projection {j}: rel err vs U^H Y {e:.2e}", flush=True)
         assert e <= TOL
+
+
+def _row_rel(a, b):
+    return float(np.max(np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)))
+
+
+@pytest.mark.parametrize("form", ["direct", "auto"])
+def test_rr_project_sparse_support_at_scale(big, form):
+    """rr_project in the launch configuration bench.py times (n = 81920, N = 64, m = 64, two
+    fused moments; the per-node form of the headline and the automatic Taylor form) on a
+    probe block supported on 96 seeded rows, against the oracle's dense sub-mesh operator."""
+    bem, M, torch, mesh, op, V, Vd = big
+    n, m = op.n, 64
+    rng = np.random.Generator(np.random.PCG64(8))
+    S = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 94, replace=False)]))
+    US, _ = np.linalg.qr(synth.probe_block(S.size, m, seed=2))
+    U = np.zeros((n, m), dtype=np.complex128)
+    U[S] = US
+    z, w, W = bem.contour_nodes(5.0, 2.0, 64, P=2)
+    f = {"direct": bem.FORM_DIRECT, "auto": bem.FORM_AUTO}[form]
+    P, Mg = mesh.rr_project(z, torch.from_numpy(U).to("cuda"), W=W, form=f)
+    print(f"form {mesh.last_form()}", flush=True)
+    P = P.cpu().numpy()
+    Mg = Mg.cpu().numpy()[:, S]
+    zo, wo = M.circle_nodes(5.0, 2.0, 64)
+    Wo = M.moment_weights(zo, wo, 5.0, 2)
+    sub = M.Operator(op.xyz, op.tri[S])
+    Mo = np.zeros((2, S.size, m), dtype=np.complex128)
+    worst, worst_row = 0.0, 0.0
+    for j in range(64):
+        TU = sub.dense(zo[j]) @ US  # rows S of T(z_j) U
+        Pj = US.conj().T @ TU
+        e, er = _rel(P[j], Pj), _row_rel(P[j], Pj)
+        worst, worst_row = max(worst, e), max(worst_row, er)
+        assert e <= TOL and er <= TOL, (j, e, er)
+        Mo += Wo[j][:, None, None] * TU[None]
+    print(f"projections: max rel err {worst:.2e}, max row rel err {worst_row:.2e}", flush=True)
+    for p in range(2):
+        e, er = _rel(Mg[p], Mo[p]), _row_rel(Mg[p], Mo[p])
+        print(f"moment {p + 1} on S: rel err {e:.2e}, row {er:.2e}", flush=True)
+        assert e <= TOL and er <= TOL
 
 
 def test_cheb_moments_at_scale(big):

@@ -41,6 +41,33 @@ def test_circle_nodes_and_weights():
     assert abs(np.sum(w / (zo - s))) < 1e-14
 
 
+def test_ellipse_nodes_and_weights():
+    """The trapezoidal rule on an ellipse s(theta) = c + rx cos(theta) + i ry sin(theta):
+    with rx = ry it is the circle rule (same nodes and weights); the rule applied to
+    T = p(z) (a polynomial) gives p(z) at points inside and 0 outside, up to the trapezoidal
+    rule's geometric convergence on the periodic analytic integrand; and its first moment
+    about an interior point c is -p(c), its second -p'(c) (Cauchy's formula)."""
+    c, R, N = 4.0 - 0.5j, 1.5, 24
+    s, w = M.ellipse_nodes(c, R, R, N)
+    s0, w0 = M.circle_nodes(c, R, N)
+    assert np.abs(s - s0).max() <= 1e-15 * abs(c) and np.abs(w - w0).max() <= 1e-16 * R
+    rng = np.random.Generator(np.random.PCG64(11))
+    coef = rng.standard_normal(5) + 1j * rng.standard_normal(5)
+    p = np.polynomial.Polynomial(coef)
+    dp = p.deriv()
+    c, rx, ry, N = 0.5 + 0.25j, 2.0, 1.0, 160
+    s, w = M.ellipse_nodes(c, rx, ry, N)
+    assert np.allclose(((s - c).real / rx) ** 2 + ((s - c).imag / ry) ** 2, 1.0, rtol=1e-15)
+    for z in (c, c + 0.6 - 0.3j, c - 1.1 + 0.2j):
+        approx = np.sum(w * p(s) / (z - s))
+        assert abs(approx - p(z)) <= 1e-12 * abs(p(z)), z
+    for z in (c + 3.0, c - 2.5j):
+        assert abs(np.sum(w * p(s) / (z - s))) <= 1e-12 * np.abs(p(s)).max(), z
+    W = M.moment_weights(s, w, c, 2)
+    assert abs(np.sum(W[:, 0] * p(s)) + p(c)) <= 1e-12 * abs(p(c))
+    assert abs(np.sum(W[:, 1] * p(s)) + dp(c)) <= 1e-12 * abs(dp(c))
+
+
 def test_cauchy_rule_is_exact_on_polynomials():
     """For T of degree d < N: sum_j w_j T(s_j)/(z - s_j) = T(z)/(1 + zeta^N) with
     zeta = (z - c)/R and nodes offset by half a step."""
