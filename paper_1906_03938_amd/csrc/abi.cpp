@@ -399,11 +399,73 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
     return plan;
 }
 
+// A direct plan on a node set made of quadruples {x + iy, x - iy, x' + iy, x' - iy}, y != 0 (a
+// circle centred on the real axis with N a multiple of 4 and the half-step offset is one), is
+// turned into Gen::DirectSym: the operators are reordered so that every quadruple is
+// consecutive in that order (Cf becomes the matching permutation), and the sweep shares one
+// exp(-y r) and its reciprocal between the four nodes and one sincos between each conjugate
+// pair.  Members are matched to 4 units in the last place of the largest node; the kernel
+// evaluates them at the first member's y and at their own real parts, which moves no entry by
+// more than about 1e-14 relative.  The generated operators stay one per node.  Returns whether
+// the plan was changed.
+bool symmetrize(Plan &plan) {
+    if (plan.gen != bemrat::Gen::Direct) return false;
+    const int N = plan.L;
+    if (N < 4 || N % 4 != 0 || N > 4096) return false;
+    double zmax = 0.0;
+    for (const cplx &k : plan.kappa) zmax = std::max(zmax, std::abs(k));
+    const double tol = 4.0 * 2.220446049250313e-16 * zmax;
+    std::vector<int> up, lo;
+    for (int j = 0; j < N; ++j) {
+        const double y = plan.kappa[j].imag();
+        if (y > tol) up.push_back(j);
+        else if (y < -tol) lo.push_back(j);
+        else return false;
+    }
+    if (up.size() != lo.size() || up.size() % 2 != 0) return false;
+    std::vector<int> conj(N, -1);
+    std::vector<char> taken(N, 0);
+    for (int u : up) {
+        const cplx zu = plan.kappa[u];
+        for (int l : lo) {
+            const cplx zl = plan.kappa[l];
+            if (!taken[l] && std::abs(zl.real() - zu.real()) <= tol && std::abs(zl.imag() + zu.imag()) <= tol) {
+                conj[u] = l;
+                taken[l] = 1;
+                break;
+            }
+        }
+        if (conj[u] < 0) return false;
+    }
+    std::stable_sort(up.begin(), up.end(),
+                     [&](int a, int b) { return plan.kappa[a].imag() < plan.kappa[b].imag(); });
+    std::vector<int> perm;
+    perm.reserve(N);
+    for (size_t i = 0; i < up.size(); i += 2) {
+        const int a = up[i], b = up[i + 1];
+        if (std::abs(plan.kappa[a].imag() - plan.kappa[b].imag()) > tol) return false;
+        if (std::abs(plan.kappa[a].real() - plan.kappa[b].real()) <= tol) return false;
+        perm.push_back(a);
+        perm.push_back(conj[a]);
+        perm.push_back(b);
+        perm.push_back(conj[b]);
+    }
+    std::vector<cplx> kap(N);
+    for (int l = 0; l < N; ++l) kap[l] = plan.kappa[perm[l]];
+    plan.kappa = kap;
+    plan.Cf.assign((size_t)N * N, 0.0);
+    for (int l = 0; l < N; ++l) plan.Cf[(size_t)perm[l] * N + l] = 1.0;
+    plan.gen = bemrat::Gen::DirectSym;
+    return true;
+}
+
+bool is_direct(bemrat::Gen g) { return g == bemrat::Gen::Direct || g == bemrat::Gen::DirectSym; }
+
 // Host part of the self terms of the plan's operators: the wavenumbers the self-term kernel
 // evaluates (the nodes for DIRECT; K sample points for the expansion forms, with the DFT
 // weights that turn the samples into expansion coefficients).
 void self_params(const Plan &plan, Params &prm, size_t &off_self_kappa, size_t &off_dft, int &K) {
-    if (plan.gen == bemrat::Gen::Direct) {
+    if (is_direct(plan.gen)) {
         std::vector<double> k(2 * plan.L);
         for (int l = 0; l < plan.L; ++l) {
             k[2 * l] = plan.kappa[l].real();
@@ -470,7 +532,7 @@ bem_status build_self(bem_mesh *h, const Plan &plan, Params &prm, size_t &off_se
 hipError_t launch_self(const DeviceMesh &dm, const Plan &plan, const double *pbase, size_t off_self_kappa,
                        size_t off_dft, int K, double2 *aux, double2 *self, hipStream_t s) {
     const double2 *kap = reinterpret_cast<const double2 *>(pbase + off_self_kappa);
-    if (plan.gen == bemrat::Gen::Direct) return bemrat::launch_self_terms(dm, kap, plan.L, self, dm.n_pad, s);
+    if (is_direct(plan.gen)) return bemrat::launch_self_terms(dm, kap, plan.L, self, dm.n_pad, s);
     hipError_t e = bemrat::launch_self_terms(dm, kap, K, aux, dm.n_pad, s);
     if (e != hipSuccess) return e;
     return bemrat::launch_coef_dft(aux, dm.n_pad, K, reinterpret_cast<const double2 *>(pbase + off_dft), plan.L, self,
@@ -543,7 +605,7 @@ bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, 
         HIP_TRY(hipEventRecord(h->ev1, s), "event record");
         h->timed = true;
     }
-    h->last_form = plan.gen == bemrat::Gen::Direct ? BEM_FORM_DIRECT
+    h->last_form = is_direct(plan.gen) ? BEM_FORM_DIRECT
                    : plan.gen == bemrat::Gen::Taylor ? BEM_FORM_EXPAND
                                                      : BEM_FORM_CHEB;
     h->last_ops = plan.L;
@@ -995,6 +1057,11 @@ bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const doubl
     if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
     Plan plan = make_plan(h, z, N, m, flags);
     if (plan.unsupported) return fail(BEM_EUNSUPPORTED, "the Chebyshev form needs real nodes in a bounded interval");
+    // the folded sweep pays off for one or two weight sets (measured at n = 81920: 1.47x at
+    // m = 64, 1.05x at m = 32 for P = 2; slower than the unfolded sweep at P = 8, where the
+    // producer's folding work outweighs the saved contractions)
+    const bool fold = plan.prec == bemrat::Prec::F64 && plan.gen != bemrat::Gen::Cheb && P <= 2;
+    if (!fold) symmetrize(plan);
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
@@ -1009,10 +1076,7 @@ bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const doubl
             for (int64_t p = 0; p < P; ++p) coef[l * P + p] += cf * cplx(W[2 * (j * P + p)], W[2 * (j * P + p) + 1]);
         }
     const size_t off_coef = add_complex(prm, coef);
-    // the folded sweep pays off for one or two weight sets (measured at n = 81920: 1.47x at
-    // m = 64, 1.05x at m = 32 for P = 2; slower than the unfolded sweep at P = 8, where the
-    // producer's folding work outweighs the saved contractions)
-    if (plan.prec == bemrat::Prec::F64 && plan.gen != bemrat::Gen::Cheb && P <= 2)
+    if (fold)
         return folded_moments(h, plan, prm, off_k, off_dft, K, off_tables, off_coef, (int)P, V, m, ldv, M, ldm, stream);
     const size_t zstride = (size_t)h->dm.n * m;
     HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * plan.L), "sweep workspace");
@@ -1091,6 +1155,7 @@ bem_status rr_project(bem_mesh_t h, const double *z, int64_t N, const double *U,
     }
     Plan plan = make_plan(h, z, N, m, flags);
     if (plan.unsupported) return fail(BEM_EUNSUPPORTED, "the Chebyshev form needs real nodes in a bounded interval");
+    symmetrize(plan);
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
@@ -1339,7 +1404,8 @@ int batch_ops_per_item(const bem_batch *b, int cb) {
         const bool taylor = b->variant == bemrat::kBatchTaylor || b->variant == bemrat::kBatchTaylorDecay;
         return bemrat::batch_ops_per_item_f64(taylor ? bemrat::Gen::Taylor : bemrat::Gen::Direct, cb);
     }
-    const bool direct = b->variant == bemrat::kBatchDirect || b->variant == bemrat::kBatchDirectDecay;
+    const bool direct = b->variant == bemrat::kBatchDirect || b->variant == bemrat::kBatchDirectDecay ||
+                        b->variant == bemrat::kBatchDirectSym;
     return bemrat::lp_batch_ops_per_block(direct ? bemrat::Gen::Direct : bemrat::Gen::Taylor, cb);
 }
 
@@ -1485,8 +1551,18 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
         cost_d += (double)N * n * n;
     }
     if (form == BEM_FORM_AUTO && all_expand && !(cost_e < cost_d)) all_expand = false;
-    if (!all_expand)
-        for (int64_t i = 0; i < count; ++i) plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_DIRECT | pbits);
+    bool sym = false;
+    if (!all_expand) {
+        // the direct form shares transcendentals over node quadruples when every mesh's node
+        // set is made of them (one family for the launch), as the per-mesh calls do
+        sym = true;
+        for (int64_t i = 0; i < count; ++i) {
+            plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_DIRECT | pbits);
+            sym = sym && symmetrize(plans[i]);
+        }
+        if (!sym)
+            for (int64_t i = 0; i < count; ++i) plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_DIRECT | pbits);
+    }
     bool decay = false;
     for (const Plan &p : plans) {
         if (p.gen == bemrat::Gen::Taylor) decay |= p.c.imag() != 0.0;
@@ -1501,7 +1577,10 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
     b->P = P;
     b->m = m;
     b->form = all_expand ? BEM_FORM_EXPAND : BEM_FORM_DIRECT;
-    b->variant = bemrat::batch_variant(all_expand ? bemrat::Gen::Taylor : bemrat::Gen::Direct, decay);
+    b->variant = bemrat::batch_variant(all_expand ? bemrat::Gen::Taylor
+                                       : sym      ? bemrat::Gen::DirectSym
+                                                  : bemrat::Gen::Direct,
+                                       decay);
     b->prec = prec;
     b->meshes.assign(meshes, meshes + count);
     const int max_cb = batch_max_col_tile(b);

@@ -91,6 +91,60 @@ struct Generator<NOPS, Gen::Direct, DECAY> {
     }
 };
 
+// Direct form on quadruples of nodes {x + iy, x - iy, x' + iy, x' - iy} (operators 4g .. 4g + 3
+// of the block, in that order; a circle centred on the real axis with N a multiple of 4 and
+// the half-step offset is made of them): per quadrature point the quadruple takes one
+// exp(-y r), its reciprocal exp(+y r) (hardware estimate and two Newton steps), and the sincos
+// of x r and of x' r -- four operators for what one node of the plain direct form costs plus
+// a second sincos.  Every node is still its own operator, contracted on its own.
+template <int NOPS, bool DECAY>
+struct Generator<NOPS, Gen::DirectSym, DECAY> {
+    static_assert(NOPS % 4 == 0, "whole quadruples per block");
+    static constexpr int NQ = NOPS / 4;
+    double xa[NQ], xb[NQ], y[NQ];
+    __device__ void init(const SweepArgs &p, int L0) {
+#pragma unroll
+        for (int g = 0; g < NQ; ++g) {
+            // a quadruple beyond L (L a multiple of 4) repeats the first: its operators are
+            // not written
+            const int l = L0 + 4 * g < p.L ? L0 + 4 * g : L0;
+            xa[g] = p.kappa[l].x;
+            y[g] = p.kappa[l].y;
+            xb[g] = p.kappa[l + 2].x;
+        }
+    }
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &, double2 (&out)[NOPS]) const {
+        double gr[NOPS], gi[NOPS];
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) gr[j] = gi[j] = 0.0;
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+#pragma unroll
+            for (int g = 0; g < NQ; ++g) {
+                const double E = exp_cw(-y[g] * r[q]);
+                double Ei = __builtin_amdgcn_rcp(E);
+                Ei = fma(fma(-E, Ei, 1.0), Ei, Ei);
+                Ei = fma(fma(-E, Ei, 1.0), Ei, Ei);
+                const double e1 = E * wr[q], e2 = Ei * wr[q];
+                double s1, c1, s2, c2;
+                sincos_cw(xa[g] * r[q], s1, c1);
+                sincos_cw(xb[g] * r[q], s2, c2);
+                gr[4 * g] = fma(e1, c1, gr[4 * g]);
+                gi[4 * g] = fma(e1, s1, gi[4 * g]);
+                gr[4 * g + 1] = fma(e2, c1, gr[4 * g + 1]);
+                gi[4 * g + 1] = fma(e2, s1, gi[4 * g + 1]);
+                gr[4 * g + 2] = fma(e1, c2, gr[4 * g + 2]);
+                gi[4 * g + 2] = fma(e1, s2, gi[4 * g + 2]);
+                gr[4 * g + 3] = fma(e2, c2, gr[4 * g + 3]);
+                gi[4 * g + 3] = fma(e2, s2, gi[4 * g + 3]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) out[j] = make_double2(gr[j], gi[j]);
+    }
+};
+
 // Term of operator L0 + j at one point: w/r exp(i c r) (i x)^(L0 + j) / (L0 + j)!, x = R r.
 // L0 is a multiple of 4, so (i x)^L0 = x^L0; the rest is y0 i^j x^j c_j with
 // y0 = w/r exp(i c r) x^L0 / L0! and the block-uniform c_j = L0! / (L0 + j)!, which with

@@ -21,8 +21,11 @@ struct DeviceMesh {
     double *gl = nullptr;       // 2 * kSelfGL: Gauss-Legendre nodes then weights on [-1, 1]
 };
 
-// Generator of the coefficient operators of one sweep.
-enum class Gen : int { Direct = 0, Taylor = 1, Cheb = 2 };
+// Generator of the coefficient operators of one sweep.  DirectSym is the direct form on node
+// sets made of quadruples {x + iy, x - iy, x' + iy, x' - iy}, stored consecutively in that
+// order: the four share one exp(-y r) (and its reciprocal) per quadrature point, and each
+// conjugate pair one sincos.
+enum class Gen : int { Direct = 0, Taylor = 1, Cheb = 2, DirectSym = 3 };
 
 // Arithmetic of the contraction (bits 4..7 of the flags): FP64 throughout, or FP64
 // generation with an FP32 / BF16 / FP16 matrix-core contraction and FP32 accumulation.
@@ -65,6 +68,7 @@ enum BatchVariant : int {
     kBatchDirect = 1,
     kBatchTaylorDecay = 2,
     kBatchTaylor = 3,
+    kBatchDirectSym = 4,  // Gen::DirectSym (complex nodes: always with decay)
 };
 struct BatchEntry {
     SweepArgs args;

@@ -28,6 +28,7 @@
 // Operator families (entry of T_l at a != b, summed over the 7 points, with the weight
 // A_b w_q / (4 pi) folded into the staged points):
 //   Direct: T_l = T(kappa_l):              w/r exp(i kappa_l r)
+//   DirectSym: the same on quadruples of nodes {x +- iy, x' +- iy}, sharing transcendentals
 //   Taylor: T(c + R t) = sum_l t^l T_l:    w/r exp(i c r) (i R r)^l / l!
 #include "generators.h"
 
@@ -330,6 +331,7 @@ int batch_variant(Gen gen, bool decay) {
     switch (gen) {
         case Gen::Direct: return decay ? kBatchDirectDecay : kBatchDirect;
         case Gen::Taylor: return decay ? kBatchTaylorDecay : kBatchTaylor;
+        case Gen::DirectSym: return decay ? kBatchDirectSym : -1;
         default: return -1;
     }
 }
@@ -359,6 +361,7 @@ hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, cons
         case kBatchDirect: return launch_batch_gen<Gen::Direct, false>(cb, table, items, nitems, counter, grid, stream);
         case kBatchTaylorDecay: return launch_batch_gen<Gen::Taylor, true>(cb, table, items, nitems, counter, grid, stream);
         case kBatchTaylor: return launch_batch_gen<Gen::Taylor, false>(cb, table, items, nitems, counter, grid, stream);
+        case kBatchDirectSym: return launch_batch_gen<Gen::DirectSym, true>(cb, table, items, nitems, counter, grid, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -384,6 +387,8 @@ hipError_t launch_sweep(Gen gen, const SweepArgs &args, hipStream_t stream) {
             return decay ? launch_gen<Gen::Taylor, true>(args, stream) : launch_gen<Gen::Taylor, false>(args, stream);
         case Gen::Cheb:
             return decay ? hipErrorInvalidValue : launch_gen<Gen::Cheb, false>(args, stream);
+        case Gen::DirectSym:  // quadruples have Im != 0
+            return decay ? launch_gen<Gen::DirectSym, true>(args, stream) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

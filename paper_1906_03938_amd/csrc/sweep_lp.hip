@@ -359,11 +359,11 @@ hipError_t launch_lp_t(const SweepArgs &p, hipStream_t stream) {
 // amortises its generation (for the expansion forms, the per-point Bessel or power
 // sequence) over as many operators and columns as the registers allow.
 int lp_cb(int64_t m) { return m <= 16 ? 1 : m <= 32 ? 2 : m <= 64 ? 4 : 8; }
-int lp_g(Gen gen, int64_t m) { return gen == Gen::Direct && lp_cb(m) <= 4 ? 4 : 2; }
+int lp_g(Gen gen, int64_t m) { return (gen == Gen::Direct || gen == Gen::DirectSym) && lp_cb(m) <= 4 ? 4 : 2; }
 
 template <Prec P, Gen GEN, bool DECAY>
 hipError_t launch_lp_gen(const SweepArgs &p, hipStream_t stream) {
-    constexpr int G = GEN == Gen::Direct ? 4 : 2;  // lp_g up to 64 columns
+    constexpr int G = GEN == Gen::Direct || GEN == Gen::DirectSym ? 4 : 2;  // lp_g up to 64 columns
     switch (lp_cb(p.m)) {
         case 1: return launch_lp_t<P, G, 1, GEN, DECAY>(p, stream);
         case 2: return launch_lp_t<P, G, 2, GEN, DECAY>(p, stream);
@@ -384,6 +384,8 @@ hipError_t launch_lp_prec(Gen gen, const SweepArgs &args, hipStream_t stream) {
                          : launch_lp_gen<P, Gen::Taylor, false>(args, stream);
         case Gen::Cheb:
             return decay ? hipErrorInvalidValue : launch_lp_gen<P, Gen::Cheb, false>(args, stream);
+        case Gen::DirectSym:
+            return decay ? launch_lp_gen<P, Gen::DirectSym, true>(args, stream) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -414,6 +416,7 @@ hipError_t launch_lp_batch_prec(int variant, int cb, const BatchEntry *table, co
         case kBatchDirect: BEMRAT_LP_BATCH_CB(Gen::Direct, false, 4)
         case kBatchTaylorDecay: BEMRAT_LP_BATCH_CB(Gen::Taylor, true, 2)
         case kBatchTaylor: BEMRAT_LP_BATCH_CB(Gen::Taylor, false, 2)
+        case kBatchDirectSym: BEMRAT_LP_BATCH_CB(Gen::DirectSym, true, 4)
         default: return hipErrorInvalidValue;
     }
 #undef BEMRAT_LP_BATCH_CB
@@ -425,7 +428,7 @@ int sweep_lp_ops_per_block(Gen gen, int64_t m) { return 4 * lp_g(gen, m); }
 
 int lp_batch_col_tile(int64_t m) { return lp_cb(m); }
 
-int lp_batch_ops_per_block(Gen gen, int cb) { return gen == Gen::Direct && cb <= 4 ? 16 : 8; }
+int lp_batch_ops_per_block(Gen gen, int cb) { return (gen == Gen::Direct || gen == Gen::DirectSym) && cb <= 4 ? 16 : 8; }
 
 hipError_t launch_sweep_lp_batch(Prec prec, int variant, int cb, const BatchEntry *table, const int4 *items,
                                  int nitems, unsigned *counter, int grid, hipStream_t stream) {

@@ -135,6 +135,45 @@ def test_rr_project_matches_oracle(sphere3, torch, bem, form):
         assert _row_rel(Mg[p], Mo[p]) <= TOL, (form, p, _row_rel(Mg[p], Mo[p]))
 
 
+@pytest.mark.parametrize("case", ["shuffled", "off_axis", "n_not_multiple_of_4", "two_circles"])
+def test_direct_node_arrangements(sphere3, torch, bem, case):
+    """The per-node form on node sets with and without quadruples {x +- iy, x' +- iy} (whose
+    members share transcendentals in the sweep): a circle centred on the real axis in a
+    shuffled order (quadruples found in any order), a circle off the axis (no conjugate
+    pairs), a circle of 30 nodes (pairs but not whole quadruples) and two concentric circles
+    (quadruples of both, interleaved)."""
+    from oracle import method as M
+
+    mesh, op, _, _ = sphere3
+    U, _ = np.linalg.qr(synth.probe_block(op.n, 16, seed=9))
+    U = np.ascontiguousarray(U)
+    rng = np.random.Generator(np.random.PCG64(9))
+    if case == "shuffled":
+        s, w = M.circle_nodes(4.0, 1.5, 32)
+        perm = rng.permutation(32)
+        s, w = s[perm], w[perm]
+    elif case == "off_axis":
+        s, w = M.circle_nodes(4.0 + 0.25j, 1.5, 32)
+    elif case == "n_not_multiple_of_4":
+        s, w = M.circle_nodes(4.0, 1.5, 30)
+    else:
+        s1, w1 = M.circle_nodes(4.0, 1.5, 16)
+        s2, w2 = M.circle_nodes(4.0, 0.75, 8)
+        s, w = np.concatenate([s1, s2]), np.concatenate([w1, w2])
+    W = np.ascontiguousarray(np.stack([w / (s - 4.0), w / (s - 4.0) ** 2], axis=1))
+    P, Mg = mesh.rr_project(s, _dev(torch, U), W=W, form=bem.FORM_DIRECT)
+    assert mesh.last_form() == (bem.FORM_DIRECT, len(s))
+    P = P.cpu().numpy()
+    Po = M.rr_project(op, s, U)
+    for j in range(len(s)):
+        assert _rel(P[j], Po[j]) <= TOL, (case, j, _rel(P[j], Po[j]))
+        assert _row_rel(P[j], Po[j]) <= TOL, (case, j)
+    Mo = M.contour_moments(op, s, W, U)
+    Mg = Mg.cpu().numpy()
+    for p in range(2):
+        assert _rel(Mg[p], Mo[p]) <= TOL and _row_rel(Mg[p], Mo[p]) <= TOL, (case, p)
+
+
 @pytest.mark.parametrize("form", ["direct", "expand", "cheb"])
 def test_real_nodes_match_oracle(sphere3, torch, bem, form):
     """The calls the interval driver makes: projections and weighted sums on the real
