@@ -167,6 +167,22 @@ bem_status contour_moments(bem_mesh_t mesh, const double *z, int64_t N, const do
                            int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
                            int64_t ldm, uint32_t flags, hipStream_t stream);
 
+/* contour_moments for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same arguments, results
+ * and kernels as contour_moments, but every piece of device workspace (parameter block, self
+ * terms, probe copy, folded diagonal, generated products) is taken from the library's static
+ * scratch array of 128 MiB per device instead of the handle's buffers, and nothing is
+ * allocated (no hipMalloc, hipFree or allocating library routine; the parameter block is
+ * staged through the handle's pinned buffer of 1 MiB, sized when the handle was created).
+ * Sizes whose workspace exceeds the array (e.g. n = 81920 with m = 64 in the folded form needs
+ * about 212 MB) or whose parameter block exceeds the staging buffer return BEM_EINVAL and
+ * launch nothing.  All calls of this entry point on one GPU share that GPU's array, which keeps
+ * the last call's contents: calls that overlap in time on one device (two streams, two host
+ * threads) race and must be avoided by the caller.  Errors: those of contour_moments. */
+bem_status contour_moments_noalloc(bem_mesh_t mesh, const double *z, int64_t N, const double *W,
+                                   int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
+                                   int64_t ldm, uint32_t flags, hipStream_t stream);
+
 /* Chebyshev coefficient blocks C[l] = sum_k coef[l][k] T(kappa_k) V, l < L <= N, on the
  * first-kind points of [a, b] (paper, eq. Chebyshev; nodes and coef as in
  * bem_cheb_nodes).  a < b real.  flags: BEM_FORM_* as for contour_moments.  V: device n x m (ldv >= m).  C: device, L blocks of

@@ -31,6 +31,7 @@ EXPORTS = [
     "bem_assemble_sum", "bem_batch_create", "bem_batch_destroy", "bem_batch_layout", "bem_batch_moments",
     "bem_batch_set_timing", "bem_batch_last_kernel_ms",
     "bem_mesh_set_nearfield", "bem_mesh_nearfield", "bem_nearfield_moments", "bem_nearfield_sum",
+    "contour_moments_noalloc",
 ]
 
 
@@ -67,6 +68,7 @@ def lib():
     L.bem_self_terms.argtypes = [_vp, _dp, _i64, _vp, _vp]
     L.bem_assemble_apply.argtypes = [_vp, _dp, _i64, _vp, _i64, _i64, _vp, _i64, _u32, _vp]
     L.contour_moments.argtypes = [_vp, _dp, _i64, _dp, _i64, _vp, _i64, _i64, _vp, _i64, _u32, _vp]
+    L.contour_moments_noalloc.argtypes = [_vp, _dp, _i64, _dp, _i64, _vp, _i64, _i64, _vp, _i64, _u32, _vp]
     L.cheb_moments.argtypes = [_vp, ctypes.c_double, ctypes.c_double, _i64, _i64, _vp, _i64, _i64, _vp, _i64,
                                _u32, _vp]
     L.rr_project.argtypes = [_vp, _dp, _i64, _vp, _i64, _i64, _vp, _dp, _i64, _vp, _i64, _u32, _vp]
@@ -249,6 +251,17 @@ class Mesh:
         M = self._out(W.shape[1], m) if out is None else _out_blocks(out, W.shape[1], self.n, m, "out")
         _check(lib().contour_moments(self._h, _hp(z), z.size, _hp(W), W.shape[1], pv, m, ldv,
                                      ctypes.c_void_p(M.data_ptr()), M.stride(1), form, _stream()))
+        return M
+
+    def contour_moments_noalloc(self, z, W, V, out, form=FORM_AUTO):
+        """contour_moments with the library's static scratch as workspace (no device
+        allocation); `out` (P, n, m) complex128 must be given."""
+        z = _host_complex(z)
+        W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(z.size, -1))
+        pv, m, ldv = _block(V, "V")
+        M = _out_blocks(out, W.shape[1], self.n, m, "out")
+        _check(lib().contour_moments_noalloc(self._h, _hp(z), z.size, _hp(W), W.shape[1], pv, m, ldv,
+                                             ctypes.c_void_p(M.data_ptr()), M.stride(1), form, _stream()))
         return M
 
     def set_nearfield(self, eta: float):

@@ -68,6 +68,10 @@ struct Buffer {
     T *as() const { return static_cast<T *>(ptr); }
 };
 
+// Capacity of a handle's pinned parameter staging from its creation on (the allocation-free
+// entry point takes parameter blocks up to this size).
+constexpr size_t kStagingBytes = size_t(1) << 20;
+
 // Pinned host staging for per-call parameters; reused once its last upload completed.
 struct Staging {
     void *host = nullptr;
@@ -232,14 +236,81 @@ struct Params {
     }
 };
 
-bem_status upload(bem_mesh *h, const Params &p, hipStream_t s) {
+// Copies the parameter block to `dst` (device) through the handle's pinned staging buffer.
+// With `noalloc` the staging buffer is not grown (it holds kStagingBytes from the handle's
+// creation on), and a larger block is an argument error.
+bem_status upload_to(bem_mesh *h, const Params &p, double *dst, bool noalloc, hipStream_t s) {
     const size_t bytes = p.d.size() * sizeof(double);
+    if (noalloc && bytes > h->staging.bytes)
+        return fail(BEM_EINVAL, "parameter block of " + std::to_string(bytes) + " bytes exceeds the " +
+                                    std::to_string(h->staging.bytes) + "-byte staging buffer of an allocation-free call");
     HIP_TRY(h->staging.ensure(bytes), "staging buffer");
-    HIP_TRY(h->params.ensure(bytes), "parameter buffer");
     std::memcpy(h->staging.host, p.d.data(), bytes);
-    HIP_TRY(hipMemcpyAsync(h->params.ptr, h->staging.host, bytes, hipMemcpyHostToDevice, s), "parameter upload");
+    HIP_TRY(hipMemcpyAsync(dst, h->staging.host, bytes, hipMemcpyHostToDevice, s), "parameter upload");
     HIP_TRY(hipEventRecord(h->staging.done, s), "event record");
     h->staging.pending = true;
+    return BEM_OK;
+}
+
+bem_status upload(bem_mesh *h, const Params &p, hipStream_t s) {
+    HIP_TRY(h->params.ensure(p.d.size() * sizeof(double)), "parameter buffer");
+    return upload_to(h, p, h->params.as<double>(), false, s);
+}
+
+// Device workspace of one sweep call: the parameter block, the self-term table and samples,
+// the zero-padded probe copy, the folded diagonal, the generated products Z and the probe
+// scale.  Every entry point takes it from the handle's buffers (grown on demand), except
+// contour_moments_noalloc, which carves the same pieces out of the library's static scratch
+// array.
+struct Work {
+    double *params = nullptr;
+    double2 *self = nullptr, *aux = nullptr, *probe = nullptr, *fself = nullptr, *Z = nullptr;
+    unsigned long long *vmax = nullptr;
+};
+struct Need {
+    size_t params = 0, self = 0, aux = 0, probe = 0, fself = 0, Z = 0, vmax = 0;
+};
+
+bem_status acquire_handle(bem_mesh *h, const Need &n, Work &w) {
+    HIP_TRY(h->params.ensure(n.params), "parameter buffer");
+    HIP_TRY(h->self.ensure(n.self), "self-term table");
+    HIP_TRY(h->aux.ensure(n.aux), "self-term samples");
+    HIP_TRY(h->probe.ensure(n.probe), "probe copy");
+    HIP_TRY(h->fself.ensure(n.fself), "folded self terms");
+    HIP_TRY(h->Z.ensure(n.Z), "sweep workspace");
+    HIP_TRY(h->vmax.ensure(n.vmax), "probe scale");
+    w.params = h->params.as<double>();
+    w.self = h->self.as<double2>();
+    w.aux = h->aux.as<double2>();
+    w.probe = h->probe.as<double2>();
+    w.fself = h->fself.as<double2>();
+    w.Z = h->Z.as<double2>();
+    w.vmax = h->vmax.as<unsigned long long>();
+    return BEM_OK;
+}
+
+// The pieces laid out one after another in the current device's scratch array, each at a
+// 256-byte boundary; BEM_EINVAL when they do not fit (nothing is launched).
+bem_status acquire_scratch(const Need &n, Work &w) {
+    void *base = nullptr;
+    size_t cap = 0;
+    HIP_TRY(bemrat::scratch_region(&base, &cap), "scratch array address");
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = static_cast<unsigned char *>(base) + off;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    w.params = static_cast<double *>(take(n.params));
+    w.self = static_cast<double2 *>(take(n.self));
+    w.aux = static_cast<double2 *>(take(n.aux));
+    w.probe = static_cast<double2 *>(take(n.probe));
+    w.fself = static_cast<double2 *>(take(n.fself));
+    w.Z = static_cast<double2 *>(take(n.Z));
+    w.vmax = static_cast<unsigned long long *>(take(n.vmax));
+    if (off > cap)
+        return fail(BEM_EINVAL, "the call needs " + std::to_string(off) + " bytes of workspace; the allocation-free "
+                                "entry point has " + std::to_string(cap));
     return BEM_OK;
 }
 
@@ -563,22 +634,33 @@ bemrat::SweepArgs sweep_args(const DeviceMesh &dm, const Plan &plan, const doubl
     return a;
 }
 
+// Workspace of a sweep of `plan` (self terms through K samples) on probe blocks of m columns;
+// the parameter block, Z and the folded diagonal are added by the caller.
+Need sweep_need(const bem_mesh *h, const Plan &plan, int K, int64_t m) {
+    Need n;
+    const size_t n_pad = (size_t)h->dm.n_pad;
+    n.self = sizeof(double2) * (size_t)plan.L * n_pad;
+    n.aux = sizeof(double2) * (size_t)K * n_pad;
+    const int64_t m_pad = plan.prec == bemrat::Prec::F64 ? bemrat::sweep_m_pad(m) : bemrat::sweep_lp_m_pad(m);
+    n.probe = sizeof(double2) * n_pad * (size_t)m_pad;
+    n.vmax = plan.prec == bemrat::Prec::F64 ? 0 : sizeof(unsigned long long);
+    return n;
+}
+
 // Runs self terms + sweep for `plan` on probe block V; Z receives L blocks (zstride, ldz).
-bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, int64_t ldv,
-                     double2 *Z, int64_t ldz, int64_t zstride, Params &prm, size_t off_self_kappa,
-                     size_t off_dft, int K, size_t off_tables, hipStream_t s) {
+// The parameter block is at w.params already.
+bem_status run_sweep(bem_mesh *h, const Plan &plan, const Work &w, const double *V, int64_t m, int64_t ldv,
+                     double2 *Z, int64_t ldz, int64_t zstride, size_t off_self_kappa, size_t off_dft, int K,
+                     size_t off_tables, hipStream_t s) {
     const DeviceMesh &dm = h->dm;
-    const double *pbase = h->params.as<double>();
-    HIP_TRY(launch_self(dm, plan, pbase, off_self_kappa, off_dft, K, h->aux.as<double2>(), h->self.as<double2>(), s),
-            "self-term kernel");
+    const double *pbase = w.params;
+    HIP_TRY(launch_self(dm, plan, pbase, off_self_kappa, off_dft, K, w.aux, w.self, s), "self-term kernel");
     // zero-padded copy of the probe block read by the sweep
     const int64_t m_pad = plan.prec == bemrat::Prec::F64 ? bemrat::sweep_m_pad(m) : bemrat::sweep_lp_m_pad(m);
-    const size_t np = (size_t)dm.n_pad * m_pad;
-    HIP_TRY(h->probe.ensure(np * sizeof(double2)), "probe copy");
-    double2 *Vp2 = h->probe.as<double2>();
+    double2 *Vp2 = w.probe;
     HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V), ldv, dm.n, m, dm.n_pad, m_pad, Vp2, s),
             "probe copy kernel");
-    bemrat::SweepArgs a = sweep_args(dm, plan, pbase, off_self_kappa, off_tables, h->self.as<double2>());
+    bemrat::SweepArgs a = sweep_args(dm, plan, pbase, off_self_kappa, off_tables, w.self);
     a.Vp2 = Vp2;
     a.m_pad = m_pad;
     a.V = reinterpret_cast<const double2 *>(V);
@@ -594,11 +676,10 @@ bem_status run_sweep(bem_mesh *h, const Plan &plan, const double *V, int64_t m, 
         // entries ~ A_b w_q / (4 pi r): scaled to ~ w_q / r, well inside the FP16 range;
         // the probe block by 1 / max |V| (a device reduction into the workspace)
         a.a_scale = 4.0 * 3.14159265358979323846 / h->mean_area;
-        HIP_TRY(h->vmax.ensure(sizeof(unsigned long long)), "probe scale");
-        HIP_TRY(bemrat::launch_absmax(a.V, ldv, dm.n, m, h->vmax.as<unsigned long long>(), s), "probe scale kernel");
-        a.vmax = h->vmax.as<unsigned long long>();
+        HIP_TRY(bemrat::launch_absmax(a.V, ldv, dm.n, m, w.vmax, s), "probe scale kernel");
+        a.vmax = w.vmax;
         HIP_TRY(bemrat::launch_sweep_lp(plan.prec, plan.gen, a, s), "reduced-precision sweep kernel");
-        HIP_TRY(bemrat::launch_add_diag(h->self.as<double2>(), dm.n_pad, a.V, ldv, Z, ldz, zstride, dm.n, m, plan.L, s),
+        HIP_TRY(bemrat::launch_add_diag(w.self, dm.n_pad, a.V, ldv, Z, ldz, zstride, dm.n, m, plan.L, s),
                 "diagonal kernel");
     }
     if (h->timing) {
@@ -804,6 +885,9 @@ bem_status bem_mesh_create(const double *xyz, int64_t nv, const int32_t *tri, in
     if (e == hipSuccess) e = hipEventCreate(&h->ev0);
     if (e == hipSuccess) e = hipEventCreate(&h->ev1);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->staging.done, hipEventDisableTiming);
+    // pinned staging of the per-call parameter block, sized once here so that the
+    // allocation-free entry point never has to grow it
+    if (e == hipSuccess) e = h->staging.ensure(kStagingBytes);
     if (e == hipSuccess) e = hipMalloc(&staging, sizeof(double) * 3 * nv + sizeof(int32_t) * 3 * n);
     if (e != hipSuccess) {
         st = hip_fail(e, "mesh allocation");
@@ -991,37 +1075,40 @@ bem_status bem_assemble_apply(bem_mesh_t h, const double *kappa, int64_t nk, con
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
     int K = 0;
-    if ((st = build_self(h, plan, prm, off_k, off_dft, K, stream)) != BEM_OK) return st;
-    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
-    return run_sweep(h, plan, V, m, ldv, reinterpret_cast<double2 *>(Y), ldy, h->dm.n * ldy, prm, off_k, off_dft,
-                     K, off_tables, stream);
+    self_params(plan, prm, off_k, off_dft, K);
+    Need need = sweep_need(h, plan, K, m);
+    need.params = prm.d.size() * sizeof(double);
+    Work w;
+    if ((st = acquire_handle(h, need, w)) != BEM_OK) return st;
+    if ((st = upload_to(h, prm, w.params, false, stream)) != BEM_OK) return st;
+    return run_sweep(h, plan, w, V, m, ldv, reinterpret_cast<double2 *>(Y), ldy, h->dm.n * ldy, off_k, off_dft, K,
+                     off_tables, stream);
 }
 
 
+}  // extern "C"
+
+namespace {
+
 // Folded moments (FP64, direct or expansion plans, P <= kFoldMax): the sweep generates every
 // operator of each entry and contracts only the P combinations sum_l coef[l][p] T_l, written
-// straight to M; the diagonal is the same combination of the self terms.
-bem_status folded_moments(bem_mesh *h, const Plan &plan, Params &prm, size_t off_k, size_t off_dft, int K,
+// straight to M; the diagonal is the same combination of the self terms.  The parameter
+// block is at w.params already.
+bem_status folded_moments(bem_mesh *h, const Plan &plan, const Work &w, size_t off_k, size_t off_dft, int K,
                           size_t off_tables, size_t off_coef, int P, const double *V, int64_t m, int64_t ldv,
                           double *M, int64_t ldm, hipStream_t s) {
-    bem_status st = upload(h, prm, s);
-    if (st != BEM_OK) return st;
     const DeviceMesh &dm = h->dm;
-    const double *pbase = h->params.as<double>();
+    const double *pbase = w.params;
     const double2 *coef = reinterpret_cast<const double2 *>(pbase + off_coef);
-    HIP_TRY(launch_self(dm, plan, pbase, off_k, off_dft, K, h->aux.as<double2>(), h->self.as<double2>(), s),
-            "self-term kernel");
-    HIP_TRY(h->fself.ensure(sizeof(double2) * (size_t)P * dm.n_pad), "folded self terms");
+    HIP_TRY(launch_self(dm, plan, pbase, off_k, off_dft, K, w.aux, w.self, s), "self-term kernel");
     // fself[p][a] = sum_l coef[l][p] self_l[a]: the recombination kernel with one column
-    HIP_TRY(bemrat::launch_combine(h->self.as<double2>(), dm.n_pad, 1, plan.L, coef, P, dm.n_pad, 1,
-                                   h->fself.as<double2>(), 1, s),
+    HIP_TRY(bemrat::launch_combine(w.self, dm.n_pad, 1, plan.L, coef, P, dm.n_pad, 1, w.fself, 1, s),
             "folded self-term kernel");
     const int64_t m_pad = bemrat::sweep_m_pad(m);
-    HIP_TRY(h->probe.ensure((size_t)dm.n_pad * m_pad * sizeof(double2)), "probe copy");
-    double2 *Vp2 = h->probe.as<double2>();
+    double2 *Vp2 = w.probe;
     HIP_TRY(bemrat::launch_prep_probe(reinterpret_cast<const double2 *>(V), ldv, dm.n, m, dm.n_pad, m_pad, Vp2, s),
             "probe copy kernel");
-    bemrat::SweepArgs a = sweep_args(dm, plan, pbase, off_k, off_tables, h->fself.as<double2>());
+    bemrat::SweepArgs a = sweep_args(dm, plan, pbase, off_k, off_tables, w.fself);
     a.L = P;
     a.Lgen = plan.L;
     a.fcoef = coef;
@@ -1044,8 +1131,11 @@ bem_status folded_moments(bem_mesh *h, const Plan &plan, Params &prm, size_t off
     return BEM_OK;
 }
 
-bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const double *W, int64_t P, const double *V,
-                           int64_t m, int64_t ldv, double *M, int64_t ldm, uint32_t flags, hipStream_t stream) {
+// contour_moments with its workspace from the handle (noalloc = false) or from the static
+// scratch array (noalloc = true: nothing is allocated, sizes beyond the array are rejected).
+bem_status contour_moments_impl(bem_mesh_t h, const double *z, int64_t N, const double *W, int64_t P,
+                                const double *V, int64_t m, int64_t ldv, double *M, int64_t ldm, uint32_t flags,
+                                bool noalloc, hipStream_t stream) {
     if (!h) return fail(BEM_EINVAL, "mesh is NULL");
     DeviceGuard guard(h->device);
     bem_status st = check_flags(flags);
@@ -1066,7 +1156,7 @@ bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const doubl
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
     int K = 0;
-    if ((st = build_self(h, plan, prm, off_k, off_dft, K, stream)) != BEM_OK) return st;
+    self_params(plan, prm, off_k, off_dft, K);
     // combine coefficients: coef[l][p] = sum_j Cf[j][l] W[j][p]
     std::vector<cplx> coef((size_t)plan.L * P, 0.0);
     for (int64_t j = 0; j < N; ++j)
@@ -1076,19 +1166,37 @@ bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const doubl
             for (int64_t p = 0; p < P; ++p) coef[l * P + p] += cf * cplx(W[2 * (j * P + p)], W[2 * (j * P + p) + 1]);
         }
     const size_t off_coef = add_complex(prm, coef);
-    if (fold)
-        return folded_moments(h, plan, prm, off_k, off_dft, K, off_tables, off_coef, (int)P, V, m, ldv, M, ldm, stream);
+    Need need = sweep_need(h, plan, K, m);
+    need.params = prm.d.size() * sizeof(double);
     const size_t zstride = (size_t)h->dm.n * m;
-    HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * plan.L), "sweep workspace");
-    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
-    double2 *Z = h->Z.as<double2>();
-    if ((st = run_sweep(h, plan, V, m, ldv, Z, m, zstride, prm, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
+    if (fold) need.fself = sizeof(double2) * (size_t)P * h->dm.n_pad;
+    else need.Z = sizeof(double2) * zstride * plan.L;
+    Work w;
+    if ((st = noalloc ? acquire_scratch(need, w) : acquire_handle(h, need, w)) != BEM_OK) return st;
+    if ((st = upload_to(h, prm, w.params, noalloc, stream)) != BEM_OK) return st;
+    if (fold)
+        return folded_moments(h, plan, w, off_k, off_dft, K, off_tables, off_coef, (int)P, V, m, ldv, M, ldm, stream);
+    if ((st = run_sweep(h, plan, w, V, m, ldv, w.Z, m, zstride, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
         return st;
-    HIP_TRY(bemrat::launch_combine(Z, zstride, m, plan.L,
-                                   reinterpret_cast<const double2 *>(h->params.as<double>() + off_coef), (int)P,
-                                   h->dm.n, m, reinterpret_cast<double2 *>(M), ldm, stream),
+    HIP_TRY(bemrat::launch_combine(w.Z, zstride, m, plan.L, reinterpret_cast<const double2 *>(w.params + off_coef),
+                                   (int)P, h->dm.n, m, reinterpret_cast<double2 *>(M), ldm, stream),
             "combine kernel");
     return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bem_status contour_moments(bem_mesh_t h, const double *z, int64_t N, const double *W, int64_t P, const double *V,
+                           int64_t m, int64_t ldv, double *M, int64_t ldm, uint32_t flags, hipStream_t stream) {
+    return contour_moments_impl(h, z, N, W, P, V, m, ldv, M, ldm, flags, false, stream);
+}
+
+bem_status contour_moments_noalloc(bem_mesh_t h, const double *z, int64_t N, const double *W, int64_t P,
+                                   const double *V, int64_t m, int64_t ldv, double *M, int64_t ldm, uint32_t flags,
+                                   hipStream_t stream) {
+    return contour_moments_impl(h, z, N, W, P, V, m, ldv, M, ldm, flags, true, stream);
 }
 
 bem_status cheb_moments(bem_mesh_t h, double a, double b, int64_t N, int64_t L, const double *V, int64_t m,
@@ -1125,14 +1233,16 @@ bem_status cheb_moments(bem_mesh_t h, double a, double b, int64_t N, int64_t L, 
         }
     const size_t off_coef = add_complex(prm, coef);
     const size_t zstride = (size_t)h->dm.n * m;
-    HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * plan.L), "sweep workspace");
-    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
-    double2 *Z = h->Z.as<double2>();
-    if ((st = run_sweep(h, plan, V, m, ldv, Z, m, zstride, prm, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
+    Need need = sweep_need(h, plan, K, m);
+    need.params = prm.d.size() * sizeof(double);
+    need.Z = sizeof(double2) * zstride * plan.L;
+    Work w;
+    if ((st = acquire_handle(h, need, w)) != BEM_OK) return st;
+    if ((st = upload_to(h, prm, w.params, false, stream)) != BEM_OK) return st;
+    if ((st = run_sweep(h, plan, w, V, m, ldv, w.Z, m, zstride, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
         return st;
-    HIP_TRY(bemrat::launch_combine(Z, zstride, m, plan.L,
-                                   reinterpret_cast<const double2 *>(h->params.as<double>() + off_coef), (int)L,
-                                   h->dm.n, m, reinterpret_cast<double2 *>(C), ldc, stream),
+    HIP_TRY(bemrat::launch_combine(w.Z, zstride, m, plan.L, reinterpret_cast<const double2 *>(w.params + off_coef),
+                                   (int)L, h->dm.n, m, reinterpret_cast<double2 *>(C), ldc, stream),
             "combine kernel");
     return BEM_OK;
 }
@@ -1178,13 +1288,17 @@ bem_status rr_project(bem_mesh_t h, const double *z, int64_t N, const double *U,
     const size_t zstride = (size_t)n * m;
     const int64_t rows_per_chunk = 4096;
     const int nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
-    HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * plan.L), "sweep workspace");
+    Need need = sweep_need(h, plan, K, m);
+    need.params = prm.d.size() * sizeof(double);
+    need.Z = sizeof(double2) * zstride * plan.L;
+    Work w;
+    if ((st = acquire_handle(h, need, w)) != BEM_OK) return st;
     HIP_TRY(h->partial.ensure(sizeof(double2) * (size_t)plan.L * nchunks * m * m), "projection workspace");
-    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
-    double2 *Z = h->Z.as<double2>();
-    if ((st = run_sweep(h, plan, U, m, ldu, Z, m, zstride, prm, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
+    if ((st = upload_to(h, prm, w.params, false, stream)) != BEM_OK) return st;
+    double2 *Z = w.Z;
+    if ((st = run_sweep(h, plan, w, U, m, ldu, Z, m, zstride, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
         return st;
-    const double *pbase = h->params.as<double>();
+    const double *pbase = w.params;
     HIP_TRY(bemrat::launch_project_partial(reinterpret_cast<const double2 *>(U), ldu, Z, zstride, m, plan.L, n, m,
                                            rows_per_chunk, nchunks, h->partial.as<double2>(), stream),
             "projection kernel");

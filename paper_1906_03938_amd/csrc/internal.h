@@ -149,4 +149,10 @@ hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const in
                             int p0, int P, double kmax, const double2 *V, int64_t ldv, int64_t m,
                             double2 *M, int64_t ldm, double2 *S, int64_t lds, hipStream_t stream);
 
+// Static device scratch array of the allocation-free entry point (scratch.hip): 128 MiB per
+// device.  scratch_region returns the current device's copy (its address is looked up once per
+// device) and its size.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+hipError_t scratch_region(void **ptr, size_t *bytes);
+
 }  // namespace bemrat
