@@ -257,6 +257,106 @@ bem_status bem_nearfield_sum(bem_mesh_t mesh, const double *z, int64_t N, const 
 bem_status bem_assemble_sum(bem_mesh_t mesh, const double *z, int64_t N, const double *c, double *S,
                             int64_t lds, uint32_t flags, hipStream_t stream);
 
+/* ------------------------------------------------- learned near-field correction --- */
+
+/* A surrogate for the near-field quadrature (not a step of the paper's method): a perceptron
+ * with three hidden layers of 128 tanh units maps a near pair's source triangle, target point
+ * and wavenumber to the correction dT = (integral of g over the triangle) - (its 7-point value),
+ * trained on the GPU by the kernels below on triples labelled by bem_nf_labels; the quadrature
+ * of bem_nearfield_moments stays the fallback outside the network's trust region and its judge.
+ *
+ * Inputs (19, padded to BEM_NET_INPUTS floats per row): in the unit frame of the source
+ * triangle (its longest edge A -> B on the x axis, the first longest of P0P1, P1P2, P2P0;
+ * lengths divided by h = |B - A|; third vertex C = (p, q), q > 0; mirrored across u = 1/2 when
+ * p > 1/2) the target is (u, v, w), and the inputs are (p - 0.25)/0.25, (q - 0.5)/0.4,
+ * (u - 0.5)/1.5, (v - 0.3)/1.5, |w|, 2 Re(kappa h) - 1, Im(kappa h)/0.3, r0 - 1, 0.5/r0,
+ * 0.3/r_k (k < 7), 0.5/s_k (k < 3); r0 is the distance to the centroid, r_k to the points of
+ * Radon's rule (centroid; barycentric weight (9 - 2 sqrt 15)/21 on A, B, C; weight
+ * (9 + 2 sqrt 15)/21 on A, B, C), s_k to A, B, C.  The outputs y (2) give
+ * dT = h (S_re y_0 + i S_im y_1) / (4 pi r0^4), S the model's output scales.
+ * Parameters: BEM_NET_PARAMS floats (device), row-major out x in: W1 [128 x 32] (input columns
+ * 19..31 unused), b1 [128], W2 [128 x 128], b2, W3 [128 x 128], b3, W4 [2 x 128], b4 [2]. */
+#define BEM_NET_PARAMS 37506
+#define BEM_NET_INPUTS 32
+#define BEM_NET_BINS 8
+
+/* Number of network parameters (BEM_NET_PARAMS), for binding checks. */
+int64_t bem_net_params(void);
+
+/* Training labels from the library's near-field quadrature: out[s] = (integral over triangle
+ * P9[s] of g(|x[s] - y|), g(r) = exp(i kappa[s] r)/(4 pi r)) - (Radon's 7-point value of the same
+ * integral), s < S.  P9: device S x 9 doubles (three vertices); x: device S x 3; kappa, out:
+ * device S complex.  The integral is the polar form of bem_nearfield_moments (accurate to about
+ * 1e-14 relative while |kappa| h <~ 2).  Errors: BEM_EINVAL, BEM_EDEVICE. */
+bem_status bem_nf_labels(const double *P9, const double *x, const double *kappa, int64_t S, double *out,
+                         hipStream_t stream);
+
+/* Network inputs of the triples (P9[s], x[s], kappa[s]): X device S x BEM_NET_INPUTS floats
+ * (columns 19.. zero), aux device S x 4 doubles (h, r0, Re kappa h, Im kappa h).
+ * Errors: BEM_EINVAL, BEM_EDEVICE. */
+bem_status bem_net_features(const double *P9, const double *x, const double *kappa, int64_t S, float *X,
+                            double *aux, hipStream_t stream);
+
+/* FP32 forward pass of B rows of inputs X (device B x BEM_NET_INPUTS): Y device B x 2.
+ * Errors: BEM_EINVAL, BEM_EDEVICE. */
+bem_status bem_net_forward(const float *params, const float *X, int64_t B, float *Y, hipStream_t stream);
+
+/* Device workspace (floats) bem_net_gradient needs for a batch of B rows; -1 if B < 1. */
+int64_t bem_net_work_floats(int64_t B);
+
+/* Loss (1/B) sum_b sum_o (Y_bo - T_bo)^2 of the batch (targets T device B x 2) and its gradient
+ * with respect to the parameters, by back-propagation on the FP32 matrix cores: grad device
+ * BEM_NET_PARAMS floats, loss device 1 float, work device bem_net_work_floats(B) floats (caller
+ * owned; the call allocates nothing).  Per-tile gradients are summed in a fixed order: results
+ * are bitwise reproducible.  Errors: BEM_EINVAL, BEM_EDEVICE. */
+bem_status bem_net_gradient(const float *params, const float *X, const float *T, int64_t B, float *work,
+                            float *grad, float *loss, hipStream_t stream);
+
+/* One Adam update (Kingma and Ba, 2015; beta1 0.9, beta2 0.999, eps 1e-8) of the parameters
+ * with gradient grad and moment estimates m, v (all device BEM_NET_PARAMS floats), step >= 1
+ * (bias corrections 1 - beta^step), learning rate lr > 0.  Errors: BEM_EINVAL, BEM_EDEVICE. */
+bem_status bem_net_adam(float *params, const float *grad, float *m, float *v, int64_t step, double lr,
+                        hipStream_t stream);
+
+/* A trained network and its trust region: pairs whose target lies at least dmin (in units of
+ * the source triangle's longest edge h) from the triangle, whose triangle has every angle at
+ * least min_angle_deg, with max_j |Re kappa_j| h <= kh_re_max, max_j |Im kappa_j| h <= kh_im_max,
+ * every Re kappa_j >= 0, and whose distance falls in a bin [bin_edges[i], bin_edges[i+1]) with
+ * bin_trusted[i] != 0, use the network; every other pair the quadrature. */
+typedef struct {
+    const float *params;               /* device, BEM_NET_PARAMS floats */
+    double out_scale[2];               /* S_re, S_im */
+    double dmin, min_angle_deg, kh_re_max, kh_im_max;
+    double bin_edges[BEM_NET_BINS + 1];
+    int bin_trusted[BEM_NET_BINS];
+} bem_net_model;
+
+/* As bem_nearfield_moments, with the corrections of the pairs inside the model's trust region
+ * taken from the network (FP16 on the matrix cores, FP32 accumulation; accurate to the model's
+ * validation error, not to FP64) and the others from the quadrature:
+ *   M[p] += sum_j W[j][p] dT(z_j) V.
+ * The network's corrections of a pair are folded with the weights in FP64, the pairs are
+ * applied in a fixed order: results are deterministic.  fallback_pairs [host, may be NULL]:
+ * receives the number of pairs the quadrature handled (the call then synchronises `stream`).
+ * Workspace (packed FP16 weights, one folded correction per pair and weight set, one flag per
+ * pair) is the handle's, allocated on first use of a size.  Errors: BEM_EINVAL, BEM_ENOMEM,
+ * BEM_EDEVICE. */
+bem_status bem_nearfield_moments_net(bem_mesh_t mesh, const bem_net_model *model, const double *z, int64_t N,
+                                     const double *W, int64_t P, const double *V, int64_t m, int64_t ldv,
+                                     double *M, int64_t ldm, int64_t *fallback_pairs, hipStream_t stream);
+
+/* Near-field corrections of the Rayleigh-Ritz projections (paper, Section 3, B^_j = U^H B_j U):
+ *   Pout[j] += U^H dT(z_j) U,  j < N <= 4096,
+ * dT the mesh's near-field correction (the quadrature when model is NULL; else the model's
+ * network inside its trust region and the quadrature outside), so rr_project followed by this
+ * call gives the projections of the corrected operator.  The per-node corrections dT(z_j) U are
+ * formed in the handle's workspace (N x n x m complex, allocated on first use of a size) and
+ * projected with rr_project's fixed-order reduction.  z [host]: N complex.  U: device n x m
+ * (ldu >= m).  Pout: device N x m x m, read and written.  Without a near-pair list Pout is left
+ * unchanged.  Errors: BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE. */
+bem_status bem_nearfield_project(bem_mesh_t mesh, const bem_net_model *model, const double *z, int64_t N,
+                                 const double *U, int64_t m, int64_t ldu, double *Pout, hipStream_t stream);
+
 /* ------------------------------------------------------------- batched form --- */
 
 /* A batch of meshes, each with its own node set and moment weights, whose contour moments

@@ -32,7 +32,20 @@ EXPORTS = [
     "bem_batch_set_timing", "bem_batch_last_kernel_ms",
     "bem_mesh_set_nearfield", "bem_mesh_nearfield", "bem_nearfield_moments", "bem_nearfield_sum",
     "contour_moments_noalloc",
+    "bem_net_params", "bem_nf_labels", "bem_net_features", "bem_net_forward", "bem_net_work_floats",
+    "bem_net_gradient", "bem_net_adam", "bem_nearfield_moments_net", "bem_nearfield_project",
 ]
+
+NET_PARAMS = 37506
+NET_INPUTS = 32
+NET_BINS = 8
+
+
+class NetModelC(ctypes.Structure):
+    """The C struct bem_net_model (include/bemrat.h)."""
+    _fields_ = [("params", ctypes.c_void_p), ("out_scale", ctypes.c_double * 2), ("dmin", ctypes.c_double),
+                ("min_angle_deg", ctypes.c_double), ("kh_re_max", ctypes.c_double), ("kh_im_max", ctypes.c_double),
+                ("bin_edges", ctypes.c_double * (NET_BINS + 1)), ("bin_trusted", ctypes.c_int * NET_BINS)]
 
 
 class BemError(RuntimeError):
@@ -92,10 +105,25 @@ def lib():
     L.bem_mesh_nearfield.argtypes = [_vp, ctypes.POINTER(_i64), _vp, _vp]
     L.bem_nearfield_moments.argtypes = [_vp, _dp, _i64, _dp, _i64, _vp, _i64, _i64, _vp, _i64, _vp]
     L.bem_nearfield_sum.argtypes = [_vp, _dp, _i64, _dp, _vp, _i64, _vp]
+    L.bem_net_params.argtypes = []
+    L.bem_nf_labels.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp]
+    L.bem_net_features.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp]
+    L.bem_net_forward.argtypes = [_vp, _vp, _i64, _vp, _vp]
+    L.bem_net_work_floats.argtypes = [_i64]
+    L.bem_net_gradient.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]
+    L.bem_net_adam.argtypes = [_vp, _vp, _vp, _vp, _i64, ctypes.c_double, _vp]
+    L.bem_nearfield_moments_net.argtypes = [_vp, ctypes.POINTER(NetModelC), _dp, _i64, _dp, _i64, _vp, _i64, _i64, _vp,
+                                            _i64, ctypes.POINTER(_i64), _vp]
+    L.bem_nearfield_project.argtypes = [_vp, ctypes.POINTER(NetModelC), _dp, _i64, _vp, _i64, _i64, _vp, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("bem_mesh_destroy", "bem_mesh_size", "bem_last_error", "bem_batch_destroy"):
+        if name not in ("bem_mesh_destroy", "bem_mesh_size", "bem_last_error", "bem_batch_destroy", "bem_net_params",
+                        "bem_net_work_floats"):
             f.restype = ctypes.c_int
+    L.bem_net_params.restype = _i64
+    L.bem_net_work_floats.restype = _i64
+    if L.bem_net_params() != NET_PARAMS:
+        raise ImportError("libbemrat.so was built with a different network layout")
     _lib = L
     return L
 
@@ -263,6 +291,37 @@ class Mesh:
         _check(lib().contour_moments_noalloc(self._h, _hp(z), z.size, _hp(W), W.shape[1], pv, m, ldv,
                                              ctypes.c_void_p(M.data_ptr()), M.stride(1), form, _stream()))
         return M
+
+    def nearfield_moments_net(self, model, z, W, V, out=None, count_fallback=False):
+        """Adds the near-field correction sum_j W[j, p] dT(z_j) V to out (zeros if None), with
+        the network of `model` (a bem_net_model, see nfnet.NearFieldNet.c_model) inside its
+        trust region and the quadrature elsewhere.  Returns out, or (out, number of pairs the
+        quadrature handled) with count_fallback."""
+        z = _host_complex(z)
+        W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(z.size, -1))
+        pv, m, ldv = _block(V, "V")
+        M = self._out(W.shape[1], m) if out is None else _out_blocks(out, W.shape[1], self.n, m, "out")
+        if out is None:
+            M.zero_()
+        cnt = _i64(0)
+        _check(lib().bem_nearfield_moments_net(self._h, ctypes.byref(model), _hp(z), z.size, _hp(W), W.shape[1], pv, m,
+                                               ldv, ctypes.c_void_p(M.data_ptr()), M.stride(1),
+                                               ctypes.byref(cnt) if count_fallback else None, _stream()))
+        return (M, int(cnt.value)) if count_fallback else M
+
+    def nearfield_project(self, z, U, P, model=None):
+        """Adds U^H dT(z_j) U to the projections P (N x m x m complex128, device) in place: the
+        quadrature's correction, or the network's inside the trust region of `model` (a
+        bem_net_model)."""
+        torch = _torch()
+        z = _host_complex(z)
+        pu, m, ldu = _block(U, "U")
+        if not isinstance(P, torch.Tensor) or P.dtype != torch.complex128 or not P.is_cuda or not P.is_contiguous() \
+                or tuple(P.shape) != (z.size, m, m):
+            raise ValueError(f"P must be a contiguous ({z.size}, {m}, {m}) complex128 CUDA tensor")
+        _check(lib().bem_nearfield_project(self._h, ctypes.byref(model) if model is not None else None, _hp(z), z.size,
+                                           pu, m, ldu, ctypes.c_void_p(P.data_ptr()), _stream()))
+        return P
 
     def set_nearfield(self, eta: float):
         """Builds (eta > 0) or removes (eta = 0) the mesh's near-pair list."""
@@ -437,3 +496,83 @@ class Batch:
 
 def stream_status():
     _check(lib().bem_stream_status(_stream()))
+
+
+# ------------------------------------------------------------- learned near field
+
+
+def _dev_tensor(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def nf_labels(P9, x, kappa):
+    """dT = integral - 7-point value for each (triangle P9[s] (S x 9 or S x 3 x 3 float64),
+    target x[s] (S x 3), wavenumber kappa[s] (complex128)), by the library's quadrature."""
+    torch = _torch()
+    S = kappa.shape[0]
+    out = torch.empty(S, dtype=torch.complex128, device="cuda")
+    _check(lib().bem_nf_labels(_dev_tensor(P9.reshape(S, 9), torch.float64, (S, 9), "P9"),
+                               _dev_tensor(x, torch.float64, (S, 3), "x"),
+                               _dev_tensor(kappa, torch.complex128, (S,), "kappa"), S, ctypes.c_void_p(out.data_ptr()),
+                               _stream()))
+    return out
+
+
+def net_features(P9, x, kappa):
+    """(X (S x 32 float32 network inputs), aux (S x 4 float64: h, r0, Re kappa h, Im kappa h))."""
+    torch = _torch()
+    S = kappa.shape[0]
+    X = torch.empty((S, NET_INPUTS), dtype=torch.float32, device="cuda")
+    aux = torch.empty((S, 4), dtype=torch.float64, device="cuda")
+    _check(lib().bem_net_features(_dev_tensor(P9.reshape(S, 9), torch.float64, (S, 9), "P9"),
+                                  _dev_tensor(x, torch.float64, (S, 3), "x"),
+                                  _dev_tensor(kappa, torch.complex128, (S,), "kappa"), S, ctypes.c_void_p(X.data_ptr()),
+                                  ctypes.c_void_p(aux.data_ptr()), _stream()))
+    return X, aux
+
+
+def net_forward(params, X, out=None):
+    """FP32 forward pass: Y (B x 2) of inputs X (B x 32)."""
+    torch = _torch()
+    B = X.shape[0]
+    Y = torch.empty((B, 2), dtype=torch.float32, device="cuda") if out is None else out
+    _check(lib().bem_net_forward(_dev_tensor(params, torch.float32, (NET_PARAMS,), "params"),
+                                 _dev_tensor(X, torch.float32, (B, NET_INPUTS), "X"), B,
+                                 _dev_tensor(Y, torch.float32, (B, 2), "out"), _stream()))
+    return Y
+
+
+def net_work(B):
+    torch = _torch()
+    return torch.empty(int(lib().bem_net_work_floats(int(B))), dtype=torch.float32, device="cuda")
+
+
+def net_gradient(params, X, T, work=None, grad=None, loss=None):
+    """(grad, loss) of the mean squared error (1/B) sum (Y - T)^2 on the batch (X, T)."""
+    torch = _torch()
+    B = X.shape[0]
+    work = net_work(B) if work is None else work
+    grad = torch.empty(NET_PARAMS, dtype=torch.float32, device="cuda") if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float32, device="cuda") if loss is None else loss
+    if work.numel() < lib().bem_net_work_floats(B):
+        raise ValueError("work is too small")
+    _check(lib().bem_net_gradient(_dev_tensor(params, torch.float32, (NET_PARAMS,), "params"),
+                                  _dev_tensor(X, torch.float32, (B, NET_INPUTS), "X"),
+                                  _dev_tensor(T, torch.float32, (B, 2), "T"), B, ctypes.c_void_p(work.data_ptr()),
+                                  _dev_tensor(grad, torch.float32, (NET_PARAMS,), "grad"),
+                                  _dev_tensor(loss, torch.float32, (1,), "loss"), _stream()))
+    return grad, loss
+
+
+def net_adam(params, grad, m, v, step, lr):
+    """One Adam update of params (in place) with moment estimates m, v (in place)."""
+    torch = _torch()
+    args = [_dev_tensor(t, torch.float32, (NET_PARAMS,), n) for t, n in ((params, "params"), (grad, "grad"), (m, "m"),
+                                                                          (v, "v"))]
+    _check(lib().bem_net_adam(*args, int(step), float(lr), _stream()))
+

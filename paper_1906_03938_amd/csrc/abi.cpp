@@ -109,6 +109,7 @@ struct bem_mesh {
     // near field: host centroids and squared longest edges (the list's test), device list
     std::vector<double> nf_cen, nf_h2;
     Buffer nf_rowptr, nf_col, nf_gl;
+    Buffer net_frag, net_F, net_flag;  // learned correction: packed weights, folds, fallback flags
     int64_t nf_pairs = 0;
     double nf_eta = 0.0;
     Staging staging;
@@ -817,6 +818,157 @@ bem_status sync_status(hipStream_t s) {
 
 }  // namespace
 
+namespace {
+
+// Nodes j with a nonzero weight W[j][p] for some p in [p0, p0 + P) (W is N x Pstride, host).
+std::vector<int> active_nodes(const double *W, int64_t N, int64_t Pstride, int64_t p0, int64_t P) {
+    std::vector<int> out;
+    for (int64_t j = 0; j < N; ++j)
+        for (int64_t p = p0; p < p0 + P; ++p)
+            if (W[2 * (j * Pstride + p)] != 0.0 || W[2 * (j * Pstride + p) + 1] != 0.0) {
+                out.push_back((int)j);
+                break;
+            }
+    return out;
+}
+
+// Appends int32 values to the parameter block (packed into its doubles); returns the offset.
+size_t add_ints(Params &prm, const std::vector<int> &v) {
+    std::vector<double> d((v.size() + 1) / 2 + 1, 0.0);
+    std::memcpy(d.data(), v.data(), sizeof(int) * v.size());
+    return prm.add(d.data(), d.size());
+}
+
+// Near-field corrections of moments, M[p] += sum_j W[j][p] dT(z_j) V: by the quadrature
+// (model NULL) or by the model's network inside its trust region and the quadrature outside.
+// Each launch integrates only the nodes with a nonzero weight among its weight sets.
+bem_status nearfield_moments_impl(bem_mesh *h, const bem_net_model *model, const double *z, int64_t N,
+                                  const double *W, int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
+                                  int64_t ldm, int64_t *fallback_pairs, hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_kappas(h, z, N, "z");
+    if (st != BEM_OK) return st;
+    if (N > (int64_t)1 << 20) return fail(BEM_EINVAL, "too many nodes");
+    if (!W || P < 1 || P > (int64_t)1 << 20) return fail(BEM_EINVAL, "need W and 1 <= P <= 2^20");
+    if (!finite_c(W, N * P)) return fail(BEM_EINVAL, "W has a non-finite value");
+    if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
+    if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
+    if (model) {
+        if (!model->params || !is_device_ptr(model->params))
+            return fail(BEM_EINVAL, "model parameters are NULL or not device memory");
+        for (int i = 0; i < BEM_NET_BINS; ++i)
+            if (!(model->bin_edges[i] <= model->bin_edges[i + 1])) return fail(BEM_EINVAL, "bin edges must increase");
+    }
+    if (fallback_pairs) *fallback_pairs = 0;
+    if (h->nf_pairs == 0) return BEM_OK;  // no near pairs: nothing to add
+    Params prm;
+    const size_t off_z = prm.add(z, 2 * (size_t)N);
+    const size_t off_w = prm.add(W, 2 * (size_t)(N * P));
+    double kmax = 0.0, kre_max = 0.0, kim_max = 0.0, kre_min = 1e300;
+    for (int64_t j = 0; j < N; ++j) {
+        const cplx k(z[2 * j], z[2 * j + 1]);
+        kmax = std::max(kmax, std::abs(k));
+        kre_max = std::max(kre_max, std::abs(k.real()));
+        kim_max = std::max(kim_max, std::abs(k.imag()));
+        kre_min = std::min(kre_min, k.real());
+    }
+    // node lists per launch: network chunks of kNetMaxP and quadrature chunks of kNfFold sets
+    struct Chunk {
+        int64_t p0, P;
+        size_t off;
+        int nn;
+    };
+    std::vector<Chunk> net_chunks, quad_chunks;
+    auto plan_chunks = [&](int64_t width, std::vector<Chunk> &out) {
+        for (int64_t p0 = 0; p0 < P; p0 += width) {
+            const int64_t Pc = std::min<int64_t>(width, P - p0);
+            const std::vector<int> nodes = active_nodes(W, N, P, p0, Pc);
+            out.push_back({p0, Pc, add_ints(prm, nodes), (int)nodes.size()});
+        }
+    };
+    if (model) plan_chunks(bemrat::kNetMaxP, net_chunks);
+    plan_chunks(bemrat::kNfFold, quad_chunks);
+    const int64_t pairs = h->nf_pairs;
+    if (model) {
+        HIP_TRY(h->net_frag.ensure((size_t)bemrat::net_frag_bytes()), "packed network");
+        HIP_TRY(h->net_F.ensure(sizeof(double2) * (size_t)pairs * P), "pair folds");
+        HIP_TRY(h->net_flag.ensure((size_t)pairs), "fallback flags");
+    }
+    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
+    const double *base = h->params.as<double>();
+    const double2 *kap = reinterpret_cast<const double2 *>(base + off_z);
+    const double2 *Wd = reinterpret_cast<const double2 *>(base + off_w);
+    const int64_t *rowptr = h->nf_rowptr.as<int64_t>();
+    const int32_t *col = h->nf_col.as<int32_t>();
+    if (!model) {
+        for (const Chunk &c : quad_chunks) {
+            if (c.nn == 0) continue;
+            HIP_TRY(bemrat::launch_nearfield(h->dm, h->nf_gl.as<double>(), rowptr, col, kap, (int)N, Wd, (int)P,
+                                             (int)c.p0, (int)c.P, kmax, reinterpret_cast<const double2 *>(V), ldv, m,
+                                             reinterpret_cast<double2 *>(M), ldm, nullptr, 0,
+                                             reinterpret_cast<const int *>(base + c.off), c.nn, stream),
+                    "near-field kernel");
+        }
+        return BEM_OK;
+    }
+    double2 *F = h->net_F.as<double2>();
+    unsigned char *flag = h->net_flag.as<unsigned char>();
+    HIP_TRY(bemrat::launch_net_pack(model->params, h->net_frag.ptr, stream), "network packing kernel");
+    bemrat::NetFoldParams q{};
+    q.mesh = &h->dm;
+    q.rowptr = rowptr;
+    q.col = col;
+    q.npairs = pairs;
+    q.kappa = kap;
+    q.N = (int)N;
+    q.W = Wd;
+    q.Pstride = (int)P;
+    q.frag = h->net_frag.ptr;
+    q.params = model->params;
+    q.S_re = model->out_scale[0];
+    q.S_im = model->out_scale[1];
+    q.dmin = model->dmin;
+    q.tan_min = std::tan(model->min_angle_deg * 3.14159265358979323846 / 180.0);
+    q.kh_re_max = model->kh_re_max;
+    q.kh_im_max = model->kh_im_max;
+    q.kre_max = kre_max;
+    q.kim_max = kim_max;
+    // wavenumbers with a negative real part lie outside the trained range: quadrature for all
+    if (kre_min < 0.0) q.kh_re_max = -1.0;
+    for (int i = 0; i <= BEM_NET_BINS; ++i) q.bin_edges[i] = model->bin_edges[i];
+    for (int i = 0; i < BEM_NET_BINS; ++i) q.bin_ok[i] = model->bin_trusted[i] != 0;
+    q.F = F;
+    q.flag = flag;
+    for (const Chunk &c : net_chunks) {
+        q.p0 = (int)c.p0;
+        q.P = (int)c.P;
+        q.nodes = reinterpret_cast<const int *>(base + c.off);
+        q.nnodes = c.nn;
+        HIP_TRY(bemrat::launch_net_fold(q, stream), "network fold kernel");
+    }
+    // the pairs outside the trust region: the quadrature, folded into the same array
+    for (const Chunk &c : quad_chunks)
+        HIP_TRY(bemrat::launch_nearfield_fold(h->dm, h->nf_gl.as<double>(), rowptr, col, flag, kap, (int)N, Wd, (int)P,
+                                              (int)c.p0, (int)c.P, kmax, F, reinterpret_cast<const int *>(base + c.off),
+                                              c.nn, stream),
+                "near-field fold kernel");
+    HIP_TRY(bemrat::launch_pair_apply(h->dm, rowptr, col, F, (int)P, reinterpret_cast<const double2 *>(V), ldv, m,
+                                      reinterpret_cast<double2 *>(M), ldm, stream),
+            "pair apply kernel");
+    if (fallback_pairs) {
+        std::vector<unsigned char> fl((size_t)pairs);
+        HIP_TRY(hipMemcpyAsync(fl.data(), flag, (size_t)pairs, hipMemcpyDeviceToHost, stream), "flag download");
+        HIP_TRY(hipStreamSynchronize(stream), "stream synchronize");
+        int64_t c = 0;
+        for (unsigned char f : fl) c += f != 0;
+        *fallback_pairs = c;
+    }
+    return BEM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *bem_last_error(void) { return g_error.c_str(); }
@@ -944,6 +1096,9 @@ void bem_mesh_destroy(bem_mesh_t h) {
     h->probe.release();
     h->vmax.release();
     h->fself.release();
+    h->net_frag.release();
+    h->net_F.release();
+    h->net_flag.release();
     h->nf_rowptr.release();
     h->nf_col.release();
     h->nf_gl.release();
@@ -1409,33 +1564,7 @@ bem_status bem_mesh_nearfield(bem_mesh_t h, int64_t *pairs, int64_t *rowptr, int
 bem_status bem_nearfield_moments(bem_mesh_t h, const double *z, int64_t N, const double *W, int64_t P,
                                  const double *V, int64_t m, int64_t ldv, double *M, int64_t ldm,
                                  hipStream_t stream) {
-    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
-    DeviceGuard guard(h->device);
-    bem_status st = check_kappas(h, z, N, "z");
-    if (st != BEM_OK) return st;
-    if (N > (int64_t)1 << 20) return fail(BEM_EINVAL, "too many nodes");
-    if (!W || P < 1 || P > (int64_t)1 << 20) return fail(BEM_EINVAL, "need W and 1 <= P <= 2^20");
-    if (!finite_c(W, N * P)) return fail(BEM_EINVAL, "W has a non-finite value");
-    if ((st = check_block(V, m, ldv, "V")) != BEM_OK) return st;
-    if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
-    if (h->nf_pairs == 0) return BEM_OK;  // no near pairs: nothing to add
-    Params prm;
-    const size_t off_z = prm.add(z, 2 * (size_t)N);
-    const size_t off_w = prm.add(W, 2 * (size_t)(N * P));
-    double kmax = 0.0;
-    for (int64_t j = 0; j < N; ++j) kmax = std::max(kmax, std::abs(cplx(z[2 * j], z[2 * j + 1])));
-    if ((st = upload(h, prm, stream)) != BEM_OK) return st;
-    const double *base = h->params.as<double>();
-    for (int64_t p0 = 0; p0 < P; p0 += bemrat::kNfFold) {
-        const int Pc = (int)std::min<int64_t>(bemrat::kNfFold, P - p0);
-        HIP_TRY(bemrat::launch_nearfield(h->dm, h->nf_gl.as<double>(), h->nf_rowptr.as<int64_t>(),
-                                         h->nf_col.as<int32_t>(), reinterpret_cast<const double2 *>(base + off_z),
-                                         (int)N, reinterpret_cast<const double2 *>(base + off_w), (int)P, (int)p0, Pc,
-                                         kmax, reinterpret_cast<const double2 *>(V), ldv, m,
-                                         reinterpret_cast<double2 *>(M), ldm, nullptr, 0, stream),
-                "near-field kernel");
-    }
-    return BEM_OK;
+    return nearfield_moments_impl(h, nullptr, z, N, W, P, V, m, ldv, M, ldm, nullptr, stream);
 }
 
 bem_status bem_nearfield_sum(bem_mesh_t h, const double *z, int64_t N, const double *c, double *S, int64_t lds,
@@ -1459,7 +1588,7 @@ bem_status bem_nearfield_sum(bem_mesh_t h, const double *z, int64_t N, const dou
     HIP_TRY(bemrat::launch_nearfield(h->dm, h->nf_gl.as<double>(), h->nf_rowptr.as<int64_t>(), h->nf_col.as<int32_t>(),
                                      reinterpret_cast<const double2 *>(base + off_z), (int)N,
                                      reinterpret_cast<const double2 *>(base + off_c), 1, 0, 1, kmax, nullptr, 0, 0,
-                                     nullptr, 0, reinterpret_cast<double2 *>(S), lds, stream),
+                                     nullptr, 0, reinterpret_cast<double2 *>(S), lds, nullptr, 0, stream),
             "near-field kernel");
     return BEM_OK;
 }
@@ -1873,3 +2002,126 @@ bem_status bem_batch_last_kernel_ms(bem_batch_t b, float *ms) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- learned near field
+
+namespace {
+
+bool device_ptrs(std::initializer_list<const void *> ps) {
+    for (const void *p : ps)
+        if (!is_device_ptr(p)) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t bem_net_params(void) { return bemrat::kNetParams; }
+
+bem_status bem_nf_labels(const double *P9, const double *x, const double *kappa, int64_t S, double *out,
+                         hipStream_t stream) {
+    if (S < 1) return fail(BEM_EINVAL, "need S >= 1");
+    if (!device_ptrs({P9, x, kappa, out})) return fail(BEM_EINVAL, "P9, x, kappa and out must be device memory");
+    double gl[2 * 16 + 2 * 10];
+    gauss_legendre(16, gl, gl + 16);
+    gauss_legendre(10, gl + 32, gl + 42);
+    double r[28], rule[28];
+    radon_rule(r);  // 7 x 3 barycentric weights, then the 7 weights
+    for (int q = 0; q < 7; ++q) {
+        for (int c = 0; c < 3; ++c) rule[4 * q + c] = r[3 * q + c];
+        rule[4 * q + 3] = r[21 + q];
+    }
+    HIP_TRY(bemrat::launch_nf_labels(P9, x, reinterpret_cast<const double2 *>(kappa), S,
+                                     reinterpret_cast<double2 *>(out), gl, rule, stream),
+            "label kernel");
+    return BEM_OK;
+}
+
+bem_status bem_net_features(const double *P9, const double *x, const double *kappa, int64_t S, float *X, double *aux,
+                            hipStream_t stream) {
+    if (S < 1) return fail(BEM_EINVAL, "need S >= 1");
+    if (!device_ptrs({P9, x, kappa, X, aux})) return fail(BEM_EINVAL, "all arrays must be device memory");
+    HIP_TRY(bemrat::launch_net_features(P9, x, reinterpret_cast<const double2 *>(kappa), S, X, aux, stream),
+            "feature kernel");
+    return BEM_OK;
+}
+
+bem_status bem_net_forward(const float *params, const float *X, int64_t B, float *Y, hipStream_t stream) {
+    if (B < 1) return fail(BEM_EINVAL, "need B >= 1");
+    if (!device_ptrs({params, X, Y})) return fail(BEM_EINVAL, "params, X and Y must be device memory");
+    HIP_TRY(bemrat::launch_net_forward(params, X, B, Y, stream), "forward kernel");
+    return BEM_OK;
+}
+
+int64_t bem_net_work_floats(int64_t B) {
+    if (B < 1) return -1;
+    const int64_t slots = bemrat::net_slots(B);
+    return slots * (bemrat::kNetParams + 1);
+}
+
+bem_status bem_net_gradient(const float *params, const float *X, const float *T, int64_t B, float *work, float *grad,
+                            float *loss, hipStream_t stream) {
+    if (B < 1) return fail(BEM_EINVAL, "need B >= 1");
+    if (!device_ptrs({params, X, T, work, grad, loss}))
+        return fail(BEM_EINVAL, "params, X, T, work, grad and loss must be device memory");
+    const int64_t slots = bemrat::net_slots(B);
+    HIP_TRY(bemrat::launch_net_gradient(params, X, T, B, work, work + slots * bemrat::kNetParams, grad, loss, stream),
+            "gradient kernels");
+    return BEM_OK;
+}
+
+bem_status bem_net_adam(float *params, const float *grad, float *m, float *v, int64_t step, double lr,
+                        hipStream_t stream) {
+    if (step < 1 || !(lr > 0.0) || !std::isfinite(lr)) return fail(BEM_EINVAL, "need step >= 1 and lr > 0");
+    if (!device_ptrs({params, grad, m, v})) return fail(BEM_EINVAL, "params, grad, m and v must be device memory");
+    const double b1 = 0.9, b2 = 0.999;
+    const double c1 = 1.0 - std::pow(b1, (double)step), c2 = 1.0 - std::pow(b2, (double)step);
+    HIP_TRY(bemrat::launch_net_adam(params, grad, m, v, (float)lr, (float)b1, (float)b2, 1e-8f, (float)c1, (float)c2,
+                                    stream),
+            "Adam kernel");
+    return BEM_OK;
+}
+
+bem_status bem_nearfield_moments_net(bem_mesh_t h, const bem_net_model *model, const double *z, int64_t N,
+                                     const double *W, int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
+                                     int64_t ldm, int64_t *fallback_pairs, hipStream_t stream) {
+    if (!model) return fail(BEM_EINVAL, "model is NULL");
+    return nearfield_moments_impl(h, model, z, N, W, P, V, m, ldv, M, ldm, fallback_pairs, stream);
+}
+
+bem_status bem_nearfield_project(bem_mesh_t h, const bem_net_model *model, const double *z, int64_t N, const double *U,
+                                 int64_t m, int64_t ldu, double *Pout, hipStream_t stream) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    DeviceGuard guard(h->device);
+    bem_status st = check_kappas(h, z, N, "z");
+    if (st != BEM_OK) return st;
+    if (N > 4096) return fail(BEM_EINVAL, "at most 4096 nodes");
+    if ((st = check_block(U, m, ldu, "U")) != BEM_OK) return st;
+    if (!Pout || !is_device_ptr(Pout)) return fail(BEM_EINVAL, "Pout is not device memory");
+    if (h->nf_pairs == 0) return BEM_OK;
+    const int64_t n = h->dm.n;
+    const size_t zstride = (size_t)n * m;
+    // per-node corrections Y_j = dT(z_j) U, then Pout[j] += U^H Y_j
+    std::vector<double> eye(2 * (size_t)N * N, 0.0);
+    for (int64_t j = 0; j < N; ++j) eye[2 * (j * N + j)] = 1.0;
+    const int64_t rows_per_chunk = 4096;
+    const int nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
+    HIP_TRY(h->Z.ensure(sizeof(double2) * zstride * N), "correction workspace");
+    HIP_TRY(h->partial.ensure(sizeof(double2) * (size_t)N * nchunks * m * m), "projection workspace");
+    double2 *Y = h->Z.as<double2>();
+    HIP_TRY(hipMemsetAsync(Y, 0, sizeof(double2) * zstride * N, stream), "workspace clear");
+    if ((st = nearfield_moments_impl(h, model, z, N, eye.data(), N, U, m, ldu, reinterpret_cast<double *>(Y), m,
+                                     nullptr, stream)) != BEM_OK)
+        return st;
+    HIP_TRY(bemrat::launch_project_partial(reinterpret_cast<const double2 *>(U), ldu, Y, zstride, m, (int)N, n, m,
+                                           rows_per_chunk, nchunks, h->partial.as<double2>(), stream),
+            "projection kernel");
+    HIP_TRY(bemrat::launch_project_add(h->partial.as<double2>(), nchunks, (int)N, m, reinterpret_cast<double2 *>(Pout),
+                                       stream),
+            "projection reduction kernel");
+    return BEM_OK;
+}
+
+}  // extern "C"
+

@@ -113,10 +113,10 @@ __global__ void project_reduce_kernel(double2 *__restrict__ partial, int nchunks
     base[0] = make_double2(sr, si);
 }
 
-// out[j] = sum_l coef[j][l] Q_l, Q_l = partial[l][0]
+// out[j] (+)= sum_l coef[j][l] Q_l, Q_l = partial[l][0]
 __global__ void project_mix_kernel(const double2 *__restrict__ partial, int nchunks, int L,
                                    int64_t mm, const double2 *__restrict__ coef, int N,
-                                   double2 *__restrict__ out) {
+                                   double2 *__restrict__ out, int accumulate) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)N * mm) return;
     const int64_t j = idx / mm, e = idx % mm;
@@ -127,10 +127,40 @@ __global__ void project_mix_kernel(const double2 *__restrict__ partial, int nchu
         sr += w.x * q.x - w.y * q.y;
         si += w.x * q.y + w.y * q.x;
     }
+    if (accumulate) {
+        const double2 o = out[j * mm + e];
+        sr = o.x + sr;
+        si = o.y + si;
+    }
     out[j * mm + e] = make_double2(sr, si);
 }
 
+// out[l] += sum over chunks of partial[l][chunk], in chunk order
+__global__ void project_add_kernel(const double2 *__restrict__ partial, int nchunks, int L, int64_t mm,
+                                   double2 *__restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)L * mm) return;
+    const int64_t l = idx / mm, e = idx % mm;
+    const double2 *base = partial + l * nchunks * mm + e;
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+        sr += base[c * mm].x;
+        si += base[c * mm].y;
+    }
+    const double2 o = out[idx];
+    out[idx] = make_double2(o.x + sr, o.y + si);
+}
+
 }  // namespace
+
+hipError_t launch_project_add(const double2 *partial, int nchunks, int L, int64_t m, double2 *out,
+                              hipStream_t stream) {
+    const int64_t mm = m * m;
+    const int bs = 256;
+    hipLaunchKernelGGL(project_add_kernel, dim3((unsigned)((L * mm + bs - 1) / bs)), dim3(bs), 0, stream, partial,
+                       nchunks, L, mm, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_combine(const double2 *Z, int64_t zstride, int64_t ldz, int L, const double2 *coef,
                           int P, int64_t n, int64_t m, double2 *out, int64_t ldo, hipStream_t stream) {
@@ -156,7 +186,7 @@ hipError_t launch_project_partial(const double2 *U, int64_t ldu, const double2 *
 }
 
 hipError_t launch_project_finish(const double2 *partial, int nchunks, int L, int64_t m,
-                                 const double2 *coef, int N, double2 *out, hipStream_t stream) {
+                                 const double2 *coef, int N, double2 *out, hipStream_t stream, bool accumulate) {
     const int64_t mm = m * m;
     const int bs = 256;
     hipLaunchKernelGGL(project_reduce_kernel, dim3((unsigned)((L * mm + bs - 1) / bs)), dim3(bs), 0,
@@ -164,7 +194,7 @@ hipError_t launch_project_finish(const double2 *partial, int nchunks, int L, int
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(project_mix_kernel, dim3((unsigned)((N * mm + bs - 1) / bs)), dim3(bs), 0,
-                       stream, partial, nchunks, L, mm, coef, N, out);
+                       stream, partial, nchunks, L, mm, coef, N, out, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

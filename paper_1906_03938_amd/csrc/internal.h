@@ -135,7 +135,10 @@ hipError_t launch_project_partial(const double2 *U, int64_t ldu, const double2 *
                                   hipStream_t stream);
 hipError_t launch_project_finish(const double2 *partial, int nchunks, int L, int64_t m,
                                  const double2 *coef, int N, double2 *out,
-                                 hipStream_t stream);
+                                 hipStream_t stream, bool accumulate = false);
+// out[l] += sum over the chunks of partial[l] (the projections U^H Z_l themselves, added)
+hipError_t launch_project_add(const double2 *partial, int nchunks, int L, int64_t m, double2 *out,
+                              hipStream_t stream);
 
 // Near-field correction (nearfield.hip): M[p0 + p][a, :] += sum_j W[j][p0 + p] sum_{b in
 // row a of (rowptr, col)} (integral - 7-point value of T_ab(kappa_j)) V[b, :], p < P <= kNfFold;
@@ -147,7 +150,66 @@ constexpr int kNfFold = 8;
 hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const int64_t *rowptr,
                             const int32_t *col, const double2 *kappa, int N, const double2 *W, int Pstride,
                             int p0, int P, double kmax, const double2 *V, int64_t ldv, int64_t m,
-                            double2 *M, int64_t ldm, double2 *S, int64_t lds, hipStream_t stream);
+                            double2 *M, int64_t ldm, double2 *S, int64_t lds, const int *nodes, int nnodes,
+                            hipStream_t stream);
+
+// Near-field fold mode: the corrections of the pairs k with flag[k] != 0 only, folded with
+// weight columns p0 .. p0 + P - 1 and written to F[k * Pstride + p0 + p] (F pairs x Pstride).
+// nodes (device, nnodes entries) lists the nodes with a nonzero weight in those columns (all N
+// when null); launch_nearfield takes the same list.
+hipError_t launch_nearfield_fold(const DeviceMesh &mesh, const double *gl16, const int64_t *rowptr,
+                                 const int32_t *col, const unsigned char *flag, const double2 *kappa, int N,
+                                 const double2 *W, int Pstride, int p0, int P, double kmax, double2 *F,
+                                 const int *nodes, int nnodes, hipStream_t stream);
+// Labels of the learned correction: out[s] = integral - 7-point value of triangle P9[s] (9
+// doubles) at target x[s] (3 doubles) and wavenumber kappa[s]; gl52 the 16- and 10-point
+// Gauss-Legendre rules (nodes then weights of each), rule28 Radon's rule (3 barycentric weights
+// and the weight, per point).  Host pointers gl52 and rule28 are read before the call returns.
+hipError_t launch_nf_labels(const double *P9, const double *x, const double2 *kappa, int64_t S, double2 *out,
+                            const double *gl52, const double *rule28, hipStream_t stream);
+
+// The learned near-field correction (nfnet.hip): a perceptron 19 -> 128 -> 128 -> 128 -> 2
+// (tanh), FP32 parameters in one array (W1 [128 x 32], b1, W2 [128 x 128], b2, W3, b3,
+// W4 [2 x 128], b4).
+constexpr int kNetHidden = 128, kNetIn = 19, kNetInPad = 32, kNetOut = 2;
+constexpr int64_t kNetParams = (int64_t)kNetHidden * kNetInPad + kNetHidden +
+                               2 * ((int64_t)kNetHidden * kNetHidden + kNetHidden) + (int64_t)kNetOut * kNetHidden +
+                               kNetOut;
+constexpr int kNetBins = 8;   // distance bins of the trust region
+constexpr int kNetMaxP = 2;   // weight sets per fold launch (the host loops over chunks)
+hipError_t launch_net_features(const double *P9, const double *x, const double2 *kappa, int64_t S, float *X, double *aux,
+                               hipStream_t stream);
+int64_t net_slots(int64_t B);  // gradient slots of a batch of B samples
+hipError_t launch_net_forward(const float *params, const float *X, int64_t B, float *Y, hipStream_t stream);
+hipError_t launch_net_gradient(const float *params, const float *X, const float *T, int64_t B, float *partial,
+                               float *loss_part, float *grad, float *loss, hipStream_t stream);
+hipError_t launch_net_adam(float *params, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
+                           float eps, float c1, float c2, hipStream_t stream);
+int64_t net_frag_bytes();
+hipError_t launch_net_pack(const float *params, void *frag, hipStream_t stream);
+struct NetFoldParams {
+    const DeviceMesh *mesh;
+    const int64_t *rowptr;
+    const int32_t *col;
+    int64_t npairs;
+    const double2 *kappa;
+    int N;
+    const double2 *W;  // N x Pstride; this launch folds columns p0 .. p0 + P - 1 (P <= kNetMaxP) into F
+    int Pstride, p0, P;
+    const void *frag;
+    const float *params;
+    double S_re, S_im;
+    double dmin, tan_min, kh_re_max, kh_im_max, kre_max, kim_max;
+    double bin_edges[kNetBins + 1];
+    int bin_ok[kNetBins];
+    double2 *F;
+    unsigned char *flag;
+    const int *nodes;  // nodes with a nonzero weight in this launch's columns (all N when null)
+    int nnodes;
+};
+hipError_t launch_net_fold(const NetFoldParams &q, hipStream_t stream);
+hipError_t launch_pair_apply(const DeviceMesh &mesh, const int64_t *rowptr, const int32_t *col, const double2 *F, int P,
+                             const double2 *V, int64_t ldv, int64_t m, double2 *M, int64_t ldm, hipStream_t stream);
 
 // Static device scratch array of the allocation-free entry point (scratch.hip): 128 MiB per
 // device.  scratch_region returns the current device's copy (its address is looked up once per

@@ -57,7 +57,104 @@ struct NfArgs {
     int64_t ldm, mstride;
     double2 *S;            // dense mode (P = 1): S[a][b] += folded correction, row stride lds
     int64_t lds;
+    // fold mode (Fout non-null): only the pairs k with flag[k] != 0 are integrated, and their
+    // folded corrections are written to Fout[k * Fstride + p0 + p] instead of being applied
+    double2 *Fout;
+    const unsigned char *flag;
+    int Fstride;
+    // nodes with a nonzero weight among this launch's weight sets (all N when null): only these
+    // are integrated
+    const int *nodes;
+    int nnodes;
 };
+
+// Geometry of the polar integral of one (target, source triangle) pair: the target's height
+// |d| over the plane, and per edge the sign and size of its in-plane distance, the start and
+// width of the sinh-transformed angle panels, their number and their rule (16 or 10 points).
+struct NfGeom {
+    double ad;
+    double esg[3], eap[3], eu0[3], eh[3];
+    int enp[3], enq[3];
+};
+
+__device__ __forceinline__ void nf_geometry(const double (&P)[3][3], const double (&x)[3], double kmax, NfGeom &o) {
+    // unit normal, height and foot of x
+    const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+    const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+    double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double nn = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    for (int c = 0; c < 3; ++c) nv[c] /= nn;
+    const double d = (x[0] - P[0][0]) * nv[0] + (x[1] - P[0][1]) * nv[1] + (x[2] - P[0][2]) * nv[2];
+    o.ad = fabs(d);
+    const double xp[3] = {x[0] - d * nv[0], x[1] - d * nv[1], x[2] - d * nv[2]};
+    // per edge: sign of p, |p|, start of the u-interval, panel width and count
+    for (int e = 0; e < 3; ++e) {
+        const double *A = P[e], *B = P[(e + 1) % 3];
+        double tv[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+        const double len = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
+        for (int c = 0; c < 3; ++c) tv[c] /= len;
+        // outward in-plane normal of the edge: t x n
+        const double u[3] = {tv[1] * nv[2] - tv[2] * nv[1], tv[2] * nv[0] - tv[0] * nv[2],
+                             tv[0] * nv[1] - tv[1] * nv[0]};
+        const double ax = A[0] - xp[0], ay = A[1] - xp[1], az = A[2] - xp[2];
+        const double bx = B[0] - xp[0], by = B[1] - xp[1], bz = B[2] - xp[2];
+        const double pe = ax * u[0] + ay * u[1] + az * u[2];
+        const double sA = ax * tv[0] + ay * tv[1] + az * tv[2];
+        const double sB = bx * tv[0] + by * tv[1] + bz * tv[2];
+        const double ap = fabs(pe);
+        if (!(ap > 1e-30 * len)) {  // x' on the edge line: the fan triangle is empty
+            o.esg[e] = 0.0;
+            o.eap[e] = 0.0;
+            o.eu0[e] = 0.0;
+            o.eh[e] = 0.0;
+            o.enp[e] = 0;
+            o.enq[e] = 0;
+            continue;
+        }
+        const double u0 = asinh(sA / ap), u1 = asinh(sB / ap);
+        const double rmax = fmax(sqrt(ap * ap + sA * sA), sqrt(ap * ap + sB * sB));
+        const double want = fmax(0.5 * (u1 - u0), 0.5 * kmax * rmax);
+        const int np = want >= kNfMaxPanels ? kNfMaxPanels : (want <= 1.0 ? 1 : (int)ceil(want));
+        o.esg[e] = pe > 0.0 ? 1.0 : -1.0;
+        o.eap[e] = ap;
+        o.eu0[e] = u0;
+        o.eh[e] = (u1 - u0) / np;
+        o.enp[e] = np;
+        // an interval of at most 1 in u and 1 in phase: the nearest singularity lies pi/2
+        // away, a Bernstein ellipse of parameter 6.4 (error ~ 6.4^-20 at 10 points)
+        o.enq[e] = want <= 0.5 ? kNfGLShort : kNfGL;
+    }
+}
+
+// The angular integrals s = sum_e sign(p_e) int delta E(i kappa delta) dphi of NN wavenumbers
+// (kr + i ki) at once, over the panels of `o` (the integral over the triangle is then
+// e^{i kappa |d|} s / (4 pi)).
+template <int NN>
+__device__ __forceinline__ void nf_radial(const NfGeom &o, const double *gl, const double (&kr)[NN],
+                                          const double (&ki)[NN], double (&sr)[NN], double (&si)[NN]) {
+    const double ad = o.ad;
+    for (int e = 0; e < 3; ++e) {
+        for (int pn = 0; pn < o.enp[e]; ++pn) {
+            const double mid = o.eu0[e] + (pn + 0.5) * o.eh[e];
+            const double scale = 0.5 * o.eh[e] * o.esg[e];
+            const int nq = o.enq[e];
+            const double *glx = nq == kNfGL ? gl : gl + 2 * kNfGL;
+            for (int k = 0; k < nq; ++k) {
+                const double uu = mid + 0.5 * o.eh[e] * glx[k];
+                const double ch = cosh(uu);
+                const double rho = o.eap[e] * ch;
+                const double dl = rho * rho / (sqrt(rho * rho + ad * ad) + ad);
+                const double wt = scale * glx[nq + k] * dl / ch;
+#pragma unroll
+                for (int s = 0; s < NN; ++s) {
+                    const double2 E = exprel(-ki[s] * dl, kr[s] * dl);  // w = i kappa delta
+                    sr[s] += wt * E.x;
+                    si[s] += wt * E.y;
+                }
+            }
+        }
+    }
+}
 
 __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
     __shared__ double2 red[kNfThreads][kNfFold];
@@ -80,7 +177,7 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
         double2 *acc = red[t];
 #pragma unroll
         for (int p = 0; p < kNfFold; ++p) acc[p] = make_double2(0.0, 0.0);
-        if (i < cnt) {
+        if (i < cnt && (!g.flag || g.flag[base + i])) {
             const int64_t b = g.col[base + i];
             if (grp == 0) cols[i] = (int32_t)b;
             double P[3][3];
@@ -89,94 +186,31 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) P[v][c] = g.vtx[9 * b + 3 * v + c];
             const double x[3] = {xa.x, xa.y, xa.z};
-            // unit normal, height and foot of x
-            const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
-            const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
-            double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                            e1[0] * e2[1] - e1[1] * e2[0]};
-            const double nn = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-            for (int c = 0; c < 3; ++c) nv[c] /= nn;
-            const double d = (x[0] - P[0][0]) * nv[0] + (x[1] - P[0][1]) * nv[1] + (x[2] - P[0][2]) * nv[2];
-            const double ad = fabs(d);
-            const double xp[3] = {x[0] - d * nv[0], x[1] - d * nv[1], x[2] - d * nv[2]};
-            // per edge: sign of p, |p|, start of the u-interval, panel width and count
-            double esg[3], eap[3], eu0[3], eh[3];
-            int enp[3], enq[3];
-            for (int e = 0; e < 3; ++e) {
-                const double *A = P[e], *B = P[(e + 1) % 3];
-                double tv[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
-                const double len = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
-                for (int c = 0; c < 3; ++c) tv[c] /= len;
-                // outward in-plane normal of the edge: t x n
-                const double u[3] = {tv[1] * nv[2] - tv[2] * nv[1], tv[2] * nv[0] - tv[0] * nv[2],
-                                     tv[0] * nv[1] - tv[1] * nv[0]};
-                const double ax = A[0] - xp[0], ay = A[1] - xp[1], az = A[2] - xp[2];
-                const double bx = B[0] - xp[0], by = B[1] - xp[1], bz = B[2] - xp[2];
-                const double pe = ax * u[0] + ay * u[1] + az * u[2];
-                const double sA = ax * tv[0] + ay * tv[1] + az * tv[2];
-                const double sB = bx * tv[0] + by * tv[1] + bz * tv[2];
-                const double ap = fabs(pe);
-                if (!(ap > 1e-30 * len)) {  // x' on the edge line: the fan triangle is empty
-                    esg[e] = 0.0;
-                    eap[e] = 0.0;
-                    eu0[e] = 0.0;
-                    eh[e] = 0.0;
-                    enp[e] = 0;
-                    enq[e] = 0;
-                    continue;
-                }
-                const double u0 = asinh(sA / ap), u1 = asinh(sB / ap);
-                const double rmax = fmax(sqrt(ap * ap + sA * sA), sqrt(ap * ap + sB * sB));
-                const double want = fmax(0.5 * (u1 - u0), 0.5 * g.kmax * rmax);
-                const int np = want >= kNfMaxPanels ? kNfMaxPanels : (want <= 1.0 ? 1 : (int)ceil(want));
-                esg[e] = pe > 0.0 ? 1.0 : -1.0;
-                eap[e] = ap;
-                eu0[e] = u0;
-                eh[e] = (u1 - u0) / np;
-                enp[e] = np;
-                // an interval of at most 1 in u and 1 in phase: the nearest singularity lies
-                // pi/2 away, a Bernstein ellipse of parameter 6.4 (error ~ 6.4^-20 at 10 points)
-                enq[e] = want <= 0.5 ? kNfGLShort : kNfGL;
-            }
+            NfGeom geo;
+            nf_geometry(P, x, g.kmax, geo);
+            const double ad = geo.ad;
             // this thread's nodes j = grp + G * s, s = 0, 1, ..., taken kNfNodes at a time: the
             // geometry of each quadrature point is computed once per chunk, and the chunk's
             // independent series evaluations overlap in the pipeline
-            for (int j0 = grp; j0 < g.N; j0 += G * kNfNodes) {
+            const int nn = g.nodes ? g.nnodes : g.N;
+            for (int j0 = grp; j0 < nn; j0 += G * kNfNodes) {
                 double kr[kNfNodes], ki[kNfNodes], sr[kNfNodes], si[kNfNodes];
 #pragma unroll
                 for (int s = 0; s < kNfNodes; ++s) {
-                    const int j = j0 + s * G;
+                    const int jj = j0 + s * G;
+                    const int j = jj < nn ? (g.nodes ? g.nodes[jj] : jj) : g.N;
                     const double2 kj = j < g.N ? g.kappa[j] : make_double2(0.0, 0.0);
                     kr[s] = kj.x;
                     ki[s] = kj.y;
                     sr[s] = 0.0;
                     si[s] = 0.0;
                 }
-                for (int e = 0; e < 3; ++e) {
-                    for (int pn = 0; pn < enp[e]; ++pn) {
-                        const double mid = eu0[e] + (pn + 0.5) * eh[e];
-                        const double scale = 0.5 * eh[e] * esg[e];
-                        const int nq = enq[e];
-                        const double *glx = nq == kNfGL ? g.gl : g.gl + 2 * kNfGL;
-                        for (int k = 0; k < nq; ++k) {
-                            const double uu = mid + 0.5 * eh[e] * glx[k];
-                            const double ch = cosh(uu);
-                            const double rho = eap[e] * ch;
-                            const double dl = rho * rho / (sqrt(rho * rho + d * d) + ad);
-                            const double wt = scale * glx[nq + k] * dl / ch;
-#pragma unroll
-                            for (int s = 0; s < kNfNodes; ++s) {
-                                const double2 E = exprel(-ki[s] * dl, kr[s] * dl);  // w = i kappa delta
-                                sr[s] += wt * E.x;
-                                si[s] += wt * E.y;
-                            }
-                        }
-                    }
-                }
+                nf_radial<kNfNodes>(geo, g.gl, kr, ki, sr, si);
 #pragma unroll
                 for (int s = 0; s < kNfNodes; ++s) {
-                    const int j = j0 + s * G;
-                    if (j >= g.N) break;
+                    const int jj = j0 + s * G;
+                    if (jj >= nn) break;
+                    const int j = g.nodes ? g.nodes[jj] : jj;
                     // e^{i kappa |d|} / (4 pi)
                     double s0, c0;
                     sincos(kr[s] * ad, &s0, &c0);
@@ -217,6 +251,15 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
             fold[k][p] = s;
         }
         __syncthreads();
+        if (g.Fout) {
+            // fold mode: store the flagged pairs' folded corrections
+            for (int idx = t; idx < cnt * g.P; idx += kNfThreads) {
+                const int k = idx / g.P, p = idx % g.P;
+                if (g.flag[base + k]) g.Fout[(base + k) * g.Fstride + g.p0 + p] = fold[k][p];
+            }
+            __syncthreads();
+            continue;
+        }
         if (g.S) {
             // dense mode: add the folded corrections to the matrix (one thread per pair)
             if (t < cnt) {
@@ -251,7 +294,8 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
 hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const int64_t *rowptr,
                             const int32_t *col, const double2 *kappa, int N, const double2 *W, int Pstride,
                             int p0, int P, double kmax, const double2 *V, int64_t ldv, int64_t m,
-                            double2 *M, int64_t ldm, double2 *S, int64_t lds, hipStream_t stream) {
+                            double2 *M, int64_t ldm, double2 *S, int64_t lds, const int *nodes, int nnodes,
+                            hipStream_t stream) {
     NfArgs g;
     g.colloc = mesh.colloc;
     g.quad = mesh.quad;
@@ -274,7 +318,108 @@ hipError_t launch_nearfield(const DeviceMesh &mesh, const double *gl16, const in
     g.mstride = mesh.n * ldm;
     g.S = S;
     g.lds = lds;
+    g.Fout = nullptr;
+    g.flag = nullptr;
+    g.Fstride = 0;
+    g.nodes = nodes;
+    g.nnodes = nnodes;
     hipLaunchKernelGGL(nearfield_kernel, dim3((unsigned)mesh.n), dim3(kNfThreads), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_nearfield_fold(const DeviceMesh &mesh, const double *gl16, const int64_t *rowptr,
+                                 const int32_t *col, const unsigned char *flag, const double2 *kappa, int N,
+                                 const double2 *W, int Pstride, int p0, int P, double kmax, double2 *F,
+                                 const int *nodes, int nnodes, hipStream_t stream) {
+    NfArgs g{};
+    g.colloc = mesh.colloc;
+    g.quad = mesh.quad;
+    g.vtx = mesh.vtx;
+    g.gl = gl16;
+    g.rowptr = rowptr;
+    g.col = col;
+    g.kappa = kappa;
+    g.W = W;
+    g.N = N;
+    g.Pstride = Pstride;
+    g.p0 = p0;
+    g.P = P;
+    g.kmax = kmax;
+    g.Fout = F;
+    g.flag = flag;
+    g.Fstride = Pstride;
+    g.nodes = nodes;
+    g.nnodes = nnodes;
+    hipLaunchKernelGGL(nearfield_kernel, dim3((unsigned)mesh.n), dim3(kNfThreads), 0, stream, g);
+    return hipGetLastError();
+}
+
+namespace {
+
+// Labels for the learned correction: for sample s, the triangle P9[s] (3 vertices), the
+// target x[s] and the wavenumber kappa[s], dT = (integral of g over the triangle, by the polar
+// form above) - (Radon's 7-point value on the same triangle).  One thread per sample.
+struct NfLabelArgs {
+    const double *P9, *x;
+    const double2 *kappa;
+    double2 *out;
+    int64_t S;
+    double gl[2 * kNfGL + 2 * kNfGLShort];
+    double rule[kQuad * 4];  // barycentric weights of P0, P1, P2 and the weight (sum 1) per point
+};
+
+__global__ __launch_bounds__(256) void nf_label_kernel(NfLabelArgs g) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.S) return;
+    double P[3][3];
+    for (int v = 0; v < 3; ++v)
+        for (int c = 0; c < 3; ++c) P[v][c] = g.P9[9 * s + 3 * v + c];
+    const double x[3] = {g.x[3 * s], g.x[3 * s + 1], g.x[3 * s + 2]};
+    const double2 kap = g.kappa[s];
+    const double kr[1] = {kap.x}, ki[1] = {kap.y};
+    NfGeom geo;
+    nf_geometry(P, x, sqrt(kap.x * kap.x + kap.y * kap.y), geo);
+    double sr[1] = {0.0}, si[1] = {0.0};
+    nf_radial<1>(geo, g.gl, kr, ki, sr, si);
+    const double inv4pi = 0.25 / 3.14159265358979323846;
+    double s0, c0;
+    sincos(kap.x * geo.ad, &s0, &c0);
+    const double m0 = exp(-kap.y * geo.ad) * inv4pi;
+    double dr = m0 * (c0 * sr[0] - s0 * si[0]), di = m0 * (c0 * si[0] + s0 * sr[0]);
+    const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+    const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+    const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                 cz = e1[0] * e2[1] - e1[1] * e2[0];
+    const double area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    for (int q = 0; q < kQuad; ++q) {
+        const double *rq = g.rule + 4 * q;
+        double y[3];
+        for (int c = 0; c < 3; ++c) y[c] = rq[0] * P[0][c] + rq[1] * P[1][c] + rq[2] * P[2][c];
+        const double qx = x[0] - y[0], qy = x[1] - y[1], qz = x[2] - y[2];
+        const double r = sqrt(qx * qx + qy * qy + qz * qz);
+        double sq, cq;
+        sincos(kap.x * r, &sq, &cq);
+        const double mq = exp(-kap.y * r) * area * rq[3] * inv4pi / r;
+        dr -= mq * cq;
+        di -= mq * sq;
+    }
+    g.out[s] = make_double2(dr, di);
+}
+
+}  // namespace
+
+hipError_t launch_nf_labels(const double *P9, const double *x, const double2 *kappa, int64_t S, double2 *out,
+                            const double *gl52, const double *rule28, hipStream_t stream) {
+    NfLabelArgs g;
+    g.P9 = P9;
+    g.x = x;
+    g.kappa = kappa;
+    g.out = out;
+    g.S = S;
+    for (int i = 0; i < 2 * kNfGL + 2 * kNfGLShort; ++i) g.gl[i] = gl52[i];
+    for (int i = 0; i < kQuad * 4; ++i) g.rule[i] = rule28[i];
+    if (S <= 0) return hipSuccess;
+    hipLaunchKernelGGL(nf_label_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, stream, g);
     return hipGetLastError();
 }
 

@@ -88,12 +88,22 @@ def _assemble(mesh, z, c, flags):
     return mesh.assemble_sum(z, c, form=flags)
 
 
-def _residuals(mesh, dev, lam, X, chunk=16, nearfield=False):
+def _nearfield_add(mesh, model, z, W, Xd, out):
+    """out += sum_j W[j, p] dT(z_j) Xd: the quadrature's correction (model None) or the
+    network's inside the trust region of `model` (a nfnet.NearFieldNet)."""
+    if model is None:
+        mesh.nearfield_moments(z, W, Xd, out=out)
+    else:
+        mesh.nearfield_moments_net(model.c_model(), z, W, Xd, out=out)
+    return out
+
+
+def _residuals(mesh, dev, lam, X, chunk=16, nearfield=False, model=None):
     """Relative residuals ||T(lam_k) x_k|| / ||x_k||.  Up to `chunk` pairs share one
     bem_assemble_apply call (all their wavenumbers applied to all their vectors, the diagonal
     kept): the direct sweep generates its operators in blocks of 8, so one call per pair would
     generate 8 operators for each.  nearfield: T is the operator with the mesh's near-field
-    correction (bem_nearfield_moments with per-node weights adds dT(lam_k) X)."""
+    correction (added with per-node weights: dT(lam_k) X), by the quadrature or by `model`."""
     lam = np.asarray(lam, dtype=np.complex128)
     out = np.empty(lam.size)
     for k0 in range(0, lam.size, chunk):
@@ -101,20 +111,11 @@ def _residuals(mesh, dev, lam, X, chunk=16, nearfield=False):
         Xd = dev(X[:, k0:k1])
         Y = mesh.assemble_apply(lam[k0:k1], Xd)
         if nearfield:
-            mesh.nearfield_moments(lam[k0:k1], np.eye(k1 - k0), Xd, out=Y)
+            _nearfield_add(mesh, model, lam[k0:k1], np.eye(k1 - k0), Xd, Y)
         Y = Y.cpu().numpy()
         for k in range(k0, k1):
             out[k] = np.linalg.norm(Y[k - k0, :, k - k0]) / np.linalg.norm(X[:, k])
     return out
-
-
-def _project_correction(mesh, z, Ud):
-    """U^H dT(z_j) U for every node (N x m x m, device), dT the mesh's near-field correction:
-    from the per-node corrections dT(z_j) U (bem_nearfield_moments with identity weights)."""
-    import torch
-
-    dY = mesh.nearfield_moments(z, np.eye(len(z)), Ud)
-    return torch.matmul(Ud.conj().T.contiguous(), dY)
 
 
 class ContourSolver:
@@ -127,7 +128,11 @@ class ContourSolver:
 
         self.torch = torch
         self.mesh = mesh
-        self.nearfield = bool(nearfield)  # solve with the mesh's near-field-corrected operator
+        # solve with the mesh's near-field-corrected operator: True for the quadrature's
+        # correction, a trained nfnet.NearFieldNet for the network's (the quadrature outside its
+        # trust region; S keeps the quadrature's correction)
+        self.nf_model = nearfield if hasattr(nearfield, "c_model") else None
+        self.nearfield = self.nf_model is not None or bool(nearfield)
         self.n = mesh.n
         self.c = complex(c)
         self.radius = float(radius)
@@ -152,7 +157,7 @@ class ContourSolver:
         Xd = self._dev(X)
         M = self.mesh.contour_moments(self.z, W, Xd, form=self.sweep_flags)
         if self.nearfield:
-            self.mesh.nearfield_moments(self.z, W, Xd, out=M)
+            _nearfield_add(self.mesh, self.nf_model, self.z, W, Xd, M)
         return M.cpu().numpy()
 
     def r_lam(self, x, lam):
@@ -163,7 +168,7 @@ class ContourSolver:
         xd = self._dev(x)
         R = self.mesh.contour_moments(self.z, W, xd, form=self.sweep_flags)
         if self.nearfield:
-            self.mesh.nearfield_moments(self.z, W, xd, out=R)
+            _nearfield_add(self.mesh, self.nf_model, self.z, W, xd, R)
         k = self.torch.arange(lam.size, device=R.device)
         return R[k, :, k].T.cpu().numpy()
 
@@ -259,7 +264,7 @@ class ContourSolver:
         Ud = self._dev(U)
         P = self.mesh.rr_project(self.z, Ud, form=self.rr_flags)
         if self.nearfield:
-            P = P + _project_correction(self.mesh, self.z, Ud)
+            self.mesh.nearfield_project(self.z, Ud, P, None if self.nf_model is None else self.nf_model.c_model())
         P = P.cpu().numpy()
         Bhat = [self.w[j] * P[j] for j in range(self.N)]
         m = U.shape[1]
@@ -272,7 +277,7 @@ class ContourSolver:
         return lam, Y
 
     def residuals(self, lam, X):
-        return _residuals(self.mesh, self._dev, lam, X, nearfield=self.nearfield)
+        return _residuals(self.mesh, self._dev, lam, X, nearfield=self.nearfield, model=self.nf_model)
 
     # -- Algorithm 3 with restarts -------------------------------------------------------
     def solve(self, U0):
@@ -309,7 +314,8 @@ def eigs_in_contour(mesh, c, radius, N, U0, q=10, tol=1e-12, max_outer=30, sweep
     projections; residuals are always evaluated in FP64.  lu: where the Schur complement is
     factorised ("host", "device" or "auto", see DenseFactor).  nearfield: solve with the
     operator corrected on the mesh's near-pair list (Mesh.set_nearfield) in every sweep, in S,
-    the projections and the residuals."""
+    the projections and the residuals: True for the quadrature's correction, a trained
+    nfnet.NearFieldNet for the network's (quadrature outside its trust region and in S)."""
     return ContourSolver(mesh, c, radius, N, q=q, tol=tol, max_outer=max_outer, sweep_prec=sweep_prec,
                          rr_prec=rr_prec, lu=lu, nearfield=nearfield).solve(U0)
 
@@ -469,7 +475,7 @@ class IntervalSolver:
         Ud = self._dev(U)
         P = self.mesh.rr_project(self.z, Ud, form=self.rr_flags)
         if self.nearfield:
-            P = P + _project_correction(self.mesh, self.z, Ud)
+            self.mesh.nearfield_project(self.z, Ud, P)
         P = P.cpu().numpy()
         Bhat = np.einsum("lj,jab->lab", self.coef, P)
         A, M = self.reduced_pencil(Bhat)

@@ -27,6 +27,7 @@ __all__ = [
     "ellipsoid_batch",
     "probe_block",
     "mesh_edges_ok",
+    "nearfield_samples",
 ]
 
 
@@ -243,3 +244,78 @@ def mesh_edges_ok(tri: np.ndarray) -> bool:
     e = np.sort(e, axis=1)
     _, counts = np.unique(e, axis=0, return_counts=True)
     return bool(np.all(counts == 2))
+
+
+def _point_triangle_distance_2d(x, p, q):
+    """Distance from points x (k x 3) to the triangles (0,0,0), (1,0,0), (p,q,0) (arrays of k)."""
+    A = np.zeros((len(p), 3))
+    B = np.zeros((len(p), 3))
+    B[:, 0] = 1.0
+    C = np.stack([p, q, np.zeros_like(p)], axis=1)
+
+    def seg(a, b):
+        d = b - a
+        t = np.clip(np.einsum("ij,ij->i", x - a, d) / np.einsum("ij,ij->i", d, d), 0.0, 1.0)
+        return np.linalg.norm(x - (a + t[:, None] * d), axis=1)
+
+    # inside test of the projection by barycentric coordinates
+    xp = x.copy()
+    xp[:, 2] = 0.0
+    v0, v1, v2 = B - A, C - A, xp - A
+    d00 = np.einsum("ij,ij->i", v0, v0)
+    d01 = np.einsum("ij,ij->i", v0, v1)
+    d11 = np.einsum("ij,ij->i", v1, v1)
+    d20 = np.einsum("ij,ij->i", v2, v0)
+    d21 = np.einsum("ij,ij->i", v2, v1)
+    den = d00 * d11 - d01 * d01
+    lb = (d11 * d20 - d01 * d21) / den
+    lc = (d00 * d21 - d01 * d20) / den
+    inside = (lb >= 0.0) & (lc >= 0.0) & (lb + lc <= 1.0)
+    out = np.minimum(np.minimum(seg(A, B), seg(B, C)), seg(C, A))
+    return np.where(inside, np.abs(x[:, 2]), out)
+
+
+def nearfield_samples(count: int, seed: int, dmin: float = 0.15, rmax: float = 2.0, kh_re=(0.0, 1.0),
+                      kh_im=(-0.3, 0.3), min_angle_deg: float = 20.0, coplanar_frac: float = 0.5,
+                      coplanar_w: float = 0.1):
+    """Seeded (triangle, target, wavenumber) triples for training and validating the learned
+    near-field correction, in the unit frame of a source triangle: A = (0,0,0), B = (1,0,0)
+    (its longest edge, length 1), C = (p, q, 0) with p in [0, 1/2] and every angle at least
+    `min_angle_deg` (p, q uniform over that region); the target uniform in the ball of radius
+    `rmax` about the centroid (the near-pair test |x_a - x_b| < eta h_b with eta = rmax), with a
+    fraction `coplanar_frac` moved to heights |w| <= coplanar_w (the neighbours on a smooth
+    surface lie close to the plane), and at least `dmin` from the triangle; the wavenumber times
+    the edge length uniform in the rectangle kh_re x kh_im.  Rejection sampling from
+    numpy.random.PCG64(seed).  Returns P (count x 3 x 3), x (count x 3), kh (count, complex)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tmin = np.tan(np.deg2rad(min_angle_deg))
+    Ps, xs, ks = [], [], []
+    have = 0
+    while have < count:
+        k = 4 * (count - have) + 64
+        p = rng.uniform(0.0, 0.5, k)
+        q = rng.uniform(0.0, 0.87, k)
+        ok = (q <= np.sqrt(np.maximum(2.0 * p - p * p, 0.0))) & (q >= (1.0 - p) * tmin) & (q >= p * tmin)
+        d = rng.normal(size=(k, 3))
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        r = rmax * rng.uniform(0.0, 1.0, k) ** (1.0 / 3.0)
+        cen = np.stack([(1.0 + p) / 3.0, q / 3.0, np.zeros(k)], axis=1)
+        x = cen + r[:, None] * d
+        flat = rng.uniform(0.0, 1.0, k) < coplanar_frac
+        wz = rng.uniform(-coplanar_w, coplanar_w, k)
+        x[:, 2] = np.where(flat, wz, x[:, 2])
+        kr = rng.uniform(kh_re[0], kh_re[1], k)
+        ki = rng.uniform(kh_im[0], kh_im[1], k)
+        ok &= np.linalg.norm(x - cen, axis=1) < rmax
+        ok &= _point_triangle_distance_2d(x, p, q) >= dmin
+        idx = np.nonzero(ok)[0][: count - have]
+        P = np.zeros((idx.size, 3, 3))
+        P[:, 1, 0] = 1.0
+        P[:, 2, 0] = p[idx]
+        P[:, 2, 1] = q[idx]
+        Ps.append(P)
+        xs.append(x[idx])
+        ks.append(kr[idx] + 1j * ki[idx])
+        have += idx.size
+    return np.concatenate(Ps), np.concatenate(xs), np.concatenate(ks)
+

@@ -223,6 +223,12 @@ class SplitMesh(DenseMesh):
         S += torch.from_numpy(sum(c[j] * self._d(z[j]) for j in range(len(z))))
         return S
 
+    def nearfield_project(self, z, U, P, model=None):
+        Un = U.numpy()
+        for j in range(len(z)):
+            P[j] += torch.from_numpy(Un.conj().T @ (self._d(z[j]) @ Un))
+        return P
+
 
 @pytest.mark.parametrize("route", ["contour", "interval"])
 def test_nearfield_option_corrects_every_sweep(route):

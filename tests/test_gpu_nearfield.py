@@ -265,3 +265,28 @@ def test_interval_eigs_of_corrected_operator_match_golden(bem, torch, oracle_lib
     assert lam.size == lam_o.size and res.max() <= 1e-12
     for lo in lam_o:
         assert np.min(np.abs(lam - lo)) <= 1e-10 * abs(lo)
+
+
+def test_nearfield_project_matches_oracle(bem, torch, oracle_lib):
+    """rr_project followed by bem_nearfield_project gives the projections U^H T_nf(z_j) U of
+    the corrected operator: against the oracle's dense corrected operator (1e-12 per node, per
+    row); rows of the per-node corrections are integrated only for the nodes of each chunk."""
+    from oracle import method as M
+
+    xyz, tri = synth.icosphere(3)
+    op = M.Operator(xyz, tri, nearfield_eta=2.0)
+    U, _ = np.linalg.qr(synth.probe_block(op.n, 8, seed=4))
+    U = np.ascontiguousarray(U)
+    s, w = M.circle_nodes(4.0, 1.5, 20)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        Ud = _dev(torch, U)
+        P = mesh.rr_project(s, Ud)
+        mesh.nearfield_project(s, Ud, P)
+        P = P.cpu().numpy()
+    Po = M.rr_project(op, s, U)
+    for j in range(len(s)):
+        e = np.linalg.norm(P[j] - Po[j]) / np.linalg.norm(Po[j])
+        er = np.max(np.linalg.norm(P[j] - Po[j], axis=1) / np.linalg.norm(Po[j], axis=1))
+        assert e <= TOL and er <= TOL, (j, e, er)
+
