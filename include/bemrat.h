@@ -406,6 +406,44 @@ bem_status bem_batch_moments(bem_batch_t batch, const double *V, double *M, hipS
 bem_status bem_batch_set_timing(bem_batch_t batch, int on);
 bem_status bem_batch_last_kernel_ms(bem_batch_t batch, float *ms);
 
+/* ------------------------------------------------- dense LU of the inverse iteration --- */
+
+/* Inverse iteration on the linearised Cauchy approximation (Section 3, eq. sc2-sc5, the
+ * step of Algorithm 1) solves with one n x n matrix, the Schur complement S = M_1 (for the
+ * Chebyshev form, the matrix G of its linearisation), factorised once: P S = L U with
+ * partial (row) pivoting.  These calls factorise and solve with a dense complex matrix held
+ * in device memory; every index is formed in 64 bits, so n is limited only by memory
+ * (n = 81920 takes 107 GB).  Each is a sequence of kernel launches on `stream`; they
+ * allocate nothing.  The pivot of column j is the row i >= j with the largest
+ * |Re a_ij| + |Im a_ij| (LAPACK's zgetrf measure; ties to the smaller row).  The trailing
+ * updates run on the FP64 matrix cores (Gauss's three-multiplication complex product), so L
+ * and U agree with zgetrf's to rounding, with the same pivots except where two candidates
+ * are within rounding of each other.  Results are bitwise reproducible. */
+
+/* Device workspace in bytes of bem_lu_factor (m = 0) or of bem_lu_solve with m right-hand
+ * sides; -1 if n < 1 or m < 0. */
+int64_t bem_lu_work_bytes(int64_t n, int64_t m);
+
+/* In-place factorisation of A (device, n x n, row stride lda >= n): on return the strictly
+ * lower part holds L's multipliers, the upper part U.  ipiv (device, n int64): row ipiv[j]
+ * (0-based, >= j) was swapped with row j at step j, LAPACK's order; perm (device, n int64):
+ * their product, row i of P A is row perm[i] of A.  info (device, 1 int64) is set to 0, or
+ * to j + 1 for the first column j without a nonzero finite pivot candidate (the matrix is
+ * singular to working precision, or holds a NaN; U[j][j] is then that column's diagonal
+ * value and the factorisation continues).  work: bem_lu_work_bytes(n, 0) bytes (device).
+ * Errors: BEM_EINVAL (n < 1, lda < n, null or host pointers, work too small), BEM_EDEVICE. */
+bem_status bem_lu_factor(double *A, int64_t n, int64_t lda, int64_t *ipiv, int64_t *perm, int64_t *info,
+                         void *work, int64_t work_bytes, hipStream_t stream);
+
+/* X = A^-1 B from the factors of bem_lu_factor (LU, lda, perm) for m right-hand sides:
+ * B device n x m (row stride ldb >= m), X device n x m (row stride ldx >= m; must not
+ * overlap B); the row permutation, then forward substitution with L and backward with U.
+ * work: bem_lu_work_bytes(n, m) bytes (device).  A zero diagonal entry of U gives
+ * non-finite values in X (check the factorisation's info).
+ * Errors: BEM_EINVAL (sizes, strides, null or host pointers, work too small), BEM_EDEVICE. */
+bem_status bem_lu_solve(const double *LU, int64_t n, int64_t lda, const int64_t *perm, const double *B, int64_t ldb,
+                        double *X, int64_t ldx, int64_t m, void *work, int64_t work_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- diagnostics --- */
 
 /* Form the last sweep call on this handle used: BEM_FORM_DIRECT, BEM_FORM_EXPAND or

@@ -7,7 +7,9 @@ may import this module.  It never imports the product package.
 
 Every function below writes out the plain definition it cites.  Dense linear algebra
 (matrix products, LU, QR, the QZ algorithm) is delegated to NumPy/SciPy as library
-primitives; the BEM operator comes from the C core in bem_oracle.c.
+primitives inside the method's steps; the LU with partial pivoting is also written out
+(lu_partial_pivoting) as the reference of the library's own factorisation.  The BEM
+operator comes from the C core in bem_oracle.c.
 
 Readings of passages that are ambiguous or garbled in the paper (each one is listed in
 the design notes):
@@ -247,6 +249,53 @@ def relative_residual(op: Operator, lam, x):
 # ----------------------------------------------------------------------------------
 # Subspace construction: Algorithm 1 (corrected) inside Algorithm 3 with restarts
 # ----------------------------------------------------------------------------------
+
+
+def lu_partial_pivoting(A):
+    """Gaussian elimination with row pivoting, P A = L U, of the one matrix inverse iteration
+    factorises before its q steps (the Schur complement S of eq. sc3-sc4, or G of the
+    Chebyshev form; Section 3).  Column by column: the pivot is the row i >= j with the
+    largest |Re a_ij| + |Im a_ij| (the first of equal ones), rows j and the pivot row are
+    exchanged across the whole matrix, then every row i > j gets l_ij = a_ij / a_jj and loses
+    l_ij times row j.  Returns (LU, ipiv) in LAPACK's layout: L's multipliers below the
+    diagonal, U on and above it, ipiv[j] the row exchanged with row j at step j (0-based).
+    An all-zero candidate column leaves row j in place and its multipliers zero.  A
+    rectangular A takes min(rows, columns) steps (the pivots of the leading columns do not
+    depend on the columns after them)."""
+    A = np.array(A, dtype=np.complex128)
+    n = min(A.shape)
+    ipiv = np.zeros(n, dtype=np.int64)
+    for j in range(n):
+        col = np.abs(A[j:, j].real) + np.abs(A[j:, j].imag)
+        p = j + int(np.argmax(col))
+        ipiv[j] = p
+        if p != j:
+            A[[j, p], :] = A[[p, j], :]
+        if A[j, j] != 0:
+            A[j + 1:, j] = A[j + 1:, j] / A[j, j]
+        else:
+            A[j + 1:, j] = 0.0
+        A[j + 1:, j + 1:] -= np.outer(A[j + 1:, j], A[j, j + 1:])
+    return A, ipiv
+
+
+def lu_solve_factors(LU, ipiv, B):
+    """A^-1 B from the factors of lu_partial_pivoting: the row exchanges applied to B in
+    order, forward substitution with the unit lower L, backward substitution with U."""
+    X = np.array(B, dtype=np.complex128)
+    vec = X.ndim == 1
+    if vec:
+        X = X[:, None]
+    n = LU.shape[0]
+    for j in range(n):
+        p = int(ipiv[j])
+        if p != j:
+            X[[j, p], :] = X[[p, j], :]
+    for i in range(n):
+        X[i] -= LU[i, :i] @ X[:i]
+    for i in range(n - 1, -1, -1):
+        X[i] = (X[i] - LU[i, i + 1:] @ X[i + 1:]) / LU[i, i]
+    return X[:, 0] if vec else X
 
 
 def inverse_power_step(Bs, s, shift, v, u, S_lu=None):

@@ -34,6 +34,7 @@ EXPORTS = [
     "contour_moments_noalloc",
     "bem_net_params", "bem_nf_labels", "bem_net_features", "bem_net_forward", "bem_net_work_floats",
     "bem_net_gradient", "bem_net_adam", "bem_nearfield_moments_net", "bem_nearfield_project",
+    "bem_lu_work_bytes", "bem_lu_factor", "bem_lu_solve",
 ]
 
 NET_PARAMS = 37506
@@ -115,13 +116,17 @@ def lib():
     L.bem_nearfield_moments_net.argtypes = [_vp, ctypes.POINTER(NetModelC), _dp, _i64, _dp, _i64, _vp, _i64, _i64, _vp,
                                             _i64, ctypes.POINTER(_i64), _vp]
     L.bem_nearfield_project.argtypes = [_vp, ctypes.POINTER(NetModelC), _dp, _i64, _vp, _i64, _i64, _vp, _vp]
+    L.bem_lu_work_bytes.argtypes = [_i64, _i64]
+    L.bem_lu_factor.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _vp]
+    L.bem_lu_solve.argtypes = [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("bem_mesh_destroy", "bem_mesh_size", "bem_last_error", "bem_batch_destroy", "bem_net_params",
-                        "bem_net_work_floats"):
+                        "bem_net_work_floats", "bem_lu_work_bytes"):
             f.restype = ctypes.c_int
     L.bem_net_params.restype = _i64
     L.bem_net_work_floats.restype = _i64
+    L.bem_lu_work_bytes.restype = _i64
     if L.bem_net_params() != NET_PARAMS:
         raise ImportError("libbemrat.so was built with a different network layout")
     _lib = L
@@ -576,3 +581,44 @@ def net_adam(params, grad, m, v, step, lr):
                                                                           (v, "v"))]
     _check(lib().bem_net_adam(*args, int(step), float(lr), _stream()))
 
+
+class LU:
+    """The library's dense LU (bem_lu_factor) of a complex128 CUDA matrix A, in place: A is
+    overwritten by its factors.  solve(B) returns A^-1 B for a complex128 CUDA tensor B (n x m)."""
+
+    def __init__(self, A):
+        torch = _torch()
+        ptr, n, lda = _block(A, "A")
+        if A.shape[0] != n:
+            raise ValueError("A must be square")
+        self.A, self.n = A, n
+        self.ipiv = torch.empty(n, dtype=torch.int64, device=A.device)
+        self.perm = torch.empty(n, dtype=torch.int64, device=A.device)
+        self._info = torch.empty(1, dtype=torch.int64, device=A.device)
+        wb = lib().bem_lu_work_bytes(n, 0)
+        work = torch.empty(wb, dtype=torch.uint8, device=A.device)
+        _check(lib().bem_lu_factor(ptr, n, lda, ctypes.c_void_p(self.ipiv.data_ptr()),
+                                   ctypes.c_void_p(self.perm.data_ptr()), ctypes.c_void_p(self._info.data_ptr()),
+                                   ctypes.c_void_p(work.data_ptr()), wb, _stream()))
+        self._work = work
+
+    @property
+    def info(self) -> int:
+        """0, or j + 1 for the first column j without a nonzero finite pivot (synchronises)."""
+        return int(self._info.item())
+
+    def solve(self, B, out=None):
+        torch = _torch()
+        bp, m, ldb = _block(B, "B")
+        if B.shape[0] != self.n:
+            raise ValueError(f"B must have {self.n} rows")
+        X = torch.empty((self.n, m), dtype=torch.complex128, device=B.device) if out is None else out
+        xp, mx, ldx = _block(X, "out")
+        if X.shape[0] != self.n or mx != m:
+            raise ValueError("out must have the shape of B")
+        wb = lib().bem_lu_work_bytes(self.n, m)
+        work = torch.empty(wb, dtype=torch.uint8, device=B.device)
+        _check(lib().bem_lu_solve(ctypes.c_void_p(self.A.data_ptr()), self.n, self.A.stride(0),
+                                  ctypes.c_void_p(self.perm.data_ptr()), bp, ldb, xp, ldx, m,
+                                  ctypes.c_void_p(work.data_ptr()), wb, _stream()))
+        return X

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbemrat.so")
-SOURCES = ["abi.cpp", "mesh.hip", "sweep.hip", "sweep_lp.hip", "combine.hip", "assemble.hip", "nearfield.hip", "scratch.hip", "nfnet.hip"]
+SOURCES = ["abi.cpp", "mesh.hip", "sweep.hip", "sweep_lp.hip", "combine.hip", "assemble.hip", "nearfield.hip", "scratch.hip", "nfnet.hip", "lu.hip"]
 HEADERS = ["internal.h", "generators.h", "devmath.h"]
 
 

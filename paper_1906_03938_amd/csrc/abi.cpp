@@ -2083,6 +2083,34 @@ bem_status bem_net_adam(float *params, const float *grad, float *m, float *v, in
     return BEM_OK;
 }
 
+int64_t bem_lu_work_bytes(int64_t n, int64_t m) {
+    if (n < 1 || m < 0) return -1;
+    return m == 0 ? bemrat::lu_factor_work_bytes() : bemrat::lu_solve_work_bytes(n, m);
+}
+
+bem_status bem_lu_factor(double *A, int64_t n, int64_t lda, int64_t *ipiv, int64_t *perm, int64_t *info, void *work,
+                         int64_t work_bytes, hipStream_t stream) {
+    if (n < 1 || lda < n) return fail(BEM_EINVAL, "need n >= 1 and lda >= n");
+    if (!device_ptrs({A, ipiv, perm, info, work})) return fail(BEM_EINVAL, "A, ipiv, perm, info and work must be device memory");
+    if (work_bytes < bemrat::lu_factor_work_bytes()) return fail(BEM_EINVAL, "work is smaller than bem_lu_work_bytes(n, 0)");
+    HIP_TRY(bemrat::lu_factor(reinterpret_cast<double2 *>(A), n, lda, ipiv, perm, info, work, stream), "LU kernels");
+    return BEM_OK;
+}
+
+bem_status bem_lu_solve(const double *LU, int64_t n, int64_t lda, const int64_t *perm, const double *B, int64_t ldb,
+                        double *X, int64_t ldx, int64_t m, void *work, int64_t work_bytes, hipStream_t stream) {
+    if (n < 1 || m < 1 || lda < n || ldb < m || ldx < m) return fail(BEM_EINVAL, "need n, m >= 1, lda >= n, ldb and ldx >= m");
+    if (!device_ptrs({LU, perm, B, X, work})) return fail(BEM_EINVAL, "LU, perm, B, X and work must be device memory");
+    if (work_bytes < bemrat::lu_solve_work_bytes(n, m)) return fail(BEM_EINVAL, "work is smaller than bem_lu_work_bytes(n, m)");
+    const char *b0 = reinterpret_cast<const char *>(B), *x0 = reinterpret_cast<const char *>(X);
+    const int64_t bb = ((n - 1) * ldb + m) * 16, xb = ((n - 1) * ldx + m) * 16;
+    if (b0 < x0 + xb && x0 < b0 + bb) return fail(BEM_EINVAL, "X overlaps B");
+    HIP_TRY(bemrat::lu_solve(reinterpret_cast<const double2 *>(LU), n, lda, perm, reinterpret_cast<const double2 *>(B),
+                             ldb, reinterpret_cast<double2 *>(X), ldx, m, work, stream),
+            "LU solve kernels");
+    return BEM_OK;
+}
+
 bem_status bem_nearfield_moments_net(bem_mesh_t h, const bem_net_model *model, const double *z, int64_t N,
                                      const double *W, int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
                                      int64_t ldm, int64_t *fallback_pairs, hipStream_t stream) {

@@ -211,6 +211,14 @@ hipError_t launch_net_fold(const NetFoldParams &q, hipStream_t stream);
 hipError_t launch_pair_apply(const DeviceMesh &mesh, const int64_t *rowptr, const int32_t *col, const double2 *F, int P,
                              const double2 *V, int64_t ldv, int64_t m, double2 *M, int64_t ldm, hipStream_t stream);
 
+// Dense complex LU with partial pivoting and its solves (lu.hip).
+int64_t lu_factor_work_bytes();
+int64_t lu_solve_work_bytes(int64_t n, int64_t m);
+hipError_t lu_factor(double2 *A, int64_t n, int64_t lda, int64_t *ipiv, int64_t *perm, int64_t *info, void *work,
+                     hipStream_t stream);
+hipError_t lu_solve(const double2 *LU, int64_t n, int64_t lda, const int64_t *perm, const double2 *B, int64_t ldb,
+                    double2 *X, int64_t ldx, int64_t m, void *work, hipStream_t stream);
+
 // Static device scratch array of the allocation-free entry point (scratch.hip): 128 MiB per
 // device.  scratch_region returns the current device's copy (its address is looked up once per
 // device) and its size.

@@ -11,9 +11,8 @@ restarts from them.
 
 Every application of the BEM operator is a library sweep (contour_moments, cheb_moments, rr_project,
 bem_assemble_apply), and the n x n matrix of the inverse iteration (the Schur complement S,
-or G for the Chebyshev form) is generated densely on the device by bem_assemble_sum.  Its
-LU factorisation runs on the host through SciPy (LAPACK) for small n, or on the device
-through torch.linalg (the ROCm solver library) for large n, where the host would need hours;
+or G for the Chebyshev form) is generated densely on the device by bem_assemble_sum, and
+factorised and solved with by the library's own LU kernels (bem_lu_factor, bem_lu_solve);
 the rest of the host algebra is QR of n x nu blocks and QZ of the (N+1) nu pencil.
 
 Inverse iteration without storing the N v-blocks.  With shift s = c, d_i = z_i - s,
@@ -37,33 +36,25 @@ import scipy.linalg as sla
 
 from . import _lib
 
-# n above which the inverse iteration's LU runs on the device ("auto")
-DEVICE_LU_MIN_N = 4096
 # size of the Cauchy pencil above which Rayleigh-Ritz takes the shift-invert Arnoldi route
 DENSE_QZ_MAX = 1200
 
 
 class DenseFactor:
-    """LU factorisation of a dense n x n complex matrix held on the device, with solves for
-    host right-hand sides: on the host through SciPy ("host") or on the device through
-    torch.linalg ("device", in place: the matrix passed in is overwritten by its factors);
-    "auto" takes the device above DEVICE_LU_MIN_N unknowns."""
+    """LU factorisation P S = L U (partial pivoting) of the dense n x n complex matrix of the
+    inverse iteration, held on the device, with solves for host right-hand sides.  "device"
+    (and "auto"): the library's own kernels (bem_lu_factor, bem_lu_solve), in place -- the
+    matrix passed in is overwritten by its factors, so no second n x n array is needed, and
+    every index is 64-bit, so n is bounded by memory only.  "host": SciPy (LAPACK) on a host
+    copy, for driver tests without a GPU."""
 
     def __init__(self, S, mode="auto"):
-        import torch
-
-        self.torch = torch
-        n = S.shape[0]
-        self.mode = ("device" if n > DEVICE_LU_MIN_N else "host") if mode == "auto" else mode
+        self.mode = "device" if mode == "auto" else mode
         if self.mode == "device":
-            if n * n >= 2 ** 31:
-                # the solver library takes 32-bit sizes and leading dimensions; element offsets
-                # of a larger matrix are not guaranteed to be formed in 64 bits
-                raise ValueError(f"device LU supports n <= 46340 (n^2 < 2^31), got n = {n}")
-            # factorised in place (S is overwritten): the factors need no second n x n array
-            self.piv = torch.empty(n, dtype=torch.int32, device=S.device)
-            torch.linalg.lu_factor(S, out=(S, self.piv))
-            self.LU = S
+            self.lu = _lib.LU(S)
+            info = self.lu.info
+            if info:
+                raise np.linalg.LinAlgError(f"matrix is singular to working precision (pivot column {info - 1})")
         elif self.mode == "host":
             self.lu = sla.lu_factor(S.cpu().numpy())
         else:
@@ -73,8 +64,12 @@ class DenseFactor:
         B = np.asarray(B, dtype=np.complex128)
         if self.mode == "host":
             return sla.lu_solve(self.lu, B)
-        Bd = self.torch.from_numpy(np.ascontiguousarray(B)).to("cuda")
-        return self.torch.linalg.lu_solve(self.LU, self.piv, Bd).cpu().numpy()
+        import torch
+
+        vec = B.ndim == 1
+        Bd = torch.from_numpy(np.ascontiguousarray(B.reshape(B.shape[0], -1))).to("cuda")
+        X = self.lu.solve(Bd).cpu().numpy()
+        return X[:, 0] if vec else X
 
 
 def _assemble(mesh, z, c, flags):

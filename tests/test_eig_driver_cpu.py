@@ -41,11 +41,19 @@ class DenseMesh:
 
 
 class CpuSolver(ContourSolver):
+    """The contour driver on host tensors, its LU through SciPy (lu="host")."""
+
+    def __init__(self, *args, **kw):
+        super().__init__(*args, lu="host", **kw)
+
     def _dev(self, a):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
 
 
 class CpuIntervalSolver(IntervalSolver):
+    def __init__(self, *args, **kw):
+        super().__init__(*args, lu="host", **kw)
+
     def _dev(self, a):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
 
@@ -182,15 +190,13 @@ def test_shift_invert_ritz_equals_dense_qz():
         assert cos > 1 - 1e-9, (k, cos)
 
 
-def test_device_lu_size_guard():
-    """The device factorisation refuses matrices whose element count reaches 2^31 (the
-    solver library takes 32-bit sizes) before touching the matrix; the host mode and
-    unknown modes are checked the same way."""
+def test_dense_factor_modes():
+    """The device factorisation takes complex128 CUDA tensors only (checked before anything
+    is launched); the host mode solves; unknown modes are refused."""
     from paper_1906_03938_amd.eig import DenseFactor
 
-    S = torch.empty((46341, 1), dtype=torch.complex128)  # only the shape is read
-    with pytest.raises(ValueError, match="46340"):
-        DenseFactor(S, "device")
+    with pytest.raises(TypeError, match="CUDA"):
+        DenseFactor(torch.eye(4, dtype=torch.complex128), "device")
     with pytest.raises(ValueError, match="unknown"):
         DenseFactor(torch.eye(4, dtype=torch.complex128), "gpu")
     A = torch.from_numpy(np.array([[2.0, 1.0], [1.0, 3.0]], dtype=np.complex128))
