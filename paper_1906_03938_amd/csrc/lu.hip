@@ -13,22 +13,25 @@
 //     for each sub-panel of kSub = 32 columns s0 .. s1:
 //       for each column j: the pivot is the largest |Re a_ij| + |Im a_ij| over rows i >= j
 //       (LAPACK's izamax measure; ties to the smaller row; the search runs fused into the
-//       previous column's elimination); rows j and ipiv[j] are swapped across the outer panel; rows i > j get
-//       l_ij = a_ij / a_jj and a_ic -= l_ij a_jc for the sub-panel's columns c > j;
+//       previous column's elimination); rows j and ipiv[j] are swapped across the outer
+//       panel; rows i > j get l_ij = a_ij / a_jj and a_ic -= l_ij a_jc for the sub-panel's
+//       columns c > j;
 //       then the sub-panel's rows of the outer panel's remaining columns by forward
 //       substitution, and the rows below by a complex GEMM with K = 32;
 //     the panel's swaps are applied to every column outside it;
-//     U12 = L11^-1 A12 by blocked forward substitution (32 rows at a time);
+//     U12 = L11^-1 A12 by blocked forward substitution;
 //     A22 -= L21 U12: complex GEMM with K = kb.
 // The GEMM forms each complex product with Gauss's three real multiplications
 // (P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); Re = P1 - P2, Im = P3 - P1 - P2) on
-// v_mfma_f64_16x16x4f64, through LDS in stages of 16 k with the next stage's global loads in
-// flight during the current stage's MFMAs.
+// v_mfma_f64_16x16x4f64: 128 x 64 output tiles, 8 waves of 32 x 32 (two waves per SIMD, so
+// one wave's barrier waits and LDS reads hide behind the other's MFMAs), double-buffered LDS
+// stages of 16 k with the next stage's global loads in flight during the current MFMAs.
 //
-// Solves (forward with the unit lower L, then backward with U, 32 rows at a time): the rows'
-// product with the solved part is a split-K MFMA GEMM into partial sums, and one kernel per
-// 32-row block adds the partial sums and solves with the diagonal block (one thread per
-// right-hand side column, the block in LDS).
+// Triangular blocks (U12 above, and the solves): up to 256 rows at a time, one workgroup per
+// 8 right-hand-side columns holding the block's rows in LDS; 32-row diagonal sub-blocks are
+// solved by 32 lanes per column with shuffles, and each solved sub-block updates the block's
+// remaining rows.  The solves take the rows' product with the already solved part as a
+// split-K MFMA GEMM into partial sums, summed in a fixed order.
 #include <algorithm>
 
 #include "internal.h"
@@ -43,11 +46,13 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int kSub = 32;         // sub-panel width, triangular block size of the solves
+constexpr int kSub = 32;         // sub-panel width, diagonal sub-block of the triangular blocks
 constexpr int64_t kPanel = 256;  // outer panel width (the trailing GEMM's K)
+constexpr int kBlock = 256;      // rows of a triangular block
+constexpr int kBlockCols = 8;    // right-hand-side columns per triangular-block workgroup
 constexpr int kStageK = 16;      // k per LDS stage of the GEMM
 constexpr int kPivotBlocks = 1024;
-constexpr int64_t kSolveChunk = 1024;  // split-K chunk of the solves
+constexpr int64_t kSolveChunk = 512;  // split-K chunk of the solves
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -69,18 +74,18 @@ struct ZgemmArgs {
     double2 *part;   // split-K: part[z][M][N] = A[:, chunk z] B[chunk z, :]
 };
 
-// One workgroup of 4 waves per BM x BN output tile (blockIdx.y, blockIdx.x) and k chunk
-// (blockIdx.z); waves on a WGM x WGN grid, each owning TM x TN MFMA tiles of 16 x 16.
-// MFMA operand layout: lane (ci = lane & 15, ck = lane >> 4) holds A[ci][ck] and B[ck][ci]; the
-// result's register q holds row ck + 4 q, column ci.
+// One workgroup of WGM x WGN waves per BM x BN output tile (blockIdx.y, blockIdx.x) and k chunk
+// (blockIdx.z); each wave owns TM x TN MFMA tiles of 16 x 16.  MFMA operand layout: lane
+// (ci = lane & 15, ck = lane >> 4) holds A[ci][ck] and B[ck][ci]; the result's register q
+// holds row ck + 4 q, column ci.
 template <int WGM, int WGN, int TM, int TN>
-__global__ __launch_bounds__(256) void zgemm_kernel(ZgemmArgs g) {
-    static_assert(WGM * WGN == 4, "4 waves");
+__global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(ZgemmArgs g) {
+    constexpr int NT = 64 * WGM * WGN;
     constexpr int BM = WGM * 16 * TM, BN = WGN * 16 * TN, KS = kStageK;
-    constexpr int LA = BM * KS / 256, LB = KS * BN / 256;
-    static_assert(LA * 256 == BM * KS && LB * 256 == KS * BN, "whole staging loads");
-    __shared__ double2 sA[BM][KS + 1];
-    __shared__ double2 sB[KS][BN];
+    constexpr int LA = BM * KS / NT, LB = KS * BN / NT;
+    static_assert(LA * NT == BM * KS && LB * NT == KS * BN, "whole staging loads");
+    __shared__ double2 sA[2][BM][KS + 1];
+    __shared__ double2 sB[2][KS][BN];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63, ci = lane & 15, ck = lane >> 4;
     const int wm = w / WGN, wn = w % WGN;
     const int64_t row0 = (int64_t)blockIdx.y * BM, col0 = (int64_t)blockIdx.x * BN;
@@ -97,48 +102,54 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZgemmArgs g) {
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int l = 0; l < LA; ++l) {
-            const int idx = t + 256 * l, r = idx / KS, kk = idx % KS;
+            const int idx = t + NT * l, r = idx / KS, kk = idx % KS;
             const int64_t gr = row0 + r, gk = k0 + kk;
             ra[l] = (gr < g.M && gk < kz) ? g.A[gr * g.lda + gk] : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int l = 0; l < LB; ++l) {
-            const int idx = t + 256 * l, kk = idx / BN, c = idx % BN;
+            const int idx = t + NT * l, kk = idx / BN, c = idx % BN;
             const int64_t gk = k0 + kk, gc = col0 + c;
             rb[l] = (gk < kz && gc < g.N) ? g.B[gk * g.ldb + gc] : make_double2(0.0, 0.0);
         }
     };
-    load(ka);
-    for (int64_t k0 = ka; k0 < kz; k0 += KS) {
-        __syncthreads();  // the previous stage's reads of sA, sB are done
+    auto store = [&](int b) {
 #pragma unroll
         for (int l = 0; l < LA; ++l) {
-            const int idx = t + 256 * l;
-            sA[idx / KS][idx % KS] = ra[l];
+            const int idx = t + NT * l;
+            sA[b][idx / KS][idx % KS] = ra[l];
         }
 #pragma unroll
         for (int l = 0; l < LB; ++l) {
-            const int idx = t + 256 * l;
-            sB[idx / BN][idx % BN] = rb[l];
+            const int idx = t + NT * l;
+            sB[b][idx / BN][idx % BN] = rb[l];
         }
-        __syncthreads();
-        if (k0 + KS < kz) load(k0 + KS);
+    };
+    // Stage s is computed from buffer s & 1; after computing it a wave stores stage s + 1
+    // (loaded during stage s - 1) into the other buffer, which every wave finished reading
+    // before the previous barrier, and issues the loads of stage s + 2.
+    load(ka);
+    store(0);
+    if (ka + KS < kz) load(ka + KS);
+    __syncthreads();
+    int b = 0;
+    for (int64_t k0 = ka; k0 < kz; k0 += KS) {
 #pragma unroll
         for (int ks = 0; ks < KS; ks += 4) {
             double ar[TM], ai[TM], as[TM], br[TN], bi[TN], bs[TN];
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
-                const double2 a = sA[wm * 16 * TM + 16 * i + ci][ks + ck];
+                const double2 a = sA[b][wm * 16 * TM + 16 * i + ci][ks + ck];
                 ar[i] = a.x;
                 ai[i] = a.y;
                 as[i] = a.x + a.y;
             }
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-                const double2 b = sB[ks + ck][wn * 16 * TN + 16 * j + ci];
-                br[j] = b.x;
-                bi[j] = b.y;
-                bs[j] = b.x + b.y;
+                const double2 v = sB[b][ks + ck][wn * 16 * TN + 16 * j + ci];
+                br[j] = v.x;
+                bi[j] = v.y;
+                bs[j] = v.x + v.y;
             }
 #pragma unroll
             for (int i = 0; i < TM; ++i)
@@ -149,6 +160,12 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZgemmArgs g) {
                     P3[i][j] = mfma(as[i], bs[j], P3[i][j]);
                 }
         }
+        if (k0 + KS < kz) {
+            store(b ^ 1);
+            if (k0 + 2 * KS < kz) load(k0 + 2 * KS);
+        }
+        __syncthreads();
+        b ^= 1;
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -171,29 +188,25 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZgemmArgs g) {
             }
 }
 
-// Trailing updates: 128 x 64 tiles, waves 2 x 2 of 64 x 32.
-constexpr int kBigWGM = 2, kBigWGN = 2, kBigTM = 4, kBigTN = 2;
-constexpr int kBigBM = kBigWGM * 16 * kBigTM, kBigBN = kBigWGN * 16 * kBigTN;
-// Split-K products of the solves: 32 x 64 tiles, waves 2 x 2 of 16 x 32.
-constexpr int kSolWGM = 2, kSolWGN = 2, kSolTM = 1, kSolTN = 2;
-constexpr int kSolBM = kSolWGM * 16 * kSolTM, kSolBN = kSolWGN * 16 * kSolTN;
-static_assert(kSolBM == kSub, "a solve block is one tile row");
+// 128 x 64 tiles, 8 waves of 32 x 32.
+constexpr int kWGM = 4, kWGN = 2, kTM = 2, kTN = 2;
+constexpr int kBM = kWGM * 16 * kTM, kBN = kWGN * 16 * kTN;
 
 hipError_t gemm_sub(double2 *C, int64_t ldc, const double2 *A, int64_t lda, const double2 *B, int64_t ldb, int64_t M,
                     int64_t N, int64_t K, hipStream_t s) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
     ZgemmArgs g{C, ldc, A, lda, B, ldb, M, N, K, K, nullptr};
-    dim3 grid((unsigned)((N + kBigBN - 1) / kBigBN), (unsigned)((M + kBigBM - 1) / kBigBM), 1);
-    hipLaunchKernelGGL((zgemm_kernel<kBigWGM, kBigWGN, kBigTM, kBigTN>), grid, dim3(256), 0, s, g);
+    dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM), 1);
+    hipLaunchKernelGGL((zgemm_kernel<kWGM, kWGN, kTM, kTN>), grid, dim3(64 * kWGM * kWGN), 0, s, g);
     return hipGetLastError();
 }
 
-// part[z] = A[0:M, chunk z] B[chunk z, 0:N] for the kSolveChunk chunks of [0, K); M <= kSub.
+// part[z] = A[0:M, chunk z] B[chunk z, 0:N] for the kSolveChunk chunks z < nz of [0, K).
 hipError_t gemm_part(double2 *part, const double2 *A, int64_t lda, const double2 *B, int64_t ldb, int64_t M,
                      int64_t N, int64_t K, int nz, hipStream_t s) {
     ZgemmArgs g{nullptr, 0, A, lda, B, ldb, M, N, K, kSolveChunk, part};
-    dim3 grid((unsigned)((N + kSolBN - 1) / kSolBN), 1, (unsigned)nz);
-    hipLaunchKernelGGL((zgemm_kernel<kSolWGM, kSolWGN, kSolTM, kSolTN>), grid, dim3(256), 0, s, g);
+    dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM), (unsigned)nz);
+    hipLaunchKernelGGL((zgemm_kernel<kWGM, kWGN, kTM, kTN>), grid, dim3(64 * kWGM * kWGN), 0, s, g);
     return hipGetLastError();
 }
 
@@ -372,68 +385,109 @@ __global__ __launch_bounds__(256) void lu_init_kernel(int64_t *__restrict__ perm
     if (i == 0) *info = 0;
 }
 
-// Forward substitution with the unit lower rb x rb block L (rb <= kSub) on rows 0 .. rb of B,
-// columns [c0, c1): one thread per column, the block in LDS.  With part set, B's rows first
-// lose the sum of the nz split-K partial products part[z][r][c - c0].
-__global__ __launch_bounds__(256) void trsm_lower_kernel(const double2 *__restrict__ L, int64_t ldl,
-                                                         double2 *__restrict__ B, int64_t ldb, int rb, int64_t c0,
-                                                         int64_t c1, const double2 *__restrict__ part, int nz) {
-    __shared__ double2 sL[kSub][kSub];
-    for (int i = threadIdx.x; i < kSub * kSub; i += 256) {
-        const int r = i / kSub, q = i % kSub;
-        sL[r][q] = (r < rb && q < r) ? L[r * ldl + q] : make_double2(0.0, 0.0);
+// Triangular block solve in place: rows [0, rb) (rb <= kBlock) of X, columns [c0, c1), with the
+// rb x rb diagonal block T: unit lower (forward substitution, UPPER false) or upper with its
+// diagonal (backward substitution, UPPER true).  One workgroup per kBlockCols columns holds
+// the block's rows in LDS.  Per 32-row diagonal sub-block (top down, or bottom up): lane
+// r < 32 of column group c keeps row r of column c; for each q in order, the solved value
+// x_q is shuffled from lane q and lanes on the unsolved side subtract T[r][q] x_q (for U,
+// lane q first divides by T[q][q]).  Then each thread takes one row of the block's unsolved
+// side and subtracts its product with the sub-block's 32 solved rows, for all the columns.
+template <bool UPPER>
+__global__ __launch_bounds__(256) void block_trsm_kernel(const double2 *__restrict__ T, int64_t ldt,
+                                                         double2 *__restrict__ X, int64_t ldx, int rb, int64_t c0,
+                                                         int64_t c1) {
+    __shared__ double2 sX[kBlock][kBlockCols];
+    __shared__ double2 sD[kSub][kSub + 1];
+    const int t = threadIdx.x;
+    const int64_t cb = c0 + (int64_t)blockIdx.x * kBlockCols;
+    const int nc = (int)(c1 - cb < kBlockCols ? c1 - cb : kBlockCols);
+    for (int i = t; i < rb * kBlockCols; i += 256) {
+        const int r = i / kBlockCols, c = i % kBlockCols;
+        sX[r][c] = c < nc ? X[r * ldx + cb + c] : make_double2(0.0, 0.0);
+    }
+    const int nsub = (rb + kSub - 1) / kSub;
+    const int lane = t & 31, col = t >> 5;
+    for (int it = 0; it < nsub; ++it) {
+        const int s0 = (UPPER ? nsub - 1 - it : it) * kSub;
+        const int sn = rb - s0 < kSub ? rb - s0 : kSub;
+        __syncthreads();
+        for (int i = t; i < kSub * kSub; i += 256) {
+            const int r = i / kSub, q = i % kSub;
+            sD[r][q] = (r < sn && q < sn) ? T[(int64_t)(s0 + r) * ldt + s0 + q] : make_double2(r == q ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+        // diagonal sub-block: 32 lanes per column (8 columns = 256 threads)
+        double2 x = lane < sn ? sX[s0 + lane][col] : make_double2(0.0, 0.0);
+        if (!UPPER) {
+            for (int q = 0; q < kSub - 1; ++q) {
+                const double2 xq = make_double2(__shfl(x.x, q, 32), __shfl(x.y, q, 32));
+                if (lane > q) x = csub(x, cmul(sD[lane][q], xq));
+            }
+        } else {
+            for (int q = kSub - 1; q >= 0; --q) {
+                if (lane == q) {
+                    const double2 d = sD[q][q];
+                    const double den = d.x * d.x + d.y * d.y;
+                    x = make_double2((x.x * d.x + x.y * d.y) / den, (x.y * d.x - x.x * d.y) / den);
+                }
+                const double2 xq = make_double2(__shfl(x.x, q, 32), __shfl(x.y, q, 32));
+                if (lane < q) x = csub(x, cmul(sD[lane][q], xq));
+            }
+        }
+        if (lane < sn) sX[s0 + lane][col] = x;
+        __syncthreads();
+        // the block's unsolved rows lose their product with the solved sub-block
+        const int ra = UPPER ? 0 : s0 + sn, rz = UPPER ? s0 : rb;
+        for (int r = ra + t; r < rz; r += 256) {
+            double2 acc[kBlockCols];
+#pragma unroll
+            for (int c = 0; c < kBlockCols; ++c) acc[c] = make_double2(0.0, 0.0);
+            const double2 *Tr = T + (int64_t)r * ldt + s0;
+            for (int q = 0; q < sn; ++q) {
+                const double2 l = Tr[q];
+#pragma unroll
+                for (int c = 0; c < kBlockCols; ++c) {
+                    const double2 v = sX[s0 + q][c];
+                    acc[c].x += l.x * v.x - l.y * v.y;
+                    acc[c].y += l.x * v.y + l.y * v.x;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kBlockCols; ++c) sX[r][c] = csub(sX[r][c], acc[c]);
+        }
     }
     __syncthreads();
-    const int64_t c = c0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= c1) return;
-    const int64_t m = c1 - c0;
-    double2 x[kSub];
-#pragma unroll
-    for (int r = 0; r < kSub; ++r) {
-        x[r] = r < rb ? B[r * ldb + c] : make_double2(0.0, 0.0);
-        if (part && r < rb)
-            for (int z = 0; z < nz; ++z) x[r] = csub(x[r], part[((int64_t)z * rb + r) * m + (c - c0)]);
+    for (int i = t; i < rb * kBlockCols; i += 256) {
+        const int r = i / kBlockCols, c = i % kBlockCols;
+        if (c < nc) X[r * ldx + cb + c] = sX[r][c];
     }
-#pragma unroll
-    for (int r = 1; r < kSub; ++r) {
-#pragma unroll
-        for (int q = 0; q < r; ++q) x[r] = csub(x[r], cmul(sL[r][q], x[q]));
-        if (r - 1 < rb) B[(r - 1) * ldb + c] = x[r - 1];
-    }
-    if (rb == kSub) B[(kSub - 1) * ldb + c] = x[kSub - 1];
 }
 
-// Backward substitution with the upper rb x rb block U (diagonal included, rb <= kSub) on rows
-// 0 .. rb of B, columns [0, m), after subtracting the nz split-K partials (as above).
-__global__ __launch_bounds__(256) void trsm_upper_kernel(const double2 *__restrict__ U, int64_t ldu,
-                                                         double2 *__restrict__ B, int64_t ldb, int rb, int64_t m,
-                                                         const double2 *__restrict__ part, int nz) {
-    __shared__ double2 sU[kSub][kSub];
-    for (int i = threadIdx.x; i < kSub * kSub; i += 256) {
-        const int r = i / kSub, q = i % kSub;
-        sU[r][q] = (r < rb && q < rb && q >= r) ? U[r * ldu + q] : make_double2(r == q ? 1.0 : 0.0, 0.0);
+// X[r][c] -= sum over z < nz of part[z][r][c] (fixed order), r < rb, c < m.
+__global__ __launch_bounds__(256) void part_sum_kernel(double2 *__restrict__ X, int64_t ldx, int rb, int64_t m,
+                                                       const double2 *__restrict__ part, int nz) {
+    const int64_t item = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (item >= (int64_t)rb * m) return;
+    const int64_t r = item / m, c = item % m;
+    double sr = 0.0, si = 0.0;
+    for (int z = 0; z < nz; ++z) {
+        const double2 p = part[((int64_t)z * rb + r) * m + c];
+        sr += p.x;
+        si += p.y;
     }
-    __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= m) return;
-    double2 x[kSub];
-#pragma unroll
-    for (int r = 0; r < kSub; ++r) {
-        x[r] = r < rb ? B[r * ldb + c] : make_double2(0.0, 0.0);
-        if (part && r < rb)
-            for (int z = 0; z < nz; ++z) x[r] = csub(x[r], part[((int64_t)z * rb + r) * m + c]);
-    }
-#pragma unroll
-    for (int r = kSub - 1; r >= 0; --r) {
-#pragma unroll
-        for (int q = r + 1; q < kSub; ++q) x[r] = csub(x[r], cmul(sU[r][q], x[q]));
-        const double2 d = sU[r][r];
-        const double den = d.x * d.x + d.y * d.y;
-        x[r] = make_double2((x[r].x * d.x + x[r].y * d.y) / den, (x[r].y * d.x - x[r].x * d.y) / den);
-    }
-#pragma unroll
-    for (int r = 0; r < kSub; ++r)
-        if (r < rb) B[r * ldb + c] = x[r];
+    double2 &o = X[r * ldx + c];
+    o = make_double2(o.x - sr, o.y - si);
+}
+
+hipError_t block_trsm(bool upper, const double2 *T, int64_t ldt, double2 *X, int64_t ldx, int rb, int64_t c0,
+                      int64_t c1, hipStream_t s) {
+    const unsigned nb = (unsigned)((c1 - c0 + kBlockCols - 1) / kBlockCols);
+    if (upper)
+        hipLaunchKernelGGL(block_trsm_kernel<true>, dim3(nb), dim3(256), 0, s, T, ldt, X, ldx, rb, c0, c1);
+    else
+        hipLaunchKernelGGL(block_trsm_kernel<false>, dim3(nb), dim3(256), 0, s, T, ldt, X, ldx, rb, c0, c1);
+    return hipGetLastError();
 }
 
 // X[i][c] = B[perm[i]][c]
@@ -454,7 +508,7 @@ int64_t lu_factor_work_bytes() { return kPivotBlocks * (int64_t)(sizeof(double) 
 
 int64_t lu_solve_work_bytes(int64_t n, int64_t m) {
     const int64_t nz = (n + kSolveChunk - 1) / kSolveChunk;
-    return nz * kSub * m * (int64_t)sizeof(double2);
+    return nz * kBlock * m * (int64_t)sizeof(double2);
 }
 
 hipError_t lu_factor(double2 *A, int64_t n, int64_t lda, int64_t *ipiv, int64_t *perm, int64_t *info, void *work,
@@ -487,9 +541,9 @@ hipError_t lu_factor(double2 *A, int64_t n, int64_t lda, int64_t *ipiv, int64_t 
             // the sub-panel's rows of the outer panel's remaining columns, then the rows below
             const int64_t c1 = k + kb;
             if (c1 > s1) {
-                hipLaunchKernelGGL(trsm_lower_kernel, dim3(blocks(c1 - s1)), dim3(256), 0, s, A + s0 * lda + s0, lda,
-                                   A + s0 * lda, lda, (int)(s1 - s0), s1, c1, (const double2 *)nullptr, 0);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
+                if ((e = block_trsm(false, A + s0 * lda + s0, lda, A + s0 * lda, lda, (int)(s1 - s0), s1, c1, s)) !=
+                    hipSuccess)
+                    return e;
                 if ((e = gemm_sub(A + s1 * lda + s1, lda, A + s1 * lda + s0, lda, A + s0 * lda + s1, lda, n - s1,
                                   c1 - s1, s1 - s0, s)) != hipSuccess)
                     return e;
@@ -499,17 +553,9 @@ hipError_t lu_factor(double2 *A, int64_t n, int64_t lda, int64_t *ipiv, int64_t 
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int64_t c0 = k + kb;
         if (c0 < n) {
-            // U12 = L11^-1 A12, 32 rows at a time
-            for (int64_t r0 = k; r0 < c0; r0 += kSub) {
-                const int64_t r1 = std::min<int64_t>(r0 + kSub, c0);
-                hipLaunchKernelGGL(trsm_lower_kernel, dim3(blocks(n - c0)), dim3(256), 0, s, A + r0 * lda + r0, lda,
-                                   A + r0 * lda, lda, (int)(r1 - r0), c0, n, (const double2 *)nullptr, 0);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-                if ((e = gemm_sub(A + r1 * lda + c0, lda, A + r1 * lda + r0, lda, A + r0 * lda + c0, lda, c0 - r1,
-                                  n - c0, r1 - r0, s)) != hipSuccess)
-                    return e;
-            }
-            // A22 -= L21 U12
+            // U12 = L11^-1 A12, then A22 -= L21 U12
+            if ((e = block_trsm(false, A + k * lda + k, lda, A + k * lda, lda, (int)kb, c0, n, s)) != hipSuccess)
+                return e;
             if ((e = gemm_sub(A + c0 * lda + c0, lda, A + c0 * lda + k, lda, A + k * lda + c0, lda, n - c0, n - c0, kb,
                               s)) != hipSuccess)
                 return e;
@@ -524,31 +570,30 @@ hipError_t lu_solve(const double2 *LU, int64_t n, int64_t lda, const int64_t *pe
     hipError_t e;
     hipLaunchKernelGGL(permute_rows_kernel, dim3(blocks(n * m)), dim3(256), 0, s, B, ldb, perm, n, m, X, ldx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // L Y = P B
-    for (int64_t r0 = 0; r0 < n; r0 += kSub) {
-        const int rb = (int)std::min<int64_t>(kSub, n - r0);
-        int nz = 0;
+    // L Y = P B, kBlock rows at a time: the rows' product with the solved part (split-K
+    // partials, then their sum), then the diagonal block
+    for (int64_t r0 = 0; r0 < n; r0 += kBlock) {
+        const int rb = (int)std::min<int64_t>(kBlock, n - r0);
         if (r0 > 0) {
-            nz = (int)((r0 + kSolveChunk - 1) / kSolveChunk);
+            const int nz = (int)((r0 + kSolveChunk - 1) / kSolveChunk);
             if ((e = gemm_part(part, LU + r0 * lda, lda, X, ldx, rb, m, r0, nz, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(part_sum_kernel, dim3(blocks((int64_t)rb * m)), dim3(256), 0, s, X + r0 * ldx, ldx, rb,
+                               m, (const double2 *)part, nz);
         }
-        hipLaunchKernelGGL(trsm_lower_kernel, dim3(blocks(m)), dim3(256), 0, s, LU + r0 * lda + r0, lda, X + r0 * ldx,
-                           ldx, rb, (int64_t)0, m, nz ? part : nullptr, nz);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = block_trsm(false, LU + r0 * lda + r0, lda, X + r0 * ldx, ldx, rb, 0, m, s)) != hipSuccess) return e;
     }
     // U X = Y, from the bottom
-    for (int64_t r0 = (n - 1) / kSub * kSub; r0 >= 0; r0 -= kSub) {
-        const int rb = (int)std::min<int64_t>(kSub, n - r0);
+    for (int64_t r0 = (n - 1) / kBlock * kBlock; r0 >= 0; r0 -= kBlock) {
+        const int rb = (int)std::min<int64_t>(kBlock, n - r0);
         const int64_t k0 = r0 + rb;
-        int nz = 0;
         if (k0 < n) {
-            nz = (int)((n - k0 + kSolveChunk - 1) / kSolveChunk);
+            const int nz = (int)((n - k0 + kSolveChunk - 1) / kSolveChunk);
             if ((e = gemm_part(part, LU + r0 * lda + k0, lda, X + k0 * ldx, ldx, rb, m, n - k0, nz, s)) != hipSuccess)
                 return e;
+            hipLaunchKernelGGL(part_sum_kernel, dim3(blocks((int64_t)rb * m)), dim3(256), 0, s, X + r0 * ldx, ldx, rb,
+                               m, (const double2 *)part, nz);
         }
-        hipLaunchKernelGGL(trsm_upper_kernel, dim3(blocks(m)), dim3(256), 0, s, LU + r0 * lda + r0, lda, X + r0 * ldx,
-                           ldx, rb, m, nz ? part : nullptr, nz);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = block_trsm(true, LU + r0 * lda + r0, lda, X + r0 * ldx, ldx, rb, 0, m, s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
