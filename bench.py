@@ -148,7 +148,48 @@ def precision_form():
         forms[name]["speedup_vs_f64"] = forms[name]["value"] / base
     return {"workload": w["name"], "mesh": f"box 1.0x0.8x0.6, face grid 126x101x76, n={n}",
             "interval": [w["a"], w["b"]], "nodes": w["N"], "m": w["m"], "call": "cheb_moments, all N blocks",
-            "forms": forms, "eigen_box752": eig}
+            "forms": forms, "eigen_box752": eig, "equal_accuracy": equal_accuracy()}
+
+
+def equal_accuracy(counts=(50, 40, 30)):
+    """The whole interval eigen-solve (Chebyshev route, [6.5, 8], N = 24, 8 probes, seed 3, q = 10)
+    on the 1.0 x 0.8 x 0.6 box of 4 (nx ny + nx nz + ny nz) triangles (n = 18,800 for the
+    default grid) with every sweep in FP64, and with the subspace sweeps in FP32 or BF16 and
+    the Rayleigh-Ritz projections in FP64, each stopped at relative residual 1e-6; the
+    eigenvalue error of each against an FP64 solve stopped at 1e-12, and the wall time of each
+    solve (G assembled and factorised on the device included)."""
+    import numpy as np
+    import torch
+
+    import paper_1906_03938_amd as bem
+    import synth
+    from paper_1906_03938_amd.eig import eigs_in_interval
+
+    xyz, tri = synth.box_surface((1.0, 0.8, 0.6), counts)
+    n = tri.shape[0]
+    U0 = synth.probe_block(n, 8, seed=3)
+    out = {"mesh": f"box 1.0x0.8x0.6, face grid {counts[0]}x{counts[1]}x{counts[2]}, n={n}",
+           "interval": [6.5, 8.0], "nodes": 24, "probes": 8, "tol": 1e-6, "runs": {}}
+    with bem.Mesh(xyz, tri) as mesh:
+        lam_ref, _, _, _ = eigs_in_interval(mesh, 6.5, 8.0, 24, U0, q=10, tol=1e-12, max_outer=8)
+        out["reference_eigenvalues"] = [[float(l.real), float(l.imag)] for l in lam_ref]
+        for name, sp in (("f64", bem.PREC_F64), ("f32_sweeps_f64_rr", bem.PREC_F32),
+                         ("bf16_sweeps_f64_rr", bem.PREC_BF16)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lam, _, res, outer = eigs_in_interval(mesh, 6.5, 8.0, 24, U0, q=10, tol=1e-6, max_outer=8, sweep_prec=sp,
+                                                  rr_prec=bem.PREC_F64)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            err = (float(np.max(np.abs(np.sort_complex(lam) - np.sort_complex(lam_ref)) / np.abs(lam_ref)))
+                   if lam.size == lam_ref.size else None)
+            out["runs"][name] = {"seconds": t, "found": int(lam.size), "rel_err_vs_f64_1e-12": err,
+                                 "max_rel_residual": float(res.max()) if res.size else None,
+                                 "outer_iterations": int(outer)}
+    f64 = out["runs"]["f64"]["seconds"]
+    for r in out["runs"].values():
+        r["speedup_vs_f64"] = f64 / r["seconds"]
+    return out
 
 
 BATCH_WORKLOAD = dict(name="ellipsoids-64", count=64, seed=4, freq=(10, 44), axes=(0.5, 1.5), centre=(3.0, 7.0),
@@ -196,10 +237,36 @@ def batched_form():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kms = batch.last_kernel_ms()
+    eager_out = out.clone()
     L = batch.operators.astype(np.float64)
     units = float(np.sum(w["N"] * sizes ** 2 * w["m"]))
     flops = float(np.sum(8.0 * L * sizes ** 2 * w["m"]))
     achieved = flops / (kms * 1e-3) / 1e12
+    # the same call captured once in a HIP graph (the path a serving loop takes) and replayed;
+    # timing events are off so the capture holds only the call's own kernels
+    batch.set_timing(False)
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        batch.moments(Vd, out=out)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.moments(Vd, out=out)
+    graph.replay()
+    torch.cuda.synchronize()
+    replay_ms = []
+    for _ in range(2):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        e1.synchronize()
+        replay_ms.append(e0.elapsed_time(e1))
+    graph_ms = float(np.median(replay_ms))
+    graph_equal = bool(torch.equal(out, eager_out))
+    batch.set_timing(True)
     # the same moments by one call per mesh
     Vs = [torch.from_numpy(v).to("cuda") for v in V]
     outs = [torch.empty((w["P"], int(n), w["m"]), dtype=torch.complex128, device="cuda") for n in sizes]
@@ -251,6 +318,9 @@ def batched_form():
         "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
         "per_mesh_calls": {"seconds": wall_seq, "value": units / wall_seq},
         "speedup_vs_per_mesh_calls": wall_seq / wall,
+        "graph_replay": {"ms": graph_ms, "value": units / (graph_ms * 1e-3),
+                         "speedup_vs_per_mesh_calls": wall_seq / (graph_ms * 1e-3),
+                         "bitwise_equal_to_eager": graph_equal},
         "max_rel_diff_vs_per_mesh_calls": diff,
         "reduced_precision": lp,
     }
@@ -260,15 +330,14 @@ def batched_form():
     return res
 
 
-def large_eigen(freq):
-    """Eigen-extraction at large n (opt-in, --large-eigen F): the class-I geodesic unit sphere of
-    frequency F (n = 20 F^2; F = 45 gives n = 40500, near the largest n the device LU takes),
-    circle |z - 5| = 2, N = 64 nodes, 32 probes (seed 2), q = 10, tol 1e-12; the Schur
-    complement generated densely on the device and factorised there (in place).  Reports the
-    eigenvalues with their relative residuals, the outer iterations, the times of the
-    assembly, of assembly + factorisation and of the whole solve, and the distance of each
-    eigenvalue to the nearest interior Dirichlet eigenvalue of the unit sphere (the
-    discretisation error)."""
+def large_eigen(level):
+    """Eigen-extraction at large n (opt-in, --large-eigen L): the unit icosphere of level L
+    (n = 20 4^L; L = 6 is the sweep's n = 81920), circle |z - 5| = 2, N = 64 nodes, 32 probes
+    (seed 2), q = 10, tol 1e-12; the Schur complement generated densely on the device and
+    factorised there in place by the library's LU.  Reports the eigenvalues with their
+    relative residuals, the outer iterations, the times of the assembly, of the
+    factorisation and of the whole solve, and the distance of each eigenvalue to the nearest
+    interior Dirichlet eigenvalue of the unit sphere (the discretisation error)."""
     import numpy as np
     import torch
 
@@ -298,7 +367,7 @@ def large_eigen(freq):
                   f"({', '.join(f'{k} {v:.0f} s' for k, v in phase.items())})", file=sys.stderr, flush=True)
             return res
 
-    xyz, tri = synth.geodesic_sphere(freq)
+    xyz, tri = synth.icosphere(level)
     n = tri.shape[0]
     tab = np.loadtxt(os.path.join(ROOT, "tests", "golden", "sphere_dirichlet_eigs.txt"))
     t0 = time.perf_counter()
@@ -314,11 +383,130 @@ def large_eigen(freq):
         torch.cuda.synchronize()
     total = time.perf_counter() - t0
     dist = [float(np.min(np.abs(l - tab[:, 0]))) for l in lam]
-    return {"workload": f"geodesic unit sphere, frequency {freq}, n={n}", "contour": "|z - 5| = 2, N = 64", "m": 32,
+    return {"workload": f"unit icosphere level {level}, n={n}", "contour": "|z - 5| = 2, N = 64", "m": 32,
             "eigenvalues": [[float(l.real), float(l.imag)] for l in lam], "count": int(lam.size),
             "max_rel_residual": float(res.max()) if res.size else None, "outer_iterations": int(outer),
             "assembly_seconds": t_asm, "assembly_plus_device_lu_seconds": t_lu, "total_seconds": total,
             "phase_seconds": phase, "max_distance_to_sphere_eigenvalue": max(dist) if dist else None}
+
+
+def learned_near_field(freq=158, train_count=400_000, steps=20000):
+    """The learned near-field correction on the harmonic sphere of 20 freq^2 triangles (seed 5;
+    n = 499,280 at freq 158), contour |z - 5| = 1.5, N = 32 nodes, P = 2 moments, m = 64 probes
+    (seed 5), near pairs within 2 longest edges.  Trains the network on the GPU (seeded samples
+    labelled by the library's quadrature), then times, on the mesh, the folded moment sweep
+    once and the correction with the quadrature and with the network (median of 3), and
+    compares the corrected moments: |M_net - M_quad| / |M_quad| per moment (the quadrature
+    is the judge), beside the uncorrected moments' distance from the same judge."""
+    import numpy as np
+    import torch
+
+    import paper_1906_03938_amd as bem
+    import synth
+    from paper_1906_03938_amd import nfnet
+
+    t0 = time.perf_counter()
+    net = nfnet.train(train_count=train_count, val_count=50_000, seed=31, steps=steps, batch=2048, bound=0.25)
+    t_train = time.perf_counter() - t0
+    xyz, tri = synth.harmonic_sphere(freq, seed=5)
+    n = len(tri)
+    z, w, W = bem.contour_nodes(5.0, 1.5, 32, P=2)
+    V = torch.from_numpy(synth.probe_block(n, 64, seed=5)).to("cuda")
+    res = {"workload": f"harmonic sphere f={freq}, n={n}", "contour": "|z - 5| = 1.5, N = 32, P = 2", "m": 64,
+           "train_samples": train_count, "train_steps": steps, "train_seconds": t_train,
+           "train_loss_first_last": [net.history[0][1], net.history[-1][1]],
+           "bins_trusted": net.bin_trusted, "bin_validation_error": net.bin_error}
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        res["pairs"] = int(mesh.nearfield_list()[1].size)
+        mesh.set_timing(True)
+        M = mesh.contour_moments(z, W, V)  # once: about 40 s of kernel time at n = 499,280
+        res["sweep_ms"] = mesh.last_kernel_ms()
+        res["sweep_form"] = {bem.FORM_DIRECT: "direct", bem.FORM_EXPAND: "expand"}.get(mesh.last_form()[0], "other")
+        mesh.set_timing(False)
+        Mq = torch.zeros_like(M)
+        Mn = torch.zeros_like(M)
+
+        def timed(f, out):
+            f(out)
+            ms = []
+            for _ in range(3):
+                out.zero_()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                f(out)
+                e1.record()
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            return float(np.median(ms))
+
+        model = net.c_model()
+        res["quadrature_ms"] = timed(lambda o: mesh.nearfield_moments(z, W, V, out=o), Mq)
+        res["network_ms"] = timed(lambda o: mesh.nearfield_moments_net(model, z, W, V, out=o), Mn)
+        _, fb = mesh.nearfield_moments_net(model, z, W, V, out=torch.zeros_like(M), count_fallback=True)
+        res["fallback_pairs"] = int(fb)
+        res["network_speedup"] = res["quadrature_ms"] / res["network_ms"]
+        full_q, full_n, none = M + Mq, M + Mn, M
+        res["moment_error_network_vs_quadrature"] = [
+            float(torch.linalg.vector_norm(full_n[p] - full_q[p]) / torch.linalg.vector_norm(full_q[p])) for p in range(2)]
+        res["moment_error_uncorrected_vs_quadrature"] = [
+            float(torch.linalg.vector_norm(none[p] - full_q[p]) / torch.linalg.vector_norm(full_q[p])) for p in range(2)]
+        res["correction_error_network"] = [
+            float(torch.linalg.vector_norm(Mn[p] - Mq[p]) / torch.linalg.vector_norm(Mq[p])) for p in range(2)]
+    print(f"bench: learned near field: quadrature {res['quadrature_ms']:.1f} ms, network {res['network_ms']:.1f} ms",
+          file=sys.stderr, flush=True)
+    return res
+
+
+def dense_lu(n=32768, m=64):
+    """The inverse iteration's dense LU (bem_lu_factor, bem_lu_solve) on a seeded n x n complex
+    Gaussian matrix (torch's Philox generator, seed 1): factorisation time and rate counted as
+    8/3 n^3 real flops (the complex LU's flops; the GEMM issues 3/4 of them as MFMA work),
+    one solve with m right-hand sides and its relative residual, and the ROCm solver library's
+    factorisation of the same matrix (torch.linalg.lu_factor; it takes 32-bit sizes, so only
+    for n^2 < 2^31) for comparison."""
+    import torch
+
+    from paper_1906_03938_amd import _lib
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    A0 = torch.complex(torch.randn((n, n), dtype=torch.float64, device="cuda", generator=g),
+                       torch.randn((n, n), dtype=torch.float64, device="cuda", generator=g))
+    B = torch.complex(torch.randn((n, m), dtype=torch.float64, device="cuda", generator=g),
+                      torch.randn((n, m), dtype=torch.float64, device="cuda", generator=g))
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    A = A0.clone()
+    torch.cuda.synchronize()
+    e0.record()
+    lu = _lib.LU(A)
+    e1.record()
+    X = lu.solve(B)
+    e2.record()
+    torch.cuda.synchronize()
+    t_f, t_s = e0.elapsed_time(e1) * 1e-3, e1.elapsed_time(e2)
+    res = (torch.linalg.matrix_norm(A0 @ X - B) / (torch.linalg.matrix_norm(A0) * torch.linalg.matrix_norm(X))).item()
+    flops = 8.0 / 3.0 * n ** 3
+    out = {"n": n, "matrix": "complex Gaussian, torch Philox seed 1", "info": lu.info, "factor_seconds": t_f,
+           "factor_tflops": flops / t_f / 1e12, "flop_count": "8/3 n^3", "fp64_mfma_peak_tflops": 78.6,
+           "frac_of_peak": flops / t_f / 1e12 / 78.6, "mfma_issued_frac": 0.75 * flops / t_f / 1e12 / 78.6,
+           "solve_m": m, "solve_ms": t_s, "solve_rel_residual": res}
+    del lu, X
+    print(f"bench: dense LU n = {n}: {t_f:.2f} s", file=sys.stderr, flush=True)
+    if n * n < 2 ** 31:
+        A.copy_(A0)
+        piv = torch.empty(n, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        e0.record()
+        torch.linalg.lu_factor(A, out=(A, piv))
+        e1.record()
+        torch.cuda.synchronize()
+        t_r = e0.elapsed_time(e1) * 1e-3
+        out["rocsolver_factor_seconds"] = t_r
+        out["speedup_vs_rocsolver"] = t_r / t_f
+    del A, A0, B
+    torch.cuda.empty_cache()
+    return out
 
 
 def near_field(mesh, U, z, W, sweep_kernel_ms, eta=2.0, freq=158):
@@ -403,9 +591,13 @@ def main():
     ap.add_argument("--no-precision-form", action="store_true")
     ap.add_argument("--no-batched-form", action="store_true")
     ap.add_argument("--no-near-field", action="store_true")
-    ap.add_argument("--large-eigen", type=int, default=0, metavar="F",
-                    help="also run the eigen-extraction on the geodesic sphere of frequency F (n = 20 F^2) "
-                         "with the LU on the device")
+    ap.add_argument("--no-dense-lu", action="store_true")
+    ap.add_argument("--no-learned-near-field", action="store_true")
+    ap.add_argument("--dense-lu-only", type=int, default=0, metavar="N",
+                    help="only run the dense LU section at size N and print its JSON")
+    ap.add_argument("--large-eigen", type=int, default=0, metavar="L",
+                    help="also run the eigen-extraction on the unit icosphere of level L (n = 20 4^L; "
+                         "L = 6: n = 81920, about 8 minutes) with the library's LU")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -414,6 +606,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep's multi-GPU "
               "row split is a design note, not built.", file=sys.stderr)
         sys.exit(2)
+    if args.dense_lu_only:
+        print(json.dumps({"dense_lu": dense_lu(args.dense_lu_only)}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -575,6 +770,12 @@ def main():
     if not args.no_batched_form:
         out["batched_form"] = batched_form()
         progress("batched form done")
+    if not args.no_learned_near_field:
+        out["learned_near_field"] = learned_near_field()
+        progress("learned near field done")
+    if not args.no_dense_lu:
+        out["dense_lu"] = dense_lu()
+        progress("dense LU done")
     if args.large_eigen:
         out["large_eigen"] = large_eigen(args.large_eigen)
     if not args.no_cpu_baseline:

@@ -424,9 +424,11 @@ Plan make_plan(const bem_mesh *h, const double *z, int64_t N, int64_t m, uint32_
         plan.L = Lc;
         plan.c = c;
         plan.R = R;
-        // a multiple of 8 (the recurrence runs 8 steps per trip) at least need + 10 and at
-        // least the block's top index
-        plan.miller_M = std::max((need + 10 + 7) / 8 * 8, Lc);
+        // a multiple of 8 (the recurrence runs 8 steps per trip) at least need + 10 (FP64
+        // and FP32: Bessel values to a few units of 1e-16) or need (BF16 and FP16: to 2e-10,
+        // against the 1e-5 / 1e-6 truncation) and at least the block's top index
+        const bool lp16 = prec == bemrat::Prec::BF16 || prec == bemrat::Prec::F16;
+        plan.miller_M = std::max((need + (lp16 ? 0 : 10) + 7) / 8 * 8, Lc);
         plan.Cf.resize((size_t)N * Lc);
         const cplx ipow[4] = {cplx(1, 0), cplx(0, 1), cplx(-1, 0), cplx(0, -1)};
         for (int64_t j = 0; j < N; ++j) {
@@ -522,12 +524,21 @@ bool symmetrize(Plan &plan) {
         perm.push_back(b);
         perm.push_back(conj[b]);
     }
+    // every quadruple's real parts must be mirror images about one centre c (the generator
+    // forms exp(i x' r) as exp(2icr) conj(exp(i x r))), to 4 units of rounding of |z| (a phase
+    // error of at most 8 eps |z|_max r)
+    const double c0 = 0.5 * (plan.kappa[perm[0]].real() + plan.kappa[perm[2]].real());
+    for (int g = 0; g < N; g += 4) {
+        const double mid = 0.5 * (plan.kappa[perm[g]].real() + plan.kappa[perm[g + 2]].real());
+        if (std::abs(mid - c0) > tol) return false;
+    }
     std::vector<cplx> kap(N);
     for (int l = 0; l < N; ++l) kap[l] = plan.kappa[perm[l]];
     plan.kappa = kap;
     plan.Cf.assign((size_t)N * N, 0.0);
     for (int l = 0; l < N; ++l) plan.Cf[(size_t)perm[l] * N + l] = 1.0;
     plan.gen = bemrat::Gen::DirectSym;
+    plan.c = cplx(c0, 0.0);
     return true;
 }
 

@@ -63,6 +63,28 @@ __host__ __device__ __forceinline__ void sincos_cw(double x, double &s, double &
     c = __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, cy) ^ flip);
 }
 
+// Sine and cosine for entries that are rounded to BF16 or FP16 afterwards: the argument is
+// reduced in FP64 to t = x/(2 pi) - rint(x/(2 pi)) in [-1/2, 1/2] revolutions (the product's
+// rounding, |x| 2^-53/(2 pi), is below 2^-33 revolutions for the admissible |x| <= 1e6) and
+// evaluated by the FP32 hardware sine and cosine, which take revolutions.  Absolute error
+// 1.2e-7 (measured on the device over [-1/2, 1/2] against FP64), against relative roundings
+// of 2^-9 (BF16) and 2^-12 (FP16) of the entries.
+__device__ __forceinline__ void sincos_lowp(double x, double &s, double &c) {
+    const double t = x * 0.15915494309189535;
+    const float f = (float)(t - rint(t));
+    s = (double)__builtin_amdgcn_sinf(f);
+    c = (double)__builtin_amdgcn_cosf(f);
+}
+
+// sincos_cw, or sincos_lowp for entries bound to a 16-bit type.
+template <bool LOWP>
+__device__ __forceinline__ void sincos_gen(double x, double &s, double &c) {
+    if constexpr (LOWP)
+        sincos_lowp(x, s, c);
+    else
+        sincos_cw(x, s, c);
+}
+
 // exp(x): reduce by ln 2 to |y| <= ln2/2, exp(x) = 2^k exp(y).
 __host__ __device__ __forceinline__ double exp_cw(double x) {
     constexpr double log2e = 1.4426950408889634;

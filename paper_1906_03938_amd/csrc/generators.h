@@ -1,6 +1,8 @@
 // Operator-entry generators shared by the FP64 sweep and the reduced-precision sweep:
 // for one (target row, source triangle) and the 7 quadrature points, the entries of a block
 // of NOPS consecutive coefficient operators (Direct, Taylor or Chebyshev family), in FP64.
+// With LOWP (entries bound for a BF16 or FP16 contraction) the sines and cosines come from
+// the FP32 hardware after an FP64 reduction (sincos_lowp), 1.2e-7 absolute.
 #pragma once
 
 #include <type_traits>
@@ -59,11 +61,11 @@ __device__ __forceinline__ double rsqrt_pos(double a) {
 
 // Entries of the NOPS operators L0 .. L0 + NOPS - 1 at one (row, triangle) off the
 // diagonal, from the distances r_q and weights w_q / r_q of the 7 quadrature points.
-template <int NOPS, Gen GEN, bool DECAY>
+template <int NOPS, Gen GEN, bool DECAY, bool LOWP = false>
 struct Generator;
 
-template <int NOPS, bool DECAY>
-struct Generator<NOPS, Gen::Direct, DECAY> {
+template <int NOPS, bool DECAY, bool LOWP>
+struct Generator<NOPS, Gen::Direct, DECAY, LOWP> {
     double kr[NOPS], ki[NOPS];
     __device__ void init(const SweepArgs &p, int L0) {
 #pragma unroll
@@ -82,7 +84,7 @@ struct Generator<NOPS, Gen::Direct, DECAY> {
             for (int q = 0; q < kQuad; ++q) {
                 const double e = DECAY ? exp_cw(-ki[j] * r[q]) * wr[q] : wr[q];
                 double sn, cs;
-                sincos_cw(kr[j] * r[q], sn, cs);
+                sincos_gen<LOWP>(kr[j] * r[q], sn, cs);
                 gr = fma(e, cs, gr);
                 gi = fma(e, sn, gi);
             }
@@ -92,17 +94,21 @@ struct Generator<NOPS, Gen::Direct, DECAY> {
 };
 
 // Direct form on quadruples of nodes {x + iy, x - iy, x' + iy, x' - iy} (operators 4g .. 4g + 3
-// of the block, in that order; a circle centred on the real axis with N a multiple of 4 and
-// the half-step offset is made of them): per quadrature point the quadruple takes one
-// exp(-y r), its reciprocal exp(+y r) (hardware estimate and two Newton steps), and the sincos
-// of x r and of x' r -- four operators for what one node of the plain direct form costs plus
-// a second sincos.  Every node is still its own operator, contracted on its own.
-template <int NOPS, bool DECAY>
-struct Generator<NOPS, Gen::DirectSym, DECAY> {
+// of the block, in that order) whose real parts are mirror images about one centre c on the
+// real axis, x' = 2c - x (a circle centred on the real axis with N a multiple of 4 and the
+// half-step offset is made of them; c in c_re): per quadrature point the block takes
+// exp(2icr) once, and each quadruple one exp(-y r), its reciprocal exp(+y r) (hardware
+// estimate and two Newton steps) and the sincos of x r, with exp(i x' r) = exp(2icr) times
+// the conjugate of exp(i x r) -- four operators for what one node of the plain direct form
+// costs.  Every node is still its own operator, contracted on its own.
+template <int NOPS, bool DECAY, bool LOWP>
+struct Generator<NOPS, Gen::DirectSym, DECAY, LOWP> {
     static_assert(NOPS % 4 == 0, "whole quadruples per block");
     static constexpr int NQ = NOPS / 4;
-    double xa[NQ], xb[NQ], y[NQ];
+    double xa[NQ], y[NQ];
+    double c2;
     __device__ void init(const SweepArgs &p, int L0) {
+        c2 = 2.0 * p.c_re;
 #pragma unroll
         for (int g = 0; g < NQ; ++g) {
             // a quadruple beyond L (L a multiple of 4) repeats the first: its operators are
@@ -110,7 +116,6 @@ struct Generator<NOPS, Gen::DirectSym, DECAY> {
             const int l = L0 + 4 * g < p.L ? L0 + 4 * g : L0;
             xa[g] = p.kappa[l].x;
             y[g] = p.kappa[l].y;
-            xb[g] = p.kappa[l + 2].x;
         }
     }
     __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
@@ -120,6 +125,8 @@ struct Generator<NOPS, Gen::DirectSym, DECAY> {
         for (int j = 0; j < NOPS; ++j) gr[j] = gi[j] = 0.0;
 #pragma unroll
         for (int q = 0; q < kQuad; ++q) {
+            double sc, cc;  // exp(2icr)
+            sincos_gen<LOWP>(c2 * r[q], sc, cc);
 #pragma unroll
             for (int g = 0; g < NQ; ++g) {
                 const double E = exp_cw(-y[g] * r[q]);
@@ -127,17 +134,17 @@ struct Generator<NOPS, Gen::DirectSym, DECAY> {
                 Ei = fma(fma(-E, Ei, 1.0), Ei, Ei);
                 Ei = fma(fma(-E, Ei, 1.0), Ei, Ei);
                 const double e1 = E * wr[q], e2 = Ei * wr[q];
-                double s1, c1, s2, c2;
-                sincos_cw(xa[g] * r[q], s1, c1);
-                sincos_cw(xb[g] * r[q], s2, c2);
+                double s1, c1;
+                sincos_gen<LOWP>(xa[g] * r[q], s1, c1);
+                const double c2v = fma(cc, c1, sc * s1), s2v = fma(sc, c1, -(cc * s1));
                 gr[4 * g] = fma(e1, c1, gr[4 * g]);
                 gi[4 * g] = fma(e1, s1, gi[4 * g]);
                 gr[4 * g + 1] = fma(e2, c1, gr[4 * g + 1]);
                 gi[4 * g + 1] = fma(e2, s1, gi[4 * g + 1]);
-                gr[4 * g + 2] = fma(e1, c2, gr[4 * g + 2]);
-                gi[4 * g + 2] = fma(e1, s2, gi[4 * g + 2]);
-                gr[4 * g + 3] = fma(e2, c2, gr[4 * g + 3]);
-                gi[4 * g + 3] = fma(e2, s2, gi[4 * g + 3]);
+                gr[4 * g + 2] = fma(e1, c2v, gr[4 * g + 2]);
+                gi[4 * g + 2] = fma(e1, s2v, gi[4 * g + 2]);
+                gr[4 * g + 3] = fma(e2, c2v, gr[4 * g + 3]);
+                gi[4 * g + 3] = fma(e2, s2v, gi[4 * g + 3]);
             }
         }
 #pragma unroll
@@ -150,8 +157,8 @@ struct Generator<NOPS, Gen::DirectSym, DECAY> {
 // y0 = w/r exp(i c r) x^L0 / L0! and the block-uniform c_j = L0! / (L0 + j)!, which with
 // i^j is applied once to the sum over the points.  The power x^j is a running product, so
 // no per-operator factor can be hoisted out of the point loop and kept live.
-template <int NOPS, bool DECAY>
-struct Generator<NOPS, Gen::Taylor, DECAY> {
+template <int NOPS, bool DECAY, bool LOWP>
+struct Generator<NOPS, Gen::Taylor, DECAY, LOWP> {
     static constexpr int B = NOPS;  // L0 = z B
     int z;
     double inv_fact;                // 1 / L0!
@@ -194,7 +201,7 @@ struct Generator<NOPS, Gen::Taylor, DECAY> {
             const double x = xq[q], pw = pwq[q];
             const double e = (DECAY ? exp_cw(-p.c_im * r[q]) * wr[q] : wr[q]) * pw;
             double sn, cs;
-            sincos_cw(p.c_re * r[q], sn, cs);
+            sincos_gen<LOWP>(p.c_re * r[q], sn, cs);
             const double yr = e * cs, yi = e * sn;
             // sum_q y x^j (c_j and i^j are applied once per operator below)
             double xp = x;
@@ -227,8 +234,8 @@ struct Generator<NOPS, Gen::Taylor, DECAY> {
 // advanced by x^8 (the chain's last power times x) and the factorial ratios continue, so
 // the transcendental work per point is paid once for 16 operators.  When the second half
 // lies beyond L (L a multiple of 8) it is skipped and returned as zeros.
-template <bool DECAY>
-struct Generator<16, Gen::Taylor, DECAY> {
+template <bool DECAY, bool LOWP>
+struct Generator<16, Gen::Taylor, DECAY, LOWP> {
     int z, L0;
     double inv_fact;  // 1 / L0!
     __device__ void init(const SweepArgs &p, int L0_) {
@@ -250,7 +257,7 @@ struct Generator<16, Gen::Taylor, DECAY> {
             }
             const double e = (DECAY ? exp_cw(-p.c_im * r[q]) * wr[q] : wr[q]) * pw;
             double sn, cs;
-            sincos_cw(p.c_re * r[q], sn, cs);
+            sincos_gen<LOWP>(p.c_re * r[q], sn, cs);
             xq[q] = x;
             yr[q] = e * cs;
             yi[q] = e * sn;
@@ -422,8 +429,8 @@ struct FoldGenerator<NOPS, Gen::Direct, DECAY> {
 // values are scaled down by 2^-400 if they exceed 2^400 (they grow like M! (2/x)^M for
 // small x; eight steps grow them by less than 2^250 for x >= 1e-7 and M <= 96), and a
 // factor f carries that scaling to the block's values stored earlier.
-template <int NOPS, bool DECAY>
-struct Generator<NOPS, Gen::Cheb, DECAY> {
+template <int NOPS, bool DECAY, bool LOWP>
+struct Generator<NOPS, Gen::Cheb, DECAY, LOWP> {
     int L0, M;
     __device__ void init(const SweepArgs &p, int L0_) {
         L0 = L0_;
@@ -494,7 +501,7 @@ struct Generator<NOPS, Gen::Cheb, DECAY> {
             rs = fma(fma(-S[q], rs, 1.0), rs, rs);
             const double nrm = f[q] * rs;
             double sn, cs;
-            sincos_cw(p.c_re * r[Q0 + q], sn, cs);
+            sincos_gen<LOWP>(p.c_re * r[Q0 + q], sn, cs);
             const double yr = wr[Q0 + q] * cs * nrm, yi = wr[Q0 + q] * sn * nrm;
 #pragma unroll
             for (int j = 0; j < NOPS; ++j) {

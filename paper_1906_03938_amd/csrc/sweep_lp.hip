@@ -5,10 +5,11 @@
 // entries of stage s + 1 while consumer waves 4-7 contract stage s through double-buffered
 // LDS), with these differences:
 // * The producer generates in FP64 (the shared generators; on gfx950 FP32 and FP64 vector
-//   instructions issue at the same rate when packed FP32 is not used), then scales the
-//   entries by a_scale (which keeps them inside the FP16 range) and rounds the real part,
-//   the imaginary part and their sum (Gauss's three-multiplication product) to the
-//   contraction type.  The probe rows are scaled by 1 / max |V| (computed on the device by
+//   instructions issue at the same rate when packed FP32 is not used; for BF16 and FP16 the
+//   sines and cosines come from the FP32 hardware after an FP64 reduction), with the entry
+//   scale a_scale (which keeps them inside the FP16 range) folded into the point weights,
+//   and rounds the real part, the imaginary part and their sum (Gauss's
+//   three-multiplication product) to the contraction type.  The probe rows are scaled by 1 / max |V| (computed on the device by
 //   absmax_kernel before the sweep, so any probe block stays inside the FP16 range) and
 //   rounded the same way when staged; the epilogue undoes both scales.
 // * Diagonal entries are stored as zero: the exact FP64 self terms are added afterwards by
@@ -116,7 +117,7 @@ __device__ __forceinline__ void sweep_lp_tile(const SweepArgs &p, int64_t row0, 
         const double4 xa = ld<CAST>(p.colloc, grow);
         const double scale = p.a_scale;
         const float vs = (float)(1.0 / vscale_of(p.vmax));
-        Generator<NOPS, GEN, DECAY> gen;
+        Generator<NOPS, GEN, DECAY, P != Prec::F32> gen;
         gen.init(p, L0);
         // staged probe element i of this thread: stage triangle (tid + 256 i) / NC, column
         // tid % NC (256 is a multiple of NC); kept in FP32, as it is rounded anyway
@@ -150,16 +151,19 @@ __device__ __forceinline__ void sweep_lp_tile(const SweepArgs &p, int64_t row0, 
                 }
                 if (tid < QN && it + 1 < nstages) sQ[buf ^ 1][tid] = rq;
                 const bool diag = it * kStage + btri == grow;
+                // the entry scale rides on the point weights (every generator is linear in
+                // them); the diagonal gets weight 0 (it is added in FP64 afterwards)
+                const double s = diag ? 0.0 : scale;
                 double r[kQuad], wr[kQuad];
 #pragma unroll
                 for (int q = 0; q < kQuad; ++q) {
                     const double4 y = sQ[buf][btri * kQuad + q];
                     const double dx = xa.x - y.x, dy = xa.y - y.y, dz = xa.z - y.z;
                     double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    r2 = diag ? 1.0 : r2;  // the diagonal is added in FP64 afterwards
+                    r2 = diag ? 1.0 : r2;
                     const double rinv = rsqrt_pos(r2);
                     r[q] = r2 * rinv;
-                    wr[q] = y.w * rinv;
+                    wr[q] = y.w * s * rinv;
                 }
                 if (it + 1 < nstages) {
 #pragma unroll
@@ -171,10 +175,9 @@ __device__ __forceinline__ void sweep_lp_tile(const SweepArgs &p, int64_t row0, 
                 if (tid < QN && it + 2 < nstages) rq = ld<CAST>(p.quad, (it + 2) * QN + tid);
                 double2 a[NOPS];
                 gen.entries(r, wr, p, a);
-                const double s = diag ? 0.0 : scale;
 #pragma unroll
                 for (int j = 0; j < NOPS; ++j) {
-                    const float ar = (float)(a[j].x * s), ai = (float)(a[j].y * s);
+                    const float ar = (float)a[j].x, ai = (float)a[j].y;
                     sA[buf][a_index<K16>(j, 0, brow, btri)] = LP::cvt(ar);
                     sA[buf][a_index<K16>(j, 1, brow, btri)] = LP::cvt(ai);
                     sA[buf][a_index<K16>(j, 2, brow, btri)] = LP::cvt(ar + ai);

@@ -73,14 +73,12 @@ class DenseFactor:
 
 
 def _assemble(mesh, z, c, flags):
-    """sum_j c_j T(z_j) on the device: generated directly in FP64 (bem_assemble_sum), or, when
-    the sweeps run at reduced precision, by one sweep of the identity at that precision."""
-    if flags & _lib.PREC_MASK:
-        import torch
-
-        eye = torch.eye(mesh.n, dtype=torch.complex128, device="cuda")
-        return mesh.contour_moments(z, np.asarray(c, dtype=np.complex128)[:, None], eye, form=flags)[0]
-    return mesh.assemble_sum(z, c, form=flags)
+    """sum_j c_j T(z_j) on the device, generated directly in FP64 (bem_assemble_sum) with the
+    sweeps' form.  The matrix the LU factorises stays FP64 when the sweeps run at reduced
+    precision: the inverse iteration's subspace is then as accurate as those sweeps, and the
+    matrix costs one generation pass instead of a reduced-precision sweep of the n x n
+    identity."""
+    return mesh.assemble_sum(z, c, form=flags & ~_lib.PREC_MASK)
 
 
 def _nearfield_add(mesh, model, z, W, Xd, out):

@@ -11,7 +11,8 @@
   block's values recorded on the way down, normalised by J_0 + 2 sum J_2k = 1) and of the
   host's choice of the start index M (10 above the truncation length of the tail bound, rounded
   up to a multiple of 8), against scipy.special.jv over the admissible x = beta r in
-  (1e-7, beta diam], within 1.5e-15 absolute (the values are at most 1).
+  (1e-7, beta diam], within 1.5e-15 absolute (the values are at most 1); and, for BF16 and
+  FP16 entries, M at the truncation length itself, within 1e-8.
 """
 import os
 import shutil
@@ -121,3 +122,22 @@ def test_miller_recurrence_matches_scipy(xmax, tol):
             worst = max(worst, float(np.max(np.abs(np.array(got) - ref))))
     print(f"x <= {xmax:.3f}, L = {L}, M = {M}: max |J - jv| = {worst:.2e}")
     assert worst <= 1.5e-15
+
+
+@pytest.mark.parametrize("xmax,tol", [(1.0, 1e-5), (3.0 * np.sqrt(2.0), 1e-5), (6.0, 1e-6), (12.0, 1e-5),
+                                      (12.0, 1e-6), (30.0, 1e-6)])
+def test_miller_recurrence_16bit_start(xmax, tol):
+    """For BF16 and FP16 entries (truncation tolerances 1e-5 and 1e-6) the recurrence starts at
+    the truncation length itself (no margin above it, rounded up to a multiple of 8): the
+    Bessel values it forms stay within 1e-8 of scipy's, far below the 2^-9 / 2^-12 rounding of
+    the entries."""
+    L, need = _cheb_length(xmax, 8, tol)
+    M = max((need + 7) // 8 * 8, L)
+    xs = np.concatenate([[1e-7, 1e-4, 1e-2], np.linspace(0.05, xmax, 200)])
+    worst = 0.0
+    for x in xs:
+        for L0 in range(0, L, 8):
+            got = _miller_block(float(x), M, L0, 8)
+            worst = max(worst, float(np.max(np.abs(np.array(got) - jv(np.arange(L0, L0 + 8), x)))))
+    print(f"x <= {xmax:.3f}, tol {tol}: L = {L}, M = {M}: max |J - jv| = {worst:.2e}")
+    assert worst <= 1e-8
