@@ -390,11 +390,12 @@ def large_eigen(level):
             "phase_seconds": phase, "max_distance_to_sphere_eigenvalue": max(dist) if dist else None}
 
 
-def learned_near_field(freq=158, train_count=400_000, steps=20000):
+def learned_near_field(freq=158, train_count=2_000_000, steps=40000):
     """The learned near-field correction on the harmonic sphere of 20 freq^2 triangles (seed 5;
     n = 499,280 at freq 158), contour |z - 5| = 1.5, N = 32 nodes, P = 2 moments, m = 64 probes
-    (seed 5), near pairs within 2 longest edges.  Trains the network on the GPU (seeded samples
-    labelled by the library's quadrature), then times, on the mesh, the folded moment sweep
+    (seed 5), near pairs within 2 longest edges.  Trains the network on the GPU with the
+    training driver's defaults (2 M seeded samples labelled by the library's quadrature,
+    100 k for validation, 40,000 Adam steps of 2048, trust bound 0.2), then times, on the mesh, the folded moment sweep
     once and the correction with the quadrature and with the network (median of 3), and
     compares the corrected moments: |M_net - M_quad| / |M_quad| per moment (the quadrature
     is the judge), beside the uncorrected moments' distance from the same judge."""
@@ -406,7 +407,7 @@ def learned_near_field(freq=158, train_count=400_000, steps=20000):
     from paper_1906_03938_amd import nfnet
 
     t0 = time.perf_counter()
-    net = nfnet.train(train_count=train_count, val_count=50_000, seed=31, steps=steps, batch=2048, bound=0.25)
+    net = nfnet.train(train_count=train_count, val_count=100_000, seed=31, steps=steps, batch=2048)
     t_train = time.perf_counter() - t0
     xyz, tri = synth.harmonic_sphere(freq, seed=5)
     n = len(tri)
@@ -595,6 +596,9 @@ def main():
     ap.add_argument("--no-learned-near-field", action="store_true")
     ap.add_argument("--dense-lu-only", type=int, default=0, metavar="N",
                     help="only run the dense LU section at size N and print its JSON")
+    ap.add_argument("--only", default="", metavar="SECTIONS",
+                    help="only run the named sections (comma-separated: precision_form, batched_form, "
+                         "learned_near_field, dense_lu, eigen_check) and print their JSON")
     ap.add_argument("--large-eigen", type=int, default=0, metavar="L",
                     help="also run the eigen-extraction on the unit icosphere of level L (n = 20 4^L; "
                          "L = 6: n = 81920, about 8 minutes) with the library's LU")
@@ -608,6 +612,18 @@ def main():
         sys.exit(2)
     if args.dense_lu_only:
         print(json.dumps({"dense_lu": dense_lu(args.dense_lu_only)}), flush=True)
+        return
+    if args.only:
+        sections = {"precision_form": precision_form, "batched_form": batched_form,
+                    "learned_near_field": learned_near_field, "dense_lu": dense_lu, "eigen_check": eigen_check}
+        res = {}
+        for name in args.only.split(","):
+            if name not in sections:
+                print(f"unknown section {name!r}; known: {', '.join(sections)}", file=sys.stderr)
+                sys.exit(2)
+            res[name] = sections[name]()
+            print(f"bench: {name} done", file=sys.stderr, flush=True)
+        print(json.dumps(res), flush=True)
         return
 
     import numpy as np
