@@ -447,6 +447,16 @@ def learned_near_field(freq=158, train_count=2_000_000, steps=40000):
         _, fb = mesh.nearfield_moments_net(model, z, W, V, out=torch.zeros_like(M), count_fallback=True)
         res["fallback_pairs"] = int(fb)
         res["network_speedup"] = res["quadrature_ms"] / res["network_ms"]
+        # the network frozen at the contour centre (one evaluation per pair), freeze_tol 1e-2
+        fmodel = net.frozen(1e-2).c_model()
+        Mfz = torch.zeros_like(M)
+        res["frozen_ms"] = timed(lambda o: mesh.nearfield_moments_net(fmodel, z, W, V, out=o), Mfz)
+        _, fbf = mesh.nearfield_moments_net(fmodel, z, W, V, out=torch.zeros_like(M), count_fallback=True)
+        res["frozen_fallback_pairs"] = int(fbf)
+        res["frozen_speedup"] = res["quadrature_ms"] / res["frozen_ms"]
+        res["moment_error_frozen_vs_quadrature"] = [
+            float(torch.linalg.vector_norm((M + Mfz)[p] - (M + Mq)[p]) / torch.linalg.vector_norm((M + Mq)[p]))
+            for p in range(2)]
         full_q, full_n, none = M + Mq, M + Mn, M
         res["moment_error_network_vs_quadrature"] = [
             float(torch.linalg.vector_norm(full_n[p] - full_q[p]) / torch.linalg.vector_norm(full_q[p])) for p in range(2)]

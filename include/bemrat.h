@@ -322,13 +322,21 @@ bem_status bem_net_adam(float *params, const float *grad, float *m, float *v, in
  * the source triangle's longest edge h) from the triangle, whose triangle has every angle at
  * least min_angle_deg, with max_j |Re kappa_j| h <= kh_re_max, max_j |Im kappa_j| h <= kh_im_max,
  * every Re kappa_j >= 0, and whose distance falls in a bin [bin_edges[i], bin_edges[i+1]) with
- * bin_trusted[i] != 0, use the network; every other pair the quadrature. */
+ * bin_trusted[i] != 0, use the network; every other pair the quadrature.
+ * freeze_tol: 0 evaluates the network at every node z_j.  A positive value evaluates it once
+ * per pair, at the centre c of the nodes' bounding box, for the pairs (inside the region above)
+ * with s k h^2 <= freeze_tol, s = max_j |z_j - c|, k = max_j |z_j|: the correction is then
+ * dT(c) at every node (dT depends on kappa only through the 7-point rule's error on the
+ * smooth part of the kernel, so s k h^2 estimates its relative change over the nodes), and it
+ * folds as dT(c) sum_j W[j][p]; the other pairs take the quadrature.  One evaluation per pair
+ * instead of one per node. */
 typedef struct {
     const float *params;               /* device, BEM_NET_PARAMS floats */
     double out_scale[2];               /* S_re, S_im */
     double dmin, min_angle_deg, kh_re_max, kh_im_max;
     double bin_edges[BEM_NET_BINS + 1];
     int bin_trusted[BEM_NET_BINS];
+    double freeze_tol;
 } bem_net_model;
 
 /* As bem_nearfield_moments, with the corrections of the pairs inside the model's trust region

@@ -46,7 +46,8 @@ class NetModelC(ctypes.Structure):
     """The C struct bem_net_model (include/bemrat.h)."""
     _fields_ = [("params", ctypes.c_void_p), ("out_scale", ctypes.c_double * 2), ("dmin", ctypes.c_double),
                 ("min_angle_deg", ctypes.c_double), ("kh_re_max", ctypes.c_double), ("kh_im_max", ctypes.c_double),
-                ("bin_edges", ctypes.c_double * (NET_BINS + 1)), ("bin_trusted", ctypes.c_int * NET_BINS)]
+                ("bin_edges", ctypes.c_double * (NET_BINS + 1)), ("bin_trusted", ctypes.c_int * NET_BINS),
+                ("freeze_tol", ctypes.c_double)]
 
 
 class BemError(RuntimeError):

@@ -870,6 +870,8 @@ bem_status nearfield_moments_impl(bem_mesh *h, const bem_net_model *model, const
             return fail(BEM_EINVAL, "model parameters are NULL or not device memory");
         for (int i = 0; i < BEM_NET_BINS; ++i)
             if (!(model->bin_edges[i] <= model->bin_edges[i + 1])) return fail(BEM_EINVAL, "bin edges must increase");
+        if (!(model->freeze_tol >= 0.0) || !std::isfinite(model->freeze_tol))
+            return fail(BEM_EINVAL, "freeze_tol must be finite and >= 0");
     }
     if (fallback_pairs) *fallback_pairs = 0;
     if (h->nf_pairs == 0) return BEM_OK;  // no near pairs: nothing to add
@@ -898,7 +900,33 @@ bem_status nearfield_moments_impl(bem_mesh *h, const bem_net_model *model, const
             out.push_back({p0, Pc, add_ints(prm, nodes), (int)nodes.size()});
         }
     };
-    if (model) plan_chunks(bemrat::kNetMaxP, net_chunks);
+    // frozen wavenumber: the centre of the nodes' bounding box, the nodes' spread about it and
+    // the sums of the weights of every set
+    const bool frozen = model && model->freeze_tol > 0.0;
+    cplx kc = 0.0;
+    double h2max = 0.0;
+    size_t off_ws = 0;
+    if (frozen) {
+        double rmin = 1e300, rmax = -1e300, imin = 1e300, imax = -1e300;
+        for (int64_t j = 0; j < N; ++j) {
+            rmin = std::min(rmin, z[2 * j]);
+            rmax = std::max(rmax, z[2 * j]);
+            imin = std::min(imin, z[2 * j + 1]);
+            imax = std::max(imax, z[2 * j + 1]);
+        }
+        kc = cplx(0.5 * (rmin + rmax), 0.5 * (imin + imax));
+        double spread = 0.0;
+        for (int64_t j = 0; j < N; ++j) spread = std::max(spread, std::abs(cplx(z[2 * j], z[2 * j + 1]) - kc));
+        h2max = spread > 0.0 && kmax > 0.0 ? model->freeze_tol / (spread * kmax) : 1e300;
+        std::vector<double> ws(2 * (size_t)P, 0.0);
+        for (int64_t p = 0; p < P; ++p)
+            for (int64_t j = 0; j < N; ++j) {
+                ws[2 * p] += W[2 * (j * P + p)];
+                ws[2 * p + 1] += W[2 * (j * P + p) + 1];
+            }
+        off_ws = prm.add(ws.data(), ws.size());
+    }
+    if (model && !frozen) plan_chunks(bemrat::kNetMaxP, net_chunks);
     plan_chunks(bemrat::kNfFold, quad_chunks);
     const int64_t pairs = h->nf_pairs;
     if (model) {
@@ -951,6 +979,18 @@ bem_status nearfield_moments_impl(bem_mesh *h, const bem_net_model *model, const
     for (int i = 0; i < BEM_NET_BINS; ++i) q.bin_ok[i] = model->bin_trusted[i] != 0;
     q.F = F;
     q.flag = flag;
+    q.Wsum = nullptr;
+    if (frozen) {
+        // one launch for every weight set: one evaluation per pair at kc
+        q.Wsum = reinterpret_cast<const double2 *>(base + off_ws);
+        q.kc = make_double2(kc.real(), kc.imag());
+        q.h2max = h2max;
+        q.p0 = 0;
+        q.P = (int)P;
+        q.nodes = nullptr;
+        q.nnodes = 0;
+        HIP_TRY(bemrat::launch_net_fold(q, stream), "network fold kernel (frozen wavenumber)");
+    }
     for (const Chunk &c : net_chunks) {
         q.p0 = (int)c.p0;
         q.P = (int)c.P;

@@ -206,6 +206,11 @@ struct NetFoldParams {
     unsigned char *flag;
     const int *nodes;  // nodes with a nonzero weight in this launch's columns (all N when null)
     int nnodes;
+    // frozen wavenumber (Wsum non-null): one evaluation per pair at kc, for pairs with
+    // h^2 <= h2max, folded with Wsum[p] = sum_j W[j][p] for every p < P (any P)
+    const double2 *Wsum;
+    double2 kc;
+    double h2max;
 };
 hipError_t launch_net_fold(const NetFoldParams &q, hipStream_t stream);
 hipError_t launch_pair_apply(const DeviceMesh &mesh, const int64_t *rowptr, const int32_t *col, const double2 *F, int P,

@@ -409,6 +409,9 @@ struct NetFoldArgs {
     unsigned char *flag;   // npairs: 1 = quadrature
     const int *nodes;      // nodes with a nonzero weight in this launch's columns (all N when null)
     int nnodes;
+    const double2 *Wsum;   // frozen wavenumber: sum_j W[j][p0 + p], p < P
+    double2 kc;
+    double h2max;
 };
 
 constexpr int kNetWaves = 8;     // waves per workgroup (one LDS copy of the weights)
@@ -561,6 +564,135 @@ __global__ __launch_bounds__(64 * kNetWaves) __attribute__((amdgpu_waves_per_eu(
     }
 }
 
+// Frozen-wavenumber inference: the correction of a pair is taken as its value at the centre kc
+// of the node set for every node (dT depends on kappa only through the rule's error on the
+// smooth part of the kernel, so it changes over the nodes by about max_j |z_j - kc| |kappa|
+// h^2 relative; the host turns the caller's bound on that into h2max).  A wave evaluates 16
+// pairs per pass, one per MFMA column (the four lanes of a column form its pair's inputs),
+// and F[k][p0 + p] = dT_k(kc) Wsum[p] for every p < P.
+__global__ __launch_bounds__(64 * kNetWaves) __attribute__((amdgpu_waves_per_eu(4, 4))) void net_fold_frozen_kernel(
+    NetFoldArgs g) {
+    __shared__ v4h sW[kFragTiles * 64];
+    __shared__ float sB[3 * H + NO];
+    __shared__ float sF[kNetWaves][16][kNetInPad + 1];  // each wave's 16 pairs' inputs
+    for (int i = threadIdx.x; i < kFragTiles * 64; i += blockDim.x) sW[i] = g.frag[i];
+    for (int i = threadIdx.x; i < 3 * H + NO; i += blockDim.x)
+        sB[i] = i < H ? g.params[ob1 + i] : i < 2 * H ? g.params[ob2 + i - H] : i < 3 * H ? g.params[ob3 + i - 2 * H]
+                                                                                            : g.params[ob4 + i - 3 * H];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, ci = lane & 15, ck = lane >> 4, wv = threadIdx.x >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * kNetWaves + wv;
+    const int64_t nwaves = (int64_t)gridDim.x * kNetWaves;
+    const double inv4pi = 0.25 / 3.14159265358979323846;
+    // contiguous ranges of whole 16-pair passes per wave
+    const int64_t passes = (g.npairs + 15) / 16;
+    const int64_t per = (passes + nwaves - 1) / nwaves;
+    const int64_t k0 = wave * per * 16;
+    const int64_t k1 = k0 + per * 16 < g.npairs ? k0 + per * 16 : g.npairs;
+    int64_t a = 0;  // row of the wave's current pass start (uniform)
+    if (k0 < k1) {
+        int64_t lo = 0, hi = g.n;  // rowptr[lo] <= k0 < rowptr[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) / 2;
+            if (g.rowptr[mid] <= k0) lo = mid;
+            else hi = mid;
+        }
+        a = lo;
+    }
+    float(*fw)[kNetInPad + 1] = sF[wv];
+    for (int64_t kb = k0; kb < k1; kb += 16) {
+        const int64_t k = kb + ci;
+        const bool have = k < k1;
+        int64_t ak = a;
+        if (have)
+            while (g.rowptr[ak + 1] <= k) ++ak;
+        // the pass's last pair's row starts the next pass
+        a = __shfl(ak, 15);
+        bool ok = false;
+        double scale = 0.0;
+        if (have) {
+            const int64_t b = g.col[k];
+            double P[3][3];
+            for (int v = 0; v < 3; ++v)
+                for (int c = 0; c < 3; ++c) P[v][c] = g.vtx[9 * b + 3 * v + c];
+            const double4 xa = g.colloc[ak];
+            const double x[3] = {xa.x, xa.y, xa.z};
+            double p, q, u, v, w, h, r0;
+            net_frame(P, x, p, q, u, v, w, h);
+            float f[kNetIn];
+            net_geometry_inputs(p, q, u, v, w, f, r0);
+            const double dist = unit_distance(p, q, u, v, w);
+            ok = dist >= g.dmin && q >= (1.0 - p) * g.tan_min && q >= p * g.tan_min && g.kre_max * h <= g.kh_re_max &&
+                 g.kim_max * h <= g.kh_im_max && h * h <= g.h2max;
+            if (ok) {
+                int bin = -1;
+                for (int i = 0; i < kNetBins; ++i)
+                    if (dist >= g.bin_edges[i] && dist < g.bin_edges[i + 1]) bin = i;
+                ok = bin >= 0 && g.bin_ok[bin];
+            }
+            f[5] = (float)(2.0 * g.kc.x * h - 1.0);
+            f[6] = (float)(g.kc.y * h / 0.3);
+            scale = h * inv4pi / (r0 * r0 * r0 * r0);
+            if (ck == 0) {
+#pragma unroll
+                for (int i = 0; i < kNetIn; ++i) fw[ci][i] = f[i];
+#pragma unroll
+                for (int i = kNetIn; i < kNetInPad; ++i) fw[ci][i] = 0.0f;
+            }
+        } else if (ck == 0) {
+#pragma unroll
+            for (int i = 0; i < kNetInPad; ++i) fw[ci][i] = 0.0f;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        v4h xin[2];
+#pragma unroll
+        for (int kbk = 0; kbk < 2; ++kbk)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xin[kbk][i] = (_Float16)fw[ci][16 * kbk + 4 * ck + i];
+        v4h act[8];
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+            v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kbk = 0; kbk < 2; ++kbk) d = mfma16(sW[(kFragW1 + nb * 2 + kbk) * 64 + lane], xin[kbk], d);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) act[nb][i] = (_Float16)tanh_fast(d[i] + sB[16 * nb + 4 * ck + i]);
+        }
+#pragma unroll
+        for (int layer = 0; layer < 2; ++layer) {
+            const int base = layer == 0 ? kFragW2 : kFragW3;
+            const float *bias = sB + H * (layer + 1);
+            v4f d[8];
+#pragma unroll
+            for (int nb = 0; nb < 8; ++nb) {
+                d[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kbk = 0; kbk < 8; ++kbk) d[nb] = mfma16(sW[(base + nb * 8 + kbk) * 64 + lane], act[kbk], d[nb]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int nb = 0; nb < 8; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) act[nb][i] = (_Float16)tanh_fast(d[nb][i] + bias[16 * nb + 4 * ck + i]);
+        }
+        v4f y = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kbk = 0; kbk < 8; ++kbk) y = mfma16(sW[(kFragW4 + kbk) * 64 + lane], act[kbk], y);
+        // column ci's outputs sit in lane ci (ck == 0), registers 0 and 1
+        if (have && ck == 0) {
+            g.flag[k] = ok ? 0 : 1;
+            const double tr = ok ? scale * g.S_re * (double)(y[0] + sB[3 * H]) : 0.0;
+            const double ti = ok ? scale * g.S_im * (double)(y[1] + sB[3 * H + 1]) : 0.0;
+            for (int pp = 0; pp < g.P; ++pp) {
+                const double2 ws = g.Wsum[pp];
+                g.F[k * g.Pstride + g.p0 + pp] = make_double2(ws.x * tr - ws.y * ti, ws.x * ti + ws.y * tr);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // the inputs of this pass are read before the next is staged
+    }
+}
+
 // M[p][a, :] += sum over the pairs k of row a of F[k][p] V[col[k], :] (one workgroup per row),
 // added in chunks of 64 pairs in the order of the list, as the quadrature kernel applies its
 // folds (so a model that trusts no pair reproduces its moments bitwise).
@@ -650,7 +782,7 @@ hipError_t launch_net_pack(const float *params, void *frag, hipStream_t stream) 
 
 hipError_t launch_net_fold(const NetFoldParams &q, hipStream_t stream) {
     if (q.npairs <= 0) return hipSuccess;
-    if (q.P < 1 || q.P > kNetMaxP) return hipErrorInvalidValue;
+    if (q.P < 1 || (!q.Wsum && q.P > kNetMaxP)) return hipErrorInvalidValue;
     NetFoldArgs g;
     g.colloc = q.mesh->colloc;
     g.vtx = q.mesh->vtx;
@@ -680,8 +812,18 @@ hipError_t launch_net_fold(const NetFoldParams &q, hipStream_t stream) {
     g.flag = q.flag;
     g.nodes = q.nodes;
     g.nnodes = q.nnodes;
+    g.Wsum = q.Wsum;
+    g.kc = q.kc;
+    g.h2max = q.h2max;
     int cus = 256, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (q.Wsum) {
+        const int64_t passes = (q.npairs + 15) / 16;
+        const int64_t want = (passes + kNetWaves - 1) / kNetWaves;
+        const unsigned grid = (unsigned)(want < 2 * cus ? want : 2 * cus);
+        hipLaunchKernelGGL(net_fold_frozen_kernel, dim3(grid), dim3(64 * kNetWaves), 0, stream, g);
+        return hipGetLastError();
+    }
     const int64_t want = (q.npairs + kNetWaves - 1) / kNetWaves;
     const unsigned grid = (unsigned)(want < 2 * cus ? want : 2 * cus);
     hipLaunchKernelGGL(net_fold_kernel, dim3(grid), dim3(64 * kNetWaves), 0, stream, g);

@@ -78,6 +78,7 @@ class NearFieldNet:
     min_angle_deg: float = MIN_ANGLE
     kh_re_max: float = KH_RE[1]
     kh_im_max: float = KH_IM[1]
+    freeze_tol: float = 0.0                          # > 0: one evaluation per pair (bem_net_model)
     history: list = field(default_factory=list)      # (step, loss)
     stats: dict = field(default_factory=dict)
 
@@ -94,6 +95,7 @@ class NearFieldNet:
             m.bin_edges[i] = e
         for i, t in enumerate(self.bin_trusted):
             m.bin_trusted[i] = 1 if t else 0
+        m.freeze_tol = float(self.freeze_tol)
         self._c = m
         return m
 
@@ -101,6 +103,14 @@ class NearFieldNet:
         """A copy whose bins are trusted as given (a list of 8 booleans)."""
         c = NearFieldNet(**{k: getattr(self, k) for k in self.__dataclass_fields__})
         c.bin_trusted = [bool(t) for t in trusted]
+        return c
+
+    def frozen(self, tol=1e-2):
+        """A copy evaluated once per pair at the centre of the node set, for the pairs whose
+        estimated relative change of the correction over the nodes (spread x |kappa|max x h^2)
+        is at most tol (bem_net_model.freeze_tol); 0 restores per-node evaluation."""
+        c = NearFieldNet(**{k: getattr(self, k) for k in self.__dataclass_fields__})
+        c.freeze_tol = float(tol)
         return c
 
 

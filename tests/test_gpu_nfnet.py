@@ -216,6 +216,53 @@ def test_inference_matches_oracle_network(env, trained):
     assert np.abs(got - ref).max() <= 1e-2 * np.abs(ref).max()
 
 
+def test_frozen_inference_matches_oracle_network(env, trained):
+    """Frozen wavenumber (bem_net_model.freeze_tol > 0): one evaluation per pair at the centre
+    kc of the nodes' bounding box, used for every node.  With W = I and V = I the moments are
+    the per-pair corrections: both nodes get the same value, equal to the oracle's FP64 network
+    at kc for the pairs inside the trust region; with a bound no pair meets (1e-12) every pair
+    takes the quadrature and the moments equal the quadrature's bitwise."""
+    bem, _lib, nfnet, O, _clib, torch = env
+    xyz, tri = synth.icosphere(3)
+    n = len(tri)
+    z = np.array([4.6 + 0.3j, 5.2 - 0.4j])
+    kc = complex(0.5 * (z.real.min() + z.real.max()), 0.5 * (z.imag.min() + z.imag.max()))
+    W = np.eye(2, dtype=np.complex128)
+    allt = trained.with_trust([True] * 8)
+    params = trained.params.cpu().numpy().astype(np.float64)
+    I = _dev(torch, np.eye(n, dtype=np.complex128))
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        Mf, fb = mesh.nearfield_moments_net(allt.frozen(1e9).c_model(), z, W, I, count_fallback=True)
+        Mz, fbz = mesh.nearfield_moments_net(allt.frozen(1e-12).c_model(), z, W, I, count_fallback=True)
+        Mq = mesh.nearfield_moments(z, W, I)
+        rp, col = mesh.nearfield_list()
+    assert fbz == col.size and torch.equal(Mz, Mq)
+    Mf = Mf.cpu().numpy()
+    P3 = xyz[tri]
+    cen = P3.mean(axis=1)
+    tmin = np.tan(np.deg2rad(trained.min_angle_deg))
+    kre, kim = np.abs(z.real).max(), np.abs(z.imag).max()
+    got, ref = [], []
+    for a in range(0, n, 8):
+        for i in range(rp[a], rp[a + 1]):
+            b = col[i]
+            p, q, u, v, w, h = O.canonical(P3[b], cen[a])
+            d = nfnet.unit_distance(np.array([p]), np.array([q]), np.array([u]), np.array([v]), np.array([w]))[0]
+            m = 1e-9
+            if not (d >= trained.dmin + m and q >= (1 - p) * tmin + m and q >= p * tmin + m
+                    and kre * h <= trained.kh_re_max - m and kim * h <= trained.kh_im_max - m):
+                continue
+            assert Mf[0, a, b] == Mf[1, a, b]
+            got.append(Mf[0, a, b])
+            ref.append(O.correction(params, trained.out_scale, P3[b], cen[a], kc))
+    got, ref = np.array(got), np.array(ref)
+    print(f"{got.size} frozen pair corrections, fallback pairs {fb}; max |fp16 - oracle| / max |dT| = "
+          f"{np.abs(got - ref).max() / np.abs(ref).max():.2e}", flush=True)
+    assert got.size > 50
+    assert np.abs(got - ref).max() <= 1e-2 * np.abs(ref).max()
+
+
 def test_learned_correction_beats_no_correction(env, trained):
     """Moments of the corrected operator (7-point sweep plus near-field correction) against the
     quadrature judge: with the network's correction the error is a fraction of the correction
@@ -274,20 +321,27 @@ def test_gain_on_eigenvalues(env, trained):
 
 
 def test_gain_on_harmonic_sphere(env, trained):
+    """Config 5's mesh and contour (harmonic-499280, |z - 5| = 1.5, N = 32, P = 2, m = 64): the
+    network's correction of the leading moment within half of the quadrature's, per node and
+    frozen at the contour centre (freeze_tol 1e-2), each trusting some pairs; the frozen mode
+    (one evaluation per pair) faster than the quadrature.  Times are printed."""
     bem, _lib, nfnet, O, _clib, torch = env
     xyz, tri = synth.harmonic_sphere(158, seed=5)
     n = len(tri)
     z, w, W = bem.contour_nodes(5.0, 1.5, 32, P=2)
     V = _dev(torch, synth.probe_block(n, 64, seed=5))
+    frozen = trained.frozen(1e-2)
     with bem.Mesh(xyz, tri) as mesh:
         mesh.set_nearfield(2.0)
         pairs = mesh.nearfield_list()[1].size
         Mq = mesh.nearfield_moments(z, W, V)
         Mn, fb = mesh.nearfield_moments_net(trained.c_model(), z, W, V, count_fallback=True)
+        Mf, fbf = mesh.nearfield_moments_net(frozen.c_model(), z, W, V, count_fallback=True)
         torch.cuda.synchronize()
         times = {}
         for name, f in (("quadrature", lambda: mesh.nearfield_moments(z, W, V, out=Mq.zero_())),
-                        ("network", lambda: mesh.nearfield_moments_net(trained.c_model(), z, W, V, out=Mn.zero_()))):
+                        ("network", lambda: mesh.nearfield_moments_net(trained.c_model(), z, W, V, out=Mn.zero_())),
+                        ("frozen", lambda: mesh.nearfield_moments_net(frozen.c_model(), z, W, V, out=Mf.zero_()))):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             f()
@@ -295,7 +349,10 @@ def test_gain_on_harmonic_sphere(env, trained):
             e1.synchronize()
             times[name] = e0.elapsed_time(e1)
         err = [float(torch.linalg.vector_norm(Mn[p] - Mq[p]) / torch.linalg.vector_norm(Mq[p])) for p in range(2)]
-    print(f"harmonic-499280: {pairs} pairs, fallback {fb}; correction rel err {err}; quadrature "
-          f"{times['quadrature']:.1f} ms, network {times['network']:.1f} ms", flush=True)
-    assert err[0] <= 0.5
-    assert fb < pairs
+        errf = [float(torch.linalg.vector_norm(Mf[p] - Mq[p]) / torch.linalg.vector_norm(Mq[p])) for p in range(2)]
+    print(f"harmonic-499280: {pairs} pairs, fallback {fb} (frozen {fbf}); correction rel err per node {err}, "
+          f"frozen {errf}; quadrature {times['quadrature']:.1f} ms, network {times['network']:.1f} ms, "
+          f"frozen {times['frozen']:.1f} ms", flush=True)
+    assert err[0] <= 0.5 and errf[0] <= 0.5
+    assert fb < pairs and fbf < pairs
+    assert times["frozen"] < times["quadrature"]
