@@ -89,7 +89,13 @@ PRECISION_WORKLOAD = dict(name="box-119912", dims=(1.0, 0.8, 0.6), counts=(126, 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}  # MI355X dense matrix peaks
 
 
-def precision_form():
+def precision_sweeps():
+    """Only the timed sweeps of precision_form (the four cheb_moments calls on box-119912, no
+    eigen-solves): a short command for the reduced-precision kernels' counters."""
+    return precision_form(eigen=False)
+
+
+def precision_form(eigen=True):
     """The precision form on the box workload (1.0 x 0.8 x 0.6 box, 126 x 101 x 76 face grid,
     n = 119,912; Chebyshev blocks on [2, 8] with N = 48 nodes, m = 128 probes, seed 3): one
     cheb_moments call per arithmetic after a warm-up call at FP64, timed by the library's
@@ -127,6 +133,11 @@ def precision_form():
                            "form": {bem.FORM_DIRECT: "direct", bem.FORM_EXPAND: "expand",
                                     bem.FORM_CHEB: "cheb"}[form], "operators_generated": L,
                            "achieved_tflops": fl / (kms * 1e-3) / 1e12, "matrix_peak_tflops": PEAK_TFLOPS[name]}
+    base = forms["f64"]["value"]
+    for name in forms:
+        forms[name]["speedup_vs_f64"] = forms[name]["value"] / base
+    if not eigen:
+        return {"workload": w["name"], "forms": forms}
     ref = np.loadtxt(os.path.join(ROOT, "tests", "golden", "box752_interval_eigs.txt"))
     lam_ref = ref[0] + 1j * ref[1]
     bx, bt = synth.box_surface(w["dims"], (10, 8, 6))
@@ -143,9 +154,6 @@ def precision_form():
                 eig[f"{name}/{mode}"] = {"rel_err": err, "found": int(lam.size),
                                          "max_rel_residual": float(res.max()) if res.size else None,
                                          "outer_iterations": int(outer)}
-    base = forms["f64"]["value"]
-    for name in forms:
-        forms[name]["speedup_vs_f64"] = forms[name]["value"] / base
     return {"workload": w["name"], "mesh": f"box 1.0x0.8x0.6, face grid 126x101x76, n={n}",
             "interval": [w["a"], w["b"]], "nodes": w["N"], "m": w["m"], "call": "cheb_moments, all N blocks",
             "forms": forms, "eigen_box752": eig, "equal_accuracy": equal_accuracy()}
@@ -607,8 +615,8 @@ def main():
     ap.add_argument("--dense-lu-only", type=int, default=0, metavar="N",
                     help="only run the dense LU section at size N and print its JSON")
     ap.add_argument("--only", default="", metavar="SECTIONS",
-                    help="only run the named sections (comma-separated: precision_form, batched_form, "
-                         "learned_near_field, dense_lu, eigen_check) and print their JSON")
+                    help="only run the named sections (comma-separated: precision_form, precision_sweeps, "
+                         "batched_form, learned_near_field, dense_lu, eigen_check) and print their JSON")
     ap.add_argument("--large-eigen", type=int, default=0, metavar="L",
                     help="also run the eigen-extraction on the unit icosphere of level L (n = 20 4^L; "
                          "L = 6: n = 81920, about 8 minutes) with the library's LU")
@@ -624,7 +632,8 @@ def main():
         print(json.dumps({"dense_lu": dense_lu(args.dense_lu_only)}), flush=True)
         return
     if args.only:
-        sections = {"precision_form": precision_form, "batched_form": batched_form,
+        sections = {"precision_form": precision_form, "precision_sweeps": precision_sweeps,
+                    "batched_form": batched_form,
                     "learned_near_field": learned_near_field, "dense_lu": dense_lu, "eigen_check": eigen_check}
         res = {}
         for name in args.only.split(","):

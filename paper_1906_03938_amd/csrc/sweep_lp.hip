@@ -71,14 +71,19 @@ __device__ __forceinline__ double vscale_of(const unsigned long long *vmax) {
 }
 
 // LDS index of component c (0: real, 1: imaginary, 2: their sum) of the entry of operator j
-// at (row, stage triangle), and of a staged probe value at (stage triangle, column).
+// at (row, stage triangle), and of a staged probe value at (stage triangle, column).  The
+// 16-bit layouts keep a row's 16 triangles together (the MFMA operand reads 4 of them as one
+// 8-byte access) with a row stride of kRow16 = 20 halves (40 bytes): the 16 rows a producer
+// wave stores at once then fall on 16 different LDS banks (a 32-byte stride put them on 8,
+// measured: 11 bank-conflict cycles per LDS instruction), and the 8-byte reads stay aligned.
+constexpr int kRow16 = 20;
 template <bool K16>
 __device__ __forceinline__ int a_index(int j, int c, int row, int tri) {
-    return K16 ? ((j * 3 + c) * 16 + row) * kStage + tri : ((j * 3 + c) * kStage + tri) * 16 + row;
+    return K16 ? ((j * 3 + c) * 16 + row) * kRow16 + tri : ((j * 3 + c) * kStage + tri) * 16 + row;
 }
 template <bool K16, int NC>
 __device__ __forceinline__ int v_index(int c, int tri, int col) {
-    return K16 ? (c * NC + col) * kStage + tri : (c * kStage + tri) * NC + col;
+    return K16 ? (c * NC + col) * kRow16 + tri : (c * kStage + tri) * NC + col;
 }
 
 // LDS of one tile: double-buffered entries (3 components per operator), probe rows and
@@ -86,8 +91,9 @@ __device__ __forceinline__ int v_index(int c, int tri, int col) {
 template <Prec P, int G, int CB>
 struct LpLds {
     typedef typename Lp<P>::T T;
-    __attribute__((aligned(16))) T sA[2][4 * G * 3 * kStage * 16];
-    __attribute__((aligned(16))) T sV[2][3 * kStage * 16 * CB];
+    static constexpr int R = Lp<P>::k16 ? kRow16 : kStage;  // elements per row of 16 triangles
+    __attribute__((aligned(16))) T sA[2][4 * G * 3 * R * 16];
+    __attribute__((aligned(16))) T sV[2][3 * R * 16 * CB];
     double4 sQ[2][kStage * kQuad];
 };
 
