@@ -538,9 +538,12 @@ def near_field(mesh, U, z, W, sweep_kernel_ms, eta=2.0, freq=158):
     import paper_1906_03938_amd as bem
     import synth
 
-    def timed(msh, V, reps=3):
+    def timed(msh, V, mode, reps=3):
+        """Median ms of the correction alone (zero start) in the given mode, its result and
+        the series length it used."""
+        msh.set_nearfield_mode(mode)
         out = torch.zeros((W.shape[1], msh.n, V.shape[1]), dtype=torch.complex128, device="cuda")
-        msh.nearfield_moments(z, W, V, out=out)  # warm-up
+        msh.nearfield_moments(z, W, V, out=out)  # warm-up, and the correction itself
         ms = []
         for _ in range(reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -550,15 +553,30 @@ def near_field(mesh, U, z, W, sweep_kernel_ms, eta=2.0, freq=158):
             e1.synchronize()
             ms.append(e0.elapsed_time(e1))
         bem.stream_status()
-        return float(np.median(ms))
+        terms = msh.nearfield_last_terms()
+        out.zero_()
+        msh.nearfield_moments(z, W, V, out=out)
+        msh.set_nearfield_mode(bem.NF_AUTO)
+        return float(np.median(ms)), out, terms
+
+    def both(msh, V, key):
+        """Series form (the default) and per-node form: times, and their largest difference
+        per weight set relative to the correction's norm."""
+        ms_s, out_s, terms = timed(msh, V, bem.NF_AUTO)
+        ms_n, out_n, _ = timed(msh, V, bem.NF_NODES)
+        diff = max(float(torch.linalg.vector_norm(out_s[p] - out_n[p]) / torch.linalg.vector_norm(out_n[p]))
+                   for p in range(out_s.shape[0]))
+        del out_s, out_n
+        return {f"{key}_ms": ms_s, f"{key}_series_terms": terms, f"{key}_per_node_ms": ms_n,
+                f"{key}_series_speedup": ms_n / ms_s, f"{key}_series_vs_per_node_rel_diff": diff}
 
     res = {"eta": eta, "nodes": len(z), "weight_sets": int(W.shape[1]), "m": int(U.shape[1])}
     t0 = time.perf_counter()
     mesh.set_nearfield(eta)
     res["headline_list_s"] = time.perf_counter() - t0
     res["headline_pairs"] = int(mesh.nearfield_list()[1].size)
-    res["headline_ms"] = timed(mesh, U)
-    res["headline_fraction_of_sweep_kernel"] = res["headline_ms"] / sweep_kernel_ms
+    res.update(both(mesh, U, "headline"))
+    res["headline_fraction_of_sweep_kernel"] = res["headline_ms"] / sweep_kernel_ms if sweep_kernel_ms else None
     mesh.set_nearfield(0.0)
     xyz, tri = synth.harmonic_sphere(freq, seed=5)
     n = len(tri)
@@ -568,12 +586,29 @@ def near_field(mesh, U, z, W, sweep_kernel_ms, eta=2.0, freq=158):
         big.set_nearfield(eta)
         res["harmonic_list_s"] = time.perf_counter() - t0
         pairs = int(big.nearfield_list()[1].size)
-        ms = timed(big, V)
+        res.update(both(big, V, "harmonic"))
     res.update({"harmonic_mesh": f"harmonic sphere f={freq}, n={n}", "harmonic_pairs": pairs,
-                "harmonic_ms": ms, "pair_node_evaluations_per_s": pairs * len(z) / (ms * 1e-3)})
+                "pair_node_evaluations_per_s": pairs * len(z) / (res["harmonic_ms"] * 1e-3),
+                "pair_node_evaluations_per_s_per_node_form": pairs * len(z) / (res["harmonic_per_node_ms"] * 1e-3)})
     del V
     torch.cuda.empty_cache()
     return res
+
+
+def near_field_section():
+    """The near-field section on its own: the headline mesh, nodes, weights and probes without
+    the sweep (its fraction of the sweep kernel is then not reported)."""
+    import torch
+
+    import paper_1906_03938_amd as bem
+    import synth
+
+    w = WORKLOAD
+    xyz, tri = synth.icosphere(w["level"])
+    U = torch.from_numpy(synth.probe_block(tri.shape[0], w["m"], seed=w["seed"])).to("cuda")
+    z, _, W = bem.contour_nodes(w["c"], w["radius"], w["N"], P=w["P"])
+    with bem.Mesh(xyz, tri) as mesh:
+        return near_field(mesh, U, z, W, None)
 
 
 def eigen_check():
@@ -616,7 +651,7 @@ def main():
                     help="only run the dense LU section at size N and print its JSON")
     ap.add_argument("--only", default="", metavar="SECTIONS",
                     help="only run the named sections (comma-separated: precision_form, precision_sweeps, "
-                         "batched_form, learned_near_field, dense_lu, eigen_check) and print their JSON")
+                         "batched_form, near_field, learned_near_field, dense_lu, eigen_check) and print their JSON")
     ap.add_argument("--large-eigen", type=int, default=0, metavar="L",
                     help="also run the eigen-extraction on the unit icosphere of level L (n = 20 4^L; "
                          "L = 6: n = 81920, about 8 minutes) with the library's LU")
@@ -633,7 +668,7 @@ def main():
         return
     if args.only:
         sections = {"precision_form": precision_form, "precision_sweeps": precision_sweeps,
-                    "batched_form": batched_form,
+                    "batched_form": batched_form, "near_field": near_field_section,
                     "learned_near_field": learned_near_field, "dense_lu": dense_lu, "eigen_check": eigen_check}
         res = {}
         for name in args.only.split(","):

@@ -222,14 +222,34 @@ bem_status bem_mesh_set_nearfield(bem_mesh_t mesh, double eta);
  * col[rowptr[a] .. rowptr[a+1]).  Synchronous.  Errors: BEM_EINVAL, BEM_EDEVICE. */
 bem_status bem_mesh_nearfield(bem_mesh_t mesh, int64_t *pairs, int64_t *rowptr, int32_t *col);
 
+/* How the near-field calls below evaluate the corrections of a node set.
+ * BEM_NF_AUTO (the default): when x = max_j |z_j| R_max is small enough that x^L e^x / L! <=
+ * 1e-17 for some L in {12, 16, 24, 32} (R_max a bound on the distance from a pair's target to
+ * any point of its triangle, fixed by the list), each pair's correction is expanded as the
+ * power series dT_ab(kappa) = sum_{n<L} c_n (i kappa)^n -- the closed-form radial integral
+ * int e^{i kappa r} dr of the polar form and each 7-point term e^{i kappa r}/r expanded term by
+ * term, over the same angular points -- and folded with the weights' moments
+ * sum_j W[j][p] (i z_j)^n: one pass over the pairs per call instead of one per node; the
+ * result equals the per-node evaluation to rounding (the truncation is below 1e-17 relative).
+ * Otherwise, and with BEM_NF_NODES always, every pair is integrated at every node.
+ * Errors: BEM_EINVAL (mesh NULL, mode not one of these). */
+#define BEM_NF_AUTO 0
+#define BEM_NF_NODES 1
+bem_status bem_mesh_set_nearfield_mode(bem_mesh_t mesh, int mode);
+
+/* Series length L the last near-field call on the mesh used (0: per node, or no call yet).
+ * Errors: BEM_EINVAL. */
+bem_status bem_nearfield_last_terms(bem_mesh_t mesh, int *terms);
+
 /* Adds the near-field correction to moments of the 7-point operator:
  *   M[p] += sum_j W[j][p] dT(z_j) V,  p < P,
  * dT(z) = (near-field operator - 7-point operator) at z, nonzero only on the near pairs, so
  * contour_moments followed by this call gives the moments of the corrected operator (the
  * same sums with W[j][p] = delta_jp give T(z_j) V).  Arguments and layout as for
  * contour_moments (z, W [host]; V, M device; block p at M + 2*p*n*ldm doubles); M is read
- * and written.  Without a near-pair list M is left unchanged.  Each entry dT_ab(z_j) is
- * generated on the device per call; results are deterministic.  Errors: BEM_EINVAL,
+ * and written.  Without a near-pair list M is left unchanged.  Each entry dT_ab(z_j) (or its
+ * series, bem_mesh_set_nearfield_mode) is generated on the device per call; results are
+ * deterministic.  Errors: BEM_EINVAL,
  * BEM_ENOMEM, BEM_EDEVICE. */
 bem_status bem_nearfield_moments(bem_mesh_t mesh, const double *z, int64_t N, const double *W,
                                  int64_t P, const double *V, int64_t m, int64_t ldv, double *M,

@@ -10,6 +10,8 @@ from ._lib import (  # noqa: F401
     FORM_CHEB,
     FORM_DIRECT,
     FORM_EXPAND,
+    NF_AUTO,
+    NF_NODES,
     PREC_BF16,
     PREC_F16,
     PREC_F32,

@@ -19,6 +19,7 @@ BEM_OK, BEM_EINVAL, BEM_EMESH, BEM_ENOMEM, BEM_EDEVICE, BEM_EUNSUPPORTED = range
 FORM_AUTO, FORM_DIRECT, FORM_EXPAND, FORM_CHEB = 0, 1, 2, 3
 PREC_F64, PREC_F32, PREC_BF16, PREC_F16 = 0x00, 0x10, 0x20, 0x30
 FORM_MASK, PREC_MASK = 0x03, 0xF0
+NF_AUTO, NF_NODES = 0, 1
 STATUS_NAMES = {0: "BEM_OK", 1: "BEM_EINVAL", 2: "BEM_EMESH", 3: "BEM_ENOMEM", 4: "BEM_EDEVICE",
                 5: "BEM_EUNSUPPORTED"}
 
@@ -31,6 +32,7 @@ EXPORTS = [
     "bem_assemble_sum", "bem_batch_create", "bem_batch_destroy", "bem_batch_layout", "bem_batch_moments",
     "bem_batch_set_timing", "bem_batch_last_kernel_ms",
     "bem_mesh_set_nearfield", "bem_mesh_nearfield", "bem_nearfield_moments", "bem_nearfield_sum",
+    "bem_mesh_set_nearfield_mode", "bem_nearfield_last_terms",
     "contour_moments_noalloc",
     "bem_net_params", "bem_nf_labels", "bem_net_features", "bem_net_forward", "bem_net_work_floats",
     "bem_net_gradient", "bem_net_adam", "bem_nearfield_moments_net", "bem_nearfield_project",
@@ -105,6 +107,8 @@ def lib():
     L.bem_batch_last_kernel_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
     L.bem_mesh_set_nearfield.argtypes = [_vp, ctypes.c_double]
     L.bem_mesh_nearfield.argtypes = [_vp, ctypes.POINTER(_i64), _vp, _vp]
+    L.bem_mesh_set_nearfield_mode.argtypes = [_vp, ctypes.c_int]
+    L.bem_nearfield_last_terms.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
     L.bem_nearfield_moments.argtypes = [_vp, _dp, _i64, _dp, _i64, _vp, _i64, _i64, _vp, _i64, _vp]
     L.bem_nearfield_sum.argtypes = [_vp, _dp, _i64, _dp, _vp, _i64, _vp]
     L.bem_net_params.argtypes = []
@@ -332,6 +336,16 @@ class Mesh:
     def set_nearfield(self, eta: float):
         """Builds (eta > 0) or removes (eta = 0) the mesh's near-pair list."""
         _check(lib().bem_mesh_set_nearfield(self._h, float(eta)))
+
+    def set_nearfield_mode(self, mode: int):
+        """NF_AUTO (series form where it converges, the default) or NF_NODES (every node)."""
+        _check(lib().bem_mesh_set_nearfield_mode(self._h, int(mode)))
+
+    def nearfield_last_terms(self) -> int:
+        """Series length of the last near-field call (0: evaluated per node)."""
+        L = ctypes.c_int(0)
+        _check(lib().bem_nearfield_last_terms(self._h, ctypes.byref(L)))
+        return L.value
 
     def nearfield_list(self):
         """(rowptr[n + 1], col[pairs]) of the near-pair list as NumPy arrays."""

@@ -109,9 +109,13 @@ struct bem_mesh {
     // near field: host centroids and squared longest edges (the list's test), device list
     std::vector<double> nf_cen, nf_h2;
     Buffer nf_rowptr, nf_col, nf_gl;
+    Buffer nf_row, nf_F;  // row of each pair; the series form's folded corrections of a chunk
     Buffer net_frag, net_F, net_flag;  // learned correction: packed weights, folds, fallback flags
     int64_t nf_pairs = 0;
     double nf_eta = 0.0;
+    double nf_rmax = 0.0;    // bound on the distance from a pair's target to its triangle
+    int nf_mode = BEM_NF_AUTO;
+    int nf_last_terms = 0;   // series terms of the last near-field call (0: per node)
     Staging staging;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false, timed = false;
@@ -850,6 +854,28 @@ size_t add_ints(Params &prm, const std::vector<int> &v) {
     return prm.add(d.data(), d.size());
 }
 
+// The weights' moments the series form folds with: mu[n][p] = sum_j W[j][p0 + p] (i z_j)^n,
+// n < L, p < Pc (row-major L x Pc complex).
+size_t add_series_moments(Params &prm, const double *z, int64_t N, const double *W, int64_t Pstride, int64_t p0,
+                          int64_t Pc, int L) {
+    std::vector<double> mu(2 * (size_t)L * Pc, 0.0);
+    for (int64_t j = 0; j < N; ++j) {
+        const double kr = -z[2 * j + 1], ki = z[2 * j];  // i z_j
+        for (int64_t p = 0; p < Pc; ++p) {
+            double tr = W[2 * (j * Pstride + p0 + p)], ti = W[2 * (j * Pstride + p0 + p) + 1];
+            if (tr == 0.0 && ti == 0.0) continue;
+            for (int n = 0; n < L; ++n) {
+                mu[2 * (n * Pc + p)] += tr;
+                mu[2 * (n * Pc + p) + 1] += ti;
+                const double ur = tr * kr - ti * ki, ui = tr * ki + ti * kr;
+                tr = ur;
+                ti = ui;
+            }
+        }
+    }
+    return prm.add(mu.data(), mu.size());
+}
+
 // Near-field corrections of moments, M[p] += sum_j W[j][p] dT(z_j) V: by the quadrature
 // (model NULL) or by the model's network inside its trust region and the quadrature outside.
 // Each launch integrates only the nodes with a nonzero weight among its weight sets.
@@ -929,6 +955,15 @@ bem_status nearfield_moments_impl(bem_mesh *h, const bem_net_model *model, const
     if (model && !frozen) plan_chunks(bemrat::kNetMaxP, net_chunks);
     plan_chunks(bemrat::kNfFold, quad_chunks);
     const int64_t pairs = h->nf_pairs;
+    // series form: one moments table per quadrature chunk
+    const int L = h->nf_mode == BEM_NF_AUTO ? bemrat::nf_series_terms(kmax * h->nf_rmax) : 0;
+    h->nf_last_terms = L;
+    std::vector<size_t> mu_off;
+    if (L)
+        for (const Chunk &c : quad_chunks) mu_off.push_back(add_series_moments(prm, z, N, W, P, c.p0, c.P, L));
+    if (L && !model)
+        HIP_TRY(h->nf_F.ensure(sizeof(double2) * (size_t)pairs * std::min<int64_t>(P, bemrat::kNfFold)),
+                "near-field folds");
     if (model) {
         HIP_TRY(h->net_frag.ensure((size_t)bemrat::net_frag_bytes()), "packed network");
         HIP_TRY(h->net_F.ensure(sizeof(double2) * (size_t)pairs * P), "pair folds");
@@ -940,6 +975,21 @@ bem_status nearfield_moments_impl(bem_mesh *h, const bem_net_model *model, const
     const double2 *Wd = reinterpret_cast<const double2 *>(base + off_w);
     const int64_t *rowptr = h->nf_rowptr.as<int64_t>();
     const int32_t *col = h->nf_col.as<int32_t>();
+    if (!model && L) {
+        double2 *F = h->nf_F.as<double2>();
+        for (size_t i = 0; i < quad_chunks.size(); ++i) {
+            const Chunk &c = quad_chunks[i];
+            if (c.nn == 0) continue;
+            HIP_TRY(bemrat::launch_nearfield_series(h->dm, h->nf_gl.as<double>(), h->nf_row.as<int32_t>(), col, pairs,
+                                                    nullptr, kmax, reinterpret_cast<const double2 *>(base + mu_off[i]),
+                                                    L, (int)c.P, F, (int)c.P, 0, stream),
+                    "near-field series kernel");
+            HIP_TRY(bemrat::launch_pair_apply(h->dm, rowptr, col, F, (int)c.P, reinterpret_cast<const double2 *>(V), ldv,
+                                              m, reinterpret_cast<double2 *>(M) + c.p0 * h->dm.n * ldm, ldm, stream),
+                    "pair apply kernel");
+        }
+        return BEM_OK;
+    }
     if (!model) {
         for (const Chunk &c : quad_chunks) {
             if (c.nn == 0) continue;
@@ -999,7 +1049,12 @@ bem_status nearfield_moments_impl(bem_mesh *h, const bem_net_model *model, const
         HIP_TRY(bemrat::launch_net_fold(q, stream), "network fold kernel");
     }
     // the pairs outside the trust region: the quadrature, folded into the same array
-    for (const Chunk &c : quad_chunks)
+    for (size_t i = 0; L && i < quad_chunks.size(); ++i)
+        HIP_TRY(bemrat::launch_nearfield_series(h->dm, h->nf_gl.as<double>(), h->nf_row.as<int32_t>(), col, pairs, flag,
+                                                kmax, reinterpret_cast<const double2 *>(base + mu_off[i]), L,
+                                                (int)quad_chunks[i].P, F, (int)P, (int)quad_chunks[i].p0, stream),
+                "near-field series kernel");
+    for (const Chunk &c : L ? std::vector<Chunk>() : quad_chunks)
         HIP_TRY(bemrat::launch_nearfield_fold(h->dm, h->nf_gl.as<double>(), rowptr, col, flag, kap, (int)N, Wd, (int)P,
                                               (int)c.p0, (int)c.P, kmax, F, reinterpret_cast<const int *>(base + c.off),
                                               c.nn, stream),
@@ -1153,6 +1208,8 @@ void bem_mesh_destroy(bem_mesh_t h) {
     h->nf_rowptr.release();
     h->nf_col.release();
     h->nf_gl.release();
+    h->nf_row.release();
+    h->nf_F.release();
     if (h->staging.host) (void)hipHostFree(h->staging.host);
     if (h->staging.done) (void)hipEventDestroy(h->staging.done);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -1574,12 +1631,34 @@ bem_status bem_mesh_set_nearfield(bem_mesh_t h, double eta) {
     if (!near_list(h->nf_cen, h->nf_h2, h->dm.n, eta, rowptr, col))
         return fail(BEM_ENOMEM, "host allocation failed (near-pair list)");
     const int64_t nnz = (int64_t)col.size();
+    // the row of every pair, and a bound on the distance from a pair's target (centroid a) to
+    // any point of triangle b: |x_a - x_b| plus the centroid-to-vertex distance of b, at most
+    // two thirds of a median, itself at most the longest edge
+    std::vector<int32_t> row;
+    double rmax = 0.0;
+    try {
+        row.resize((size_t)nnz);
+    } catch (...) {
+        return fail(BEM_ENOMEM, "host allocation failed (near-pair rows)");
+    }
+    for (int64_t a = 0; a < h->dm.n; ++a)
+        for (int64_t k = rowptr[a]; k < rowptr[a + 1]; ++k) {
+            const int64_t b = col[k];
+            row[k] = (int32_t)a;
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double d = h->nf_cen[3 * a + c] - h->nf_cen[3 * b + c];
+                d2 += d * d;
+            }
+            rmax = std::max(rmax, std::sqrt(d2) + (2.0 / 3.0) * std::sqrt(h->nf_h2[b]));
+        }
     double glh[2 * 16 + 2 * 10];  // 16-point rule, then the 10-point rule (nodes, weights)
     gauss_legendre(16, glh, glh + 16);
     gauss_legendre(10, glh + 32, glh + 42);
     HIP_TRY(h->nf_rowptr.ensure(sizeof(int64_t) * rowptr.size()), "near-pair list");
     HIP_TRY(h->nf_col.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "near-pair list");
     HIP_TRY(h->nf_gl.ensure(sizeof glh), "near-field rule");
+    HIP_TRY(h->nf_row.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "near-pair rows");
     // a set-up call: synchronous copies, the device may still run earlier work on any stream
     HIP_TRY(hipDeviceSynchronize(), "device synchronize");
     HIP_TRY(hipMemcpy(h->nf_rowptr.ptr, rowptr.data(), sizeof(int64_t) * rowptr.size(), hipMemcpyHostToDevice),
@@ -1587,9 +1666,13 @@ bem_status bem_mesh_set_nearfield(bem_mesh_t h, double eta) {
     if (nnz)
         HIP_TRY(hipMemcpy(h->nf_col.ptr, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice),
                 "near-pair list upload");
+    if (nnz)
+        HIP_TRY(hipMemcpy(h->nf_row.ptr, row.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice),
+                "near-pair rows upload");
     HIP_TRY(hipMemcpy(h->nf_gl.ptr, glh, sizeof glh, hipMemcpyHostToDevice), "near-field rule upload");
     h->nf_pairs = nnz;
     h->nf_eta = eta;
+    h->nf_rmax = rmax * (1.0 + 1e-12);
     return BEM_OK;
 }
 
@@ -1609,6 +1692,20 @@ bem_status bem_mesh_nearfield(bem_mesh_t h, int64_t *pairs, int64_t *rowptr, int
     if (col && h->nf_pairs)
         HIP_TRY(hipMemcpy(col, h->nf_col.ptr, sizeof(int32_t) * h->nf_pairs, hipMemcpyDeviceToHost),
                 "near-pair list download");
+    return BEM_OK;
+}
+
+bem_status bem_mesh_set_nearfield_mode(bem_mesh_t h, int mode) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    if (mode != BEM_NF_AUTO && mode != BEM_NF_NODES) return fail(BEM_EINVAL, "mode must be BEM_NF_AUTO or BEM_NF_NODES");
+    h->nf_mode = mode;
+    return BEM_OK;
+}
+
+bem_status bem_nearfield_last_terms(bem_mesh_t h, int *terms) {
+    if (!h) return fail(BEM_EINVAL, "mesh is NULL");
+    if (!terms) return fail(BEM_EINVAL, "terms is NULL");
+    *terms = h->nf_last_terms;
     return BEM_OK;
 }
 
@@ -1634,6 +1731,23 @@ bem_status bem_nearfield_sum(bem_mesh_t h, const double *z, int64_t N, const dou
     const size_t off_c = prm.add(c, 2 * (size_t)N);
     double kmax = 0.0;
     for (int64_t j = 0; j < N; ++j) kmax = std::max(kmax, std::abs(cplx(z[2 * j], z[2 * j + 1])));
+    const int L = h->nf_mode == BEM_NF_AUTO ? bemrat::nf_series_terms(kmax * h->nf_rmax) : 0;
+    h->nf_last_terms = L;
+    if (L) {
+        const size_t off_mu = add_series_moments(prm, z, N, c, 1, 0, 1, L);
+        HIP_TRY(h->nf_F.ensure(sizeof(double2) * (size_t)h->nf_pairs), "near-field folds");
+        if ((st = upload(h, prm, stream)) != BEM_OK) return st;
+        const double *base = h->params.as<double>();
+        double2 *F = h->nf_F.as<double2>();
+        HIP_TRY(bemrat::launch_nearfield_series(h->dm, h->nf_gl.as<double>(), h->nf_row.as<int32_t>(),
+                                                h->nf_col.as<int32_t>(), h->nf_pairs, nullptr, kmax,
+                                                reinterpret_cast<const double2 *>(base + off_mu), L, 1, F, 1, 0, stream),
+                "near-field series kernel");
+        HIP_TRY(bemrat::launch_pair_dense_add(h->nf_row.as<int32_t>(), h->nf_col.as<int32_t>(), F, h->nf_pairs,
+                                              reinterpret_cast<double2 *>(S), lds, stream),
+                "pair dense add kernel");
+        return BEM_OK;
+    }
     if ((st = upload(h, prm, stream)) != BEM_OK) return st;
     const double *base = h->params.as<double>();
     HIP_TRY(bemrat::launch_nearfield(h->dm, h->nf_gl.as<double>(), h->nf_rowptr.as<int64_t>(), h->nf_col.as<int32_t>(),

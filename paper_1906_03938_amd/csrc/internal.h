@@ -161,6 +161,19 @@ hipError_t launch_nearfield_fold(const DeviceMesh &mesh, const double *gl16, con
                                  const int32_t *col, const unsigned char *flag, const double2 *kappa, int N,
                                  const double2 *W, int Pstride, int p0, int P, double kmax, double2 *F,
                                  const int *nodes, int nnodes, hipStream_t stream);
+// Series form of the near-field corrections: for each pair k (row[k], col[k]) with flag[k] != 0
+// (every pair when flag is null), F[k * Fstride + p0 + p] = sum_{n<L} c_n mu[n * P + p], p < P,
+// c_n the coefficients of dT_ab(kappa) = sum_n c_n (i kappa)^n and mu[n][p] = sum_j W[j][p]
+// (i kappa_j)^n (device, L x P); kmax sets the angular panels as in launch_nearfield.
+// L in {12, 16, 24, 32}.  nf_series_terms(x): the smallest of these with x^L e^x / L! <= 1e-17
+// for x = kappa_max R_max, or 0 when none is (then the per-node kernel is used).
+int nf_series_terms(double x);
+hipError_t launch_nearfield_series(const DeviceMesh &mesh, const double *gl16, const int32_t *row, const int32_t *col,
+                                   int64_t npairs, const unsigned char *flag, double kmax, const double2 *mu, int L,
+                                   int P, double2 *F, int Fstride, int p0, hipStream_t stream);
+// S[row[k]][col[k]] += F[k], k < npairs (dense mode of the series form).
+hipError_t launch_pair_dense_add(const int32_t *row, const int32_t *col, const double2 *F, int64_t npairs, double2 *S,
+                                 int64_t lds, hipStream_t stream);
 // Labels of the learned correction: out[s] = integral - 7-point value of triangle P9[s] (9
 // doubles) at target x[s] (3 doubles) and wavenumber kappa[s]; gl52 the 16- and 10-point
 // Gauss-Legendre rules (nodes then weights of each), rule28 Radon's rule (3 barycentric weights
@@ -213,6 +226,8 @@ struct NetFoldParams {
     double h2max;
 };
 hipError_t launch_net_fold(const NetFoldParams &q, hipStream_t stream);
+// M[p][a, :] += sum over the pairs k of row a of F[k * P + p] V[col[k], :], p < P (block p at
+// M + p * n * ldm; launched in chunks of kNfFold sets, one wave per row).
 hipError_t launch_pair_apply(const DeviceMesh &mesh, const int64_t *rowptr, const int32_t *col, const double2 *F, int P,
                              const double2 *V, int64_t ldv, int64_t m, double2 *M, int64_t ldm, hipStream_t stream);
 

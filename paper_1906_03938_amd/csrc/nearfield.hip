@@ -278,8 +278,9 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
             for (int k = 0; k < cnt; ++k) {
                 const double2 f = fold[k][p];
                 const double2 v = g.V[(int64_t)cols[k] * g.ldv + c];
-                sr += f.x * v.x - f.y * v.y;
-                si += f.x * v.y + f.y * v.x;
+                // explicit fused steps: the pair-fold apply kernel rounds the same way
+                sr = fma(-f.y, v.y, fma(f.x, v.x, sr));
+                si = fma(f.y, v.x, fma(f.x, v.y, si));
             }
             double2 *out = g.M + p * g.mstride + a * g.ldm + c;
             const double2 o = *out;
@@ -287,6 +288,216 @@ __global__ __launch_bounds__(kNfThreads) void nearfield_kernel(NfArgs g) {
         }
         __syncthreads();
     }
+}
+
+// Series form of the folded correction.  While |kappa| R is small (R the distance from the
+// target to the farthest point of triangle b) every part of dT_ab(kappa) is a short power series
+// in kappa: the radial integral of the polar form,
+//     e^{i kappa |d|} delta E(i kappa delta) = int_{|d|}^{R} e^{i kappa r} dr
+//         = sum_n (i kappa)^n (R^{n+1} - |d|^{n+1}) / (n+1)!,
+// and each 7-point term, e^{i kappa r_q} / r_q = sum_n (i kappa)^n r_q^{n-1} / n!.  Hence
+//     dT_ab(kappa) = sum_{n<L} c_n (i kappa)^n,
+//     c_n = sum_e sign(p_e) sum_points w_phi (R^{n+1} - |d|^{n+1}) / (4 pi (n+1)!)
+//           - sum_q w_q r_q^{n-1} / n!,
+// with w_phi a point's angular weight and w_q = A_b w_q / (4 pi) the 7-point weight, and the
+// folded correction of weight set p is sum_n c_n mu[n][p], mu[n][p] = sum_j W[j][p] (i kappa_j)^n
+// (formed on the host).  The angular points are those of the per-node kernel, so the two agree
+// to rounding plus the truncation, which the host bounds through x = kappa_max R_max
+// (x^L e^x / L! relative).  R^{n+1} - |d|^{n+1} is advanced as D_{n+1} = R D_n + |d|^n delta,
+// free of cancellation when R is close to |d|.  One thread per pair; the pairs are taken in
+// contiguous ranges per XCD (the L2 of an XCD then holds the triangles of neighbouring rows).
+// 1/x for finite x > 0 away from the exponent limits: the hardware estimate and two Newton
+// steps (the quadratic convergence takes it to the rounding of the last step).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double t = __builtin_amdgcn_rcp(x);
+    t = fma(fma(-x, t, 1.0), t, t);
+    return fma(fma(-x, t, 1.0), t, t);
+}
+
+// sqrt(x) for normal x > 0 away from the exponent limits: the hardware reciprocal square root
+// estimate refined by two coupled Newton steps for sqrt(x) and 1/(2 sqrt(x)) and a final
+// residual correction.
+__device__ __forceinline__ double sqrt_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
+struct NfSeriesArgs {
+    const double4 *colloc;
+    const double4 *quad;
+    const double *vtx;
+    const double *gl;
+    const int32_t *row, *col;
+    int64_t npairs, nblocks;
+    double kmax;              // panel rule of the angular integral (as the per-node kernel)
+    const double2 *mu;        // L x P, mu[n * P + p]
+    int P;
+    const unsigned char *flag;  // only the pairs with flag[k] != 0 when non-null
+    double2 *F;               // F[k * Fstride + p0 + p]
+    int Fstride, p0;
+};
+
+// Geometry of a workgroup's pairs kept between its two phases (structure of arrays).
+struct NfGeomLds {
+    double d[13][256];  // ad, esg[3], eap[3], eu0[3], eh[3]
+    int i[6][256];      // enp[3], enq[3]
+    int order[256];     // pair (thread) index by ascending angular point count
+    int count[33], start[33];
+};
+
+template <int L>
+__global__ __launch_bounds__(256) void nearfield_series_kernel(NfSeriesArgs g) {
+    __shared__ NfGeomLds sg;
+    // XCD-aware block order: the hardware deals workgroups to the 8 XCDs in turn, so block
+    // i runs on XCD i % 8; give XCD x the contiguous blocks x * per .. x * per + per - 1
+    const int64_t per = (g.nblocks + 7) / 8;
+    const int64_t blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (blk >= g.nblocks) return;  // uniform over the workgroup
+    const int t = threadIdx.x;
+    // phase 1: every thread the geometry of pair t of the block, and its bucket by angular
+    // point count (32: no work); the pairs are then handed to the lanes in bucket order, so
+    // a wave's lanes run point loops of about the same length
+    {
+        const int64_t k = blk * 256 + t;
+        int bucket = 32;
+        if (k < g.npairs && (!g.flag || g.flag[k])) {
+            const int64_t a = g.row[k], b = g.col[k];
+            double P[3][3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) P[v][c] = g.vtx[9 * b + 3 * v + c];
+            const double4 xa = g.colloc[a];
+            const double x[3] = {xa.x, xa.y, xa.z};
+            NfGeom geo;
+            nf_geometry(P, x, g.kmax, geo);
+            sg.d[0][t] = geo.ad;
+            int pts = 0;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                sg.d[1 + e][t] = geo.esg[e];
+                sg.d[4 + e][t] = geo.eap[e];
+                sg.d[7 + e][t] = geo.eu0[e];
+                sg.d[10 + e][t] = geo.eh[e];
+                sg.i[e][t] = geo.enp[e];
+                sg.i[3 + e][t] = geo.enq[e];
+                pts += geo.enp[e] * geo.enq[e];
+            }
+            bucket = pts <= 30 ? 0 : (pts - 30 + 5) / 6 < 31 ? (pts - 30 + 5) / 6 : 31;
+        }
+        if (t < 33) sg.count[t] = 0;
+        __syncthreads();
+        const int slot = atomicAdd(&sg.count[bucket], 1);
+        __syncthreads();
+        if (t == 0) {
+            int s = 0;
+            for (int q = 0; q < 33; ++q) {
+                sg.start[q] = s;
+                s += sg.count[q];
+            }
+        }
+        __syncthreads();
+        sg.order[sg.start[bucket] + slot] = t;
+        __syncthreads();
+    }
+    // phase 2: lane t takes the pair of rank t (which lane takes which pair does not change
+    // any result: each pair's sums run in its own registers)
+    const int j = sg.order[t];
+    const int64_t k = blk * 256 + j;
+    if (k >= g.npairs || (g.flag && !g.flag[k])) return;
+    const int64_t a = g.row[k], b = g.col[k];
+    const double4 xa = g.colloc[a];
+    const double x[3] = {xa.x, xa.y, xa.z};
+    NfGeom geo;
+    geo.ad = sg.d[0][j];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        geo.esg[e] = sg.d[1 + e][j];
+        geo.eap[e] = sg.d[4 + e][j];
+        geo.eu0[e] = sg.d[7 + e][j];
+        geo.eh[e] = sg.d[10 + e][j];
+        geo.enp[e] = sg.i[e][j];
+        geo.enq[e] = sg.i[3 + e][j];
+    }
+    const double ad = geo.ad;
+    double c[L];
+#pragma unroll
+    for (int n = 0; n < L; ++n) c[n] = 0.0;
+    for (int e = 0; e < 3; ++e) {
+        const int nq = geo.enq[e];
+        const double *glx = nq == kNfGL ? g.gl : g.gl + 2 * kNfGL;
+        const double half = 0.5 * geo.eh[e], scale = half * geo.esg[e];
+        for (int pn = 0; pn < geo.enp[e]; ++pn) {
+            const double mid = geo.eu0[e] + (pn + 0.5) * geo.eh[e];
+            for (int q = 0; q < nq; ++q) {
+                // cosh u = (e^u + e^-u)/2 (|u| < asinh(1e31) < 73 by the edge-line test), the
+                // reciprocals by the hardware estimate and two Newton steps
+                const double eu = exp_cw(mid + half * glx[q]);
+                const double ch = 0.5 * (eu + rcp_nr(eu));
+                const double rho = geo.eap[e] * ch;
+                const double R = sqrt_nr(rho * rho + ad * ad);  // in [rho, 2 R_max]: normal
+                const double dl = rho * rho * rcp_nr(R + ad);
+                const double w = scale * glx[nq + q] * rcp_nr(ch);
+                double D = dl, dp = dl;  // D_1 = R - |d|; dp = |d|^n delta
+                c[0] += w * D;
+#pragma unroll
+                for (int n = 1; n < L; ++n) {
+                    dp *= ad;
+                    D = R * D + dp;
+                    c[n] += w * D;
+                }
+            }
+        }
+    }
+    {
+        double f = 0.25 / 3.14159265358979323846;
+#pragma unroll
+        for (int n = 0; n < L; ++n) {
+            f /= (double)(n + 1);
+            c[n] *= f;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kQuad; ++q) {
+        const double4 y = g.quad[b * kQuad + q];
+        const double qx = x[0] - y.x, qy = x[1] - y.y, qz = x[2] - y.z;
+        const double r = sqrt(qx * qx + qy * qy + qz * qz);
+        double s = y.w * rcp_nr(r);
+        c[0] -= s;
+#pragma unroll
+        for (int n = 1; n < L; ++n) {
+            s *= r * (1.0 / (double)n);
+            c[n] -= s;
+        }
+    }
+    double2 *out = g.F + k * g.Fstride + g.p0;
+    for (int p = 0; p < g.P; ++p) {
+        double fr = 0.0, fi = 0.0;
+#pragma unroll
+        for (int n = L - 1; n >= 0; --n) {  // smallest terms first
+            const double2 m = g.mu[n * g.P + p];
+            fr += c[n] * m.x;
+            fi += c[n] * m.y;
+        }
+        out[p] = make_double2(fr, fi);
+    }
+}
+
+// S[row[k]][col[k]] += F[k] for every pair (each entry appears once in the list).
+__global__ __launch_bounds__(256) void pair_dense_add_kernel(const int32_t *__restrict__ row,
+                                                             const int32_t *__restrict__ col,
+                                                             const double2 *__restrict__ F, int64_t npairs,
+                                                             double2 *__restrict__ S, int64_t lds) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npairs) return;
+    double2 *o = S + (int64_t)row[k] * lds + col[k];
+    const double2 f = F[k], v = *o;
+    *o = make_double2(v.x + f.x, v.y + f.y);
 }
 
 }  // namespace
@@ -351,6 +562,62 @@ hipError_t launch_nearfield_fold(const DeviceMesh &mesh, const double *gl16, con
     g.nodes = nodes;
     g.nnodes = nnodes;
     hipLaunchKernelGGL(nearfield_kernel, dim3((unsigned)mesh.n), dim3(kNfThreads), 0, stream, g);
+    return hipGetLastError();
+}
+
+int nf_series_terms(double x) {
+    // smallest L of the compiled lengths with x^L e^x / L! <= 1e-17, else 0
+    if (!(x >= 0.0) || !(x < 64.0)) return 0;
+    static const int lengths[] = {12, 16, 24, 32};
+    double term = 1.0;  // x^n / n!
+    const double ex = exp(x);
+    int n = 0;
+    for (int Lc : lengths) {
+        while (n < Lc) {
+            ++n;
+            term *= x / n;
+        }
+        if (term * ex <= 1e-17) return Lc;
+    }
+    return 0;
+}
+
+hipError_t launch_nearfield_series(const DeviceMesh &mesh, const double *gl16, const int32_t *row, const int32_t *col,
+                                   int64_t npairs, const unsigned char *flag, double kmax, const double2 *mu, int L,
+                                   int P, double2 *F, int Fstride, int p0, hipStream_t stream) {
+    if (npairs <= 0) return hipSuccess;
+    NfSeriesArgs g;
+    g.colloc = mesh.colloc;
+    g.quad = mesh.quad;
+    g.vtx = mesh.vtx;
+    g.gl = gl16;
+    g.row = row;
+    g.col = col;
+    g.npairs = npairs;
+    g.nblocks = (npairs + 255) / 256;
+    g.kmax = kmax;
+    g.mu = mu;
+    g.P = P;
+    g.flag = flag;
+    g.F = F;
+    g.Fstride = Fstride;
+    g.p0 = p0;
+    const dim3 grid((unsigned)((g.nblocks + 7) / 8 * 8));
+    switch (L) {
+    case 12: hipLaunchKernelGGL(nearfield_series_kernel<12>, grid, dim3(256), 0, stream, g); break;
+    case 16: hipLaunchKernelGGL(nearfield_series_kernel<16>, grid, dim3(256), 0, stream, g); break;
+    case 24: hipLaunchKernelGGL(nearfield_series_kernel<24>, grid, dim3(256), 0, stream, g); break;
+    case 32: hipLaunchKernelGGL(nearfield_series_kernel<32>, grid, dim3(256), 0, stream, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_dense_add(const int32_t *row, const int32_t *col, const double2 *F, int64_t npairs, double2 *S,
+                                 int64_t lds, hipStream_t stream) {
+    if (npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pair_dense_add_kernel, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, stream, row, col, F,
+                       npairs, S, lds);
     return hipGetLastError();
 }
 

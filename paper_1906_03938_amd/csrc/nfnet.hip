@@ -693,32 +693,55 @@ __global__ __launch_bounds__(64 * kNetWaves) __attribute__((amdgpu_waves_per_eu(
     }
 }
 
-// M[p][a, :] += sum over the pairs k of row a of F[k][p] V[col[k], :] (one workgroup per row),
-// added in chunks of 64 pairs in the order of the list, as the quadrature kernel applies its
-// folds (so a model that trusts no pair reproduces its moments bitwise).
+// M[p][a, :] += sum over the pairs k of row a of F[k * Fstride + p] V[col[k], :], p < P <= kNfFold,
+// added in chunks of 64 pairs in the order of the list, as the per-node quadrature kernel applies
+// its folds (so a model that trusts no pair reproduces the quadrature's moments bitwise).
+template <int PC>
 __global__ __launch_bounds__(256) void pair_apply_kernel(const int64_t *__restrict__ rowptr,
                                                          const int32_t *__restrict__ col,
-                                                         const double2 *__restrict__ F, int P,
+                                                         const double2 *__restrict__ F, int Fstride,
                                                          const double2 *__restrict__ V, int64_t ldv, int64_t m,
-                                                         double2 *__restrict__ M, int64_t ldm, int64_t mstride) {
-    const int64_t a = blockIdx.x;
+                                                         double2 *__restrict__ M, int64_t ldm, int64_t mstride,
+                                                         int64_t n, int64_t nblocks) {
+    // one wave per row, its lanes over the columns, the PC weight sets of the launch per lane;
+    // rows in contiguous ranges per XCD (block i runs on XCD i % 8), so neighbouring rows,
+    // which share most of their near triangles' rows of V, meet in the same L2
+    const int64_t per = (nblocks + 7) / 8;
+    const int64_t blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    // the row is uniform over the wave: say so, so that the list and the folds are read
+    // through the scalar cache
+    const int64_t a = blk * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    if (blk >= nblocks || a >= n) return;
+    const int lane = threadIdx.x % 64;
     const int64_t beg = rowptr[a], end = rowptr[a + 1];
-    for (int64_t item = threadIdx.x; item < (int64_t)P * m; item += blockDim.x) {
-        const int p = (int)(item / m);
-        const int64_t c = item % m;
-        double2 *o = M + p * mstride + a * ldm + c;
+    if (beg == end) return;
+    for (int64_t c = lane; c < m; c += 64) {
+        double2 o[PC];
+#pragma unroll
+        for (int p = 0; p < PC; ++p) o[p] = M[p * mstride + a * ldm + c];
+        // pairs in chunks of kPairChunk, each chunk's sum added to the running value (the
+        // order of the per-node kernel's own apply phase)
         for (int64_t base = beg; base < end; base += kPairChunk) {
             const int64_t stop = end - base < kPairChunk ? end : base + kPairChunk;
-            double sr = 0.0, si = 0.0;
+            double sr[PC], si[PC];
+#pragma unroll
+            for (int p = 0; p < PC; ++p) sr[p] = si[p] = 0.0;
+#pragma unroll 8
             for (int64_t k = base; k < stop; ++k) {
-                const double2 f = F[k * P + p];
                 const double2 v = V[(int64_t)col[k] * ldv + c];
-                sr += f.x * v.x - f.y * v.y;
-                si += f.x * v.y + f.y * v.x;
+#pragma unroll
+                for (int p = 0; p < PC; ++p) {
+                    const double2 f = F[k * Fstride + p];
+                    // the per-node kernel's fused steps, for bitwise equal results
+                    sr[p] = fma(-f.y, v.y, fma(f.x, v.x, sr[p]));
+                    si[p] = fma(f.y, v.x, fma(f.x, v.y, si[p]));
+                }
             }
-            const double2 old = *o;
-            *o = make_double2(old.x + sr, old.y + si);
+#pragma unroll
+            for (int p = 0; p < PC; ++p) o[p] = make_double2(o[p].x + sr[p], o[p].y + si[p]);
         }
+#pragma unroll
+        for (int p = 0; p < PC; ++p) M[p * mstride + a * ldm + c] = o[p];
     }
 }
 
@@ -832,8 +855,35 @@ hipError_t launch_net_fold(const NetFoldParams &q, hipStream_t stream) {
 
 hipError_t launch_pair_apply(const DeviceMesh &mesh, const int64_t *rowptr, const int32_t *col, const double2 *F, int P,
                              const double2 *V, int64_t ldv, int64_t m, double2 *M, int64_t ldm, hipStream_t stream) {
-    hipLaunchKernelGGL(pair_apply_kernel, dim3((unsigned)mesh.n), dim3(256), 0, stream, rowptr, col, F, P, V, ldv, m, M,
-                       ldm, mesh.n * ldm);
+    const int64_t nblocks = (mesh.n + 3) / 4;
+    const dim3 grid((unsigned)((nblocks + 7) / 8 * 8));
+    // the sets in launches of 8, then 4, 2 and 1 (each set's sums are the same whichever
+    // launch carries it)
+    for (int p0 = 0; p0 < P;) {
+        const int left = P - p0;
+        const int pc = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        const double2 *Fp = F + p0;
+        double2 *Mp = M + (int64_t)p0 * mesh.n * ldm;
+        switch (pc) {
+        case 8:
+            hipLaunchKernelGGL(pair_apply_kernel<8>, grid, dim3(256), 0, stream, rowptr, col, Fp, P, V, ldv, m, Mp, ldm,
+                               mesh.n * ldm, mesh.n, nblocks);
+            break;
+        case 4:
+            hipLaunchKernelGGL(pair_apply_kernel<4>, grid, dim3(256), 0, stream, rowptr, col, Fp, P, V, ldv, m, Mp, ldm,
+                               mesh.n * ldm, mesh.n, nblocks);
+            break;
+        case 2:
+            hipLaunchKernelGGL(pair_apply_kernel<2>, grid, dim3(256), 0, stream, rowptr, col, Fp, P, V, ldv, m, Mp, ldm,
+                               mesh.n * ldm, mesh.n, nblocks);
+            break;
+        default:
+            hipLaunchKernelGGL(pair_apply_kernel<1>, grid, dim3(256), 0, stream, rowptr, col, Fp, P, V, ldv, m, Mp, ldm,
+                               mesh.n * ldm, mesh.n, nblocks);
+            break;
+        }
+        p0 += pc;
+    }
     return hipGetLastError();
 }
 

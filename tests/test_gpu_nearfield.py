@@ -137,6 +137,69 @@ def test_many_weight_sets_ragged_and_strided(bem, torch, oracle_lib):
         assert np.linalg.norm(Ig[j] - corr_id[j]) <= 1e-11 * np.linalg.norm(corr_id[j])
 
 
+@pytest.mark.parametrize("name", ["sphere", "box", "perturbed"])
+def test_series_and_per_node_forms_agree(bem, torch, oracle_lib, name):
+    """The default series form (each pair's correction as a power series in kappa folded with
+    the weights' moments) and the per-node form evaluate the same angular points: both match
+    the oracle, and each other to rounding, for moments (two weight sets, complex nodes) and
+    for the dense node combination."""
+    xyz, tri = _mesh(name)
+    n = len(tri)
+    z, w, W = bem.contour_nodes(4.0, 1.5, 16, P=2)
+    V = synth.probe_block(n, 16, seed=1)
+    corr = _correction_ref(xyz, tri, 2.0, z, W, V)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(2.0)
+        Vd = _dev(torch, V)
+        Cs = mesh.nearfield_moments(z, W, Vd).cpu().numpy()
+        terms = mesh.nearfield_last_terms()
+        Ss = mesh.assemble_sum(z, W[:, 0])
+        mesh.nearfield_sum(z, W[:, 0], Ss)
+        mesh.set_nearfield_mode(bem.NF_NODES)
+        Cn = mesh.nearfield_moments(z, W, Vd).cpu().numpy()
+        assert mesh.nearfield_last_terms() == 0
+        Sn = mesh.assemble_sum(z, W[:, 0])
+        mesh.nearfield_sum(z, W[:, 0], Sn)
+        mesh.set_nearfield_mode(bem.NF_AUTO)
+        Ss, Sn = Ss.cpu().numpy(), Sn.cpu().numpy()
+        with pytest.raises(bem.BemError):
+            mesh.set_nearfield_mode(2)
+    assert terms in (12, 16, 24, 32), terms
+    # error scale of either evaluation: sum_j |W[j, p]| |dT(z_j)| V, i.e. the p = 0 correction
+    # (no cancellation among its nodes) times the ratio of the weight sums; set p = 1 cancels
+    # to about 1e-5 of it, so its own norm is not the scale
+    for p in range(2):
+        ws = np.abs(W[:, p]).sum() / np.abs(W[:, 0]).sum()
+        scale = ws * np.linalg.norm(Cn[0])
+        e_sn = np.linalg.norm(Cs[p] - Cn[p]) / scale
+        e_so = np.linalg.norm(Cs[p] - corr[p]) / scale
+        print(f"{name} p={p}: {terms} terms; series vs per node {e_sn:.2e}, series vs oracle {e_so:.2e} "
+              f"(|corr_p| / scale {np.linalg.norm(Cn[p]) / scale:.1e})")
+        assert e_sn <= 1e-12 and e_so <= 1e-12
+        # row by row, on the same scale per row
+        rn = ws * np.linalg.norm(Cn[0], axis=1)
+        assert np.all(np.linalg.norm(Cs[p] - Cn[p], axis=1) <= 1e-11 * rn + 1e-300)
+    dS = Sn - Ss
+    print(f"{name}: dense node combination, series vs per node {np.abs(dS).max() / np.abs(Sn).max():.2e}")
+    assert np.abs(dS).max() <= 1e-13 * np.abs(Sn).max()
+
+
+def test_series_form_falls_back_to_per_node_when_the_series_is_long(bem, torch, oracle_lib):
+    """eta = 16 on the 80-triangle sphere: pairs span the whole surface, max |z| R_max is far
+    beyond what 32 terms resolve, so the per-node form runs (and matches the oracle)."""
+    xyz, tri = synth.perturbed_icosphere(1, 0.05, 9)
+    n = len(tri)
+    z = np.array([3.0 + 0.4j, 5.0 - 0.3j, 6.1 + 0.8j])
+    W = np.array([[1.0], [0.5 - 0.2j], [0.3j]])
+    V = synth.probe_block(n, 5, seed=3)
+    corr = _correction_ref(xyz, tri, 16.0, z, W, V)
+    with bem.Mesh(xyz, tri) as mesh:
+        mesh.set_nearfield(16.0)
+        Cg = mesh.nearfield_moments(z, W, _dev(torch, V)).cpu().numpy()
+        assert mesh.nearfield_last_terms() == 0
+    assert np.linalg.norm(Cg[0] - corr[0]) <= 1e-11 * np.linalg.norm(corr[0])
+
+
 def test_no_list_leaves_moments_unchanged_and_errors(bem, torch):
     xyz, tri = synth.icosphere(2)
     n = len(tri)

@@ -324,7 +324,9 @@ def test_gain_on_harmonic_sphere(env, trained):
     """Config 5's mesh and contour (harmonic-499280, |z - 5| = 1.5, N = 32, P = 2, m = 64): the
     network's correction of the leading moment within half of the quadrature's, per node and
     frozen at the contour centre (freeze_tol 1e-2), each trusting some pairs; the frozen mode
-    (one evaluation per pair) faster than the quadrature.  Times are printed."""
+    (one evaluation per pair) faster than the per-node quadrature, and the quadrature's series
+    form (exact to rounding, also one pass over the pairs) faster than the per-node quadrature.
+    Times are printed."""
     bem, _lib, nfnet, O, _clib, torch = env
     xyz, tri = synth.harmonic_sphere(158, seed=5)
     n = len(tri)
@@ -339,7 +341,13 @@ def test_gain_on_harmonic_sphere(env, trained):
         Mf, fbf = mesh.nearfield_moments_net(frozen.c_model(), z, W, V, count_fallback=True)
         torch.cuda.synchronize()
         times = {}
+        def per_node():
+            mesh.set_nearfield_mode(bem.NF_NODES)
+            mesh.nearfield_moments(z, W, V, out=Mq.zero_())
+            mesh.set_nearfield_mode(bem.NF_AUTO)
+
         for name, f in (("quadrature", lambda: mesh.nearfield_moments(z, W, V, out=Mq.zero_())),
+                        ("per-node quadrature", per_node),
                         ("network", lambda: mesh.nearfield_moments_net(trained.c_model(), z, W, V, out=Mn.zero_())),
                         ("frozen", lambda: mesh.nearfield_moments_net(frozen.c_model(), z, W, V, out=Mf.zero_()))):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -351,8 +359,10 @@ def test_gain_on_harmonic_sphere(env, trained):
         err = [float(torch.linalg.vector_norm(Mn[p] - Mq[p]) / torch.linalg.vector_norm(Mq[p])) for p in range(2)]
         errf = [float(torch.linalg.vector_norm(Mf[p] - Mq[p]) / torch.linalg.vector_norm(Mq[p])) for p in range(2)]
     print(f"harmonic-499280: {pairs} pairs, fallback {fb} (frozen {fbf}); correction rel err per node {err}, "
-          f"frozen {errf}; quadrature {times['quadrature']:.1f} ms, network {times['network']:.1f} ms, "
+          f"frozen {errf}; quadrature (series form) {times['quadrature']:.1f} ms, per-node quadrature "
+          f"{times['per-node quadrature']:.1f} ms, network {times['network']:.1f} ms, "
           f"frozen {times['frozen']:.1f} ms", flush=True)
     assert err[0] <= 0.5 and errf[0] <= 0.5
     assert fb < pairs and fbf < pairs
-    assert times["frozen"] < times["quadrature"]
+    assert times["frozen"] < times["per-node quadrature"]
+    assert times["quadrature"] < times["per-node quadrature"]
