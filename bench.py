@@ -404,7 +404,8 @@ def learned_near_field(freq=158, train_count=2_000_000, steps=40000):
     (seed 5), near pairs within 2 longest edges.  Trains the network on the GPU with the
     training driver's defaults (2 M seeded samples labelled by the library's quadrature,
     100 k for validation, 40,000 Adam steps of 2048, trust bound 0.2), then times, on the mesh, the folded moment sweep
-    once and the correction with the quadrature and with the network (median of 3), and
+    once and the correction with the quadrature (series form, and per node) and with the
+    network (median of 3), and
     compares the corrected moments: |M_net - M_quad| / |M_quad| per moment (the quadrature
     is the judge), beside the uncorrected moments' distance from the same judge."""
     import numpy as np
@@ -450,11 +451,17 @@ def learned_near_field(freq=158, train_count=2_000_000, steps=40000):
             return float(np.median(ms))
 
         model = net.c_model()
+        # the quadrature in its default series form (the judge) and per node
         res["quadrature_ms"] = timed(lambda o: mesh.nearfield_moments(z, W, V, out=o), Mq)
+        res["quadrature_series_terms"] = mesh.nearfield_last_terms()
+        mesh.set_nearfield_mode(bem.NF_NODES)
+        res["quadrature_per_node_ms"] = timed(lambda o: mesh.nearfield_moments(z, W, V, out=o), torch.zeros_like(M))
+        mesh.set_nearfield_mode(bem.NF_AUTO)
         res["network_ms"] = timed(lambda o: mesh.nearfield_moments_net(model, z, W, V, out=o), Mn)
         _, fb = mesh.nearfield_moments_net(model, z, W, V, out=torch.zeros_like(M), count_fallback=True)
         res["fallback_pairs"] = int(fb)
         res["network_speedup"] = res["quadrature_ms"] / res["network_ms"]
+        res["network_speedup_vs_per_node_quadrature"] = res["quadrature_per_node_ms"] / res["network_ms"]
         # the network frozen at the contour centre (one evaluation per pair), freeze_tol 1e-2
         fmodel = net.frozen(1e-2).c_model()
         Mfz = torch.zeros_like(M)
@@ -462,6 +469,7 @@ def learned_near_field(freq=158, train_count=2_000_000, steps=40000):
         _, fbf = mesh.nearfield_moments_net(fmodel, z, W, V, out=torch.zeros_like(M), count_fallback=True)
         res["frozen_fallback_pairs"] = int(fbf)
         res["frozen_speedup"] = res["quadrature_ms"] / res["frozen_ms"]
+        res["frozen_speedup_vs_per_node_quadrature"] = res["quadrature_per_node_ms"] / res["frozen_ms"]
         res["moment_error_frozen_vs_quadrature"] = [
             float(torch.linalg.vector_norm((M + Mfz)[p] - (M + Mq)[p]) / torch.linalg.vector_norm((M + Mq)[p]))
             for p in range(2)]
@@ -561,10 +569,14 @@ def near_field(mesh, U, z, W, sweep_kernel_ms, eta=2.0, freq=158):
 
     def both(msh, V, key):
         """Series form (the default) and per-node form: times, and their largest difference
-        per weight set relative to the correction's norm."""
+        per weight set on the error scale of either form, sum_j |W[j, p]| |dT(z_j)| V, taken
+        as the order-0 set's correction norm times the ratio of the weight sums (the order-1
+        set cancels to about 1e-5 of it, so its own norm is not the scale)."""
         ms_s, out_s, terms = timed(msh, V, bem.NF_AUTO)
         ms_n, out_n, _ = timed(msh, V, bem.NF_NODES)
-        diff = max(float(torch.linalg.vector_norm(out_s[p] - out_n[p]) / torch.linalg.vector_norm(out_n[p]))
+        base = float(torch.linalg.vector_norm(out_n[0]))
+        aw = np.abs(W).sum(axis=0)
+        diff = max(float(torch.linalg.vector_norm(out_s[p] - out_n[p])) / (base * aw[p] / aw[0])
                    for p in range(out_s.shape[0]))
         del out_s, out_n
         return {f"{key}_ms": ms_s, f"{key}_series_terms": terms, f"{key}_per_node_ms": ms_n,
