@@ -407,7 +407,7 @@ def learned_near_field(freq=158, train_count=2_000_000, steps=40000):
     once and the correction with the quadrature (series form, and per node) and with the
     network (median of 3), and
     compares the corrected moments: |M_net - M_quad| / |M_quad| per moment (the quadrature
-    is the judge), beside the uncorrected moments' distance from the same judge."""
+    is the reference), beside the uncorrected moments' distance from the same reference."""
     import numpy as np
     import torch
 
@@ -451,7 +451,7 @@ def learned_near_field(freq=158, train_count=2_000_000, steps=40000):
             return float(np.median(ms))
 
         model = net.c_model()
-        # the quadrature in its default series form (the judge) and per node
+        # the quadrature in its default series form (the reference) and per node
         res["quadrature_ms"] = timed(lambda o: mesh.nearfield_moments(z, W, V, out=o), Mq)
         res["quadrature_series_terms"] = mesh.nearfield_last_terms()
         mesh.set_nearfield_mode(bem.NF_NODES)

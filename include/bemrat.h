@@ -283,7 +283,7 @@ bem_status bem_assemble_sum(bem_mesh_t mesh, const double *z, int64_t N, const d
  * with three hidden layers of 128 tanh units maps a near pair's source triangle, target point
  * and wavenumber to the correction dT = (integral of g over the triangle) - (its 7-point value),
  * trained on the GPU by the kernels below on triples labelled by bem_nf_labels; the quadrature
- * of bem_nearfield_moments stays the fallback outside the network's trust region and its judge.
+ * of bem_nearfield_moments stays the fallback outside the network's trust region and its reference.
  *
  * Inputs (19, padded to BEM_NET_INPUTS floats per row): in the unit frame of the source
  * triangle (its longest edge A -> B on the x axis, the first longest of P0P1, P1P2, P2P0;

@@ -2,7 +2,7 @@
 // that maps a (source triangle, target point, wavenumber) triple to the correction
 // dT = (integral of g over the triangle) - (its 7-point value), g(r) = exp(i kappa r)/(4 pi r),
 // trained on triples labelled by the library's own polar quadrature (nearfield.hip), which
-// stays the fallback and the judge.  Not a step of the paper's method: a surrogate for the
+// stays the fallback and the reference.  Not a step of the paper's method: a surrogate for the
 // near-field refinement of the boundary integral of Section 1 (eq. GreenFun).
 //
 // Inputs.  In the unit frame of the source triangle (its longest edge A -> B on the x axis,

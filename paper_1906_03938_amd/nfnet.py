@@ -6,7 +6,7 @@ source triangle (synth.nearfield_samples) are labelled by the library's polar qu
 (bem_nf_labels), turned into inputs (bem_net_features), and fitted by mini-batch Adam on the
 mean squared error of the scaled correction (bem_net_gradient, bem_net_adam).  A held-out set
 labelled the same way gives the validation error per distance bin; bins whose error exceeds
-the bound are left to the quadrature (the model's trust region), which stays the judge.
+the bound are left to the quadrature (the model's trust region), which stays the reference.
 
 Host work here is data movement and bookkeeping only: the sampling of inputs, the output scale
 (a standard deviation of the labels), the learning-rate schedule and the per-bin error

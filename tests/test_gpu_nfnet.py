@@ -13,7 +13,7 @@ oracle/bem_oracle.c), through the C ABI.
 * the learned moments (bem_nearfield_moments_net): with no bin trusted they equal the
   quadrature's bitwise; trusted, each pair's FP16 correction matches the oracle's FP64
   network on the same parameters to 1e-2 of the largest correction, and the corrected moments
-  beat the uncorrected ones against the quadrature judge;
+  beat the uncorrected ones against the quadrature reference;
 * the gain on the near-field workload "harmonic-499280" (geodesic f = 158 sphere with
   harmonic bumps, eta = 2, |z - 5| = 1.5, N = 32, P = 2, m = 64): error of the network's
   correction against the quadrature's, and both times.
@@ -265,7 +265,7 @@ def test_frozen_inference_matches_oracle_network(env, trained):
 
 def test_learned_correction_beats_no_correction(env, trained):
     """Moments of the corrected operator (7-point sweep plus near-field correction) against the
-    quadrature judge: with the network's correction the error is a fraction of the correction
+    quadrature reference: with the network's correction the error is a fraction of the correction
     itself, the error of leaving it out, for the leading moment; the derivative moment is
     reported (per-node FP16 rounding does not cancel in its weights)."""
     bem, _lib, nfnet, O, _clib, torch = env
