@@ -109,11 +109,14 @@ def test_corrected_moments_match_oracle(bem, torch, oracle_lib, name):
     assert np.linalg.norm(corr[0]) >= 1e3 * TOL * np.linalg.norm(full[0])
 
 
-def test_many_weight_sets_ragged_and_strided(bem, torch, oracle_lib):
+@pytest.mark.parametrize("level,keep,eta,series", [(2, 301, 2.5, False), (3, 1201, 2.0, True)])
+def test_many_weight_sets_ragged_and_strided(bem, torch, oracle_lib, level, keep, eta, series):
     """P = 11 (two launches of up to 8 weight sets), per-node weights (W = I gives
-    dT(z_j) V), m = 5 inside a strided probe block, a ragged mesh size."""
-    xyz, tri = synth.perturbed_icosphere(2, 0.08, 7)
-    tri = tri[:301]
+    dT(z_j) V), m = 5 inside a strided probe block, a ragged mesh size; on the coarse mesh the
+    series would need more than 32 terms (per-node form), on the finer one it takes the series
+    form."""
+    xyz, tri = synth.perturbed_icosphere(level, 0.08, 7)
+    tri = tri[:keep]
     used = np.unique(tri)
     remap = -np.ones(len(xyz), dtype=np.int64)
     remap[used] = np.arange(used.size)
@@ -124,12 +127,13 @@ def test_many_weight_sets_ragged_and_strided(bem, torch, oracle_lib):
     W = rng.normal(size=(5, 11)) + 1j * rng.normal(size=(5, 11))
     Vfull = synth.probe_block(n, 9, seed=2)
     V = Vfull[:, 2:7]
-    corr = _correction_ref(xyz, tri, 2.5, z, W, V)
-    corr_id = _correction_ref(xyz, tri, 2.5, z, np.eye(5, dtype=np.complex128), V)
+    corr = _correction_ref(xyz, tri, eta, z, W, V)
+    corr_id = _correction_ref(xyz, tri, eta, z, np.eye(5, dtype=np.complex128), V)
     with bem.Mesh(xyz, tri) as mesh:
-        mesh.set_nearfield(2.5)
+        mesh.set_nearfield(eta)
         Vd = _dev(torch, Vfull)[:, 2:7]
         Cg = mesh.nearfield_moments(z, W, Vd).cpu().numpy()
+        assert (mesh.nearfield_last_terms() > 0) == series
         Ig = mesh.nearfield_moments(z, np.eye(5), Vd).cpu().numpy()
     for p in range(11):
         assert np.linalg.norm(Cg[p] - corr[p]) <= 1e-11 * np.linalg.norm(corr[p])
