@@ -1389,7 +1389,7 @@ bem_status folded_moments(bem_mesh *h, const Plan &plan, const Work &w, size_t o
         HIP_TRY(hipEventRecord(h->ev1, s), "event record");
         h->timed = true;
     }
-    h->last_form = plan.gen == bemrat::Gen::Direct ? BEM_FORM_DIRECT : BEM_FORM_EXPAND;
+    h->last_form = is_direct(plan.gen) ? BEM_FORM_DIRECT : BEM_FORM_EXPAND;
     h->last_ops = plan.L;
     return BEM_OK;
 }
@@ -1414,7 +1414,7 @@ bem_status contour_moments_impl(bem_mesh_t h, const double *z, int64_t N, const 
     // m = 64, 1.05x at m = 32 for P = 2; slower than the unfolded sweep at P = 8, where the
     // producer's folding work outweighs the saved contractions)
     const bool fold = plan.prec == bemrat::Prec::F64 && plan.gen != bemrat::Gen::Cheb && P <= 2;
-    if (!fold) symmetrize(plan);
+    symmetrize(plan);
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;

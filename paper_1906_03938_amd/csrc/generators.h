@@ -419,6 +419,65 @@ struct FoldGenerator<NOPS, Gen::Direct, DECAY> {
     }
 };
 
+// Direct form on node quadruples (as Generator<.., DirectSym, ..>), folded: each quadruple's
+// four entries are formed with one exp(-y r), its reciprocal and one sincos of x r per point
+// (exp(2icr) once per point for the whole entry) and folded with the weights at once.
+template <int NOPS, bool DECAY>
+struct FoldGenerator<NOPS, Gen::DirectSym, DECAY> {
+    static_assert(DECAY, "quadruples have Im != 0");
+    __device__ void init(const SweepArgs &, int) {}
+    __device__ __forceinline__ void fold(const SweepArgs &p, int l, double er, double ei, double (&ar)[NOPS],
+                                         double (&ai)[NOPS]) const {
+#pragma unroll
+        for (int k = 0; k < NOPS; ++k) {
+            if (k < p.L) {
+                const double2 w = p.fcoef[(int64_t)l * p.L + k];
+                ar[k] = fma(w.x, er, fma(-w.y, ei, ar[k]));
+                ai[k] = fma(w.x, ei, fma(w.y, er, ai[k]));
+            }
+        }
+    }
+    __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
+                                            const SweepArgs &p, double2 (&out)[NOPS]) const {
+        const double c2 = 2.0 * p.c_re;
+        double sc[kQuad], cc[kQuad];  // exp(2icr)
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) sincos_cw(c2 * r[q], sc[q], cc[q]);
+        double ar[NOPS], ai[NOPS];
+#pragma unroll
+        for (int k = 0; k < NOPS; ++k) ar[k] = ai[k] = 0.0;
+        for (int g = 0; g < p.Lgen; g += 4) {  // uniform over the block; Lgen is a multiple of 4
+            const double2 kap = p.kappa[g];
+            double gr[4], gi[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) gr[j] = gi[j] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kQuad; ++q) {
+                const double E = exp_cw(-kap.y * r[q]);
+                double Ei = __builtin_amdgcn_rcp(E);
+                Ei = fma(fma(-E, Ei, 1.0), Ei, Ei);
+                Ei = fma(fma(-E, Ei, 1.0), Ei, Ei);
+                const double e1 = E * wr[q], e2 = Ei * wr[q];
+                double s1, c1;
+                sincos_cw(kap.x * r[q], s1, c1);
+                const double c2v = fma(cc[q], c1, sc[q] * s1), s2v = fma(sc[q], c1, -(cc[q] * s1));
+                gr[0] = fma(e1, c1, gr[0]);
+                gi[0] = fma(e1, s1, gi[0]);
+                gr[1] = fma(e2, c1, gr[1]);
+                gi[1] = fma(e2, s1, gi[1]);
+                gr[2] = fma(e1, c2v, gr[2]);
+                gi[2] = fma(e1, s2v, gi[2]);
+                gr[3] = fma(e2, c2v, gr[3]);
+                gi[3] = fma(e2, s2v, gi[3]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fold(p, g + j, gr[j], gi[j], ar, ai);
+        }
+#pragma unroll
+        for (int k = 0; k < NOPS; ++k) out[k] = make_double2(ar[k], ai[k]);
+    }
+};
+
 // Chebyshev (Jacobi-Anger) form for real nodes kappa = alpha + beta xi, xi in [-1, 1]:
 // exp(i kappa r) = exp(i alpha r) sum_l eps_l i^l J_l(beta r) T_l(xi), so with the factors
 // eps_l i^l left to the host's recombination, operator l has entries

@@ -374,6 +374,8 @@ hipError_t launch_sweep_fold(Gen gen, const SweepArgs &args, hipStream_t stream)
             return decay ? launch_fold_gen<Gen::Direct, true>(args, stream) : launch_fold_gen<Gen::Direct, false>(args, stream);
         case Gen::Taylor:
             return decay ? launch_fold_gen<Gen::Taylor, true>(args, stream) : launch_fold_gen<Gen::Taylor, false>(args, stream);
+        case Gen::DirectSym:  // quadruples have Im != 0
+            return decay ? launch_fold_gen<Gen::DirectSym, true>(args, stream) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
