@@ -1353,13 +1353,13 @@ bem_status bem_assemble_apply(bem_mesh_t h, const double *kappa, int64_t nk, con
 
 namespace {
 
-// Folded moments (FP64, direct or expansion plans, P <= kFoldMax): the sweep generates every
+// Folded moments (FP64, direct or expansion plans, P <= kFoldMax = 2): the sweep generates every
 // operator of each entry and contracts only the P combinations sum_l coef[l][p] T_l, written
 // straight to M; the diagonal is the same combination of the self terms.  The parameter
 // block is at w.params already.
 bem_status folded_moments(bem_mesh *h, const Plan &plan, const Work &w, size_t off_k, size_t off_dft, int K,
-                          size_t off_tables, size_t off_coef, int P, const double *V, int64_t m, int64_t ldv,
-                          double *M, int64_t ldm, hipStream_t s) {
+                          size_t off_tables, size_t off_coef, size_t off_fcoef, int P, const double *V, int64_t m,
+                          int64_t ldv, double *M, int64_t ldm, hipStream_t s) {
     const DeviceMesh &dm = h->dm;
     const double *pbase = w.params;
     const double2 *coef = reinterpret_cast<const double2 *>(pbase + off_coef);
@@ -1374,7 +1374,7 @@ bem_status folded_moments(bem_mesh *h, const Plan &plan, const Work &w, size_t o
     bemrat::SweepArgs a = sweep_args(dm, plan, pbase, off_k, off_tables, w.fself);
     a.L = P;
     a.Lgen = plan.L;
-    a.fcoef = coef;
+    a.fcoef = reinterpret_cast<const double2 *>(pbase + off_fcoef);
     a.Vp2 = Vp2;
     a.m_pad = m_pad;
     a.V = reinterpret_cast<const double2 *>(V);
@@ -1413,7 +1413,8 @@ bem_status contour_moments_impl(bem_mesh_t h, const double *z, int64_t N, const 
     // the folded sweep pays off for one or two weight sets (measured at n = 81920: 1.47x at
     // m = 64, 1.05x at m = 32 for P = 2; slower than the unfolded sweep at P = 8, where the
     // producer's folding work outweighs the saved contractions)
-    const bool fold = plan.prec == bemrat::Prec::F64 && plan.gen != bemrat::Gen::Cheb && P <= 2;
+    const bool fold = plan.prec == bemrat::Prec::F64 && plan.gen != bemrat::Gen::Cheb && P <= 2 &&
+                      (int64_t)plan.L * P <= bemrat::kFoldCoef;
     symmetrize(plan);
     Params prm;
     const size_t off_tables = add_tables(prm);
@@ -1429,6 +1430,18 @@ bem_status contour_moments_impl(bem_mesh_t h, const double *z, int64_t N, const 
             for (int64_t p = 0; p < P; ++p) coef[l * P + p] += cf * cplx(W[2 * (j * P + p)], W[2 * (j * P + p) + 1]);
         }
     const size_t off_coef = add_complex(prm, coef);
+    // the folded generator's coefficients: for Taylor plans times each operator's own factor
+    // i^l / l! (the generator folds the plain power sums)
+    size_t off_fcoef = off_coef;
+    if (fold && plan.gen == bemrat::Gen::Taylor) {
+        std::vector<cplx> fc(coef);
+        cplx f = 1.0;
+        for (int l = 0; l < plan.L; ++l) {
+            if (l > 0) f *= cplx(0.0, 1.0 / l);
+            for (int64_t p = 0; p < P; ++p) fc[l * P + p] *= f;
+        }
+        off_fcoef = add_complex(prm, fc);
+    }
     Need need = sweep_need(h, plan, K, m);
     need.params = prm.d.size() * sizeof(double);
     const size_t zstride = (size_t)h->dm.n * m;
@@ -1438,7 +1451,8 @@ bem_status contour_moments_impl(bem_mesh_t h, const double *z, int64_t N, const 
     if ((st = noalloc ? acquire_scratch(need, w) : acquire_handle(h, need, w)) != BEM_OK) return st;
     if ((st = upload_to(h, prm, w.params, noalloc, stream)) != BEM_OK) return st;
     if (fold)
-        return folded_moments(h, plan, w, off_k, off_dft, K, off_tables, off_coef, (int)P, V, m, ldv, M, ldm, stream);
+        return folded_moments(h, plan, w, off_k, off_dft, K, off_tables, off_coef, off_fcoef, (int)P, V, m, ldv, M,
+                              ldm, stream);
     if ((st = run_sweep(h, plan, w, V, m, ldv, w.Z, m, zstride, off_k, off_dft, K, off_tables, stream)) != BEM_OK)
         return st;
     HIP_TRY(bemrat::launch_combine(w.Z, zstride, m, plan.L, reinterpret_cast<const double2 *>(w.params + off_coef),

@@ -306,23 +306,35 @@ struct Generator<16, Gen::Taylor, DECAY, LOWP> {
     }
 };
 
-// Folded generators: all p.Lgen operators of one entry, combined into the NOPS outputs
-// out[k] = sum_l fcoef[l][k] T_l (k < p.L; zero beyond).  The Taylor form computes each
-// point's distance, exp(i c r) and weight once and runs the power chain through all the
-// operators in passes of eight (the point term advanced by x^8 between passes, the factorial
-// ratios continuing); the direct form generates its nodes in passes of eight.
-template <int NOPS, Gen GEN, bool DECAY>
+// Folded generators: all p.Lgen operators of one entry, combined into the outputs
+// out[k] = sum_l fcoef[l][k] T_l, k < KL = p.L (zero beyond, up to NOPS), the coefficients
+// read from the block's LDS copy (set_coef).  The Taylor form computes each point's distance, exp(i c r)
+// and weight once and runs the power chain through all the operators in passes of eight
+// (the point term advanced by x^8 between passes; the factors i^l / l! are in the
+// coefficients); the direct form generates its nodes in passes of eight (of quadruples for
+// DirectSym).
+typedef const __attribute__((address_space(3))) double lds_double;
+struct FoldCoef {
+    const double2 *fc = nullptr;  // LDS, Lgen x L
+    __device__ void set_coef(const double2 *c) { fc = c; }
+    __device__ __forceinline__ double2 coef(int i) const {
+        lds_double *d = (lds_double *)fc;
+        return make_double2(d[2 * i], d[2 * i + 1]);
+    }
+};
+
+template <int NOPS, Gen GEN, bool DECAY, int KL>
 struct FoldGenerator;
 
-template <int NOPS, bool DECAY>
-struct FoldGenerator<NOPS, Gen::Taylor, DECAY> {
+template <int NOPS, bool DECAY, int KL>
+struct FoldGenerator<NOPS, Gen::Taylor, DECAY, KL> : FoldCoef {
     __device__ void init(const SweepArgs &, int) {}
     __device__ __forceinline__ void fold(const SweepArgs &p, int l, double er, double ei, double (&ar)[NOPS],
                                          double (&ai)[NOPS]) const {
 #pragma unroll
-        for (int k = 0; k < NOPS; ++k) {
-            if (k < p.L) {
-                const double2 w = p.fcoef[(int64_t)l * p.L + k];
+        for (int k = 0; k < KL; ++k) {
+            {
+                const double2 w = coef(l * p.L + k);
                 ar[k] = fma(w.x, er, fma(-w.y, ei, ar[k]));
                 ai[k] = fma(w.x, ei, fma(w.y, er, ai[k]));
             }
@@ -343,7 +355,7 @@ struct FoldGenerator<NOPS, Gen::Taylor, DECAY> {
         double ar[NOPS], ai[NOPS];
 #pragma unroll
         for (int k = 0; k < NOPS; ++k) ar[k] = ai[k] = 0.0;
-        double c = 1.0;  // 1 / l!
+#pragma unroll 1
         for (int h = 0; h < p.Lgen; h += 8) {  // uniform over the block
             double gr[8], gi[8];
 #pragma unroll
@@ -364,26 +376,15 @@ struct FoldGenerator<NOPS, Gen::Taylor, DECAY> {
                 yi[q] *= xp;
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (h + j > 0) c *= p.inv_int[min(h + j, kMaxTaylor - 1)];
-                const double a = gr[j] * c, b = gi[j] * c;
-                double er, ei;
-                switch (j & 3) {  // times i^(h + j) = i^j (h a multiple of 8)
-                    case 0: er = a; ei = b; break;
-                    case 1: er = -b; ei = a; break;
-                    case 2: er = -a; ei = -b; break;
-                    default: er = b; ei = -a; break;
-                }
-                fold(p, h + j, er, ei, ar, ai);
-            }
+            for (int j = 0; j < 8; ++j) fold(p, h + j, gr[j], gi[j], ar, ai);
         }
 #pragma unroll
         for (int k = 0; k < NOPS; ++k) out[k] = make_double2(ar[k], ai[k]);
     }
 };
 
-template <int NOPS, bool DECAY>
-struct FoldGenerator<NOPS, Gen::Direct, DECAY> {
+template <int NOPS, bool DECAY, int KL>
+struct FoldGenerator<NOPS, Gen::Direct, DECAY, KL> : FoldCoef {
     __device__ void init(const SweepArgs &, int) {}
     __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
                                             const SweepArgs &p, double2 (&out)[NOPS]) const {
@@ -405,9 +406,9 @@ struct FoldGenerator<NOPS, Gen::Direct, DECAY> {
                     gi = fma(e, sn, gi);
                 }
 #pragma unroll
-                for (int k = 0; k < NOPS; ++k) {
-                    if (k < p.L) {
-                        const double2 w = p.fcoef[(int64_t)(h + j) * p.L + k];
+                for (int k = 0; k < KL; ++k) {
+                    {
+                        const double2 w = coef((h + j) * p.L + k);
                         ar[k] = fma(w.x, gr, fma(-w.y, gi, ar[k]));
                         ai[k] = fma(w.x, gi, fma(w.y, gr, ai[k]));
                     }
@@ -422,16 +423,16 @@ struct FoldGenerator<NOPS, Gen::Direct, DECAY> {
 // Direct form on node quadruples (as Generator<.., DirectSym, ..>), folded: each quadruple's
 // four entries are formed with one exp(-y r), its reciprocal and one sincos of x r per point
 // (exp(2icr) once per point for the whole entry) and folded with the weights at once.
-template <int NOPS, bool DECAY>
-struct FoldGenerator<NOPS, Gen::DirectSym, DECAY> {
+template <int NOPS, bool DECAY, int KL>
+struct FoldGenerator<NOPS, Gen::DirectSym, DECAY, KL> : FoldCoef {
     static_assert(DECAY, "quadruples have Im != 0");
     __device__ void init(const SweepArgs &, int) {}
     __device__ __forceinline__ void fold(const SweepArgs &p, int l, double er, double ei, double (&ar)[NOPS],
                                          double (&ai)[NOPS]) const {
 #pragma unroll
-        for (int k = 0; k < NOPS; ++k) {
-            if (k < p.L) {
-                const double2 w = p.fcoef[(int64_t)l * p.L + k];
+        for (int k = 0; k < KL; ++k) {
+            {
+                const double2 w = coef(l * p.L + k);
                 ar[k] = fma(w.x, er, fma(-w.y, ei, ar[k]));
                 ai[k] = fma(w.x, ei, fma(w.y, er, ai[k]));
             }

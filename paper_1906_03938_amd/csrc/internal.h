@@ -91,9 +91,13 @@ hipError_t launch_add_diag(const double2 *S, int64_t n_pad, const double2 *V, in
 int sweep_lp_ops_per_block(Gen gen, int64_t m);
 int64_t sweep_lp_m_pad(int64_t m);  // column padding of the probe copy for the reduced-precision sweep
 // Folded FP64 sweep for the moments of Direct or Taylor plans: the producer generates all
-// args.Lgen operators of each entry and folds them into args.L <= kFoldMax combinations
-// (args.fcoef), the consumers contract only those and write them to args.Z like operators.
-constexpr int kFoldMax = 8;
+// args.Lgen operators of each entry and folds them into args.L <= kFoldMax = 2 combinations
+// (args.fcoef, Lgen x L, at most kFoldCoef entries: the block keeps them in LDS), the
+// consumers contract only those and write them to args.Z like operators.  For Taylor plans
+// fcoef[l][k] carries the operator's own factor i^l / l! (the generator folds the plain
+// power sums sum_q y_q x_q^l).
+constexpr int kFoldMax = 2;
+constexpr int kFoldCoef = 512;
 hipError_t launch_sweep_fold(Gen gen, const SweepArgs &args, hipStream_t stream);
 
 // Length unit of the expansion forms (their L is a multiple of it): 8.  The FP64 sweep

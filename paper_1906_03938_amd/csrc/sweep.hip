@@ -64,9 +64,9 @@ constexpr int ops_g(Gen gen, int cb) { return gen == Gen::Taylor && cb <= 2 ? 4 
 // One tile: 16 target rows from row0, 16 CB columns from col0, operators L0 .. L0 + 4 G - 1,
 // by the 512 threads of the block.  Used by the per-call kernel (one tile per block) and by
 // the batched persistent kernel (tiles of several meshes taken from a work queue).
-template <int G, int CB, Gen GEN, bool DECAY, bool CAST, bool FOLD = false>
+template <int G, int CB, Gen GEN, bool DECAY, bool CAST, int FOLDK = 0>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &p, int64_t row0, int64_t col0, int L0,
-                                           TileLds<G, CB> &lds) {
+                                           TileLds<G, CB> &lds, double2 *sFc = nullptr) {
     constexpr int NC = 16 * CB;
     constexpr int NOPS = 4 * G;
     constexpr int VPT = kStage * NC / 256;  // staged probe elements per producer thread (1, 2, 4)
@@ -76,6 +76,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &p, int64_t row0, int
 
     const int tid = threadIdx.x;
     const int64_t nstages = p.n_pad / kStage;
+    constexpr bool FOLD = FOLDK > 0;
+    if constexpr (FOLD) {
+        // the fold coefficients (Lgen x L <= kFoldCoef) into LDS; the first barrier of both
+        // roles below publishes them
+        for (int i = tid; i < p.Lgen * p.L; i += 512) sFc[i] = ld<CAST>(p.fcoef, i);
+    }
 
     if (tid < 256) {
         // ---- producer: thread t generates row t & 15, stage triangle t >> 4
@@ -83,8 +89,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &p, int64_t row0, int
         const int brow = tid & 15, btri = tid >> 4;
         const int64_t grow = row0 + brow;
         const double4 xa = ld<CAST>(p.colloc, grow);
-        std::conditional_t<FOLD, FoldGenerator<NOPS, GEN, DECAY>, Generator<NOPS, GEN, DECAY>> gen;
+        std::conditional_t<FOLD, FoldGenerator<NOPS, GEN, DECAY, FOLDK>, Generator<NOPS, GEN, DECAY>> gen;
         gen.init(p, L0);
+        if constexpr (FOLD) gen.set_coef(sFc);
         int64_t voff[VPT];
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
@@ -215,36 +222,35 @@ __global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
 }
 
 // Folded form: one block per (row block, column block) generates every operator of its
-// entries and contracts the p.L <= 4 G folds.
-template <int G, int CB, Gen GEN, bool DECAY>
+// entries and contracts the KL = p.L (1 or 2) folds, on a tile of 4 operators.
+template <int CB, Gen GEN, bool DECAY, int KL>
 __global__ __launch_bounds__(512, 1) void sweep_fold_kernel(SweepArgs p) {
-    __shared__ TileLds<G, CB> lds;
-    sweep_tile<G, CB, GEN, DECAY, false, true>(p, (int64_t)blockIdx.x * 16, (int64_t)blockIdx.y * 16 * CB, 0, lds);
+    __shared__ TileLds<1, CB> lds;
+    __shared__ double2 sFc[kFoldCoef];
+    sweep_tile<1, CB, GEN, DECAY, false, KL>(p, (int64_t)blockIdx.x * 16, (int64_t)blockIdx.y * 16 * CB, 0, lds, sFc);
 }
 
-template <int G, int CB, Gen GEN, bool DECAY>
+template <int CB, Gen GEN, bool DECAY, int KL>
 hipError_t launch_fold_t(const SweepArgs &p, hipStream_t stream) {
     constexpr int NC = 16 * CB;
     dim3 grid((unsigned)(p.n_pad / 16), (unsigned)((p.m + NC - 1) / NC), 1u);
-    hipLaunchKernelGGL((sweep_fold_kernel<G, CB, GEN, DECAY>), grid, dim3(512), 0, stream, p);
+    hipLaunchKernelGGL((sweep_fold_kernel<CB, GEN, DECAY, KL>), grid, dim3(512), 0, stream, p);
     return hipGetLastError();
+}
+
+template <Gen GEN, bool DECAY, int KL>
+hipError_t launch_fold_k(const SweepArgs &p, hipStream_t stream) {
+    const int cb = p.m <= 16 ? 1 : (p.m <= 32 ? 2 : 4);
+    switch (cb) {
+        case 1: return launch_fold_t<1, GEN, DECAY, KL>(p, stream);
+        case 2: return launch_fold_t<2, GEN, DECAY, KL>(p, stream);
+        default: return launch_fold_t<4, GEN, DECAY, KL>(p, stream);
+    }
 }
 
 template <Gen GEN, bool DECAY>
 hipError_t launch_fold_gen(const SweepArgs &p, hipStream_t stream) {
-    const int cb = p.m <= 16 ? 1 : (p.m <= 32 ? 2 : 4);
-    if (p.L <= 4) {
-        switch (cb) {
-            case 1: return launch_fold_t<1, 1, GEN, DECAY>(p, stream);
-            case 2: return launch_fold_t<1, 2, GEN, DECAY>(p, stream);
-            default: return launch_fold_t<1, 4, GEN, DECAY>(p, stream);
-        }
-    }
-    switch (cb) {
-        case 1: return launch_fold_t<2, 1, GEN, DECAY>(p, stream);
-        case 2: return launch_fold_t<2, 2, GEN, DECAY>(p, stream);
-        default: return launch_fold_t<2, 4, GEN, DECAY>(p, stream);
-    }
+    return p.L == 1 ? launch_fold_k<GEN, DECAY, 1>(p, stream) : launch_fold_k<GEN, DECAY, 2>(p, stream);
 }
 
 template <int G, int CB, Gen GEN, bool DECAY>
@@ -367,7 +373,7 @@ hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, cons
 }
 
 hipError_t launch_sweep_fold(Gen gen, const SweepArgs &args, hipStream_t stream) {
-    if (args.L < 1 || args.L > kFoldMax || args.Lgen < 1) return hipErrorInvalidValue;
+    if (args.L < 1 || args.L > kFoldMax || args.Lgen < 1 || args.Lgen * args.L > kFoldCoef) return hipErrorInvalidValue;
     const bool decay = args.decay != 0;
     switch (gen) {
         case Gen::Direct:
