@@ -1812,7 +1812,12 @@ struct bem_batch {
     std::vector<size_t> off_coef, off_probe, off_Z;
     int64_t nitems = 0;
     std::vector<size_t> off_self;
-    Buffer params, self, probe, Z, table, items, counter, vmax;
+    // folded (FP64, one or two weight sets): each mesh's fold coefficients, folded diagonal,
+    // and the P x P identity that copies its folds out of Z
+    bool fold = false;
+    std::vector<size_t> off_fcoef, off_fself;
+    size_t off_eye = 0;
+    Buffer params, self, probe, Z, table, items, counter, vmax, fself;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timing = false, timed = false;
 };
@@ -1836,6 +1841,9 @@ int batch_max_col_tile(const bem_batch *b) {
 }
 
 hipError_t batch_launch(const bem_batch *b, int cb, int nitems, hipStream_t s) {
+    if (b->fold)
+        return bemrat::launch_sweep_fold_batch(b->variant, cb, (int)b->P, b->table.as<bemrat::BatchEntry>(),
+                                               b->items.as<int4>(), nitems, b->counter.as<unsigned>(), b->grid, s);
     if (b->prec == bemrat::Prec::F64)
         return bemrat::launch_sweep_batch(b->variant, cb, b->table.as<bemrat::BatchEntry>(), b->items.as<int4>(),
                                           nitems, b->counter.as<unsigned>(), b->grid, s);
@@ -1857,7 +1865,7 @@ std::vector<int4> batch_items(const bem_batch *b, int cb) {
     for (int64_t i : order) {
         const int64_t rblocks = b->meshes[i]->dm.n_pad / 16;
         const int ops = batch_ops_per_item(b, cb);
-        const int64_t oblocks = (b->ops[i] + ops - 1) / ops;
+        const int64_t oblocks = b->fold ? 1 : (b->ops[i] + ops - 1) / ops;
         for (int64_t ob = 0; ob < oblocks; ++ob)
             for (int64_t c = 0; c < cblocks; ++c)
                 for (int64_t r = 0; r < rblocks; ++r) items.push_back(make_int4((int)i, (int)r, (int)c, (int)ob));
@@ -1929,6 +1937,7 @@ void bem_batch_destroy(bem_batch_t b) {
     b->items.release();
     b->counter.release();
     b->vmax.release();
+    b->fself.release();
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     delete b;
@@ -2005,6 +2014,9 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
                                        decay);
     b->prec = prec;
     b->meshes.assign(meshes, meshes + count);
+    // FP64 with one or two weight sets folds them into the sweep, as contour_moments does
+    b->fold = !lp && P <= bemrat::kFoldMax;
+    for (const Plan &p : plans) b->fold = b->fold && (int64_t)p.L * P <= bemrat::kFoldCoef;
     const int max_cb = batch_max_col_tile(b);
     b->cb = max_cb;
     b->m_pad = (m + 16 * max_cb - 1) / (16 * max_cb) * (16 * max_cb);
@@ -2024,7 +2036,9 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
     b->off_coef.resize(count);
     b->off_probe.resize(count);
     b->off_Z.resize(count);
-    size_t self_total = 0, probe_total = 0, z_total = 0, aux_need = 0;
+    b->off_fcoef.assign(count, 0);
+    b->off_fself.assign(count, 0);
+    size_t self_total = 0, probe_total = 0, z_total = 0, aux_need = 0, fself_total = 0;
     for (int64_t i = 0; i < count; ++i) {
         const Plan &plan = plans[i];
         const DeviceMesh &dm = meshes[i]->dm;
@@ -2039,6 +2053,20 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
                     coef[l * P + p] += cf * cplx(Wi[2 * (j * P + p)], Wi[2 * (j * P + p) + 1]);
             }
         b->off_coef[i] = add_complex(prm, coef);
+        if (b->fold) {
+            // the generator's fold coefficients (Taylor: times i^l / l!, as contour_moments)
+            std::vector<cplx> fc(coef);
+            if (plan.gen == bemrat::Gen::Taylor) {
+                cplx f = 1.0;
+                for (int l = 0; l < plan.L; ++l) {
+                    if (l > 0) f *= cplx(0.0, 1.0 / l);
+                    for (int64_t p = 0; p < P; ++p) fc[l * P + p] *= f;
+                }
+            }
+            b->off_fcoef[i] = add_complex(prm, fc);
+            b->off_fself[i] = fself_total;
+            fself_total += (size_t)P * dm.n_pad;
+        }
         b->ops[i] = plan.L;
         b->rows[i + 1] = b->rows[i] + dm.n;
         off_self[i] = self_total;
@@ -2046,8 +2074,13 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
         b->off_probe[i] = probe_total;
         probe_total += (size_t)dm.n_pad * b->m_pad;
         b->off_Z[i] = z_total;
-        z_total += (size_t)plan.L * dm.n * m;
+        z_total += (size_t)(b->fold ? P : plan.L) * dm.n * m;
         aux_need = std::max(aux_need, (size_t)K[i] * dm.n_pad);
+    }
+    if (b->fold) {
+        std::vector<cplx> eye((size_t)P * P, 0.0);
+        for (int64_t p = 0; p < P; ++p) eye[p * P + p] = 1.0;
+        b->off_eye = add_complex(prm, eye);
     }
     Buffer aux;
     st = BEM_OK;
@@ -2064,6 +2097,7 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
         step(b->table.ensure(sizeof(bemrat::BatchEntry) * count), "batch table") &&
         step(b->counter.ensure(sizeof(unsigned)), "work counter") &&
         step(b->vmax.ensure(sizeof(unsigned long long) * count), "probe scales") &&
+        step(b->fself.ensure(sizeof(double2) * std::max<size_t>(fself_total, 1)), "folded self terms") &&
         step(aux.ensure(sizeof(double2) * std::max<size_t>(aux_need, 1)), "self-term samples") &&
         step(hipEventCreate(&b->ev0), "event") && step(hipEventCreate(&b->ev1), "event")) {
         const double *pbase = b->params.as<double>();
@@ -2074,7 +2108,20 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
             if (!step(launch_self(dm, plans[i], pbase, off_k[i], off_dft[i], K[i], aux.as<double2>(), self, stream),
                       "self-term kernel"))
                 break;
-            bemrat::SweepArgs a = sweep_args(dm, plans[i], pbase, off_k[i], off_tables, self);
+            double2 *fself = b->fself.as<double2>() + b->off_fself[i];
+            // folded: the diagonal is the same fold of the self terms (fself[p] = sum_l coef[l][p] self_l)
+            if (b->fold &&
+                !step(bemrat::launch_combine(self, dm.n_pad, 1, plans[i].L,
+                                             reinterpret_cast<const double2 *>(pbase + b->off_coef[i]), (int)P,
+                                             dm.n_pad, 1, fself, 1, stream),
+                      "folded self-term kernel"))
+                break;
+            bemrat::SweepArgs a = sweep_args(dm, plans[i], pbase, off_k[i], off_tables, b->fold ? fself : self);
+            if (b->fold) {
+                a.L = (int)P;
+                a.Lgen = plans[i].L;
+                a.fcoef = reinterpret_cast<const double2 *>(pbase + b->off_fcoef[i]);
+            }
             a.Vp2 = b->probe.as<double2>() + b->off_probe[i];
             a.m_pad = b->m_pad;
             a.Z = b->Z.as<double2>() + b->off_Z[i];
@@ -2157,9 +2204,10 @@ bem_status bem_batch_moments(bem_batch_t b, const double *V, double *M, hipStrea
                                             V2 + b->rows[i] * m, m, b->Z.as<double2>() + b->off_Z[i], m, n * m, n, m,
                                             (int)b->ops[i], stream),
                     "diagonal kernel");
-        HIP_TRY(bemrat::launch_combine(b->Z.as<double2>() + b->off_Z[i], n * m, m, (int)b->ops[i],
-                                       reinterpret_cast<const double2 *>(pbase + b->off_coef[i]), (int)b->P, n, m,
-                                       reinterpret_cast<double2 *>(M) + b->P * b->rows[i] * m, m, stream),
+        // the moments from Z: the recombination of the operators, or (folded) a copy of the folds
+        HIP_TRY(bemrat::launch_combine(b->Z.as<double2>() + b->off_Z[i], n * m, m, b->fold ? (int)b->P : (int)b->ops[i],
+                                       reinterpret_cast<const double2 *>(pbase + (b->fold ? b->off_eye : b->off_coef[i])),
+                                       (int)b->P, n, m, reinterpret_cast<double2 *>(M) + b->P * b->rows[i] * m, m, stream),
                 "combine kernel");
     }
     return BEM_OK;

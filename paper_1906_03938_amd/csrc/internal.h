@@ -111,6 +111,11 @@ int batch_ops_per_item_f64(Gen gen, int cb);  // the same for a batched work ite
 hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, const int4 *items, int nitems,
                               unsigned *counter, int grid, hipStream_t stream);
 int batch_variant(Gen gen, bool decay);  // BatchVariant of an operator family, -1 if none
+// Folded batch (FP64, P = 1 or 2 weight sets per mesh): items (mesh, row block, column block,
+// 0); each mesh's args carry L = P, Lgen, fcoef (Lgen x P <= kFoldCoef) and its folded
+// diagonal in self, and the folds land in its Z like operators.
+hipError_t launch_sweep_fold_batch(int variant, int cb, int P, const BatchEntry *table, const int4 *items, int nitems,
+                                   unsigned *counter, int grid, hipStream_t stream);
 // The same at reduced precision (each table entry carries its mesh's a_scale and probe-scale
 // pointer); cb = 1, 2, 4 or 8 16-column groups, operators per item lp_batch_ops_per_block.
 hipError_t launch_sweep_lp_batch(Prec prec, int variant, int cb, const BatchEntry *table, const int4 *items,

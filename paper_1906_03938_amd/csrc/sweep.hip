@@ -296,6 +296,32 @@ __global__ __launch_bounds__(512, 1) void sweep_batch_kernel(const BatchEntry *_
     }
 }
 
+// Folded persistent batch: as sweep_batch_kernel with the folded tile (each mesh's KL = 1 or 2
+// weight sets: every operator of an entry generated and folded, only the folds contracted);
+// the items carry no operator block.  A tile copies its mesh's fold coefficients into LDS
+// behind the previous tile's last barrier.
+template <int CB, Gen GEN, bool DECAY, int KL>
+__global__ __launch_bounds__(512, 1) void sweep_fold_batch_kernel(const BatchEntry *__restrict__ table,
+                                                                  const int4 *__restrict__ items, int nitems,
+                                                                  unsigned *__restrict__ counter) {
+    __shared__ TileLds<1, CB> lds;
+    __shared__ double2 sFc[kFoldCoef];
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(counter, 1u);
+        // the tile's own barriers keep this write behind every read of the previous value
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(s_next);
+        if (idx >= nitems) break;
+        const int4 item = items[idx];
+        const int mesh = __builtin_amdgcn_readfirstlane(item.x);
+        const SweepArgs p = table[mesh].args;
+        sweep_tile<1, CB, GEN, DECAY, true, KL>(p, (int64_t)__builtin_amdgcn_readfirstlane(item.y) * 16,
+                                                (int64_t)__builtin_amdgcn_readfirstlane(item.z) * 16 * CB, 0, lds,
+                                                sFc);
+    }
+}
+
 __global__ void batch_reset_kernel(unsigned *counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
@@ -370,6 +396,42 @@ hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, cons
         case kBatchDirectSym: return launch_batch_gen<Gen::DirectSym, true>(cb, table, items, nitems, counter, grid, stream);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <Gen GEN, bool DECAY, int KL>
+hipError_t launch_fold_batch_gen(int cb, const BatchEntry *table, const int4 *items, int nitems, unsigned *counter,
+                                 int grid, hipStream_t stream) {
+    const dim3 g(grid), b(512);
+    switch (cb) {
+        case 1: hipLaunchKernelGGL((sweep_fold_batch_kernel<1, GEN, DECAY, KL>), g, b, 0, stream, table, items, nitems, counter); break;
+        case 2: hipLaunchKernelGGL((sweep_fold_batch_kernel<2, GEN, DECAY, KL>), g, b, 0, stream, table, items, nitems, counter); break;
+        case 4: hipLaunchKernelGGL((sweep_fold_batch_kernel<4, GEN, DECAY, KL>), g, b, 0, stream, table, items, nitems, counter); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int KL>
+hipError_t launch_fold_batch_k(int variant, int cb, const BatchEntry *table, const int4 *items, int nitems,
+                               unsigned *counter, int grid, hipStream_t stream) {
+    switch (variant) {
+        case kBatchDirectDecay: return launch_fold_batch_gen<Gen::Direct, true, KL>(cb, table, items, nitems, counter, grid, stream);
+        case kBatchDirect: return launch_fold_batch_gen<Gen::Direct, false, KL>(cb, table, items, nitems, counter, grid, stream);
+        case kBatchTaylorDecay: return launch_fold_batch_gen<Gen::Taylor, true, KL>(cb, table, items, nitems, counter, grid, stream);
+        case kBatchTaylor: return launch_fold_batch_gen<Gen::Taylor, false, KL>(cb, table, items, nitems, counter, grid, stream);
+        case kBatchDirectSym: return launch_fold_batch_gen<Gen::DirectSym, true, KL>(cb, table, items, nitems, counter, grid, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_fold_batch(int variant, int cb, int P, const BatchEntry *table, const int4 *items, int nitems,
+                                   unsigned *counter, int grid, hipStream_t stream) {
+    if (grid < 1 || nitems < 0 || P < 1 || P > kFoldMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return P == 1 ? launch_fold_batch_k<1>(variant, cb, table, items, nitems, counter, grid, stream)
+                  : launch_fold_batch_k<2>(variant, cb, table, items, nitems, counter, grid, stream);
 }
 
 hipError_t launch_sweep_fold(Gen gen, const SweepArgs &args, hipStream_t stream) {

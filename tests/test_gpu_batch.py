@@ -2,7 +2,8 @@
 one generate-and-contract launch): parity with the oracle's per-mesh contour moments
 (1e-12 normwise per mesh and weight set), bitwise equality with the per-mesh entry point
 in the same form (the tiles run the same arithmetic in the same order, whatever the column
-tile the autotuner picks), graph capture and replay, error paths, and sampled-row parity
+tile the autotuner picks; one or two weight sets folded into the sweep as contour_moments
+does, more contracted per operator and recombined as rr_project's fused moments are), graph capture and replay, error paths, and sampled-row parity
 on the full 64-ellipsoid workload (geodesic frequencies 10..44, 2,000-38,720 triangles
 per mesh, circles |z - c_i| = 1 with c_i in [3, 7], N = 32, m = 32, seed 4)."""
 import numpy as np
@@ -70,17 +71,44 @@ def test_batch_matches_oracle(small, form):
 @pytest.mark.parametrize("form", ["direct", "expand"])
 @pytest.mark.parametrize("tune", [False, True])
 def test_batch_bitwise_equals_per_mesh(small, form, tune):
+    """Two weight sets: the batch folds them into the sweep, as contour_moments does per mesh
+    (the same folded tiles, whatever column tile the autotuner picks)."""
     bem, torch, spec, meshes, z, W, V, N, P, m = small
     f = {"direct": bem.FORM_DIRECT, "expand": bem.FORM_EXPAND}[form]
     with bem.Batch(meshes, z, W, m, form=f, tune=tune) as b:
         Mb = b.split(b.moments(_packed(torch, V)))
         print(form, "tune", tune, "col tile", b.col_tile, flush=True)
         for i, mesh in enumerate(meshes):
-            # the per-mesh unfolded path (rr_project's fused moments: the same sweep tiles and
-            # recombination; contour_moments itself folds one or two weight sets)
-            _, Mi = mesh.rr_project(z[i], torch.from_numpy(V[i]).to("cuda"), W=W[i], form=f)
+            Mi = mesh.contour_moments(z[i], W[i], torch.from_numpy(V[i]).to("cuda"), form=f)
             assert mesh.last_form()[0] == b.form and mesh.last_form()[1] == b.operators[i]
             assert torch.equal(Mi, Mb[i]), i
+
+
+@pytest.mark.parametrize("form", ["direct", "expand"])
+def test_batch_unfolded_bitwise_equals_per_mesh(small, form):
+    """Three weight sets: the batch contracts every operator and recombines, as rr_project's
+    fused moments do per mesh (the same sweep tiles and recombination), and matches the
+    oracle."""
+    bem, torch, spec, meshes, z, W, V, N, P, m = small
+    from oracle import method as M
+
+    f = {"direct": bem.FORM_DIRECT, "expand": bem.FORM_EXPAND}[form]
+    z3, W3 = [], []
+    for _, _, _, c in spec:
+        zi, _, Wi = bem.contour_nodes(c, 1.0, N, P=3)
+        z3.append(zi)
+        W3.append(Wi)
+    z3, W3 = np.array(z3), np.array(W3)
+    with bem.Batch(meshes, z3, W3, m, form=f) as b:
+        Mb = b.split(b.moments(_packed(torch, V)))
+        for i, mesh in enumerate(meshes):
+            _, Mi = mesh.rr_project(z3[i], torch.from_numpy(V[i]).to("cuda"), W=W3[i], form=f)
+            assert torch.equal(Mi, Mb[i]), i
+            x, t, _, c = spec[i]
+            zo, wo = M.circle_nodes(c, 1.0, N)
+            Mo = M.contour_moments(M.Operator(x, t), zo, M.moment_weights(zo, wo, c, 3), V[i])
+            for q in range(3):
+                assert _rel(Mb[i][q].cpu().numpy(), Mo[q]) <= TOL, (i, q)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -246,7 +274,7 @@ def test_batch_edge_shapes(m):
         with bem.Batch(meshes, np.array(z), np.array(W), m) as b:
             Mb = b.split(b.moments(torch.from_numpy(np.concatenate(V)).to("cuda")))
             for i, (x, t, c) in enumerate(geo):
-                _, Mi = meshes[i].rr_project(z[i], torch.from_numpy(V[i]).to("cuda"), W=W[i], form=b.form)
+                Mi = meshes[i].contour_moments(z[i], W[i], torch.from_numpy(V[i]).to("cuda"), form=b.form)
                 assert torch.equal(Mi, Mb[i]), i
                 op = M.Operator(x, t)
                 zo, wo = M.circle_nodes(c, 1.0, N)
