@@ -1,12 +1,18 @@
 """Builds libbemrat.so in-tree with hipcc for gfx950.
 
+Each source is compiled to an object of its own, the compilations running side by side,
+and the objects are linked into the shared library.
+
 Usage: python -m paper_1906_03938_amd.build  (or via __graft_entry__.build()).
 """
 from __future__ import annotations
 
 import os
+import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -16,32 +22,55 @@ SOURCES = ["abi.cpp", "mesh.hip", "sweep.hip", "sweep_lp.hip", "combine.hip", "a
 HEADERS = ["internal.h", "generators.h", "devmath.h"]
 
 
-def command(out: str = LIB, arch: str = "gfx950", extra=()):
+def flags(arch: str = "gfx950", extra=()):
     return [
-        "hipcc",
         f"--offload-arch={arch}",
         "-O3",
         "-std=c++17",
         "-fPIC",
-        "-shared",
         # keep the compiler from emitting packed FP32 instructions
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"),
         "-I", CSRC,
         *extra,
-        "-o", out,
-        *[os.path.join(CSRC, s) for s in SOURCES],
     ]
 
 
-def build(verbose: bool = False, out: str = LIB) -> str:
-    cmd = command(out)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    tmp = out + ".tmp"
-    cmd[cmd.index("-o") + 1] = tmp
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, out)
+def compile_command(src: str, obj: str, arch: str = "gfx950", extra=()):
+    return ["hipcc", *flags(arch, extra), "-c", "-o", obj, os.path.join(CSRC, src)]
+
+
+def link_command(objs, out: str, arch: str = "gfx950"):
+    return ["hipcc", f"--offload-arch={arch}", "-shared", "-fPIC", "-o", out, *objs]
+
+
+def build(verbose: bool = False, out: str = LIB, jobs: int | None = None) -> str:
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    tmpdir = tempfile.mkdtemp(prefix="bemrat_build_")
+    try:
+        objs = [os.path.join(tmpdir, s + ".o") for s in SOURCES]
+        cmds = [compile_command(s, o) for s, o in zip(SOURCES, objs)]
+
+        def run(cmd):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            return subprocess.run(cmd, capture_output=True, text=True)
+
+        with ThreadPoolExecutor(max_workers=jobs) as pool:
+            results = list(pool.map(run, cmds))
+        failed = [(c, r) for c, r in zip(cmds, results) if r.returncode != 0]
+        for c, r in failed:
+            sys.stderr.write(r.stdout + r.stderr)
+        if failed:
+            raise subprocess.CalledProcessError(failed[0][1].returncode, failed[0][0])
+        tmp = out + ".tmp"
+        link = link_command(objs, tmp)
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
+        os.replace(tmp, out)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return out
 
 

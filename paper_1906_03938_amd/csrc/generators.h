@@ -307,8 +307,8 @@ struct Generator<16, Gen::Taylor, DECAY, LOWP> {
 };
 
 // Folded generators: all p.Lgen operators of one entry, combined into the outputs
-// out[k] = sum_l fcoef[l][k] T_l, k < KL = p.L (zero beyond, up to NOPS), the coefficients
-// read from the block's LDS copy (set_coef).  The Taylor form computes each point's distance, exp(i c r)
+// out[k] = sum_l fcoef[l][k] T_l, k < KL (zero beyond, up to NOPS), the coefficients read
+// from the block's LDS copy (set_coef), rows of KL (zero from column p.L on).  The Taylor form computes each point's distance, exp(i c r)
 // and weight once and runs the power chain through all the operators in passes of eight
 // (the point term advanced by x^8 between passes; the factors i^l / l! are in the
 // coefficients); the direct form generates its nodes in passes of eight (of quadruples for
@@ -334,7 +334,7 @@ struct FoldGenerator<NOPS, Gen::Taylor, DECAY, KL> : FoldCoef {
 #pragma unroll
         for (int k = 0; k < KL; ++k) {
             {
-                const double2 w = coef(l * p.L + k);
+                const double2 w = coef(l * KL + k);
                 ar[k] = fma(w.x, er, fma(-w.y, ei, ar[k]));
                 ai[k] = fma(w.x, ei, fma(w.y, er, ai[k]));
             }
@@ -408,7 +408,7 @@ struct FoldGenerator<NOPS, Gen::Direct, DECAY, KL> : FoldCoef {
 #pragma unroll
                 for (int k = 0; k < KL; ++k) {
                     {
-                        const double2 w = coef((h + j) * p.L + k);
+                        const double2 w = coef((h + j) * KL + k);
                         ar[k] = fma(w.x, gr, fma(-w.y, gi, ar[k]));
                         ai[k] = fma(w.x, gi, fma(w.y, gr, ai[k]));
                     }
@@ -432,7 +432,7 @@ struct FoldGenerator<NOPS, Gen::DirectSym, DECAY, KL> : FoldCoef {
 #pragma unroll
         for (int k = 0; k < KL; ++k) {
             {
-                const double2 w = coef(l * p.L + k);
+                const double2 w = coef(l * KL + k);
                 ar[k] = fma(w.x, er, fma(-w.y, ei, ar[k]));
                 ai[k] = fma(w.x, ei, fma(w.y, er, ai[k]));
             }

@@ -91,13 +91,15 @@ hipError_t launch_add_diag(const double2 *S, int64_t n_pad, const double2 *V, in
 int sweep_lp_ops_per_block(Gen gen, int64_t m);
 int64_t sweep_lp_m_pad(int64_t m);  // column padding of the probe copy for the reduced-precision sweep
 // Folded FP64 sweep for the moments of Direct or Taylor plans: the producer generates all
-// args.Lgen operators of each entry and folds them into args.L <= kFoldMax = 2 combinations
-// (args.fcoef, Lgen x L, at most kFoldCoef entries: the block keeps them in LDS), the
-// consumers contract only those and write them to args.Z like operators.  For Taylor plans
-// fcoef[l][k] carries the operator's own factor i^l / l! (the generator folds the plain
-// power sums sum_q y_q x_q^l).
-constexpr int kFoldMax = 2;
+// args.Lgen operators of each entry and folds them into args.L <= kFoldMax combinations,
+// the consumers contract only those and write them to args.Z like operators.  The fold
+// runs at the width KL = fold_width(args.L) (1, 2 or 4) over args.fcoef, Lgen rows of KL
+// (zero from column L on), at most kFoldCoef entries: the block keeps them in LDS.  For
+// Taylor plans fcoef[l][k] carries the operator's own factor i^l / l! (the generator folds
+// the plain power sums sum_q y_q x_q^l).
+constexpr int kFoldMax = 4;
 constexpr int kFoldCoef = 512;
+constexpr int fold_width(int P) { return P <= 2 ? P : 4; }
 hipError_t launch_sweep_fold(Gen gen, const SweepArgs &args, hipStream_t stream);
 
 // Length unit of the expansion forms (their L is a multiple of it): 8.  The FP64 sweep
@@ -111,9 +113,11 @@ int batch_ops_per_item_f64(Gen gen, int cb);  // the same for a batched work ite
 hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, const int4 *items, int nitems,
                               unsigned *counter, int grid, hipStream_t stream);
 int batch_variant(Gen gen, bool decay);  // BatchVariant of an operator family, -1 if none
-// Folded batch (FP64, P = 1 or 2 weight sets per mesh): items (mesh, row block, column block,
-// 0); each mesh's args carry L = P, Lgen, fcoef (Lgen x P <= kFoldCoef) and its folded
-// diagonal in self, and the folds land in its Z like operators.
+// Folded batch (FP64, P <= kFoldBatchMax = 2 weight sets per mesh): items (mesh, row block,
+// column block, 0); each mesh's args carry L = P, Lgen, fcoef (Lgen rows of P, at most
+// kFoldCoef entries) and its folded diagonal in self, and the folds land in its Z like
+// operators.
+constexpr int kFoldBatchMax = 2;
 hipError_t launch_sweep_fold_batch(int variant, int cb, int P, const BatchEntry *table, const int4 *items, int nitems,
                                    unsigned *counter, int grid, hipStream_t stream);
 // The same at reduced precision (each table entry carries its mesh's a_scale and probe-scale

@@ -78,9 +78,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &p, int64_t row0, int
     const int64_t nstages = p.n_pad / kStage;
     constexpr bool FOLD = FOLDK > 0;
     if constexpr (FOLD) {
-        // the fold coefficients (Lgen x L <= kFoldCoef) into LDS; the first barrier of both
-        // roles below publishes them
-        for (int i = tid; i < p.Lgen * p.L; i += 512) sFc[i] = ld<CAST>(p.fcoef, i);
+        // the fold coefficients (Lgen rows of FOLDK, at most kFoldCoef) into LDS; the first
+        // barrier of both roles below publishes them
+        for (int i = tid; i < p.Lgen * FOLDK; i += 512) sFc[i] = ld<CAST>(p.fcoef, i);
     }
 
     if (tid < 256) {
@@ -162,7 +162,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &p, int64_t row0, int
             }
         __syncthreads();  // pairs with the producers' prologue barrier
         // with 16-operator blocks, a wave whose operators all lie beyond L (the last block of
-        // an odd number of 8-operator halves) only keeps the barrier rhythm
+        // an odd number of 8-operator halves) only keeps the barrier rhythm, as does a wave
+        // past the folds of a folded tile
         const bool active = G == 2 || L0 + w * G < p.L;
         for (int64_t it = 0; it <= nstages; ++it) {
             if (it >= 1 && active) {
@@ -222,7 +223,8 @@ __global__ __launch_bounds__(512, 1) void sweep_kernel(SweepArgs p) {
 }
 
 // Folded form: one block per (row block, column block) generates every operator of its
-// entries and contracts the KL = p.L (1 or 2) folds, on a tile of 4 operators.
+// entries and contracts its p.L folds, at the fold width KL = 1, 2 or 4, on a tile of 4
+// operators.
 template <int CB, Gen GEN, bool DECAY, int KL>
 __global__ __launch_bounds__(512, 1) void sweep_fold_kernel(SweepArgs p) {
     __shared__ TileLds<1, CB> lds;
@@ -250,7 +252,11 @@ hipError_t launch_fold_k(const SweepArgs &p, hipStream_t stream) {
 
 template <Gen GEN, bool DECAY>
 hipError_t launch_fold_gen(const SweepArgs &p, hipStream_t stream) {
-    return p.L == 1 ? launch_fold_k<GEN, DECAY, 1>(p, stream) : launch_fold_k<GEN, DECAY, 2>(p, stream);
+    switch (fold_width(p.L)) {
+        case 1: return launch_fold_k<GEN, DECAY, 1>(p, stream);
+        case 2: return launch_fold_k<GEN, DECAY, 2>(p, stream);
+        default: return launch_fold_k<GEN, DECAY, 4>(p, stream);
+    }
 }
 
 template <int G, int CB, Gen GEN, bool DECAY>
@@ -426,7 +432,7 @@ hipError_t launch_fold_batch_k(int variant, int cb, const BatchEntry *table, con
 
 hipError_t launch_sweep_fold_batch(int variant, int cb, int P, const BatchEntry *table, const int4 *items, int nitems,
                                    unsigned *counter, int grid, hipStream_t stream) {
-    if (grid < 1 || nitems < 0 || P < 1 || P > kFoldMax) return hipErrorInvalidValue;
+    if (grid < 1 || nitems < 0 || P < 1 || P > kFoldBatchMax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -435,7 +441,8 @@ hipError_t launch_sweep_fold_batch(int variant, int cb, int P, const BatchEntry 
 }
 
 hipError_t launch_sweep_fold(Gen gen, const SweepArgs &args, hipStream_t stream) {
-    if (args.L < 1 || args.L > kFoldMax || args.Lgen < 1 || args.Lgen * args.L > kFoldCoef) return hipErrorInvalidValue;
+    if (args.L < 1 || args.L > kFoldMax || args.Lgen < 1 || args.Lgen * fold_width(args.L) > kFoldCoef)
+        return hipErrorInvalidValue;
     const bool decay = args.decay != 0;
     switch (gen) {
         case Gen::Direct:

@@ -156,14 +156,23 @@ class ContourSolver:
     def r_lam(self, x, lam):
         """Columns R_lam_k x_k = sum_i w_i T(z_i) x_k / (lam_k - z_i), k < x.shape[1]: one sweep
         of the block with one weight set per column (column k of weight set k is kept)."""
+        return self.moments_and_r_lam(x, [], lam)[1]
+
+    def moments_and_r_lam(self, x, orders, lam):
+        """(M_p x for the moment orders, R_lam x as r_lam) from one sweep of x: the moment weight
+        sets and the per-column resolvent weight sets side by side in one contour_moments call
+        (the unfolded sweep's cost does not depend on the number of weight sets)."""
         lam = np.atleast_1d(np.asarray(lam, dtype=np.complex128))
-        W = np.ascontiguousarray(self.w[:, None] / (lam[None, :] - self.z[:, None]))
+        Wm = self.W[:, [p - 1 for p in orders]]
+        Wr = self.w[:, None] / (lam[None, :] - self.z[:, None])
+        W = np.ascontiguousarray(np.concatenate([Wm, Wr], axis=1))
         xd = self._dev(x)
-        R = self.mesh.contour_moments(self.z, W, xd, form=self.sweep_flags)
+        M = self.mesh.contour_moments(self.z, W, xd, form=self.sweep_flags)
         if self.nearfield:
-            _nearfield_add(self.mesh, self.nf_model, self.z, W, xd, R)
-        k = self.torch.arange(lam.size, device=R.device)
-        return R[k, :, k].T.cpu().numpy()
+            _nearfield_add(self.mesh, self.nf_model, self.z, W, xd, M)
+        P = len(orders)
+        k = self.torch.arange(lam.size, device=M.device)
+        return M[:P].cpu().numpy(), M[P + k, :, k].T.cpu().numpy()
 
     def schur_lu(self):
         """LU of S = M_1 = sum_i B_i/(z_i - c), assembled on the device."""
@@ -185,8 +194,7 @@ class ContourSolver:
         if restart:
             rho = 1.0 / (np.asarray(lam, dtype=np.complex128) - self.c)  # per column
             x = np.asarray(u0, dtype=np.complex128)
-            Mx = self.moments(x, list(range(1, q + 2)))                  # M_1 x .. M_{q+1} x
-            Rx = self.r_lam(x, lam)
+            Mx, Rx = self.moments_and_r_lam(x, list(range(1, q + 2)), lam)  # M_1 x .. M_{q+1} x, R_lam x
             base = Mx[0] + Rx                                            # (M_1 + R_lam) x
             swept.append(None)                                           # no a_1^(0) on restarts
         else:

@@ -304,12 +304,13 @@ def test_bitwise_deterministic(sphere3, torch, bem):
 
 
 @pytest.mark.parametrize("form", ["direct", "expand"])
-@pytest.mark.parametrize("P,m", [(1, 5), (2, 33), (2, 70)])
+@pytest.mark.parametrize("P,m", [(1, 5), (2, 33), (2, 70), (3, 17), (3, 70), (4, 5), (4, 33), (5, 20)])
 def test_folded_moments_match_unfolded(bem, torch, sphere3, form, P, m):
-    """contour_moments folds one or two weight sets into the sweep (every operator of an
-    entry generated, only the folds contracted); rr_project's fused moments take the
-    unfolded route (every operator contracted, then recombined).  Both evaluate the same sums
-    in FP64: they agree to rounding, and the folded result matches the oracle."""
+    """contour_moments folds up to four weight sets into the sweep (every operator of an
+    entry generated, only the folds contracted; fold widths 1, 2 and 4, the last padded with
+    a zero coefficient column for P = 3) and takes the unfolded route beyond (P = 5), as do
+    rr_project's fused moments (every operator contracted, then recombined).  Both evaluate
+    the same sums in FP64: they agree to rounding, and the result matches the oracle."""
     from oracle import method as M
 
     mesh, op, xyz, tri = sphere3

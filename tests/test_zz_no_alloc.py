@@ -36,8 +36,9 @@ def test_noalloc_equals_contour_moments(flags_name):
     import paper_1906_03938_amd as bem
 
     prec = bem.PREC_F64 if flags_name == "f64" else bem.PREC_F32
-    # (level, N, P, m): an unfolded call (P = 3, Z in the scratch), then a smaller folded one
-    for level, N, P, m, seed in ((4, 32, 3, 16, 1), (3, 16, 2, 8, 2)):
+    # (level, N, P, m): an unfolded call (P = 9 > 4 weight sets, Z in the scratch), then a
+    # smaller folded one
+    for level, N, P, m, seed in ((4, 32, 9, 16, 1), (3, 16, 2, 8, 2)):
         xyz, tri, z, W, V = _case(bem, torch, level, N, P, m, seed, prec)
         print(f"case n={tri.shape[0]} N={N} P={P} m={m} {flags_name}", flush=True)
         with bem.Mesh(xyz, tri) as mesh:
@@ -53,8 +54,8 @@ def test_noalloc_allocates_nothing_and_rejects_oversize():
 
     import paper_1906_03938_amd as bem
 
-    xyz, tri, z, W, V = _case(bem, torch, 4, 32, 3, 16, 3, 0)
-    out = torch.zeros((3, tri.shape[0], 16), dtype=torch.complex128, device="cuda")
+    xyz, tri, z, W, V = _case(bem, torch, 4, 32, 9, 16, 3, 0)
+    out = torch.zeros((9, tri.shape[0], 16), dtype=torch.complex128, device="cuda")
     with bem.Mesh(xyz, tri) as warm:  # loads the code object, warms the runtime
         warm.contour_moments_noalloc(z, W, V, out=out)
     torch.cuda.synchronize()
@@ -69,9 +70,9 @@ def test_noalloc_allocates_nothing_and_rejects_oversize():
         ref = mesh.contour_moments(z, W, V)  # the handle's workspace is allocated on this call
         assert torch.equal(out, ref)
     # a call that needs more than the scratch array: rejected, output untouched
-    xyz, tri, z, W, V = _case(bem, torch, 5, 32, 3, 64, 4, 0)
+    xyz, tri, z, W, V = _case(bem, torch, 5, 32, 9, 64, 4, 0)
     with bem.Mesh(xyz, tri) as mesh:
-        big = torch.full((3, tri.shape[0], 64), 7.0, dtype=torch.complex128, device="cuda")
+        big = torch.full((9, tri.shape[0], 64), 7.0, dtype=torch.complex128, device="cuda")
         with pytest.raises(bem.BemError, match="EINVAL"):
             mesh.contour_moments_noalloc(z, W, V, out=big)
         torch.cuda.synchronize()
