@@ -37,11 +37,27 @@ def test_sphere81920_contour_eigenvalues():
     n = tri.shape[0]
     tab = np.loadtxt(os.path.join(GOLDEN, "sphere_dirichlet_eigs.txt"))
     t0 = time.perf_counter()
+    spent = {"inverse_iteration": 0.0, "rayleigh_ritz": 0.0, "residuals": 0.0}
+
     class Progress(ContourSolver):
-        """Prints a line per outer iteration (each takes about 17 s here)."""
+        """Prints a line per outer iteration (each takes about 17 s here) and adds up the time
+        of the three phases of an outer iteration."""
+
+        def _timed(self, name, f, *a):
+            t = time.perf_counter()
+            out = f(*a)
+            torch.cuda.synchronize()
+            spent[name] += time.perf_counter() - t
+            return out
+
+        def inverse_iteration(self, u0, lam=None):
+            return self._timed("inverse_iteration", super().inverse_iteration, u0, lam)
+
+        def rayleigh_ritz(self, U):
+            return self._timed("rayleigh_ritz", super().rayleigh_ritz, U)
 
         def residuals(self, lam, X):
-            res = super().residuals(lam, X)
+            res = self._timed("residuals", super().residuals, lam, X)
             print(f"outer iteration {len(self.history) + 1}: {lam.size} Ritz values inside, max residual "
                   f"{res.max() if res.size else float('nan'):.2e}, {time.perf_counter() - t0:.0f} s", flush=True)
             return res
@@ -55,6 +71,7 @@ def test_sphere81920_contour_eigenvalues():
         lam, X, res, outer = solver.solve(synth.probe_block(n, 32, seed=2))
     print(f"n = {n}: {lam.size} eigenvalues after {outer} outer iterations, {time.perf_counter() - t0:.0f} s; "
           f"max residual {res.max():.2e}\n{np.sort_complex(lam)}", flush=True)
+    print("time per phase: " + ", ".join(f"{k} {v:.1f} s" for k, v in spent.items()), flush=True)
     assert lam.size == 17 and res.max() <= 1e-12
     lam = np.sort_complex(lam)
     # clusters of the sorted real parts
