@@ -64,10 +64,15 @@ __device__ __forceinline__ double rsqrt_pos(double a) {
 template <int NOPS, Gen GEN, bool DECAY, bool LOWP = false>
 struct Generator;
 
+// In FP64 a block whose operators run past L (the last block of a ragged L) generates only
+// those below L (the others are zero and never written); a full block takes the unrolled
+// loop over all NOPS.
 template <int NOPS, bool DECAY, bool LOWP>
 struct Generator<NOPS, Gen::Direct, DECAY, LOWP> {
     double kr[NOPS], ki[NOPS];
+    int nact;  // operators of the block below L (uniform)
     __device__ void init(const SweepArgs &p, int L0) {
+        nact = min(NOPS, p.L - L0);
 #pragma unroll
         for (int j = 0; j < NOPS; ++j) {
             const int l = min(L0 + j, p.L - 1);
@@ -75,21 +80,32 @@ struct Generator<NOPS, Gen::Direct, DECAY, LOWP> {
             ki[j] = p.kappa[l].y;
         }
     }
+    __device__ __forceinline__ double2 entry(int j, const double (&r)[kQuad], const double (&wr)[kQuad]) const {
+        double gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int q = 0; q < kQuad; ++q) {
+            const double e = DECAY ? exp_cw(-ki[j] * r[q]) * wr[q] : wr[q];
+            double sn, cs;
+            sincos_gen<LOWP>(kr[j] * r[q], sn, cs);
+            gr = fma(e, cs, gr);
+            gi = fma(e, sn, gi);
+        }
+        return make_double2(gr, gi);
+    }
     __device__ __forceinline__ void entries(const double (&r)[kQuad], const double (&wr)[kQuad],
                                             const SweepArgs &, double2 (&out)[NOPS]) const {
+        if constexpr (!LOWP) {
+            if (nact < NOPS) {
 #pragma unroll
-        for (int j = 0; j < NOPS; ++j) {
-            double gr = 0.0, gi = 0.0;
-#pragma unroll
-            for (int q = 0; q < kQuad; ++q) {
-                const double e = DECAY ? exp_cw(-ki[j] * r[q]) * wr[q] : wr[q];
-                double sn, cs;
-                sincos_gen<LOWP>(kr[j] * r[q], sn, cs);
-                gr = fma(e, cs, gr);
-                gi = fma(e, sn, gi);
+                for (int j = 0; j < NOPS; ++j) {
+                    out[j] = make_double2(0.0, 0.0);
+                    if (j < nact) out[j] = entry(j, r, wr);
+                }
+                return;
             }
-            out[j] = make_double2(gr, gi);
         }
+#pragma unroll
+        for (int j = 0; j < NOPS; ++j) out[j] = entry(j, r, wr);
     }
 };
 
