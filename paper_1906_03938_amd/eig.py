@@ -40,6 +40,27 @@ from . import _lib
 DENSE_QZ_MAX = 1200
 
 
+def _host(t):
+    """Host (numpy) copy of a device tensor, through a pinned buffer of torch's caching host
+    allocator: a copy into pageable memory runs at a fraction of the link's rate.  CPU
+    tensors (the driver's tests) are returned as they are."""
+    import torch
+
+    if not t.is_cuda:
+        return t.numpy()
+    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+    h.copy_(t)
+    return h.numpy()
+
+
+def _device(a):
+    """Device copy of a host array (complex128), staged through pinned memory."""
+    import torch
+
+    h = torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).pin_memory()
+    return h.to("cuda", non_blocking=True)
+
+
 class DenseFactor:
     """LU factorisation P S = L U (partial pivoting) of the dense n x n complex matrix of the
     inverse iteration, held on the device, with solves for host right-hand sides.  "device"
@@ -64,11 +85,8 @@ class DenseFactor:
         B = np.asarray(B, dtype=np.complex128)
         if self.mode == "host":
             return sla.lu_solve(self.lu, B)
-        import torch
-
         vec = B.ndim == 1
-        Bd = torch.from_numpy(np.ascontiguousarray(B.reshape(B.shape[0], -1))).to("cuda")
-        X = self.lu.solve(Bd).cpu().numpy()
+        X = _host(self.lu.solve(_device(B.reshape(B.shape[0], -1))))
         return X[:, 0] if vec else X
 
 
@@ -105,7 +123,7 @@ def _residuals(mesh, dev, lam, X, chunk=16, nearfield=False, model=None):
         Y = mesh.assemble_apply(lam[k0:k1], Xd)
         if nearfield:
             _nearfield_add(mesh, model, lam[k0:k1], np.eye(k1 - k0), Xd, Y)
-        Y = Y.cpu().numpy()
+        Y = _host(Y)
         for k in range(k0, k1):
             out[k] = np.linalg.norm(Y[k - k0, :, k - k0]) / np.linalg.norm(X[:, k])
     return out
@@ -141,7 +159,7 @@ class ContourSolver:
         self.history = []
 
     def _dev(self, a):
-        return self.torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to("cuda")
+        return _device(a)
 
     # -- sweeps -------------------------------------------------------------------
     def moments(self, X, orders):
@@ -151,7 +169,7 @@ class ContourSolver:
         M = self.mesh.contour_moments(self.z, W, Xd, form=self.sweep_flags)
         if self.nearfield:
             _nearfield_add(self.mesh, self.nf_model, self.z, W, Xd, M)
-        return M.cpu().numpy()
+        return _host(M)
 
     def r_lam(self, x, lam):
         """Columns R_lam_k x_k = sum_i w_i T(z_i) x_k / (lam_k - z_i), k < x.shape[1]: one sweep
@@ -172,7 +190,7 @@ class ContourSolver:
             _nearfield_add(self.mesh, self.nf_model, self.z, W, xd, M)
         P = len(orders)
         k = self.torch.arange(lam.size, device=M.device)
-        return M[:P].cpu().numpy(), M[P + k, :, k].T.cpu().numpy()
+        return _host(M[:P]), _host(M[P + k, :, k].T)
 
     def schur_lu(self):
         """LU of S = M_1 = sum_i B_i/(z_i - c), assembled on the device."""
@@ -266,7 +284,7 @@ class ContourSolver:
         P = self.mesh.rr_project(self.z, Ud, form=self.rr_flags)
         if self.nearfield:
             self.mesh.nearfield_project(self.z, Ud, P, None if self.nf_model is None else self.nf_model.c_model())
-        P = P.cpu().numpy()
+        P = _host(P)
         Bhat = [self.w[j] * P[j] for j in range(self.N)]
         m = U.shape[1]
         if (self.N + 1) * m > DENSE_QZ_MAX:
@@ -392,7 +410,7 @@ class IntervalSolver:
         return p
 
     def _dev(self, a):
-        return self.torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to("cuda")
+        return _device(a)
 
     def sweep(self, X, ages):
         W = np.ascontiguousarray(self.W_age[:, list(ages)])
@@ -400,7 +418,7 @@ class IntervalSolver:
         M = self.mesh.contour_moments(self.z, W, Xd, form=self.sweep_flags)
         if self.nearfield:
             self.mesh.nearfield_moments(self.z, W, Xd, out=M)
-        return M.cpu().numpy()
+        return _host(M)
 
     def g_lu(self):
         """LU of G = sum_l B_l T_l(s) = sum_j T(kappa_j) sum_l coef[l, j] T_l(s), assembled on
@@ -429,7 +447,7 @@ class IntervalSolver:
             Cx = self.mesh.cheb_moments(self.a, self.b, self.N, self.N, u0d, form=self.sweep_flags)
             if self.nearfield:  # C_l += sum_k coef[l, k] dT(kappa_k) u0
                 self.mesh.nearfield_moments(self.z, np.ascontiguousarray(self.coef.T), u0d, out=Cx)
-            Cx = Cx.cpu().numpy()
+            Cx = _host(Cx)
             g = self._tvals(np.asarray(xi, dtype=np.complex128))[:self.d]   # d x m
             restart = []
             for _ in range(q):
@@ -477,7 +495,7 @@ class IntervalSolver:
         P = self.mesh.rr_project(self.z, Ud, form=self.rr_flags)
         if self.nearfield:
             self.mesh.nearfield_project(self.z, Ud, P)
-        P = P.cpu().numpy()
+        P = _host(P)
         Bhat = np.einsum("lj,jab->lab", self.coef, P)
         A, M = self.reduced_pencil(Bhat)
         with np.errstate(invalid="ignore", divide="ignore"):
