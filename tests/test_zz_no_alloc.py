@@ -1,7 +1,7 @@
 """contour_moments_noalloc, the allocation-free entry point (workspace in the library's static
-scratch array), against contour_moments on the same inputs: two calls in a row on one device,
-the second smaller, in the unfolded FP64 route (generated products in the scratch), the folded
-route and a reduced-precision sweep; the results are bitwise equal (same kernels, same order).
+scratch array), against contour_moments on the same inputs: calls in a row on one device, each
+smaller than the first, in the unfolded FP64 route (generated products in the scratch), the
+folded route (fold widths 2 and 4) and a reduced-precision sweep; the results are bitwise equal (same kernels, same order).
 Device free memory is unchanged across a call on a fresh handle, and a call whose workspace
 exceeds the array is rejected before anything is launched, leaving its output untouched."""
 import ctypes
@@ -36,9 +36,9 @@ def test_noalloc_equals_contour_moments(flags_name):
     import paper_1906_03938_amd as bem
 
     prec = bem.PREC_F64 if flags_name == "f64" else bem.PREC_F32
-    # (level, N, P, m): an unfolded call (P = 9 > 4 weight sets, Z in the scratch), then a
-    # smaller folded one
-    for level, N, P, m, seed in ((4, 32, 9, 16, 1), (3, 16, 2, 8, 2)):
+    # (level, N, P, m): an unfolded call (P = 9 > 4 weight sets, Z in the scratch), then
+    # smaller folded ones (fold widths 2 and 4, the second padded for P = 3)
+    for level, N, P, m, seed in ((4, 32, 9, 16, 1), (3, 16, 2, 8, 2), (3, 16, 3, 5, 5)):
         xyz, tri, z, W, V = _case(bem, torch, level, N, P, m, seed, prec)
         print(f"case n={tri.shape[0]} N={N} P={P} m={m} {flags_name}", flush=True)
         with bem.Mesh(xyz, tri) as mesh:
