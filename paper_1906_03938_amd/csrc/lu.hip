@@ -52,7 +52,8 @@ constexpr int kBlock = 256;      // rows of a triangular block
 constexpr int kBlockCols = 8;    // right-hand-side columns per triangular-block workgroup
 constexpr int kStageK = 16;      // k per LDS stage of the GEMM
 constexpr int kPivotBlocks = 1024;
-constexpr int64_t kSolveChunk = 512;  // split-K chunk of the solves
+constexpr int64_t kSolveChunk = 512;  // split-K chunk of the solves with more than 32 columns
+constexpr int64_t kSolveChunkNarrow = 128;  // ... and with at most 32
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -193,8 +194,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void zgemm_kernel(ZgemmArgs g) {
 constexpr int kWGM = 4, kWGN = 2, kTM = 2, kTN = 3;
 constexpr int kBM = kWGM * 16 * kTM, kBN = kWGN * 16 * kTN;
 // Split-K products of the solves: 128 x 64 tiles (the right-hand sides come in 64s), 8 waves
-// of 32 x 32.
+// of 32 x 32; with at most 32 right-hand sides 64 x 32 tiles of 4 waves of 16 x 32 over
+// chunks of 128 (the wide tile would leave half its waves on zero columns, and a chunk of 512
+// gives too few workgroups to stream the panel at the rate of the chip: sphere-81920, 32
+// columns, 131 us per product).
 constexpr int kPTN = 2, kPBN = kWGN * 16 * kPTN;
+constexpr int64_t solve_chunk(int64_t m) { return m <= 32 ? kSolveChunkNarrow : kSolveChunk; }
 
 hipError_t gemm_sub(double2 *C, int64_t ldc, const double2 *A, int64_t lda, const double2 *B, int64_t ldb, int64_t M,
                     int64_t N, int64_t K, hipStream_t s) {
@@ -205,10 +210,16 @@ hipError_t gemm_sub(double2 *C, int64_t ldc, const double2 *A, int64_t lda, cons
     return hipGetLastError();
 }
 
-// part[z] = A[0:M, chunk z] B[chunk z, 0:N] for the kSolveChunk chunks z < nz of [0, K).
+// part[z] = A[0:M, chunk z] B[chunk z, 0:N] for the solve_chunk(N) chunks z < nz of [0, K).
 hipError_t gemm_part(double2 *part, const double2 *A, int64_t lda, const double2 *B, int64_t ldb, int64_t M,
                      int64_t N, int64_t K, int nz, hipStream_t s) {
-    ZgemmArgs g{nullptr, 0, A, lda, B, ldb, M, N, K, kSolveChunk, part};
+    ZgemmArgs g{nullptr, 0, A, lda, B, ldb, M, N, K, solve_chunk(N), part};
+    if (N <= 32) {
+        constexpr int NBM = kWGM * 16;
+        dim3 grid(1u, (unsigned)((M + NBM - 1) / NBM), (unsigned)nz);
+        hipLaunchKernelGGL((zgemm_kernel<kWGM, 1, 1, kPTN>), grid, dim3(64 * kWGM), 0, s, g);
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)((N + kPBN - 1) / kPBN), (unsigned)((M + kBM - 1) / kBM), (unsigned)nz);
     hipLaunchKernelGGL((zgemm_kernel<kWGM, kWGN, kTM, kPTN>), grid, dim3(64 * kWGM * kWGN), 0, s, g);
     return hipGetLastError();
@@ -468,20 +479,36 @@ __global__ __launch_bounds__(256) void block_trsm_kernel(const double2 *__restri
     }
 }
 
-// X[r][c] -= sum over z < nz of part[z][r][c] (fixed order), r < rb, c < m.
+// X[r][c] -= sum over z < nz of part[z][r][c], r < rb, c < m.  A workgroup takes 32 items
+// (consecutive in memory) and splits z into kSumSlices interleaved slices, one per 32 threads;
+// each slice sums in z order and the slices are added in slice order (a fixed order: the
+// result does not depend on the launch).  Enough workgroups to stream the partials however
+// many chunks there are.
+constexpr int kSumSlices = 8;
 __global__ __launch_bounds__(256) void part_sum_kernel(double2 *__restrict__ X, int64_t ldx, int rb, int64_t m,
                                                        const double2 *__restrict__ part, int nz) {
-    const int64_t item = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (item >= (int64_t)rb * m) return;
-    const int64_t r = item / m, c = item % m;
+    __shared__ double2 acc[kSumSlices][32];
+    const int lane = threadIdx.x & 31, slice = threadIdx.x >> 5;
+    const int64_t item = (int64_t)blockIdx.x * 32 + lane, items = (int64_t)rb * m;
     double sr = 0.0, si = 0.0;
-    for (int z = 0; z < nz; ++z) {
-        const double2 p = part[((int64_t)z * rb + r) * m + c];
-        sr += p.x;
-        si += p.y;
+    if (item < items) {
+        for (int z = slice; z < nz; z += kSumSlices) {
+            const double2 p = part[(int64_t)z * items + item];
+            sr += p.x;
+            si += p.y;
+        }
     }
-    double2 &o = X[r * ldx + c];
-    o = make_double2(o.x - sr, o.y - si);
+    acc[slice][lane] = make_double2(sr, si);
+    __syncthreads();
+    if (slice == 0 && item < items) {
+        for (int k = 1; k < kSumSlices; ++k) {
+            sr += acc[k][lane].x;
+            si += acc[k][lane].y;
+        }
+        const int64_t r = item / m, c = item % m;
+        double2 &o = X[r * ldx + c];
+        o = make_double2(o.x - sr, o.y - si);
+    }
 }
 
 hipError_t block_trsm(bool upper, const double2 *T, int64_t ldt, double2 *X, int64_t ldx, int rb, int64_t c0,
@@ -511,7 +538,7 @@ unsigned blocks(int64_t items) { return (unsigned)((items + 255) / 256); }
 int64_t lu_factor_work_bytes() { return kPivotBlocks * (int64_t)(sizeof(double) + sizeof(int64_t)); }
 
 int64_t lu_solve_work_bytes(int64_t n, int64_t m) {
-    const int64_t nz = (n + kSolveChunk - 1) / kSolveChunk;
+    const int64_t nz = (n + solve_chunk(m) - 1) / solve_chunk(m);
     return nz * kBlock * m * (int64_t)sizeof(double2);
 }
 
@@ -579,9 +606,9 @@ hipError_t lu_solve(const double2 *LU, int64_t n, int64_t lda, const int64_t *pe
     for (int64_t r0 = 0; r0 < n; r0 += kBlock) {
         const int rb = (int)std::min<int64_t>(kBlock, n - r0);
         if (r0 > 0) {
-            const int nz = (int)((r0 + kSolveChunk - 1) / kSolveChunk);
+            const int nz = (int)((r0 + solve_chunk(m) - 1) / solve_chunk(m));
             if ((e = gemm_part(part, LU + r0 * lda, lda, X, ldx, rb, m, r0, nz, s)) != hipSuccess) return e;
-            hipLaunchKernelGGL(part_sum_kernel, dim3(blocks((int64_t)rb * m)), dim3(256), 0, s, X + r0 * ldx, ldx, rb,
+            hipLaunchKernelGGL(part_sum_kernel, dim3((unsigned)(((int64_t)rb * m + 31) / 32)), dim3(256), 0, s, X + r0 * ldx, ldx, rb,
                                m, (const double2 *)part, nz);
         }
         if ((e = block_trsm(false, LU + r0 * lda + r0, lda, X + r0 * ldx, ldx, rb, 0, m, s)) != hipSuccess) return e;
@@ -591,10 +618,10 @@ hipError_t lu_solve(const double2 *LU, int64_t n, int64_t lda, const int64_t *pe
         const int rb = (int)std::min<int64_t>(kBlock, n - r0);
         const int64_t k0 = r0 + rb;
         if (k0 < n) {
-            const int nz = (int)((n - k0 + kSolveChunk - 1) / kSolveChunk);
+            const int nz = (int)((n - k0 + solve_chunk(m) - 1) / solve_chunk(m));
             if ((e = gemm_part(part, LU + r0 * lda + k0, lda, X + k0 * ldx, ldx, rb, m, n - k0, nz, s)) != hipSuccess)
                 return e;
-            hipLaunchKernelGGL(part_sum_kernel, dim3(blocks((int64_t)rb * m)), dim3(256), 0, s, X + r0 * ldx, ldx, rb,
+            hipLaunchKernelGGL(part_sum_kernel, dim3((unsigned)(((int64_t)rb * m + 31) / 32)), dim3(256), 0, s, X + r0 * ldx, ldx, rb,
                                m, (const double2 *)part, nz);
         }
         if ((e = block_trsm(true, LU + r0 * lda + r0, lda, X + r0 * ldx, ldx, rb, 0, m, s)) != hipSuccess) return e;
