@@ -1353,6 +1353,58 @@ bem_status bem_assemble_apply(bem_mesh_t h, const double *kappa, int64_t nk, con
 
 namespace {
 
+// Combination coefficients of the weight sets: coef[l][p] = sum_j Cf[j][l] W[j][p].
+std::vector<cplx> combination(const Plan &plan, const double *W, int64_t N, int64_t P) {
+    std::vector<cplx> coef((size_t)plan.L * P, 0.0);
+    for (int64_t j = 0; j < N; ++j)
+        for (int l = 0; l < plan.L; ++l) {
+            const cplx cf = plan.Cf[j * plan.L + l];
+            if (cf == cplx(0.0, 0.0)) continue;
+            for (int64_t p = 0; p < P; ++p) coef[l * P + p] += cf * cplx(W[2 * (j * P + p)], W[2 * (j * P + p) + 1]);
+        }
+    return coef;
+}
+
+// Taylor plans: the number of operators the weight sets reach.  Operator l's entries are
+// bounded by g_l = x^l / l! (x = R times the mesh diameter) times the weight, so weight set
+// p's term l is at most |coef[l][p]| g_l; the operators up to the highest l whose term exceeds
+// the truncation tolerance times the largest term of its set are reached (rounded up to the
+// length unit).  Moment weights of a circle whose centre is the expansion centre reach one
+// operator each (the trapezoidal rule integrates t^k exactly: moment p is the coefficient of
+// t^(p-1), T_(p-1) / R^(p-1)); their other coefficients are rounding noise, about sqrt(N)
+// units in the last place of the largest.  Other plans: L.
+int taylor_reach(const Plan &plan, const std::vector<cplx> &coef, int64_t P, double diameter, int64_t m) {
+    if (plan.gen != bemrat::Gen::Taylor || P < 1) return plan.L;
+    const int L = plan.L;
+    const double x = plan.R * diameter, tol = trunc_tol(plan.prec);
+    std::vector<double> g(L, 1.0);
+    for (int l = 1; l < L; ++l) g[l] = g[l - 1] * x / l;
+    std::vector<double> big(P, 0.0);
+    for (int l = 0; l < L; ++l)
+        for (int64_t p = 0; p < P; ++p) big[p] = std::max(big[p], std::abs(coef[l * P + p]) * g[l]);
+    int last = 0;
+    for (int l = 0; l < L; ++l)
+        for (int64_t p = 0; p < P; ++p)
+            if (std::abs(coef[l * P + p]) * g[l] > tol * big[p]) last = l;
+    const int unit = bemrat::sweep_ops_per_block(bemrat::Gen::Taylor, m);
+    return std::min(L, (last + unit) / unit * unit);
+}
+
+// Cuts a Taylor plan (Cf and coef) to the operators its weight sets reach; returns whether it
+// was shortened.
+bool trim_taylor(Plan &plan, std::vector<cplx> &coef, int64_t P, double diameter, int64_t m) {
+    const int L = plan.L, Lt = taylor_reach(plan, coef, P, diameter, m);
+    if (Lt >= L) return false;
+    const size_t N = plan.Cf.size() / L;
+    std::vector<cplx> Cf(N * Lt);
+    for (size_t j = 0; j < N; ++j)
+        for (int l = 0; l < Lt; ++l) Cf[j * Lt + l] = plan.Cf[j * L + l];
+    plan.Cf.swap(Cf);
+    coef.resize((size_t)Lt * P);
+    plan.L = Lt;
+    return true;
+}
+
 // The folded generator's coefficients: coef[l][p] (P columns) in rows of the fold width
 // KL = fold_width(P), zero from column P on; for Taylor plans times each operator's own
 // factor i^l / l! (the generator folds the plain power sums).
@@ -1438,21 +1490,15 @@ bem_status contour_moments_impl(bem_mesh_t h, const double *z, int64_t N, const 
     if ((st = check_block(M, m, ldm, "M")) != BEM_OK) return st;
     Plan plan = make_plan(h, z, N, m, flags);
     if (plan.unsupported) return fail(BEM_EUNSUPPORTED, "the Chebyshev form needs real nodes in a bounded interval");
-    const bool fold = plan.prec == bemrat::Prec::F64 && plan.gen != bemrat::Gen::Cheb && fold_pays(plan, P);
     symmetrize(plan);
+    std::vector<cplx> coef = combination(plan, W, N, P);
+    trim_taylor(plan, coef, P, h->diameter, m);
+    const bool fold = plan.prec == bemrat::Prec::F64 && plan.gen != bemrat::Gen::Cheb && fold_pays(plan, P);
     Params prm;
     const size_t off_tables = add_tables(prm);
     size_t off_k = 0, off_dft = 0;
     int K = 0;
     self_params(plan, prm, off_k, off_dft, K);
-    // combine coefficients: coef[l][p] = sum_j Cf[j][l] W[j][p]
-    std::vector<cplx> coef((size_t)plan.L * P, 0.0);
-    for (int64_t j = 0; j < N; ++j)
-        for (int l = 0; l < plan.L; ++l) {
-            const cplx cf = plan.Cf[j * plan.L + l];
-            if (cf == cplx(0.0, 0.0)) continue;
-            for (int64_t p = 0; p < P; ++p) coef[l * P + p] += cf * cplx(W[2 * (j * P + p)], W[2 * (j * P + p) + 1]);
-        }
     const size_t off_coef = add_complex(prm, coef);
     const size_t off_fcoef = fold ? add_complex(prm, fold_coefficients(plan, coef, (int)P)) : off_coef;
     Need need = sweep_need(h, plan, K, m);
@@ -1564,14 +1610,11 @@ bem_status rr_project(bem_mesh_t h, const double *z, int64_t N, const double *U,
     const size_t off_cf = add_complex(prm, plan.Cf);  // N x L
     size_t off_coef = 0;
     if (Pw > 0) {
-        std::vector<cplx> coef((size_t)plan.L * Pw, 0.0);
-        for (int64_t j = 0; j < N; ++j)
-            for (int l = 0; l < plan.L; ++l) {
-                const cplx cf = plan.Cf[j * plan.L + l];
-                if (cf == cplx(0.0, 0.0)) continue;
-                for (int64_t p = 0; p < Pw; ++p)
-                    coef[l * Pw + p] += cf * cplx(W[2 * (j * Pw + p)], W[2 * (j * Pw + p) + 1]);
-            }
+        // the projections need every operator; the moments combine those their weight sets
+        // reach, as contour_moments does (the coefficients past them are zero)
+        std::vector<cplx> coef = combination(plan, W, N, Pw);
+        const int reach = taylor_reach(plan, coef, Pw, h->diameter, m);
+        std::fill(coef.begin() + (size_t)reach * Pw, coef.end(), cplx(0.0, 0.0));
         off_coef = add_complex(prm, coef);
     }
     const int64_t n = h->dm.n;
@@ -2007,6 +2050,11 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
         if (!sym)
             for (int64_t i = 0; i < count; ++i) plans[i] = make_plan(meshes[i], z + 2 * i * N, N, m, BEM_FORM_DIRECT | pbits);
     }
+    // Taylor plans stop at the last operator the mesh's weight sets reach, as contour_moments'
+    for (int64_t i = 0; i < count; ++i) {
+        std::vector<cplx> coef = combination(plans[i], W + 2 * i * N * P, N, P);
+        trim_taylor(plans[i], coef, P, meshes[i]->diameter, m);
+    }
     bool decay = false;
     for (const Plan &p : plans) {
         if (p.gen == bemrat::Gen::Taylor) decay |= p.c.imag() != 0.0;
@@ -2057,15 +2105,7 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
         const Plan &plan = plans[i];
         const DeviceMesh &dm = meshes[i]->dm;
         self_params(plan, prm, off_k[i], off_dft[i], K[i]);
-        std::vector<cplx> coef((size_t)plan.L * P, 0.0);
-        const double *Wi = W + 2 * i * N * P;
-        for (int64_t j = 0; j < N; ++j)
-            for (int l = 0; l < plan.L; ++l) {
-                const cplx cf = plan.Cf[j * plan.L + l];
-                if (cf == cplx(0.0, 0.0)) continue;
-                for (int64_t p = 0; p < P; ++p)
-                    coef[l * P + p] += cf * cplx(Wi[2 * (j * P + p)], Wi[2 * (j * P + p) + 1]);
-            }
+        const std::vector<cplx> coef = combination(plan, W + 2 * i * N * P, N, P);
         b->off_coef[i] = add_complex(prm, coef);
         if (b->fold) {
             b->off_fcoef[i] = add_complex(prm, fold_coefficients(plan, coef, (int)P));
