@@ -328,3 +328,33 @@ def test_folded_moments_match_unfolded(bem, torch, sphere3, form, P, m):
         e = np.linalg.norm(Mf[p] - Mo[p]) / np.linalg.norm(Mo[p])
         print(form, P, m, p, "folded vs unfolded", d, "vs oracle", e, flush=True)
         assert d <= 1e-13 and e <= TOL
+
+
+def test_taylor_plan_stops_at_the_reach_of_the_weights(bem, torch, sphere3):
+    """Moment weights of a circle about the expansion centre reach one Taylor operator each
+    (the trapezoidal rule integrates t^k exactly), so the plan for moments of orders 1-3 stops
+    at the length unit of 8 operators and the moments still match the oracle's per-node sums;
+    resolvent weights w_j / (lam - z_j) reach further (a longer plan, still within rr_project's
+    full length), also matching the oracle."""
+    from oracle import method as M
+
+    mesh, op, _, _ = sphere3
+    V = synth.probe_block(op.n, 8, seed=4)
+    Vd = _dev(torch, V)
+    z, w, W = bem.contour_nodes(4.0, 1.5, 32, P=3)
+    s, wo = M.circle_nodes(4.0, 1.5, 32)
+    Mg = mesh.contour_moments(z, W, Vd, form=bem.FORM_EXPAND).cpu().numpy()
+    assert mesh.last_form() == (bem.FORM_EXPAND, 8)
+    Mo = M.contour_moments(op, s, M.moment_weights(s, wo, 4.0, 3), V)
+    for p in range(3):
+        assert _rel(Mg[p], Mo[p]) <= TOL, (p, _rel(Mg[p], Mo[p]))
+    mesh.rr_project(z, Vd, form=bem.FORM_EXPAND)
+    L_full = mesh.last_form()[1]
+    lam = 5.3
+    Wr = np.ascontiguousarray((w / (lam - z))[:, None])
+    Mr = mesh.contour_moments(z, Wr, Vd, form=bem.FORM_EXPAND).cpu().numpy()
+    reach = mesh.last_form()[1]
+    print("full length", L_full, "resolvent reach", reach, flush=True)
+    assert 8 < reach <= L_full
+    Mro = M.contour_moments(op, s, (wo / (lam - s))[:, None], V)
+    assert _rel(Mr[0], Mro[0]) <= TOL, _rel(Mr[0], Mro[0])
