@@ -159,10 +159,14 @@ bem_status bem_assemble_apply(bem_mesh_t mesh, const double *kappa, int64_t nk,
  * W[j][0] = w_j/(z_j - c) the sum is -S V, S = T~(c) the Schur complement).
  * z [host]: N complex nodes; W [host]: N x P complex.  V: device n x m (ldv >= m).
  * M: device, P blocks of n x m; block p starts at M + 2*p*n*ldm doubles, row stride
- * ldm >= m.  In FP64 with one or two weight sets and the DIRECT or EXPAND form, the sweep
- * folds the weights into the generated entries and contracts only the P combinations (same
- * sums, different rounding order); otherwise every generated operator is contracted and the
- * results recombined.  Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE. */
+ * ldm >= m.  The EXPAND form generates only the Taylor operators the weight sets reach
+ * (those whose largest possible contribution exceeds the expansion's truncation tolerance
+ * times the largest term of some set; moment weights of a circle about its centre reach one
+ * operator per order).  In FP64 with at most four weight sets and the DIRECT or EXPAND form,
+ * the sweep folds the weights into the generated entries and contracts only the P
+ * combinations (same sums, different rounding order); otherwise every generated operator is
+ * contracted and the results recombined.  Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM,
+ * BEM_EDEVICE. */
 bem_status contour_moments(bem_mesh_t mesh, const double *z, int64_t N, const double *W,
                            int64_t P, const double *V, int64_t m, int64_t ldv, double *M,
                            int64_t ldm, uint32_t flags, hipStream_t stream);
@@ -195,7 +199,9 @@ bem_status cheb_moments(bem_mesh_t mesh, double a, double b, int64_t N, int64_t 
 /* Rayleigh-Ritz projections Pout[j] = U^H T(z_j) U, j < N, each m x m row-major
  * contiguous (paper, Section 3: B^_j = w_j U^H T(z_j) U), optionally fused with the
  * moments M[p] = sum_j W[j][p] T(z_j) U, p < Pw, of the same sweep (W [host] N x Pw, M
- * device with row stride ldm >= m; pass W = NULL, Pw = 0, M = NULL to skip them).
+ * device with row stride ldm >= m; pass W = NULL, Pw = 0, M = NULL to skip them; in the
+ * EXPAND form the moments combine the Taylor operators their weights reach, as
+ * contour_moments does, although the projections take them all).
  * z [host]: N complex.  U: device n x m (ldu >= m).  Pout: device, N x m x m complex.
  * Errors: BEM_EINVAL, BEM_EUNSUPPORTED, BEM_ENOMEM, BEM_EDEVICE. */
 bem_status rr_project(bem_mesh_t mesh, const double *z, int64_t N, const double *U,
