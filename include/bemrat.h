@@ -478,6 +478,18 @@ bem_status bem_lu_factor(double *A, int64_t n, int64_t lda, int64_t *ipiv, int64
 bem_status bem_lu_solve(const double *LU, int64_t n, int64_t lda, const int64_t *perm, const double *B, int64_t ldb,
                         double *X, int64_t ldx, int64_t m, void *work, int64_t work_bytes, hipStream_t stream);
 
+/* Column-scaled sum of device blocks, out[r][c] = sum_{b < nb} coef[b][c] X_b[r][c], summed
+ * in the order b = 0, 1, ... (Algorithm 1 in moment-recurrence form: the right-hand side of
+ * each Schur-complement solve, S u = sum_i B_i v_i / d_i, is a sum of swept moment blocks
+ * M_p a_1, plus on restarts the block (M_1 + R_lam) x times rho^j per column, Section 3.2).
+ * blocks [host]: nb (1 <= nb <= 64) device pointers to n x m complex blocks of row stride
+ * ldx >= m.  coef: device, nb x m complex (block b's factor for column c at coef[b*m + c]).
+ * out: device n x m complex, row stride ldo >= m; it may be one of the blocks when
+ * ldo == ldx, and must not otherwise overlap one.
+ * Errors: BEM_EINVAL (sizes, strides, host pointers, overlap), BEM_EDEVICE. */
+bem_status bem_block_combine(const double *const *blocks, int64_t nb, const double *coef, int64_t n, int64_t m,
+                             int64_t ldx, double *out, int64_t ldo, hipStream_t stream);
+
 /* ---------------------------------------------------------------- diagnostics --- */
 
 /* Form the last sweep call on this handle used: BEM_FORM_DIRECT, BEM_FORM_EXPAND or

@@ -36,7 +36,7 @@ EXPORTS = [
     "contour_moments_noalloc",
     "bem_net_params", "bem_nf_labels", "bem_net_features", "bem_net_forward", "bem_net_work_floats",
     "bem_net_gradient", "bem_net_adam", "bem_nearfield_moments_net", "bem_nearfield_project",
-    "bem_lu_work_bytes", "bem_lu_factor", "bem_lu_solve",
+    "bem_lu_work_bytes", "bem_lu_factor", "bem_lu_solve", "bem_block_combine",
 ]
 
 NET_PARAMS = 37506
@@ -124,6 +124,7 @@ def lib():
     L.bem_lu_work_bytes.argtypes = [_i64, _i64]
     L.bem_lu_factor.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _i64, _vp]
     L.bem_lu_solve.argtypes = [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp]
+    L.bem_block_combine.argtypes = [ctypes.POINTER(_vp), _i64, _vp, _i64, _i64, _i64, _vp, _i64, _vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("bem_mesh_destroy", "bem_mesh_size", "bem_last_error", "bem_batch_destroy", "bem_net_params",
@@ -595,6 +596,33 @@ def net_adam(params, grad, m, v, step, lr):
     args = [_dev_tensor(t, torch.float32, (NET_PARAMS,), n) for t, n in ((params, "params"), (grad, "grad"), (m, "m"),
                                                                           (v, "v"))]
     _check(lib().bem_net_adam(*args, int(step), float(lr), _stream()))
+
+
+def block_combine(blocks, coef, out=None):
+    """out[r, c] = sum_b coef[b, c] blocks[b][r, c] on the device (bem_block_combine): blocks
+    are n x m complex128 CUDA tensors with one row stride, coef an nb x m complex array
+    (host; copied to the device), out a new n x m tensor unless given."""
+    torch = _torch()
+    blocks = list(blocks)
+    if not blocks:
+        raise ValueError("need at least one block")
+    ptrs, ldx = [], None
+    n, m = blocks[0].shape
+    for k, b in enumerate(blocks):
+        p, mb, ld = _block(b, f"blocks[{k}]")
+        if b.shape[0] != n or mb != m or (ldx is not None and ld != ldx):
+            raise ValueError("blocks must share shape and row stride")
+        ldx = ld
+        ptrs.append(p.value)
+    coef = np.ascontiguousarray(np.asarray(coef, dtype=np.complex128).reshape(len(blocks), m))
+    cd = torch.from_numpy(coef).to(blocks[0].device)
+    X = torch.empty((n, m), dtype=torch.complex128, device=blocks[0].device) if out is None else out
+    xp, mx, ldo = _block(X, "out")
+    if X.shape[0] != n or mx != m:
+        raise ValueError("out must have the blocks' shape")
+    arr = (_vp * len(ptrs))(*ptrs)
+    _check(lib().bem_block_combine(arr, len(ptrs), ctypes.c_void_p(cd.data_ptr()), n, m, ldx, xp, ldo, _stream()))
+    return X
 
 
 class LU:

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "block_combine.h"
 
 using bemrat::DeviceMesh;
 using cplx = std::complex<double>;
@@ -2381,6 +2382,28 @@ bem_status bem_lu_solve(const double *LU, int64_t n, int64_t lda, const int64_t 
     HIP_TRY(bemrat::lu_solve(reinterpret_cast<const double2 *>(LU), n, lda, perm, reinterpret_cast<const double2 *>(B),
                              ldb, reinterpret_cast<double2 *>(X), ldx, m, work, stream),
             "LU solve kernels");
+    return BEM_OK;
+}
+
+bem_status bem_block_combine(const double *const *blocks, int64_t nb, const double *coef, int64_t n, int64_t m,
+                             int64_t ldx, double *out, int64_t ldo, hipStream_t stream) {
+    if (!blocks || nb < 1 || nb > bemrat::kBlockCombineMax)
+        return fail(BEM_EINVAL, "need 1 <= nb <= 64 block pointers");
+    if (n < 1 || m < 1 || ldx < m || ldo < m) return fail(BEM_EINVAL, "need n, m >= 1, ldx and ldo >= m");
+    if (!device_ptrs({coef, out})) return fail(BEM_EINVAL, "coef and out must be device memory");
+    const int64_t xb = ((n - 1) * ldx + m) * 16, ob = ((n - 1) * ldo + m) * 16;
+    const char *o0 = reinterpret_cast<const char *>(out);
+    for (int64_t b = 0; b < nb; ++b) {
+        if (!is_device_ptr(blocks[b])) return fail(BEM_EINVAL, "every block must be device memory");
+        const char *b0 = reinterpret_cast<const char *>(blocks[b]);
+        // out may be one of the blocks (each element is read and written by one thread), not
+        // overlap one otherwise
+        if (b0 < o0 + ob && o0 < b0 + xb && !(b0 == o0 && ldo == ldx)) return fail(BEM_EINVAL, "out overlaps a block");
+    }
+    HIP_TRY(bemrat::launch_block_combine(reinterpret_cast<const double2 *const *>(blocks), (int)nb,
+                                         reinterpret_cast<const double2 *>(coef), n, m, ldx,
+                                         reinterpret_cast<double2 *>(out), ldo, stream),
+            "block combine kernel");
     return BEM_OK;
 }
 

@@ -5,7 +5,9 @@
 //           HBM-bound: every Z_l element is read once, outputs written once.
 // project:  Q_l = U^H Z_l over row chunks (partials in a fixed order, no atomics), then
 //           out_j = sum_l coef[j][l] Q_l.
+// block combine: out = sum_b coef[b] (per column) X_b over separate device blocks.
 #include "internal.h"
+#include "block_combine.h"
 
 namespace bemrat {
 
@@ -151,7 +153,39 @@ __global__ void project_add_kernel(const double2 *__restrict__ partial, int nchu
     out[idx] = make_double2(o.x + sr, o.y + si);
 }
 
+// out[r][c] = sum over b < nb of coef[b][c] X_b[r][c], in the order b = 0, 1, ... (the
+// block pointers travel in the kernel's arguments).
+struct BlockList {
+    const double2 *x[kBlockCombineMax];
+};
+
+__global__ __launch_bounds__(256) void block_combine_kernel(BlockList bl, int nb, const double2 *__restrict__ coef,
+                                                            int64_t n, int64_t m, int64_t ldx, double2 *out,
+                                                            int64_t ldo) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n * m) return;
+    const int64_t r = idx / m, c = idx % m;
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double2 w = coef[(int64_t)b * m + c];
+        const double2 v = bl.x[b][r * ldx + c];
+        sr = fma(w.x, v.x, fma(-w.y, v.y, sr));
+        si = fma(w.x, v.y, fma(w.y, v.x, si));
+    }
+    out[r * ldo + c] = make_double2(sr, si);
+}
+
 }  // namespace
+
+hipError_t launch_block_combine(const double2 *const *blocks, int nb, const double2 *coef, int64_t n, int64_t m,
+                                int64_t ldx, double2 *out, int64_t ldo, hipStream_t stream) {
+    if (nb < 1 || nb > kBlockCombineMax) return hipErrorInvalidValue;
+    BlockList bl{};
+    for (int b = 0; b < nb; ++b) bl.x[b] = blocks[b];
+    const unsigned grid = (unsigned)((n * m + 255) / 256);
+    hipLaunchKernelGGL(block_combine_kernel, dim3(grid), dim3(256), 0, stream, bl, nb, coef, n, m, ldx, out, ldo);
+    return hipGetLastError();
+}
 
 hipError_t launch_project_add(const double2 *partial, int nchunks, int L, int64_t m, double2 *out,
                               hipStream_t stream) {

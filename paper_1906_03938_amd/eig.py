@@ -89,6 +89,15 @@ class DenseFactor:
         X = _host(self.lu.solve(_device(B.reshape(B.shape[0], -1))))
         return X[:, 0] if vec else X
 
+    def solve_t(self, B):
+        """S^-1 B for an n x m tensor B: on the device in "device" mode (the result stays
+        there), through SciPy on a CPU tensor in "host" mode."""
+        if self.mode == "host":
+            import torch
+
+            return torch.from_numpy(sla.lu_solve(self.lu, B.numpy()))
+        return self.lu.solve(B)
+
 
 def _assemble(mesh, z, c, flags):
     """sum_j c_j T(z_j) on the device, generated directly in FP64 (bem_assemble_sum) with the
@@ -162,35 +171,48 @@ class ContourSolver:
         return _device(a)
 
     # -- sweeps -------------------------------------------------------------------
-    def moments(self, X, orders):
-        """M_p X for moment orders p >= 1: one contour_moments sweep of X."""
-        W = np.ascontiguousarray(self.W[:, [p - 1 for p in orders]])
-        Xd = self._dev(X)
+    def _moments_t(self, Xd, orders, sign=1.0):
+        """M_p X (sign +1) or M_p (-X) (sign -1, the weights negated: exact) for moment orders
+        p >= 1, X a device block: one contour_moments sweep; the result stays on the device."""
+        W = np.ascontiguousarray(sign * self.W[:, [p - 1 for p in orders]])
         M = self.mesh.contour_moments(self.z, W, Xd, form=self.sweep_flags)
         if self.nearfield:
             _nearfield_add(self.mesh, self.nf_model, self.z, W, Xd, M)
-        return _host(M)
+        return M
+
+    def moments(self, X, orders):
+        """M_p X for moment orders p >= 1 (host arrays): one contour_moments sweep of X."""
+        return _host(self._moments_t(self._dev(X), orders))
 
     def r_lam(self, x, lam):
         """Columns R_lam_k x_k = sum_i w_i T(z_i) x_k / (lam_k - z_i), k < x.shape[1]: one sweep
         of the block with one weight set per column (column k of weight set k is kept)."""
-        return self.moments_and_r_lam(x, [], lam)[1]
+        return _host(self._moments_and_r_lam_t(self._dev(x), [], lam)[1])
 
     def moments_and_r_lam(self, x, orders, lam):
-        """(M_p x for the moment orders, R_lam x as r_lam) from one sweep of x: the moment weight
-        sets and the per-column resolvent weight sets side by side in one contour_moments call
-        (the unfolded sweep's cost does not depend on the number of weight sets)."""
+        """(M_p x for the moment orders, R_lam x as r_lam) from one sweep of x (host arrays)."""
+        M, R = self._moments_and_r_lam_t(self._dev(x), orders, lam)
+        return _host(M), _host(R)
+
+    def _moments_and_r_lam_t(self, xd, orders, lam):
+        """The moment weight sets and the per-column resolvent weight sets side by side in one
+        contour_moments call (the unfolded sweep's cost does not depend on the number of
+        weight sets); both results stay on the device."""
         lam = np.atleast_1d(np.asarray(lam, dtype=np.complex128))
         Wm = self.W[:, [p - 1 for p in orders]]
         Wr = self.w[:, None] / (lam[None, :] - self.z[:, None])
         W = np.ascontiguousarray(np.concatenate([Wm, Wr], axis=1))
-        xd = self._dev(x)
         M = self.mesh.contour_moments(self.z, W, xd, form=self.sweep_flags)
         if self.nearfield:
             _nearfield_add(self.mesh, self.nf_model, self.z, W, xd, M)
         P = len(orders)
         k = self.torch.arange(lam.size, device=M.device)
-        return _host(M[:P]), _host(M[P + k, :, k].T)
+        return M[:P], M[P + k, :, k].T.contiguous()
+
+    def _combine(self, blocks, coef, out=None):
+        """sum_b coef[b][c] blocks[b][:, c] on the device (bem_block_combine; out may be the
+        first block)."""
+        return _lib.block_combine(blocks, coef, out=out)
 
     def schur_lu(self):
         """LU of S = M_1 = sum_i B_i/(z_i - c), assembled on the device."""
@@ -204,36 +226,41 @@ class ContourSolver:
 
     # -- Algorithm 1, q steps -------------------------------------------------------
     def inverse_iteration(self, u0, lam=None):
-        """u after q steps from v_i = u0/(c - z_i) (lam None) or v_i = u0/(lam_k - z_i)."""
+        """u after q steps from v_i = u0/(c - z_i) (lam None) or v_i = u0/(lam_k - z_i).  The
+        swept moment blocks, the right-hand sides and the iterates stay on the device (the
+        right-hand side of each step is one bem_block_combine of the swept blocks); only the
+        final block comes back."""
         lu = self.schur_lu()
         q = self.q
         restart = lam is not None
-        swept = []  # swept[k][o] = M_{o+2} a_1^(k)
+        m = np.asarray(u0).shape[1]
+        one = np.ones(m, dtype=np.complex128)
+        swept = []  # swept[k][o] = M_{o+2} a_1^(k), device
         if restart:
             rho = 1.0 / (np.asarray(lam, dtype=np.complex128) - self.c)  # per column
-            x = np.asarray(u0, dtype=np.complex128)
-            Mx, Rx = self.moments_and_r_lam(x, list(range(1, q + 2)), lam)  # M_1 x .. M_{q+1} x, R_lam x
-            base = Mx[0] + Rx                                            # (M_1 + R_lam) x
+            xd = self._dev(np.asarray(u0, dtype=np.complex128))
+            Mx, Rx = self._moments_and_r_lam_t(xd, list(range(1, q + 2)), lam)  # M_1 x .. M_{q+1} x, R_lam x
+            base = self._combine([Mx[0], Rx], np.stack([one, one]))      # (M_1 + R_lam) x
             swept.append(None)                                           # no a_1^(0) on restarts
         else:
-            swept.append(self.moments(-u0, list(range(2, q + 2))))       # a_1^(0) = -u0
-        u = u0
+            swept.append(self._moments_t(self._dev(u0), list(range(2, q + 2)), sign=-1.0))  # a_1^(0) = -u0
+        u = None
         for j in range(q):
-            acc = np.zeros_like(u0, dtype=np.complex128)
-            for k in range(j + 1):
-                if swept[k] is not None:
-                    acc += swept[k][j - k]                               # M_{j-k+2} a_1^(k)
+            blocks = [swept[k][j - k] for k in range(j + 1) if swept[k] is not None]  # M_{j-k+2} a_1^(k)
+            coef = [one] * len(blocks)
             if restart:
-                acc += base * rho[None, :] ** (j + 1)
-            u = lu.solve(acc)
+                blocks.append(base)
+                coef.append(rho ** (j + 1))
+            acc = self._combine(blocks, np.stack(coef))
+            u = lu.solve_t(acc)
             if j + 1 < q:
-                a1 = -u
                 orders = list(range(2, q - j + 1))                       # still needed by steps j+1 .. q-1
-                Ma = self.moments(a1, orders)
+                Ma = self._moments_t(u, orders, sign=-1.0)               # a_1 = -u
                 if restart:                                              # a_1 += x rho^(j+1)
-                    Ma = Ma + Mx[1:1 + len(orders)] * rho[None, None, :] ** (j + 1)
+                    for o in range(len(orders)):
+                        self._combine([Ma[o], Mx[1 + o]], np.stack([one, rho ** (j + 1)]), out=Ma[o])
                 swept.append(Ma)
-        return u
+        return np.asarray(u0) if u is None else _host(u)
 
     # -- Rayleigh-Ritz ---------------------------------------------------------------
     def reduced_pencil(self, Bhat):

@@ -41,13 +41,21 @@ class DenseMesh:
 
 
 class CpuSolver(ContourSolver):
-    """The contour driver on host tensors, its LU through SciPy (lu="host")."""
+    """The contour driver on host tensors, its LU through SciPy (lu="host"), the block sums
+    of its right-hand sides in numpy."""
 
     def __init__(self, *args, **kw):
         super().__init__(*args, lu="host", **kw)
 
     def _dev(self, a):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
+
+    def _combine(self, blocks, coef, out=None):
+        s = sum(np.asarray(coef[b])[None, :] * blocks[b].numpy() for b in range(len(blocks)))
+        if out is None:
+            return torch.from_numpy(np.ascontiguousarray(s))
+        out.copy_(torch.from_numpy(s))
+        return out
 
 
 class CpuIntervalSolver(IntervalSolver):
