@@ -1,4 +1,4 @@
-"""Eigen-extraction at the full sweep size (opt-in: set BEMRAT_LARGE_TESTS=1; about 8 minutes
+"""Eigen-extraction at the full sweep size (opt-in: set BEMRAT_LARGE_TESTS=1; about 4 minutes
 on one MI355X, of which 23 s is the LU): sphere-81920 (unit icosphere level 6), the circle
 |z - 5| = 2 with N = 64 trapezoidal nodes, 32 probes (seed 2), q = 10, tol 1e-12.  The Schur
 complement S (107 GB) is generated on the device and factorised in place by the library's
@@ -19,7 +19,7 @@ import synth
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(os.environ.get("BEMRAT_LARGE_TESTS") != "1",
-                                 reason="about 8 minutes: set BEMRAT_LARGE_TESTS=1")]
+                                 reason="about 4 minutes: set BEMRAT_LARGE_TESTS=1")]
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -40,7 +40,7 @@ def test_sphere81920_contour_eigenvalues():
     spent = {"inverse_iteration": 0.0, "rayleigh_ritz": 0.0, "residuals": 0.0}
 
     class Progress(ContourSolver):
-        """Prints a line per outer iteration (each takes about 17 s here) and adds up the time
+        """Prints a line per outer iteration (each takes about 8 s here) and adds up the time
         of the three phases of an outer iteration."""
 
         def _timed(self, name, f, *a):
