@@ -61,6 +61,18 @@ def _device(a):
     return h.to("cuda", non_blocking=True)
 
 
+def _combine_blocks(combine, blocks, coef):
+    """sum_b coef[b][c] blocks[b][:, c] through `combine` (at most 64 blocks per call: longer
+    sums continue from the previous partial sum as their first block)."""
+    blocks = list(blocks)
+    coef = np.asarray(coef, dtype=np.complex128)
+    out = combine(blocks[:64], coef[:64])
+    one = np.ones((1, coef.shape[1]), dtype=np.complex128)
+    for b0 in range(64, len(blocks), 63):
+        out = combine([out] + blocks[b0:b0 + 63], np.concatenate([one, coef[b0:b0 + 63]]), out=out)
+    return out
+
+
 class DenseFactor:
     """LU factorisation P S = L U (partial pivoting) of the dense n x n complex matrix of the
     inverse iteration, held on the device, with solves for host right-hand sides.  "device"
@@ -439,13 +451,22 @@ class IntervalSolver:
     def _dev(self, a):
         return _device(a)
 
-    def sweep(self, X, ages):
+    def _sweep_t(self, Xd, ages):
+        """Age sweeps of a device block (contour_moments on the Chebyshev nodes); the result
+        stays on the device."""
         W = np.ascontiguousarray(self.W_age[:, list(ages)])
-        Xd = self._dev(X)
         M = self.mesh.contour_moments(self.z, W, Xd, form=self.sweep_flags)
         if self.nearfield:
             self.mesh.nearfield_moments(self.z, W, Xd, out=M)
-        return _host(M)
+        return M
+
+    def sweep(self, X, ages):
+        return _host(self._sweep_t(self._dev(X), ages))
+
+    def _combine(self, blocks, coef, out=None):
+        """sum_b coef[b][c] blocks[b][:, c] on the device (bem_block_combine; out may be the
+        first block)."""
+        return _lib.block_combine(blocks, coef, out=out)
 
     def g_lu(self):
         """LU of G = sum_l B_l T_l(s) = sum_j T(kappa_j) sum_l coef[l, j] T_l(s), assembled on
@@ -461,39 +482,39 @@ class IntervalSolver:
 
     def inverse_iteration(self, u0, xi=None):
         """u after q steps of Algorithm 2 from v_l = T_l(s) u0 (xi None) or from the restart
-        blocks v_l = T_l(xi_k) u0[:, k]."""
+        blocks v_l = T_l(xi_k) u0[:, k].  The swept blocks, right-hand sides and iterates stay
+        on the device (bem_block_combine forms the right-hand sides and the restart terms);
+        only the final block comes back."""
         lu = self.g_lu()
         q = self.q
         u0 = np.asarray(u0, dtype=np.complex128)
-        swept = []                                   # swept[k][a]: age-a sweep of iterate k
+        one = np.ones(u0.shape[1], dtype=np.complex128)
+        swept = []                                   # swept[k][a]: age-a sweep of iterate k (device)
         restart = None
         if xi is None:
-            swept.append(self.sweep(u0, range(q)))
+            swept.append(self._sweep_t(self._dev(u0), range(q)))
         else:
             u0d = self._dev(u0)
             Cx = self.mesh.cheb_moments(self.a, self.b, self.N, self.N, u0d, form=self.sweep_flags)
             if self.nearfield:  # C_l += sum_k coef[l, k] dT(kappa_k) u0
                 self.mesh.nearfield_moments(self.z, np.ascontiguousarray(self.coef.T), u0d, out=Cx)
-            Cx = _host(Cx)
             g = self._tvals(np.asarray(xi, dtype=np.complex128))[:self.d]   # d x m
             restart = []
             for _ in range(q):
-                p = self._drive(g)
-                restart.append(-np.einsum("lk,lak->ak", p, Cx))
+                p = self._drive(g)                   # -sum_l p[l, k] C_l[:, k]
+                restart.append(_combine_blocks(self._combine, [Cx[l] for l in range(self.N)], -p))
                 g = p[:self.d]
             swept.append(None)
-        u = u0
+        u = None
         for j in range(q):
-            rhs = np.zeros_like(u0)
-            for k in range(j + 1):
-                if swept[k] is not None:
-                    rhs += swept[k][j - k]
+            blocks = [swept[k][j - k] for k in range(j + 1) if swept[k] is not None]
             if restart is not None:
-                rhs += restart[j]
-            u = lu.solve(rhs)
+                blocks.append(restart[j])
+            rhs = _combine_blocks(self._combine, blocks, np.stack([one] * len(blocks)))
+            u = lu.solve_t(rhs)
             if j + 1 < q:
-                swept.append(self.sweep(u, range(q - 1 - j)))
-        return u
+                swept.append(self._sweep_t(u, range(q - 1 - j)))
+        return u0 if u is None else _host(u)
 
     def reduced_pencil(self, Bhat):
         """eq. sc1_chebyshev_red: unknowns [y, v_1 .. v_{d-1}]; rows xi y = v_1,

@@ -65,6 +65,8 @@ class CpuIntervalSolver(IntervalSolver):
     def _dev(self, a):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
 
+    _combine = CpuSolver._combine
+
 
 @pytest.fixture(scope="module")
 def setup():
