@@ -266,3 +266,26 @@ def test_nearfield_option_corrects_every_sweep(route):
     assert res.max() <= 1e-12 and lam.size == lo.size
     assert np.abs(np.sort_complex(lam) - np.sort_complex(lo)).max() <= 1e-10 * np.abs(lo).max()
     assert np.abs(np.sort_complex(lp) - np.sort_complex(lo)).max() >= 1e-6 * np.abs(lo).max()
+
+
+def test_combine_blocks_continues_past_64():
+    """The drivers' block sums take at most 64 blocks per library call; longer sums (the
+    Chebyshev restart terms over N blocks) continue from the partial sum as the first block."""
+    from paper_1906_03938_amd.eig import _combine_blocks
+
+    rng = np.random.default_rng(3)
+    calls = []
+
+    def combine(blocks, coef, out=None):
+        calls.append(len(blocks))
+        assert len(blocks) <= 64 and coef.shape == (len(blocks), 5)
+        return CpuSolver._combine(None, blocks, coef, out)
+
+    for nb in (1, 64, 65, 127, 150):
+        calls.clear()
+        blocks = [torch.from_numpy(rng.standard_normal((7, 5)) + 1j * rng.standard_normal((7, 5))) for _ in range(nb)]
+        coef = rng.standard_normal((nb, 5)) + 1j * rng.standard_normal((nb, 5))
+        out = _combine_blocks(combine, blocks, coef).numpy()
+        ref = sum(coef[b][None, :] * blocks[b].numpy() for b in range(nb))
+        assert np.allclose(out, ref, rtol=1e-13, atol=1e-13), nb
+        assert sum(calls) - (len(calls) - 1) == nb  # every block once, plus the carried partial sums
