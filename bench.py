@@ -249,9 +249,9 @@ def batched_form():
     eager_out = out.clone()
     L = batch.operators.astype(np.float64)
     units = float(np.sum(w["N"] * sizes ** 2 * w["m"]))
-    # an FP64 batch with one or two weight sets folds them into the sweep (every operator of
+    # an FP64 batch with up to four weight sets folds them into the sweep (every operator of
     # an entry generated, only the P folds contracted), as contour_moments does per mesh
-    folded = w["P"] <= 2
+    folded = w["P"] <= 4
     flops = float(np.sum(8.0 * (w["P"] if folded else L) * sizes ** 2 * w["m"]))
     achieved = flops / (kms * 1e-3) / 1e12
     # the same call captured once in a HIP graph (the path a serving loop takes) and replayed;

@@ -1869,7 +1869,7 @@ struct bem_batch {
     std::vector<size_t> off_coef, off_probe, off_Z;
     int64_t nitems = 0;
     std::vector<size_t> off_self;
-    // folded (FP64, at most kFoldBatchMax = 2 weight sets): each mesh's fold coefficients, folded diagonal,
+    // folded (FP64, at most kFoldBatchMax = 4 weight sets): each mesh's fold coefficients, folded diagonal,
     // and the P x P identity that copies its folds out of Z
     bool fold = false;
     std::vector<size_t> off_fcoef, off_fself;
@@ -2076,11 +2076,10 @@ bem_status bem_batch_create(const bem_mesh_t *meshes, int64_t count, const doubl
                                        decay);
     b->prec = prec;
     b->meshes.assign(meshes, meshes + count);
-    // FP64 with one or two weight sets folds them into the sweep, as contour_moments does
-    // (which folds up to four)
+    // FP64 with up to four weight sets folds them into the sweep, as contour_moments does
     b->fold = !lp && P <= bemrat::kFoldBatchMax;
     for (const Plan &p : plans)
-        b->fold = b->fold && (int64_t)p.L * P <= bemrat::kFoldCoef;
+        b->fold = b->fold && (int64_t)p.L * bemrat::fold_width((int)P) <= bemrat::kFoldCoef;
     const int max_cb = batch_max_col_tile(b);
     b->cb = max_cb;
     b->m_pad = (m + 16 * max_cb - 1) / (16 * max_cb) * (16 * max_cb);

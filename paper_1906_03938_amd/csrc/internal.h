@@ -113,11 +113,11 @@ int batch_ops_per_item_f64(Gen gen, int cb);  // the same for a batched work ite
 hipError_t launch_sweep_batch(int variant, int cb, const BatchEntry *table, const int4 *items, int nitems,
                               unsigned *counter, int grid, hipStream_t stream);
 int batch_variant(Gen gen, bool decay);  // BatchVariant of an operator family, -1 if none
-// Folded batch (FP64, P <= kFoldBatchMax = 2 weight sets per mesh): items (mesh, row block,
-// column block, 0); each mesh's args carry L = P, Lgen, fcoef (Lgen rows of P, at most
-// kFoldCoef entries) and its folded diagonal in self, and the folds land in its Z like
-// operators.
-constexpr int kFoldBatchMax = 2;
+// Folded batch (FP64, P <= kFoldBatchMax = 4 weight sets per mesh, fold width fold_width(P)):
+// items (mesh, row block, column block, 0); each mesh's args carry L = P, Lgen, fcoef (Lgen
+// rows of the fold width, at most kFoldCoef entries) and its folded diagonal in self, and the
+// folds land in its Z like operators.
+constexpr int kFoldBatchMax = 4;
 hipError_t launch_sweep_fold_batch(int variant, int cb, int P, const BatchEntry *table, const int4 *items, int nitems,
                                    unsigned *counter, int grid, hipStream_t stream);
 // The same at reduced precision (each table entry carries its mesh's a_scale and probe-scale

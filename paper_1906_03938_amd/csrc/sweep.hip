@@ -302,8 +302,8 @@ __global__ __launch_bounds__(512, 1) void sweep_batch_kernel(const BatchEntry *_
     }
 }
 
-// Folded persistent batch: as sweep_batch_kernel with the folded tile (each mesh's KL = 1 or 2
-// weight sets: every operator of an entry generated and folded, only the folds contracted);
+// Folded persistent batch: as sweep_batch_kernel with the folded tile (each mesh's P <= 4 weight
+// sets at the fold width KL = 1, 2 or 4: every operator of an entry generated and folded, only the folds contracted);
 // the items carry no operator block.  A tile copies its mesh's fold coefficients into LDS
 // behind the previous tile's last barrier.
 template <int CB, Gen GEN, bool DECAY, int KL>
@@ -436,8 +436,11 @@ hipError_t launch_sweep_fold_batch(int variant, int cb, int P, const BatchEntry 
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return P == 1 ? launch_fold_batch_k<1>(variant, cb, table, items, nitems, counter, grid, stream)
-                  : launch_fold_batch_k<2>(variant, cb, table, items, nitems, counter, grid, stream);
+    switch (fold_width(P)) {
+        case 1: return launch_fold_batch_k<1>(variant, cb, table, items, nitems, counter, grid, stream);
+        case 2: return launch_fold_batch_k<2>(variant, cb, table, items, nitems, counter, grid, stream);
+        default: return launch_fold_batch_k<4>(variant, cb, table, items, nitems, counter, grid, stream);
+    }
 }
 
 hipError_t launch_sweep_fold(Gen gen, const SweepArgs &args, hipStream_t stream) {

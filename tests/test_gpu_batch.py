@@ -2,8 +2,9 @@
 one generate-and-contract launch): parity with the oracle's per-mesh contour moments
 (1e-12 normwise per mesh and weight set), bitwise equality with the per-mesh entry point
 in the same form (the tiles run the same arithmetic in the same order, whatever the column
-tile the autotuner picks; one or two weight sets folded into the sweep as contour_moments
-does, more contracted per operator and recombined as rr_project's fused moments are), graph capture and replay, error paths, and sampled-row parity
+tile the autotuner picks; up to four weight sets folded into the sweep as contour_moments
+does, more contracted per operator and recombined as rr_project's fused moments are), graph
+capture and replay, error paths, and sampled-row parity
 on the full 64-ellipsoid workload (geodesic frequencies 10..44, 2,000-38,720 triangles
 per mesh, circles |z - c_i| = 1 with c_i in [3, 7], N = 32, m = 32, seed 4)."""
 import numpy as np
@@ -84,30 +85,58 @@ def test_batch_bitwise_equals_per_mesh(small, form, tune):
             assert torch.equal(Mi, Mb[i]), i
 
 
+def _weights(bem, spec, N, P):
+    z, W = [], []
+    for _, _, _, c in spec:
+        zi, _, Wi = bem.contour_nodes(c, 1.0, N, P=P)
+        z.append(zi)
+        W.append(Wi)
+    return np.array(z), np.array(W)
+
+
+@pytest.mark.parametrize("form", ["direct", "expand"])
+@pytest.mark.parametrize("P", [3, 4])
+def test_batch_folds_four_weight_sets_bitwise(small, form, P):
+    """Three or four weight sets: the batch folds them at width 4 (the P = 3 coefficient rows
+    padded with a zero column), as contour_moments does per mesh, bitwise equal to it and
+    within the oracle's tolerance."""
+    bem, torch, spec, meshes, z, W, V, N, _, m = small
+    from oracle import method as M
+
+    f = {"direct": bem.FORM_DIRECT, "expand": bem.FORM_EXPAND}[form]
+    zP, WP = _weights(bem, spec, N, P)
+    with bem.Batch(meshes, zP, WP, m, form=f) as b:
+        Mb = b.split(b.moments(_packed(torch, V)))
+        for i, mesh in enumerate(meshes):
+            Mi = mesh.contour_moments(zP[i], WP[i], torch.from_numpy(V[i]).to("cuda"), form=f)
+            assert mesh.last_form()[0] == b.form and mesh.last_form()[1] == b.operators[i]
+            assert torch.equal(Mi, Mb[i]), i
+            x, t, _, c = spec[i]
+            zo, wo = M.circle_nodes(c, 1.0, N)
+            Mo = M.contour_moments(M.Operator(x, t), zo, M.moment_weights(zo, wo, c, P), V[i])
+            for q in range(P):
+                assert _rel(Mb[i][q].cpu().numpy(), Mo[q]) <= TOL, (i, q)
+
+
 @pytest.mark.parametrize("form", ["direct", "expand"])
 def test_batch_unfolded_bitwise_equals_per_mesh(small, form):
-    """Three weight sets: the batch contracts every operator and recombines, as rr_project's
+    """Five weight sets: the batch contracts every operator and recombines, as rr_project's
     fused moments do per mesh (the same sweep tiles and recombination), and matches the
     oracle."""
     bem, torch, spec, meshes, z, W, V, N, P, m = small
     from oracle import method as M
 
     f = {"direct": bem.FORM_DIRECT, "expand": bem.FORM_EXPAND}[form]
-    z3, W3 = [], []
-    for _, _, _, c in spec:
-        zi, _, Wi = bem.contour_nodes(c, 1.0, N, P=3)
-        z3.append(zi)
-        W3.append(Wi)
-    z3, W3 = np.array(z3), np.array(W3)
-    with bem.Batch(meshes, z3, W3, m, form=f) as b:
+    z5, W5 = _weights(bem, spec, N, 5)
+    with bem.Batch(meshes, z5, W5, m, form=f) as b:
         Mb = b.split(b.moments(_packed(torch, V)))
         for i, mesh in enumerate(meshes):
-            _, Mi = mesh.rr_project(z3[i], torch.from_numpy(V[i]).to("cuda"), W=W3[i], form=f)
+            _, Mi = mesh.rr_project(z5[i], torch.from_numpy(V[i]).to("cuda"), W=W5[i], form=f)
             assert torch.equal(Mi, Mb[i]), i
             x, t, _, c = spec[i]
             zo, wo = M.circle_nodes(c, 1.0, N)
-            Mo = M.contour_moments(M.Operator(x, t), zo, M.moment_weights(zo, wo, c, 3), V[i])
-            for q in range(3):
+            Mo = M.contour_moments(M.Operator(x, t), zo, M.moment_weights(zo, wo, c, 5), V[i])
+            for q in range(5):
                 assert _rel(Mb[i][q].cpu().numpy(), Mo[q]) <= TOL, (i, q)
 
 
